@@ -1,0 +1,108 @@
+"""Pins of the MoM forward solver (Eqs. 3-5, 8): Mie series, solver
+agreement, reciprocity, Born limit, the CIE data equation, noise level."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import forward, operators as ops
+
+WL = si.WORKLOADS["cfg1"]
+LAM = WL.wavelength
+K0 = ops.wavenumber(WL.freq_hz)
+
+
+def disc(eps, r=0.35, c=(0.1, -0.05)):
+    return si.Shape("ellipse", c[0] * LAM, c[1] * LAM, r * LAM, r * LAM, 0.0, complex(eps))
+
+
+def test_mie_series_converged_and_trivial():
+    tx = si.antenna_positions(8, WL.radius)
+    rx = si.antenna_positions(12, WL.radius)
+    a = forward.mie_scattered(3.0, 0.35 * LAM, (0.0, 0.0), tx, rx, K0)
+    b = forward.mie_scattered(3.0, 0.35 * LAM, (0.0, 0.0), tx, rx, K0, n_extra=40)
+    assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(a))
+    z = forward.mie_scattered(1.0, 0.35 * LAM, (0.0, 0.0), tx, rx, K0)
+    assert np.max(np.abs(z)) < 1e-14 * np.max(np.abs(a))
+
+
+@pytest.mark.slow
+def test_mom_converges_to_mie():
+    tx = si.antenna_positions(WL.n_tx, WL.radius)
+    rx = si.antenna_positions(WL.n_rx, WL.radius)
+    for eps_r in (3.0, 2.0 + 0.5j):
+        mie = forward.mie_scattered(eps_r, 0.35 * LAM, (0.1 * LAM, -0.05 * LAM), tx, rx, K0)
+        errs = []
+        for Mf in (32, 64, 128):
+            e, _ = forward.mom_solve(si.rasterize([disc(eps_r)], Mf, WL.side), WL.side, K0, tx, rx)
+            errs.append(np.linalg.norm(e - mie) / np.linalg.norm(mie))
+        # at least first-order convergence under refinement, and a bound at the finest grid
+        assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1], errs
+        assert errs[2] < 5e-3, errs
+
+
+def test_solvers_agree():
+    tx = si.antenna_positions(4, WL.radius)
+    rx = si.antenna_positions(6, WL.radius)
+    eps = si.rasterize([disc(2.5, 0.3)], 24, WL.side)
+    a, _ = forward.mom_solve(eps, WL.side, K0, tx, rx, "support")
+    b, _ = forward.mom_solve(eps, WL.side, K0, tx, rx, "dense")
+    c, _ = forward.mom_solve(eps, WL.side, K0, tx, rx, "gmres")
+    n = np.linalg.norm(a)
+    assert np.linalg.norm(a - b) < 1e-10 * n
+    assert np.linalg.norm(a - c) < 1e-10 * n
+
+
+def test_reciprocity():
+    # Tx positions = Rx positions: the scattered-field matrix is symmetric.
+    ant = si.antenna_positions(10, WL.radius)
+    shapes = si.draw_profile(WL, 3)
+    eps = si.rasterize(shapes, 32, WL.side)
+    S, _ = forward.mom_solve(eps, WL.side, K0, ant, ant)
+    assert np.max(np.abs(S - S.T)) < 1e-12 * np.max(np.abs(S))
+
+
+def test_born_limit():
+    tx = si.antenna_positions(4, WL.radius)
+    rx = si.antenna_positions(5, WL.radius)
+    M = 16
+    base = si.rasterize([disc(2.0, 0.3)], M, WL.side) - 1.0
+    gs = ops.gs_matrix(rx, M, WL.side, K0)
+    einc = ops.einc_matrix(tx, M, WL.side, K0)
+    ratios = []
+    for t in (1e-2, 5e-3, 2.5e-3):
+        chi = t * base
+        e, _ = forward.mom_solve(1.0 + chi, WL.side, K0, tx, rx)
+        born = (gs @ (chi.reshape(-1)[None, :] * einc).T).T
+        ratios.append(np.linalg.norm(e - born) / t ** 2)
+    # the remainder is O(chi^2): its ratio to t^2 is constant as t -> 0
+    assert abs(ratios[1] / ratios[0] - 1) < 0.02 and abs(ratios[2] / ratios[1] - 1) < 0.01
+
+
+@pytest.mark.parametrize("beta", [1.0, 6.0, 2.0 + 1.0j])
+def test_cie_data_equation(beta):
+    # Eq. 8: E_sca = (1/beta) G_S [I - R (I + G_D/beta)]^-1 R E_inc, R = beta chi/(beta chi + 1)
+    M = 12
+    tx = si.antenna_positions(3, WL.radius)
+    rx = si.antenna_positions(4, WL.radius)
+    eps = si.rasterize([disc(3.0, 0.3)], M, WL.side)
+    e, _ = forward.mom_solve(eps, WL.side, K0, tx, rx, "dense")
+    chi = (eps - 1).reshape(-1)
+    R = beta * chi / (beta * chi + 1)
+    G = ops.gd_dense(M, WL.side / M, K0)
+    gs = ops.gs_matrix(rx, M, WL.side, K0)
+    einc = ops.einc_matrix(tx, M, WL.side, K0)
+    A = np.eye(M * M) - R[:, None] * (np.eye(M * M) + G / beta)
+    cie = (gs @ np.linalg.solve(A, R[:, None] * einc.T) / beta).T
+    assert np.linalg.norm(cie - e) < 1e-10 * np.linalg.norm(e)
+
+
+def test_noise_level_and_reproducibility():
+    rng = np.random.default_rng(0)
+    e = rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))
+    n1, n2 = si.draw_noise(7, e.shape)
+    m1, m2 = si.draw_noise(7, e.shape)
+    assert np.array_equal(n1, m1) and np.array_equal(n2, m2)
+    for nu in (0.05, 0.1, 10 ** (-10 / 20)):
+        noisy = forward.add_noise(e, nu, n1, n2)
+        ratio = np.linalg.norm(noisy - e) / np.linalg.norm(e)
+        assert abs(ratio / nu - 1) < 0.03

@@ -1,0 +1,135 @@
+"""Pins of the start value (Sec. 3.1, Eq. 12), the CCO (Sec. 2.4, Eqs. 10-11),
+the image error and Adam (Sec. 3.3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from oracle import adam, cco, fourier, forward, init, loss, operators as ops, solver
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+WL = si.WORKLOADS["cfg1"]
+K0 = ops.wavenumber(WL.freq_hz)
+
+
+def problem(M=16, K=7, seed=0):
+    tx = si.antenna_positions(6, WL.radius)
+    rx = si.antenna_positions(8, WL.radius)
+    shapes = si.draw_profile(WL, seed)
+    es, _ = forward.mom_solve(si.rasterize(shapes, 2 * M, WL.side), WL.side, K0, tx, rx)
+    return loss.build_problem(M, K, WL.side, [WL.freq_hz], tx, rx, es), shapes
+
+
+def test_bp_scalar_is_least_squares():
+    prob, _ = problem()
+    e = prob.esca[0][2]
+    u = np.conj(prob.gs[0]).T @ e
+    v = prob.gs[0] @ u
+    gamma = np.vdot(v, e) / np.vdot(v, v)
+    f0 = np.linalg.norm(gamma * v - e)
+    for dr in np.linspace(-0.2, 0.2, 9):
+        for di in np.linspace(-0.2, 0.2, 9):
+            g = gamma * (1 + dr + 1j * di)
+            assert np.linalg.norm(g * v - e) >= f0 - 1e-15
+
+
+def test_alpha0_is_exact_line_search_of_csi():
+    prob, _ = problem()
+    a0, info = init.alpha0(prob)
+    R0, g, t = info["R0"], info["g"], info["t"]
+    f = lambda tt: init.csi_loss(prob, R0, -tt * g)
+    ft = f(t)
+    for s in np.linspace(0.0, 3.0 * t, 61):
+        assert ft <= f(s) + 1e-13
+    assert ft < f(0.0)
+
+
+def test_csi_gradient_fd():
+    prob, _ = problem()
+    _, info = init.alpha0(prob)
+    R0, g = info["R0"], info["g"]
+    z = np.zeros_like(g)
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in g.shape)
+        for d in (1.0, 1j):
+            h = 1e-6
+            zp, zm = z.copy(), z.copy()
+            zp[idx] += h * d
+            zm[idx] -= h * d
+            fd = (init.csi_loss(prob, R0, zp) - init.csi_loss(prob, R0, zm)) / (2 * h)
+            an = g[idx].real if d == 1.0 else g[idx].imag
+            assert abs(fd - an) < 1e-6 * np.max(np.abs(g))
+
+
+def test_cco_constants_are_the_papers():
+    import inspect
+    sig = inspect.signature(cco.cco)
+    assert sig.parameters["tau"].default == GOLD["cco_tau"]["value"]
+    assert sig.parameters["eta_max"].default == GOLD["cco_eta_max"]["value"]
+    assert sig.parameters["delta"].default == GOLD["cco_delta"]["value"]
+
+
+def test_cco_special_cases():
+    c = 1.3 + 0.4j
+    chi = np.full((6, 7), c)
+    assert np.allclose(cco.guided_self(chi.real), c.real, rtol=0, atol=1e-15)
+    eta = 0.1 / (1 + np.exp(-(abs(c) - 3) / 0.5))
+    assert np.allclose(cco.cco(chi), (1 + 2 * eta) * c, rtol=1e-14)
+    # eta at |chi| = tau is exactly eta_max / 2
+    chi3 = np.full((3, 3), 3.0 + 0j)
+    assert np.allclose(cco.cco(chi3), 3.0 * (1 + 2 * 0.05), rtol=1e-15)
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal((8, 9))
+    # eps -> 0: the filter is the identity (where windows are not constant)
+    assert np.max(np.abs(cco.guided_self(p, 1, 1e-14) - p)) < 1e-9
+    # eps -> infinity: the filter is a box mean of the box mean
+    assert np.max(np.abs(cco.guided_self(p, 1, 1e14) - cco.box_mean(cco.box_mean(p, 1), 1))) < 1e-12
+    # count-normalised box mean at a corner: mean of the 2 x 2 in-grid window
+    assert abs(cco.box_mean(p, 1)[0, 0] - p[:2, :2].mean()) < 1e-15
+    # with G = identity the peak |chi| never decreases
+    z = rng.standard_normal((8, 8)) * 2 + 1j * rng.standard_normal((8, 8))
+    eta = 0.1 / (1 + np.exp(-(np.abs(z) - 3) / 0.5))
+    assert np.max(np.abs((1 + 2 * eta) * z)) >= np.max(np.abs(z))
+
+
+def test_image_error_zero_at_truth():
+    eps = si.rasterize(si.draw_profile(WL, 1), 16, WL.side)
+    assert cco.image_error(eps - 1.0, eps) == 0.0
+
+
+def test_adam_first_step_and_torch():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((3, 5, 5)) + 1j * rng.standard_normal((3, 5, 5))
+    m = np.zeros(a.shape + (2,))
+    v = np.zeros(a.shape + (2,))
+    g = rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape)
+    a1, m1, v1 = adam.adam_step(a, g, m, v, 1)
+    ref = a - 1e-2 * (g.real / (np.abs(g.real) + 1e-8) + 1j * g.imag / (np.abs(g.imag) + 1e-8))
+    assert np.max(np.abs(a1 - ref)) < 1e-15
+    # multi-step sequence against torch.optim.Adam on view_as_real(alpha)
+    p = torch.tensor(a.copy())
+    p.requires_grad_(True)
+    opt = torch.optim.Adam([p], lr=GOLD["adam_lr"]["value"])
+    x, mm, vv = a.copy(), m, v
+    for t in range(1, 8):
+        gt = rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape)
+        opt.zero_grad()
+        p.grad = torch.tensor(gt)
+        opt.step()
+        x, mm, vv = adam.adam_step(x, gt, mm, vv, t)
+    assert np.max(np.abs(p.detach().numpy() - x)) < 1e-14
+
+
+@pytest.mark.slow
+def test_reconstruction_improves_on_the_start():
+    prob, shapes = problem(M=16, K=7, seed=2)
+    et = si.rasterize(shapes, 16, WL.side)
+    a0, info = init.alpha0(prob)
+    res = solver.reconstruct(prob, 60, a0, eps_true=et)
+    start = cco.image_error(cco.cco(loss.evaluate(a0, prob, grad=False)["chi"]), et)
+    assert res["loss"][-1] < res["loss"][0]
+    assert res["err"] < start
