@@ -1,0 +1,191 @@
+/*
+ * pdf.h - C ABI of the MI355X (gfx950) Physics-Driven Fourier-Spectral (PDF)
+ * inverse-scattering hot path.
+ *
+ * The library evaluates, for B independent data sets that share one
+ * measurement geometry, the composite PDF loss (Sec. 3.2, Eqs. 13-19) of
+ * truncated Fourier coefficients alpha of the induced currents (Sec. 2.3,
+ * Eq. 9) and its gradient, applies Adam (Sec. 3.3), computes the
+ * back-propagation start (Sec. 3.1), the CIE contrast and the
+ * contrast-compensated image (Sec. 2.4, Eqs. 10-11), and synthesises
+ * measured fields with an FP64 method-of-moments solve (Sec. 2.1, Eqs. 3-4).
+ *
+ * Conventions (all entry points)
+ *   - Every function returns an int status: PDF_OK (0) or a negative code.
+ *     No C++ exception crosses the ABI.  pdf_last_error(h) gives a message.
+ *   - Complex arrays are interleaved (re, im), C-contiguous, in the
+ *     handle's precision: float pairs for PDF_FP32, double pairs for PDF_FP64.
+ *   - "_dev" pointers are device pointers owned by the caller; the handle
+ *     owns its operator tables and scratch and frees them in pdf_destroy.
+ *   - Calls are asynchronous on the stream given to pdf_setup unless stated.
+ *     One handle is used from one host thread / stream at a time.
+ *   - Grid: row i runs along y, column j along x, pixel n = i*M + j, pixel
+ *     centres at centre - side/2 + (index + 1/2) * side / M.
+ *   - Fourier coefficients alpha: [B][Ni][K][K], ky outer, kx inner, both
+ *     k = -floor(K/2) ... ceil(K/2)-1.  Odd K is a centred set; even K = 2 M_F
+ *     is the paper's set of four M_F x M_F corner blocks (Sec. 2.3).
+ *     J[i][j] = sum alpha[ky][kx] exp(+2 pi i (ky i + kx j) / M).
+ *   - Time dependence exp(-i w t); Green's function (i/4) H0^(1)(k0 r).
+ */
+#ifndef PDF_H
+#define PDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PDF_OK = 0,
+  PDF_EINVAL = -1,       /* bad argument (null pointer, size out of range)        */
+  PDF_ENOMEM = -2,       /* device or host allocation failed                      */
+  PDF_EHIP = -3,         /* a HIP runtime call or kernel launch failed            */
+  PDF_ENONFINITE = -4,   /* non-finite loss, zero data norm or zero E_inc norm    */
+  PDF_EUNSUPPORTED = -5  /* valid request this build does not implement           */
+};
+
+enum { PDF_FP32 = 0, PDF_FP64 = 1 };
+
+#define PDF_PARAMS_VERSION 1
+#define PDF_LOSS_STRIDE 8   /* doubles per instance in a loss buffer */
+
+/* Loss buffer layout, per instance: [State, Data, Bound, TV, Bridge, Total,
+   max |R| (diagnostic), non-finite flag (1.0 if any term is not finite)]. */
+
+typedef struct pdf_handle pdf_handle;
+
+typedef struct {
+  int32_t M;        /* pixels per side of the inversion grid                  */
+  double side;      /* side length of the square domain, metres               */
+  double cx, cy;    /* domain centre, metres                                  */
+} pdf_grid;
+
+typedef struct {
+  int32_t n;        /* number of antennas                                     */
+  const double* xy; /* host [n][2] (x, y) positions, metres                   */
+} pdf_array;
+
+typedef struct {
+  int32_t version;     /* PDF_PARAMS_VERSION                                          */
+  int32_t precision;   /* PDF_FP32 or PDF_FP64 arithmetic for the whole path          */
+  double beta;         /* CIE contraction parameter (Sec. 2.2, Eq. 6); paper: 6       */
+  double lam_bound;    /* weight of L^Bound (Eq. 17); paper: 1e-3                     */
+  double lam_tv;       /* weight of L^TV (Eq. 18); paper: 1e-5                        */
+  double lam_bridge;   /* weight of L^Bridge (Eq. 19); paper: 1e-5                    */
+  double tau_b;        /* bridge threshold (Eq. 19); paper: 0.5                       */
+  double eps_tv;       /* added under the TV square root; 1e-12                       */
+  double eps_abs;      /* |chi| smoothing in L^Bridge, sqrt(|chi|^2 + eps_abs); 1e-12 */
+  double cco_tau;      /* CCO threshold tau (Eq. 11); paper: 3                         */
+  double cco_eta_max;  /* CCO maximum gain (Eq. 11); paper: 0.1                        */
+  double cco_delta;    /* CCO slope delta (Eq. 11); paper: 0.5                         */
+  int32_t gf_radius;   /* self-guided filter box radius; 1                             */
+  double gf_eps;       /* self-guided filter regulariser; 1e-2                         */
+  double lr;           /* Adam learning rate (Sec. 3.3); paper: 1e-2                  */
+  double adam_b1, adam_b2, adam_eps;   /* 0.9, 0.999, 1e-8                             */
+  int32_t r_stopgrad;  /* 1: treat R as a constant in the gradient                     */
+} pdf_params;
+
+/* Fill *p with the paper's defaults (precision PDF_FP32).  Host only. */
+int pdf_default_params(pdf_params* p);
+
+/* Build operator tables for one geometry (Sec. 2.1, Eqs. 3-4) and scratch for
+ * `batch` data sets.  FP64 on the host: Hankel-function tables of the domain
+ * operator G_D (circular-cell method of moments), its spectrum on the 2M x 2M
+ * circulant embedding, the receiver operator G_S [Ns][N] and the incident
+ * fields [Ni][N] (unit magnitude at the domain centre); then cast to the
+ * handle's precision and copied to the device.  Synchronous.
+ *   grid, tx, rx, params: host structs (params may be NULL for defaults).
+ *   freq_hz: frequency.  K: truncation per axis, 1 <= K <= M.
+ *   stream: hipStream_t for every later call (must not be NULL).
+ * Supported: M in {8, 16, 32, 64} (FP32) or {8, 16, 32} (FP64); Ni, Ns >= 1.
+ * Errors: PDF_EINVAL (bad sizes / null), PDF_EUNSUPPORTED (other M),
+ * PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (||E_inc|| = 0). */
+int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
+              const pdf_array* rx, int32_t K, int32_t batch,
+              const pdf_params* params, void* stream, pdf_handle** out);
+
+/* Host-only FP64 operator tables (no device work), for checking pdf_setup:
+ * ghat [2M][2M] (FFT of the embedded G_D kernel, unscaled), gs [Ns][N],
+ * einc [Ni][N], all complex128 host buffers allocated by the caller.
+ * Any output pointer may be NULL to skip it. */
+int pdf_tables_host(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
+                    const pdf_array* rx, double* ghat, double* gs, double* einc);
+
+/* Copy measured fields E_sca [B][Ni][Ns] (device, handle precision) into the
+ * handle and compute each instance's ||E_sca||^2.  Errors: PDF_EINVAL. */
+int pdf_set_data(pdf_handle* h, const void* esca_dev);
+
+/* Loss and gradient at alpha (Sec. 3.2, Eqs. 13-19; the adjoint is the chain
+ * rule through every step, with the per-pixel least-squares contrast
+ * R = beta sum J conj(E) / sum |E|^2 (Eqs. 6-7)).
+ *   alpha_dev: [B][Ni][K][K] complex.  grad_dev: same shape, may be NULL.
+ *   loss_dev: device double [B][PDF_LOSS_STRIDE], may be NULL.
+ * Gradient convention: dL/dRe + i dL/dIm (that of PyTorch). */
+int pdf_loss_grad(pdf_handle* h, const void* alpha_dev, void* grad_dev, double* loss_dev);
+
+/* One Adam step (Sec. 3.3) on alpha in place: loss and gradient at alpha,
+ * then the bias-corrected update of (Re, Im) pairs.
+ *   m_dev, v_dev: [B][Ni][K][K][2] real moment buffers (zero before step 1).
+ *   t_dev: device int32 [B], steps already taken per instance; incremented.
+ *   loss_dev: as in pdf_loss_grad (loss before the update), may be NULL.
+ * Graph-capturable: all step-dependent state is in device memory. */
+int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev,
+             int32_t* t_dev, double* loss_dev);
+
+/* Start value alpha_0 (Sec. 3.1): back-propagation image, R_0 by Eq. 7, and
+ * one gradient step on L^CSI (Eq. 12) from zero with the exact line-search
+ * step size.  alpha_dev: output [B][Ni][K][K]. */
+int pdf_init_alpha(pdf_handle* h, void* alpha_dev);
+
+/* Images at alpha: chi = R/(beta(1-R)) and the CCO image (Eqs. 10-11).
+ *   chi_dev, chi_cco_dev: [B][M][M] complex outputs, either may be NULL.
+ *   eps_true_dev: [B][M][M] complex relative permittivity, may be NULL.
+ *   err_dev: device double [B]: ||(1+chi_cco) - eps|| / ||eps||, may be NULL
+ *   (requires eps_true_dev). */
+int pdf_image(pdf_handle* h, const void* alpha_dev, void* chi_dev, void* chi_cco_dev,
+              const void* eps_true_dev, double* err_dev);
+
+typedef struct {
+  int32_t iters_run;       /* Adam steps taken by the slowest instance            */
+  int32_t n_reached;       /* instances whose image error reached its target       */
+  double seconds;          /* wall time of the call                                */
+} pdf_report;
+
+/* A full reconstruction of every instance (Sec. 3, Fig. 3): alpha_0 (or the
+ * caller's start), up to n_iter Adam steps replayed from a captured HIP graph
+ * of n_check steps, the image error checked every n_check steps against
+ * target_err_dev[b] (instances stop updating once they reach it), then the
+ * CCO image.  Synchronous.
+ *   alpha_dev: [B][Ni][K][K] in/out (in: start if start_given != 0).
+ *   eps_true_dev, target_err_dev (device double [B]): may be NULL (no early stop).
+ *   reached_iter_dev: device int32 [B], first checked step at which the
+ *   target was met (-1 if never), may be NULL.
+ *   chi_cco_dev: [B][M][M] output, may be NULL. */
+int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t start_given,
+                    void* alpha_dev, const void* eps_true_dev, const double* target_err_dev,
+                    int32_t* reached_iter_dev, void* chi_cco_dev, pdf_report* rep);
+
+/* FP64 method-of-moments synthesis of measured fields (Sec. 2.1, Eqs. 3-4):
+ * solves (I - G_D X) E = E_inc on the support of chi = eps - 1 of a fine grid
+ * and returns E_sca = G_S X E.  Stand-alone (no handle); synchronous.
+ *   grid: the fine grid; eps_host: host complex128 [M][M] relative permittivity.
+ *   esca_host: host complex128 [Ni][Ns] output.
+ *   tol: relative residual of the iterative solve (e.g. 1e-10).
+ * Errors: PDF_EINVAL, PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (no convergence). */
+int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
+                   const pdf_array* rx, const double* eps_host, double tol,
+                   double* esca_host, void* stream);
+
+/* Release everything the handle owns (waits for its stream).  NULL is a no-op. */
+void pdf_destroy(pdf_handle* h);
+
+/* Message of the last failed call on h (or of the last failed pdf_setup /
+ * pdf_tables_host / pdf_synthesize when h is NULL).  Never NULL. */
+const char* pdf_last_error(const pdf_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDF_H */

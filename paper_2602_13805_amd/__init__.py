@@ -1,0 +1,10 @@
+"""MI355X-native hot path of the Physics-Driven Fourier-Spectral (PDF) solver.
+
+The HIP library ``libpdf.so`` (sources in ``csrc/``, C ABI in ``include/pdf.h``)
+does all computation; ``binding`` marshals PyTorch device tensors into it.
+"""
+from .binding import (FP32, FP64, LOSS_NAMES, LOSS_STRIDE, PdfError, PdfLoss, Solver, default_params,
+                      load, synthesize, tables_host)
+
+__all__ = ["FP32", "FP64", "LOSS_NAMES", "LOSS_STRIDE", "PdfError", "PdfLoss", "Solver", "default_params",
+           "load", "synthesize", "tables_host"]

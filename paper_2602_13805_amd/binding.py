@@ -1,0 +1,302 @@
+"""ctypes binding of libpdf.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module checks shapes and
+dtypes, passes device pointers of PyTorch tensors, and orders the library's
+stream with PyTorch's current stream.  If the library is missing the import
+of a Solver fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdf.so")
+
+PDF_OK, PDF_EINVAL, PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE, PDF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP32, FP64 = 0, 1
+PARAMS_VERSION = 1
+LOSS_STRIDE = 8
+LOSS_NAMES = ("state", "data", "bound", "tv", "bridge", "total", "max_abs_R", "nonfinite")
+
+c_i32, c_f64, c_vp = ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("M", c_i32), ("side", c_f64), ("cx", c_f64), ("cy", c_f64)]
+
+
+class Array(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("xy", ctypes.POINTER(c_f64))]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("version", c_i32), ("precision", c_i32),
+                ("beta", c_f64), ("lam_bound", c_f64), ("lam_tv", c_f64), ("lam_bridge", c_f64),
+                ("tau_b", c_f64), ("eps_tv", c_f64), ("eps_abs", c_f64),
+                ("cco_tau", c_f64), ("cco_eta_max", c_f64), ("cco_delta", c_f64),
+                ("gf_radius", c_i32), ("gf_eps", c_f64),
+                ("lr", c_f64), ("adam_b1", c_f64), ("adam_b2", c_f64), ("adam_eps", c_f64),
+                ("r_stopgrad", c_i32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters_run", c_i32), ("n_reached", c_i32), ("seconds", c_f64)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/pdf.h
+SIGNATURES = {
+    "pdf_default_params": (c_i32, [ctypes.POINTER(Params)]),
+    "pdf_setup": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array), c_i32,
+                          c_i32, ctypes.POINTER(Params), c_vp, ctypes.POINTER(c_vp)]),
+    "pdf_tables_host": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array),
+                                c_vp, c_vp, c_vp]),
+    "pdf_set_data": (c_i32, [c_vp, c_vp]),
+    "pdf_loss_grad": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "pdf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "pdf_init_alpha": (c_i32, [c_vp, c_vp]),
+    "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                ctypes.POINTER(Report)]),
+    "pdf_synthesize": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array),
+                               c_vp, c_f64, c_vp, c_vp]),
+    "pdf_destroy": (None, [c_vp]),
+    "pdf_last_error": (ctypes.c_char_p, [c_vp]),
+}
+
+_lib = None
+
+
+class PdfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpdf error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_13805_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, handle=None):
+    if rc != PDF_OK:
+        msg = load().pdf_last_error(handle).decode()
+        raise PdfError(rc, msg)
+
+
+def default_params(precision: str = "fp32", **kw) -> Params:
+    p = Params()
+    _check(load().pdf_default_params(ctypes.byref(p)))
+    p.precision = FP64 if precision == "fp64" else FP32
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _array(xy: np.ndarray):
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+    return Array(xy.shape[0], xy.ctypes.data_as(ctypes.POINTER(c_f64))), xy
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def tables_host(M: int, side: float, freq_hz: float, tx, rx, cx: float = 0.0, cy: float = 0.0):
+    """FP64 host tables (ghat [2M,2M], gs [Ns,N], einc [Ni,N]) as computed by pdf_setup."""
+    g = Grid(M, side, cx, cy)
+    ta, txa = _array(tx)
+    ra, rxa = _array(rx)
+    ghat = np.zeros((2 * M, 2 * M), np.complex128)
+    gs = np.zeros((ra.n, M * M), np.complex128)
+    einc = np.zeros((ta.n, M * M), np.complex128)
+    _check(load().pdf_tables_host(ctypes.byref(g), freq_hz, ctypes.byref(ta), ctypes.byref(ra),
+                                  ghat.ctypes.data, gs.ctypes.data, einc.ctypes.data))
+    return ghat, gs, einc
+
+
+def synthesize(M: int, side: float, freq_hz: float, tx, rx, eps: np.ndarray, tol: float = 1e-10,
+               device: str = "cuda:0", cx: float = 0.0, cy: float = 0.0) -> np.ndarray:
+    """FP64 MoM scattered field [Ni, Ns] of the permittivity map eps [M, M] (GPU)."""
+    g = Grid(M, side, cx, cy)
+    ta, txa = _array(tx)
+    ra, rxa = _array(rx)
+    eps = np.ascontiguousarray(np.asarray(eps, dtype=np.complex128))
+    if eps.shape != (M, M):
+        raise ValueError("eps must be [M, M]")
+    out = np.zeros((ta.n, ra.n), np.complex128)
+    stream = torch.cuda.Stream(device)
+    torch.cuda.current_stream(device).synchronize()
+    _check(load().pdf_synthesize(ctypes.byref(g), freq_hz, ctypes.byref(ta), ctypes.byref(ra),
+                                 eps.ctypes.data, tol, out.ctypes.data, ctypes.c_void_p(stream.cuda_stream)))
+    return out
+
+
+class Solver:
+    """One measurement geometry with `batch` data sets on one GPU."""
+
+    def __init__(self, M: int, side: float, freq_hz: float, tx, rx, K: int, batch: int = 1,
+                 params: Optional[Params] = None, precision: str = "fp32", device: str = "cuda:0",
+                 cx: float = 0.0, cy: float = 0.0):
+        lib = load()
+        self.device = torch.device(device)
+        self.params = params if params is not None else default_params(precision)
+        self.precision = "fp64" if self.params.precision == FP64 else "fp32"
+        self.cdtype = torch.complex128 if self.precision == "fp64" else torch.complex64
+        self.rdtype = torch.float64 if self.precision == "fp64" else torch.float32
+        self.M, self.K, self.B = M, K, batch
+        self.Ni, self.Ns = len(tx), len(rx)
+        self.stream = torch.cuda.Stream(self.device)
+        g = Grid(M, side, cx, cy)
+        ta, self._tx = _array(tx)
+        ra, self._rx = _array(rx)
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib.pdf_setup(ctypes.byref(g), freq_hz, ctypes.byref(ta), ctypes.byref(ra), K, batch,
+                             ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.byref(h)))
+        self.h = h
+
+    # stream ordering around each library call
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def _call(self, fn, *args):
+        self._enter()
+        rc = fn(self.h, *args)
+        self._leave()
+        _check(rc, self.h)
+
+    def _want(self, t: torch.Tensor, shape, dtype, name, inplace: bool = False):
+        """Checks device, dtype and shape.  Read-only inputs are returned
+        contiguous; buffers written in place must already be contiguous."""
+        ok = isinstance(t, torch.Tensor) and t.device.type == self.device.type \
+            and (t.device.index or 0) == (self.device.index or 0) and t.dtype == dtype \
+            and tuple(t.shape) == tuple(shape) and (t.is_contiguous() or not inplace)
+        if not ok:
+            got = (f"{t.dtype} {tuple(t.shape)} on {t.device}, contiguous={t.is_contiguous()}"
+                   if isinstance(t, torch.Tensor) else type(t).__name__)
+            raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on {self.device}, got {got}")
+        return t if inplace else t.contiguous()
+
+    @property
+    def alpha_shape(self):
+        return (self.B, self.Ni, self.K, self.K)
+
+    def zeros_alpha(self):
+        return torch.zeros(self.alpha_shape, dtype=self.cdtype, device=self.device)
+
+    def set_data(self, esca: torch.Tensor):
+        esca = self._want(esca, (self.B, self.Ni, self.Ns), self.cdtype, "esca")
+        self._call(load().pdf_set_data, _ptr(esca))
+
+    def loss_grad(self, alpha: torch.Tensor, grad: bool = True):
+        alpha = self._want(alpha, self.alpha_shape, self.cdtype, "alpha")
+        loss = torch.empty((self.B, LOSS_STRIDE), dtype=torch.float64, device=self.device)
+        g = torch.empty_like(alpha) if grad else None
+        self._call(load().pdf_loss_grad, _ptr(alpha), _ptr(g), _ptr(loss))
+        return loss, g
+
+    def new_state(self):
+        m = torch.zeros(self.alpha_shape + (2,), dtype=self.rdtype, device=self.device)
+        v = torch.zeros_like(m)
+        t = torch.zeros(self.B, dtype=torch.int32, device=self.device)
+        return m, v, t
+
+    def step(self, alpha, m, v, t, loss: Optional[torch.Tensor] = None):
+        self._want(alpha, self.alpha_shape, self.cdtype, "alpha", inplace=True)
+        self._want(m, self.alpha_shape + (2,), self.rdtype, "m", inplace=True)
+        self._want(v, self.alpha_shape + (2,), self.rdtype, "v", inplace=True)
+        self._want(t, (self.B,), torch.int32, "t", inplace=True)
+        if loss is not None:
+            self._want(loss, (self.B, LOSS_STRIDE), torch.float64, "loss", inplace=True)
+        self._call(load().pdf_step, _ptr(alpha), _ptr(m), _ptr(v), _ptr(t), _ptr(loss))
+
+    def init_alpha(self):
+        a = self.zeros_alpha()
+        self._call(load().pdf_init_alpha, _ptr(a))
+        return a
+
+    def image(self, alpha, eps_true: Optional[torch.Tensor] = None):
+        alpha = self._want(alpha, self.alpha_shape, self.cdtype, "alpha")
+        chi = torch.empty((self.B, self.M, self.M), dtype=self.cdtype, device=self.device)
+        cco = torch.empty_like(chi)
+        err = None
+        if eps_true is not None:
+            eps_true = self._want(eps_true, (self.B, self.M, self.M), self.cdtype, "eps_true")
+            err = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        self._call(load().pdf_image, _ptr(alpha), _ptr(chi), _ptr(cco), _ptr(eps_true), _ptr(err))
+        return chi, cco, err
+
+    def reconstruct(self, n_iter: int, n_check: int = 10, alpha: Optional[torch.Tensor] = None,
+                    eps_true: Optional[torch.Tensor] = None, target: Optional[torch.Tensor] = None):
+        start_given = alpha is not None
+        a = alpha if start_given else self.zeros_alpha()
+        self._want(a, self.alpha_shape, self.cdtype, "alpha", inplace=True)
+        if target is not None:
+            target = self._want(target, (self.B,), torch.float64, "target")
+            eps_true = self._want(eps_true, (self.B, self.M, self.M), self.cdtype, "eps_true")
+        reached = torch.full((self.B,), -1, dtype=torch.int32, device=self.device)
+        cco = torch.empty((self.B, self.M, self.M), dtype=self.cdtype, device=self.device)
+        rep = Report()
+        self._call(load().pdf_reconstruct, n_iter, n_check, int(start_given), _ptr(a), _ptr(eps_true),
+                   _ptr(target), _ptr(reached), _ptr(cco), ctypes.byref(rep))
+        return dict(alpha=a, chi_cco=cco, reached=reached, iters_run=rep.iters_run,
+                    n_reached=rep.n_reached, seconds=rep.seconds)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PdfLoss(torch.autograd.Function):
+    """Total PDF loss per instance with the library's hand-written adjoint.
+
+    forward(alpha, solver, checkpoint) -> loss [B] (float64).  By default the
+    gradient from the same library call is kept for backward; with
+    checkpoint=True only alpha is kept and the gradient is recomputed.
+    """
+
+    @staticmethod
+    def forward(ctx, alpha, solver: Solver, checkpoint: bool = False):
+        loss, g = solver.loss_grad(alpha.detach().contiguous(), grad=not checkpoint)
+        ctx.solver = solver
+        ctx.checkpoint = checkpoint
+        ctx.save_for_backward(alpha.detach() if checkpoint else g)
+        return loss[:, 5].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (saved,) = ctx.saved_tensors
+        if ctx.checkpoint:
+            _, g = ctx.solver.loss_grad(saved.contiguous(), grad=True)
+        else:
+            g = saved
+        scale = grad_out.to(g.real.dtype).reshape(-1, 1, 1, 1)
+        return g * scale, None, None

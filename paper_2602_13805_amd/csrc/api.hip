@@ -1,0 +1,665 @@
+// C ABI of the PDF hot path: handle setup, the per-iteration launch sequence,
+// the start value, images and the reconstruction loop.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "conv_kernels.h"
+#include "handle.h"
+#include "init_kernels.h"
+#include "pixel_kernels.h"
+#include "tables.h"
+
+using namespace pdfk;
+
+static thread_local std::string g_last_error = "no error";
+
+#define HIP_TRY(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      return fail(h, PDF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                              \
+  } while (0)
+
+void pdf_set_global_error(const std::string& msg) { g_last_error = msg; }
+
+static int fail(pdf_handle* h, int code, const std::string& msg) {
+  if (h)
+    h->err_msg = msg;
+  else
+    g_last_error = msg;
+  return code;
+}
+
+static int check_launch(pdf_handle* h, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(h, PDF_EHIP, std::string("launch ") + what + ": " + hipGetErrorString(e));
+  return PDF_OK;
+}
+
+extern "C" int pdf_default_params(pdf_params* p) {
+  if (!p) return PDF_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->version = PDF_PARAMS_VERSION;
+  p->precision = PDF_FP32;
+  p->beta = 6.0;
+  p->lam_bound = 1e-3;
+  p->lam_tv = 1e-5;
+  p->lam_bridge = 1e-5;
+  p->tau_b = 0.5;
+  p->eps_tv = 1e-12;
+  p->eps_abs = 1e-12;
+  p->cco_tau = 3.0;
+  p->cco_eta_max = 0.1;
+  p->cco_delta = 0.5;
+  p->gf_radius = 1;
+  p->gf_eps = 1e-2;
+  p->lr = 1e-2;
+  p->adam_b1 = 0.9;
+  p->adam_b2 = 0.999;
+  p->adam_eps = 1e-8;
+  p->r_stopgrad = 0;
+  return PDF_OK;
+}
+
+static bool supported_m(int prec, int M) {
+  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 64;
+  return M == 8 || M == 16 || M == 32;
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(bytes));
+}
+
+template <typename T, int M>
+static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int nblk) {
+  using C = ConvCfg<T, M>;
+  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+    if (from_alpha) {
+      auto k = k_fwd_conv<T, M, true>;
+      set_lds(k, C::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::LDS_BYTES, h->stream, a);
+    } else {
+      auto k = k_fwd_conv<T, M, false>;
+      set_lds(k, C::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::LDS_BYTES, h->stream, a);
+    }
+    return check_launch(h, "k_fwd_conv");
+  } else {
+    return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident convolution");
+  }
+}
+
+template <typename T>
+static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
+  const int nblk = h->B * h->Ni;
+  switch (h->M) {
+    case 8: return launch_fwd_m<T, 8>(h, a, from_alpha, nblk);
+    case 16: return launch_fwd_m<T, 16>(h, a, from_alpha, nblk);
+    case 32: return launch_fwd_m<T, 32>(h, a, from_alpha, nblk);
+    case 64: return launch_fwd_m<T, 64>(h, a, from_alpha, nblk);
+  }
+  return fail(h, PDF_EUNSUPPORTED, "unsupported M");
+}
+
+template <typename T, int M>
+static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
+  using C = ConvCfg<T, M>;
+  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+    auto k = k_adj_conv<T, M>;
+    set_lds(k, C::LDS_BYTES);
+    hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::LDS_BYTES, h->stream, a);
+    return check_launch(h, "k_adj_conv");
+  } else {
+    return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident convolution");
+  }
+}
+
+template <typename T>
+static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
+  const int nblk = h->B * h->Ni;
+  switch (h->M) {
+    case 8: return launch_adj_m<T, 8>(h, a, nblk);
+    case 16: return launch_adj_m<T, 16>(h, a, nblk);
+    case 32: return launch_adj_m<T, 32>(h, a, nblk);
+    case 64: return launch_adj_m<T, 64>(h, a, nblk);
+  }
+  return fail(h, PDF_EUNSUPPORTED, "unsupported M");
+}
+
+template <typename T>
+static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx<T>* Rfix) {
+  ReduceArgs<T> a;
+  a.J = J;
+  a.E = E;
+  a.gs = (const cx<T>*)h->gs;
+  a.Rfix = Rfix;
+  a.R = (cx<T>*)h->R;
+  a.den = (T*)h->den;
+  a.chi = (cx<T>*)h->chi;
+  a.lsp = h->lsp;
+  a.Dpart = (cx<T>*)h->Dpart;
+  a.Ni = h->Ni;
+  a.Ns = h->Ns;
+  a.N = h->N;
+  a.ntiles = h->ntiles;
+  a.beta = T(h->prm.beta);
+  const size_t lds = sizeof(cx<T>) * size_t(h->Ni) * h->tile + 16 * sizeof(double);
+  set_lds(k_pixel_reduce<T>, lds);
+  hipLaunchKernelGGL(k_pixel_reduce<T>, dim3(h->ntiles, h->B), dim3(h->tile), lds, h->stream, a);
+  return check_launch(h, "k_pixel_reduce");
+}
+
+template <typename T>
+static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
+  RegArgs<T> a;
+  a.chi = (const cx<T>*)h->chi;
+  a.R = (const cx<T>*)h->R;
+  a.Dpart = (const cx<T>*)h->Dpart;
+  a.lsp = h->lsp;
+  a.esca = (const cx<T>*)h->esca;
+  a.Ss = h->Ss;
+  a.Sd = h->Sd;
+  a.d = (cx<T>*)h->dres;
+  a.gR = (cx<T>*)h->gR;
+  a.loss = loss;
+  a.tstep = tstep;
+  a.frozen = frozen;
+  a.M = h->M;
+  a.Ni = h->Ni;
+  a.Ns = h->Ns;
+  a.ntiles = h->ntiles;
+  a.beta = h->prm.beta;
+  a.lam_bound = h->prm.lam_bound;
+  a.lam_tv = h->prm.lam_tv;
+  a.lam_bridge = h->prm.lam_bridge;
+  a.tau_b = h->prm.tau_b;
+  a.eps_tv = h->prm.eps_tv;
+  a.eps_abs = h->prm.eps_abs;
+  a.r_stopgrad = h->prm.r_stopgrad;
+  const int nt = h->N < 1024 ? h->N : 1024;
+  const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
+  set_lds(k_image_reg<T>, lds);
+  hipLaunchKernelGGL(k_image_reg<T>, dim3(h->B), dim3(nt), lds, h->stream, a);
+  return check_launch(h, "k_image_reg");
+}
+
+template <typename T>
+static int launch_adj_gemm(pdf_handle* h, const cx<T>* x, cx<T>* out) {
+  const size_t lds = sizeof(cx<T>) * size_t(h->Ni) * h->Ns;
+  dim3 grid((h->N + 255) / 256, h->B);
+  if (h->Ns <= 16)
+    hipLaunchKernelGGL((k_adj_gemm<T, 16>), grid, dim3(256), lds, h->stream, (const cx<T>*)h->gs, x, out, h->Ni,
+                       h->Ns, h->N);
+  else if (h->Ns <= 32)
+    hipLaunchKernelGGL((k_adj_gemm<T, 32>), grid, dim3(256), lds, h->stream, (const cx<T>*)h->gs, x, out, h->Ni,
+                       h->Ns, h->N);
+  else
+    hipLaunchKernelGGL((k_adj_gemm<T, 64>), grid, dim3(256), lds, h->stream, (const cx<T>*)h->gs, x, out, h->Ni,
+                       h->Ns, h->N);
+  return check_launch(h, "k_adj_gemm");
+}
+
+// One evaluation of loss and gradient; with Adam buffers, also the update.
+template <typename T>
+static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
+                         void* v, int* tstep, const int* frozen) {
+  int rc;
+  FwdArgs<T> f;
+  f.in = (const cx<T>*)alpha;
+  f.einc = (const cx<T>*)h->einc;
+  f.ghat = (const cx<T>*)h->ghat;
+  f.tw = (const cx<T>*)h->tw;
+  f.J = (cx<T>*)h->J;
+  f.E = (cx<T>*)h->E;
+  f.Ni = h->Ni;
+  f.K = h->K;
+  f.beta = T(h->prm.beta);
+  if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  if ((rc = launch_reg<T>(h, loss, tstep, frozen))) return rc;
+  if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
+  AdjArgs<T> a;
+  a.J = (const cx<T>*)h->J;
+  a.E = (const cx<T>*)h->E;
+  a.e_shared = 0;
+  a.h = (const cx<T>*)h->h;
+  a.R = (const cx<T>*)h->R;
+  a.den = (const T*)h->den;
+  a.gR = (const cx<T>*)h->gR;
+  a.Ss = h->Ss;
+  a.Sd = h->Sd;
+  a.hsign = 1.0;
+  a.ghat = (const cx<T>*)h->ghat;
+  a.tw = (const cx<T>*)h->tw;
+  a.galpha = (cx<T>*)grad;
+  a.alpha = (cx<T>*)alpha_upd;
+  a.m = (T*)m;
+  a.v = (T*)v;
+  a.tstep = tstep;
+  a.frozen = frozen;
+  a.lr = h->prm.lr;
+  a.b1 = h->prm.adam_b1;
+  a.b2 = h->prm.adam_b2;
+  a.eps = h->prm.adam_eps;
+  a.Ni = h->Ni;
+  a.K = h->K;
+  a.beta = T(h->prm.beta);
+  return launch_adj<T>(h, a);
+}
+
+template <typename T>
+static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_out, const void* eps_true,
+                     double* err) {
+  int rc;
+  FwdArgs<T> f;
+  f.in = (const cx<T>*)alpha;
+  f.einc = (const cx<T>*)h->einc;
+  f.ghat = (const cx<T>*)h->ghat;
+  f.tw = (const cx<T>*)h->tw;
+  f.J = (cx<T>*)h->J;
+  f.E = (cx<T>*)h->E;
+  f.Ni = h->Ni;
+  f.K = h->K;
+  f.beta = T(h->prm.beta);
+  if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  if (chi_out)
+    HIP_TRY(hipMemcpyAsync(chi_out, h->chi, sizeof(cx<T>) * size_t(h->B) * h->N, hipMemcpyDeviceToDevice,
+                           h->stream));
+  if (cco_out || err) {
+    CcoArgs<T> c;
+    c.chi = (const cx<T>*)h->chi;
+    c.out = (cx<T>*)cco_out;
+    c.eps_true = (const cx<T>*)eps_true;
+    c.err = eps_true ? err : nullptr;
+    c.M = h->M;
+    c.r = h->prm.gf_radius;
+    c.gf_eps = h->prm.gf_eps;
+    c.tau = h->prm.cco_tau;
+    c.eta_max = h->prm.cco_eta_max;
+    c.delta = h->prm.cco_delta;
+    const int nt = h->N < 1024 ? h->N : 1024;
+    const size_t lds = 6 * sizeof(T) * size_t(h->N) + 16 * sizeof(double);
+    set_lds(k_cco<T>, lds);
+    hipLaunchKernelGGL(k_cco<T>, dim3(h->B), dim3(nt), lds, h->stream, c);
+    if ((rc = check_launch(h, "k_cco"))) return rc;
+  }
+  return PDF_OK;
+}
+
+// Start value (Sec. 3.1): BP image, R_0, single exact-line-search step on L^CSI.
+template <typename T>
+static int run_init(pdf_handle* h, void* alpha_out) {
+  int rc;
+  cx<T>* u = (cx<T>*)h->h;
+  // u_p = G_S^H e_p
+  if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->esca, u))) return rc;
+  // v_p = G_S u_p (split-K parts), gamma_p, J_BP = gamma_p u_p
+  if ((rc = launch_reduce<T>(h, u, u, nullptr))) return rc;
+  hipLaunchKernelGGL(k_bp_gamma<T>, dim3(h->B * h->Ni), dim3(256), 0, h->stream, (const cx<T>*)h->Dpart,
+                     h->ntiles, (const cx<T>*)h->esca, u, h->Ni, h->Ns, h->N);
+  if ((rc = check_launch(h, "k_bp_gamma"))) return rc;
+  // E = E_inc + G_D J_BP
+  FwdArgs<T> f;
+  f.in = u;
+  f.einc = (const cx<T>*)h->einc;
+  f.ghat = (const cx<T>*)h->ghat;
+  f.tw = (const cx<T>*)h->tw;
+  f.J = nullptr;
+  f.E = (cx<T>*)h->E;
+  f.Ni = h->Ni;
+  f.K = h->K;
+  f.beta = T(0);
+  if ((rc = launch_fwd<T>(h, f, false))) return rc;
+  hipLaunchKernelGGL(k_bp_contrast<T>, dim3((h->N + 255) / 256, h->B), dim3(256), 0, h->stream, (const cx<T>*)u,
+                     (const cx<T>*)h->E, (cx<T>*)h->R0, h->Ni, h->N, h->prm.beta);
+  if ((rc = check_launch(h, "k_bp_contrast"))) return rc;
+  // g = grad L^CSI(0): the adjoint with J = 0, E = E_inc, R = R_0 fixed, d = -e
+  if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->esca, u))) return rc;
+  AdjArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.J = nullptr;
+  a.E = (const cx<T>*)h->einc;
+  a.e_shared = 1;
+  a.h = u;
+  a.R = (const cx<T>*)h->R0;
+  a.den = nullptr;
+  a.gR = nullptr;
+  a.Ss = h->Ss;
+  a.Sd = h->Sd;
+  a.hsign = -1.0;
+  a.ghat = (const cx<T>*)h->ghat;
+  a.tw = (const cx<T>*)h->tw;
+  a.galpha = (cx<T>*)h->g0;
+  a.alpha = nullptr;
+  a.Ni = h->Ni;
+  a.K = h->K;
+  a.beta = T(h->prm.beta);
+  if ((rc = launch_adj<T>(h, a))) return rc;
+  const size_t kk = size_t(h->K) * h->K;
+  hipLaunchKernelGGL(k_sumsq<T>, dim3(h->B), dim3(256), 0, h->stream, (const cx<T>*)h->g0, size_t(h->Ni) * kk,
+                     h->gnorm);
+  if ((rc = check_launch(h, "k_sumsq"))) return rc;
+  // curvature along g: J_g = F_T^*(g), A_s g = R_0 (G_D J_g + beta J_g) - beta J_g, A_d g = G_S J_g
+  f.in = (const cx<T>*)h->g0;
+  f.einc = nullptr;
+  f.J = (cx<T>*)h->J;
+  f.E = (cx<T>*)h->E;
+  f.beta = T(h->prm.beta);
+  if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, (const cx<T>*)h->R0))) return rc;
+  hipLaunchKernelGGL(k_line_search<T>, dim3(h->B), dim3(256), 0, h->stream, h->lsp, (const cx<T>*)h->Dpart,
+                     h->ntiles, h->Ni, h->Ns, h->gnorm, h->Ss, h->Sd, (const cx<T>*)h->g0, (cx<T>*)alpha_out,
+                     int(kk));
+  return check_launch(h, "k_line_search");
+}
+
+// ------------------------------------------------------------------ setup
+
+template <typename T>
+static int upload(pdf_handle* h, void** dst, const std::vector<std::complex<double>>& src, double scale) {
+  std::vector<cx<T>> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = cx<T>{T(src[i].real() * scale), T(src[i].imag() * scale)};
+  HIP_TRY(hipMalloc(dst, sizeof(cx<T>) * tmp.size()));
+  HIP_TRY(hipMemcpy(*dst, tmp.data(), sizeof(cx<T>) * tmp.size(), hipMemcpyHostToDevice));
+  return PDF_OK;
+}
+
+template <typename T>
+static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
+  int rc;
+  const double inv = 1.0 / (double(h->P) * h->P);
+  if ((rc = upload<T>(h, &h->ghat, t.ghat, inv))) return rc;
+  std::vector<std::complex<double>> tw(h->P);
+  for (int k = 0; k < h->P; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * k / h->P);
+  if ((rc = upload<T>(h, &h->tw, tw, 1.0))) return rc;
+  if ((rc = upload<T>(h, &h->gs, t.gs, 1.0))) return rc;
+  if ((rc = upload<T>(h, &h->einc, t.einc, 1.0))) return rc;
+  // ||E_inc||^2 of the values actually used (after rounding to T)
+  double ss = 0.0;
+  for (auto& z : t.einc) {
+    const double re = double(T(z.real())), im = double(T(z.imag()));
+    ss += re * re + im * im;
+  }
+  if (!(ss > 0.0)) return fail(h, PDF_ENONFINITE, "||E_inc|| = 0");
+  HIP_TRY(hipMalloc(&h->Ss, sizeof(double)));
+  HIP_TRY(hipMemcpy(h->Ss, &ss, sizeof(double), hipMemcpyHostToDevice));
+  const size_t C = sizeof(cx<T>);
+  const size_t B = h->B, Ni = h->Ni, Ns = h->Ns, N = h->N, KK = size_t(h->K) * h->K;
+  HIP_TRY(hipMalloc(&h->Sd, sizeof(double) * B));
+  HIP_TRY(hipMalloc(&h->esca, C * B * Ni * Ns));
+  HIP_TRY(hipMalloc(&h->J, C * B * Ni * N));
+  HIP_TRY(hipMalloc(&h->E, C * B * Ni * N));
+  HIP_TRY(hipMalloc(&h->h, C * B * Ni * N));
+  HIP_TRY(hipMalloc(&h->R, C * B * N));
+  HIP_TRY(hipMalloc(&h->den, sizeof(T) * B * N));
+  HIP_TRY(hipMalloc(&h->chi, C * B * N));
+  HIP_TRY(hipMalloc(&h->gR, C * B * N));
+  HIP_TRY(hipMalloc(&h->R0, C * B * N));
+  HIP_TRY(hipMalloc(&h->Dpart, C * B * h->ntiles * Ni * Ns));
+  HIP_TRY(hipMalloc(&h->dres, C * B * Ni * Ns));
+  HIP_TRY(hipMalloc(&h->lsp, sizeof(double) * B * h->ntiles));
+  HIP_TRY(hipMalloc(&h->g0, C * B * Ni * KK));
+  HIP_TRY(hipMalloc(&h->gnorm, sizeof(double) * B));
+  HIP_TRY(hipMalloc(&h->err, sizeof(double) * B));
+  HIP_TRY(hipMalloc(&h->frozen, sizeof(int) * B));
+  HIP_TRY(hipMalloc(&h->tstep, sizeof(int) * B));
+  HIP_TRY(hipMalloc(&h->m, 2 * sizeof(T) * B * Ni * KK));
+  HIP_TRY(hipMalloc(&h->v, 2 * sizeof(T) * B * Ni * KK));
+  HIP_TRY(hipMalloc(&h->loss, sizeof(double) * 8 * B));
+  return PDF_OK;
+}
+
+static int check_geometry(const pdf_grid* grid, double freq, const pdf_array* tx, const pdf_array* rx) {
+  if (!grid || !tx || !rx || !tx->xy || !rx->xy) return fail(nullptr, PDF_EINVAL, "null argument");
+  if (grid->M < 1 || !(grid->side > 0) || !std::isfinite(grid->side) || !(freq > 0) || !std::isfinite(freq))
+    return fail(nullptr, PDF_EINVAL, "invalid grid or frequency");
+  if (tx->n < 1 || rx->n < 1) return fail(nullptr, PDF_EINVAL, "need at least one transmitter and one receiver");
+  for (int i = 0; i < 2 * tx->n; ++i)
+    if (!std::isfinite(tx->xy[i])) return fail(nullptr, PDF_EINVAL, "non-finite transmitter position");
+  for (int i = 0; i < 2 * rx->n; ++i)
+    if (!std::isfinite(rx->xy[i])) return fail(nullptr, PDF_EINVAL, "non-finite receiver position");
+  return PDF_OK;
+}
+
+extern "C" int pdf_tables_host(const pdf_grid* grid, double freq_hz, const pdf_array* tx, const pdf_array* rx,
+                               double* ghat, double* gs, double* einc) {
+  int rc = check_geometry(grid, freq_hz, tx, rx);
+  if (rc) return rc;
+  pdfh::Geometry g{grid->M, grid->side, grid->cx, grid->cy, freq_hz, tx->n, rx->n, tx->xy, rx->xy};
+  pdfh::Tables t;
+  t.want_ghat = ghat != nullptr;
+  t.want_gs = gs != nullptr;
+  t.want_einc = einc != nullptr;
+  std::string err;
+  if (pdfh::build_tables(g, &t, &err)) return fail(nullptr, PDF_EINVAL, err);
+  if (ghat) std::memcpy(ghat, t.ghat.data(), t.ghat.size() * sizeof(std::complex<double>));
+  if (gs) std::memcpy(gs, t.gs.data(), t.gs.size() * sizeof(std::complex<double>));
+  if (einc) std::memcpy(einc, t.einc.data(), t.einc.size() * sizeof(std::complex<double>));
+  return PDF_OK;
+}
+
+extern "C" void pdf_destroy(pdf_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  void* ptrs[] = {h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
+                  h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
+                  h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
+                  h->v,    h->loss};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx, const pdf_array* rx, int32_t K,
+                         int32_t batch, const pdf_params* params, void* stream, pdf_handle** out) {
+  if (!out) return fail(nullptr, PDF_EINVAL, "out is null");
+  *out = nullptr;
+  int rc = check_geometry(grid, freq_hz, tx, rx);
+  if (rc) return rc;
+  pdf_params prm;
+  if (params) {
+    if (params->version != PDF_PARAMS_VERSION) return fail(nullptr, PDF_EINVAL, "pdf_params version mismatch");
+    prm = *params;
+  } else {
+    pdf_default_params(&prm);
+  }
+  if (prm.precision != PDF_FP32 && prm.precision != PDF_FP64) return fail(nullptr, PDF_EINVAL, "bad precision");
+  if (K < 1 || K > grid->M) return fail(nullptr, PDF_EINVAL, "K must satisfy 1 <= K <= M");
+  if (batch < 1) return fail(nullptr, PDF_EINVAL, "batch must be >= 1");
+  if (!stream) return fail(nullptr, PDF_EINVAL, "a non-default stream is required");
+  if (!supported_m(prm.precision, grid->M))
+    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32 or 64 (FP64: up to 32)");
+  if (rx->n > 64) return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 receivers");
+  if (!(prm.beta > 0) || prm.gf_radius < 0) return fail(nullptr, PDF_EINVAL, "beta must be > 0");
+  pdf_handle* h = new pdf_handle();
+  h->prec = prm.precision;
+  h->prm = prm;
+  h->M = grid->M;
+  h->N = grid->M * grid->M;
+  h->P = 2 * grid->M;
+  h->K = K;
+  h->Ni = tx->n;
+  h->Ns = rx->n;
+  h->B = batch;
+  h->stream = (hipStream_t)stream;
+  const size_t csz = prm.precision == PDF_FP32 ? 8 : 16;
+  int tile = 256;
+  while (tile > 64 && size_t(h->Ni) * tile * csz > 64 * 1024) tile >>= 1;
+  if (size_t(h->Ni) * tile * csz > 64 * 1024) {
+    delete h;
+    return fail(nullptr, PDF_EUNSUPPORTED, "too many incidences for the pixel-reduction tile");
+  }
+  h->tile = tile;
+  h->ntiles = (h->N + tile - 1) / tile;
+  pdfh::Geometry g{grid->M, grid->side, grid->cx, grid->cy, freq_hz, tx->n, rx->n, tx->xy, rx->xy};
+  pdfh::Tables t;
+  std::string err;
+  if (pdfh::build_tables(g, &t, &err)) {
+    delete h;
+    return fail(nullptr, PDF_EINVAL, err);
+  }
+  rc = prm.precision == PDF_FP32 ? setup_impl<float>(h, t) : setup_impl<double>(h, t);
+  if (rc) {
+    g_last_error = h->err_msg;
+    pdf_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return PDF_OK;
+}
+
+extern "C" int pdf_set_data(pdf_handle* h, const void* esca_dev) {
+  if (!h || !esca_dev) return fail(h, PDF_EINVAL, "null argument");
+  const size_t csz = h->prec == PDF_FP32 ? 8 : 16;
+  HIP_TRY(hipMemcpyAsync(h->esca, esca_dev, csz * size_t(h->B) * h->Ni * h->Ns, hipMemcpyDeviceToDevice,
+                         h->stream));
+  const size_t len = size_t(h->Ni) * h->Ns;
+  if (h->prec == PDF_FP32)
+    hipLaunchKernelGGL(k_sumsq<float>, dim3(h->B), dim3(256), 0, h->stream, (const cx<float>*)h->esca, len, h->Sd);
+  else
+    hipLaunchKernelGGL(k_sumsq<double>, dim3(h->B), dim3(256), 0, h->stream, (const cx<double>*)h->esca, len,
+                       h->Sd);
+  int rc = check_launch(h, "k_sumsq");
+  if (rc) return rc;
+  std::vector<double> sd(h->B);
+  HIP_TRY(hipMemcpyAsync(sd.data(), h->Sd, sizeof(double) * h->B, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (double s : sd)
+    if (!(s > 0.0) || !std::isfinite(s)) return fail(h, PDF_ENONFINITE, "||E_sca|| = 0 or not finite");
+  h->data_set = true;
+  return PDF_OK;
+}
+
+extern "C" int pdf_loss_grad(pdf_handle* h, const void* alpha_dev, void* grad_dev, double* loss_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32
+             ? run_iteration<float>(h, alpha_dev, grad_dev, loss_dev, nullptr, nullptr, nullptr, nullptr, nullptr)
+             : run_iteration<double>(h, alpha_dev, grad_dev, loss_dev, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev, int32_t* t_dev,
+                        double* loss_dev) {
+  if (!h || !alpha_dev || !m_dev || !v_dev || !t_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32
+             ? run_iteration<float>(h, alpha_dev, nullptr, loss_dev, alpha_dev, m_dev, v_dev, t_dev, nullptr)
+             : run_iteration<double>(h, alpha_dev, nullptr, loss_dev, alpha_dev, m_dev, v_dev, t_dev, nullptr);
+}
+
+extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32 ? run_init<float>(h, alpha_dev) : run_init<double>(h, alpha_dev);
+}
+
+extern "C" int pdf_image(pdf_handle* h, const void* alpha_dev, void* chi_dev, void* chi_cco_dev,
+                         const void* eps_true_dev, double* err_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (err_dev && !eps_true_dev) return fail(h, PDF_EINVAL, "err_dev needs eps_true_dev");
+  return h->prec == PDF_FP32 ? run_image<float>(h, alpha_dev, chi_dev, chi_cco_dev, eps_true_dev, err_dev)
+                             : run_image<double>(h, alpha_dev, chi_dev, chi_cco_dev, eps_true_dev, err_dev);
+}
+
+template <typename T>
+static int reconstruct_impl(pdf_handle* h, int n_iter, int n_check, int start_given, void* alpha,
+                            const void* eps_true, const double* target, int* reached, void* cco_out,
+                            pdf_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  const size_t KK = size_t(h->K) * h->K;
+  const size_t nre = 2 * size_t(h->B) * h->Ni * KK;
+  if (!start_given && (rc = run_init<T>(h, alpha))) return rc;
+  const int tb = 256;
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->m, nre);
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->v, nre);
+  hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->tstep, 0, h->B);
+  hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->frozen, 0, h->B);
+  if (reached) hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, reached, -1, h->B);
+  if ((rc = check_launch(h, "fill"))) return rc;
+  const bool checking = eps_true && target;
+  if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int done = 0;
+  if (n_iter > 0) {
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int crc = PDF_OK;
+    for (int s = 0; s < n_check && crc == PDF_OK; ++s)
+      crc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen);
+    hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+    if (crc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return crc;
+    }
+    if (ce != hipSuccess) return fail(h, PDF_EHIP, std::string("capture: ") + hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  std::vector<int> fz(h->B);
+  while (done < n_iter) {
+    const int chunk = (n_iter - done < n_check) ? n_iter - done : n_check;
+    if (chunk == n_check) {
+      HIP_TRY(hipGraphLaunch(exec, h->stream));
+    } else {
+      for (int s = 0; s < chunk; ++s)
+        if ((rc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen))) return rc;
+    }
+    done += chunk;
+    if (checking) {
+      if ((rc = run_image<T>(h, alpha, nullptr, nullptr, eps_true, h->err))) return rc;
+      hipLaunchKernelGGL(k_check_target, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->err, target,
+                         h->frozen, reached, h->tstep, h->B);
+      if ((rc = check_launch(h, "k_check_target"))) return rc;
+      HIP_TRY(hipMemcpyAsync(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      int nf = 0;
+      for (int x : fz) nf += x;
+      if (nf == h->B) break;
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cco_out && (rc = run_image<T>(h, alpha, nullptr, cco_out, nullptr, nullptr))) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (rep) {
+    rep->iters_run = done;
+    int nf = 0;
+    if (checking) {
+      HIP_TRY(hipMemcpy(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost));
+      for (int x : fz) nf += x;
+    }
+    rep->n_reached = nf;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return PDF_OK;
+}
+
+extern "C" int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t start_given,
+                               void* alpha_dev, const void* eps_true_dev, const double* target_err_dev,
+                               int32_t* reached_iter_dev, void* chi_cco_dev, pdf_report* rep) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (n_iter < 0) return fail(h, PDF_EINVAL, "n_iter < 0");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32
+             ? reconstruct_impl<float>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
+                                       reached_iter_dev, chi_cco_dev, rep)
+             : reconstruct_impl<double>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
+                                        reached_iter_dev, chi_cco_dev, rep);
+}
+
+extern "C" const char* pdf_last_error(const pdf_handle* h) {
+  return h ? h->err_msg.c_str() : g_last_error.c_str();
+}

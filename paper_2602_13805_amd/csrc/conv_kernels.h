@@ -1,0 +1,238 @@
+// Per-incidence fused kernels: basis synthesis, the 2x-padded FFT convolution
+// with the domain operator, the CIE bracket, and the adjoint pass with the
+// basis analysis and Adam.  One workgroup owns one (instance, incidence) pair
+// and keeps the whole padded 2M x 2M spectrum in LDS.
+#pragma once
+
+#include "cplx.h"
+#include "fft_lds.h"
+
+namespace pdfk {
+
+template <typename T, int M_>
+struct ConvCfg {
+  static constexpr int M = M_;
+  static constexpr int P = 2 * M;
+  static constexpr int N = M * M;
+  static constexpr int LD = P + 1;  // padded row stride of the LDS tile (complex units)
+  static constexpr int NT = M >= 64 ? 1024 : (M >= 32 ? 256 : 64);
+  static constexpr int EPT_M = 8;                 // length-M transforms (basis)
+  static constexpr int EPT_R = 8;                 // length-P transforms along rows
+  static constexpr int EPT_C = P >= 16 ? 16 : P;  // length-P transforms along columns
+  static constexpr int PPT = N / NT;              // pixels owned per thread
+  static constexpr int U_SYN = CeilDiv<M*(M / EPT_M), NT>::value;
+  static constexpr int U_ROW = CeilDiv<M*(P / EPT_R), NT>::value;
+  static constexpr int U_COL = CeilDiv<P*(P / EPT_C), NT>::value;
+  static_assert(N % NT == 0, "pixel ownership must be exact");
+  static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(P) * LD + P);
+};
+
+template <typename T>
+struct GhatLoad {
+  const cx<T>* g;
+  int P;
+  bool cj;
+  __device__ __forceinline__ cx<T> operator()(int vec, int k, cx<T> x) const {
+    cx<T> w = g[k * P + vec];
+    if (cj) w.y = -w.y;
+    return x * w;
+  }
+};
+
+struct KeepBelow {
+  int lim;
+  __device__ __forceinline__ bool operator()(int, int k) const { return k < lim; }
+};
+
+// In place on the top-left M x M of the LDS tile: x -> G_D x (or G_D^H x),
+// where the spectrum ghat is pre-scaled by 1/P^2.  Entries outside the
+// M x M block are never read before being written.
+template <typename T, int M>
+__device__ __forceinline__ void conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+  using C = ConvCfg<T, M>;
+  LdsFft<T, C::P, C::EPT_R, -1, C::U_ROW>{buf, M, C::LD, 1, tw, 1}.run(M);
+  LdsFft<T, C::P, C::EPT_C, -1, C::U_COL>{buf, C::P, 1, C::LD, tw, 1}.run(M);
+  LdsFft<T, C::P, C::EPT_C, +1, C::U_COL>{buf, C::P, 1, C::LD, tw, 1}.run(
+      C::P, GhatLoad<T>{ghat, C::P, adjoint}, KeepBelow{M});
+  LdsFft<T, C::P, C::EPT_R, +1, C::U_ROW>{buf, M, C::LD, 1, tw, 1}.run(C::P, NoLoad(), KeepBelow{M});
+}
+
+__device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
+
+template <typename T>
+struct FwdArgs {
+  const cx<T>* in;     // alpha [BP][K][K] (from_alpha) or pixel currents [BP][N]
+  const cx<T>* einc;   // [Ni][N] incident fields, or null (taken as zero)
+  const cx<T>* ghat;   // [P][P] spectrum / P^2
+  const cx<T>* tw;     // [P] exp(-2 pi i k / P)
+  cx<T>* J;            // [BP][N] synthesised currents (from_alpha), may be null
+  cx<T>* E;            // [BP][N] output E_inc + G_D J + beta J
+  int Ni, K;
+  T beta;
+};
+
+// alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
+// E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
+template <typename T, int M, bool FROM_ALPHA>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) {
+  using C = ConvCfg<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + C::P * C::LD;
+  const int bp = blockIdx.x;
+  const int p = bp % a.Ni;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
+  const size_t off = size_t(bp) * C::N;
+  cx<T> jr[C::PPT];
+  if constexpr (FROM_ALPHA) {
+    for (int e = tid; e < C::N; e += C::NT) buf[(e / M) * C::LD + (e % M)] = cx<T>{T(0), T(0)};
+    __syncthreads();
+    const int K = a.K, kmin = -(K / 2);
+    const cx<T>* al = a.in + size_t(bp) * K * K;
+    for (int e = tid; e < K * K; e += C::NT) {
+      const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
+      buf[iy * C::LD + ix] = al[e];
+    }
+    __syncthreads();
+    LdsFft<T, M, C::EPT_M, +1, C::U_SYN>{buf, M, C::LD, 1, tw, C::P / M}.run();
+    LdsFft<T, M, C::EPT_M, +1, C::U_SYN>{buf, M, 1, C::LD, tw, C::P / M}.run();
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int n = tid + q * C::NT;
+      jr[q] = buf[(n / M) * C::LD + (n % M)];
+      if (a.J) a.J[off + n] = jr[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int n = tid + q * C::NT;
+      jr[q] = a.in[off + n];
+      buf[(n / M) * C::LD + (n % M)] = jr[q];
+    }
+    __syncthreads();
+  }
+  conv_core<T, M>(buf, tw, a.ghat, false);
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    cx<T> e = buf[(n / M) * C::LD + (n % M)] + a.beta * jr[q];
+    if (a.einc) e = e + a.einc[size_t(p) * C::N + n];
+    a.E[off + n] = e;
+  }
+}
+
+template <typename T>
+struct AdjArgs {
+  const cx<T>* J;      // [BP][N] currents, or null (alpha = 0)
+  const cx<T>* E;      // [BP][N], or [Ni][N] if e_shared
+  int e_shared;
+  const cx<T>* h;      // [BP][N] G_S^H (data residual or measured field)
+  const cx<T>* R;      // [B][N]
+  const T* den;        // [B][N]  sum_p |E_p|^2
+  const cx<T>* gR;     // [B][N] dL/dR from the regularisers, or null
+  const double* Ss;    // ||E_inc||^2 (scalar)
+  const double* Sd;    // [B] ||E_sca||^2
+  double hsign;        // sign applied to h
+  const cx<T>* ghat;
+  const cx<T>* tw;
+  cx<T>* galpha;       // [BP][K][K] gradient output, or null
+  cx<T>* alpha;        // Adam: parameters updated in place (null: no update)
+  T* m;
+  T* v;
+  const int* tstep;    // [B] steps taken including this one
+  const int* frozen;   // [B] nonzero: skip the update, or null
+  double lr, b1, b2, eps;
+  int Ni, K;
+  T beta;
+};
+
+// Adjoint of the loss (chain rule through Eqs. 6-7, 9, 15-16):
+//   g_s = 2 s / ||E_inc||^2,  s = R E - beta J
+//   g_E = conj(R) g_s + (beta conj(g_R) J - 2 Re(conj(g_R) R) E) / den
+//   g_J = -beta g_s + beta g_R E / den + beta g_E + G_D^H g_E + 2 G_S^H d / ||E_sca||^2
+//   g_alpha = B^H g_J  (unnormalised forward DFT on the kept modes)
+// The state loss's own derivative in R vanishes because R is its per-pixel
+// least-squares minimiser, so only the regulariser part g_R reaches R.
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) {
+  using C = ConvCfg<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + C::P * C::LD;
+  const int bp = blockIdx.x;
+  const int b = bp / a.Ni, p = bp % a.Ni;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
+  const size_t off = size_t(bp) * C::N;
+  const size_t eoff = size_t(a.e_shared ? p : bp) * C::N;
+  const size_t boff = size_t(b) * C::N;
+  const T ws = T(2.0 / a.Ss[0]);
+  const T wd = T(a.hsign * 2.0 / a.Sd[b]);
+  const T beta = a.beta;
+  cx<T> gj[C::PPT];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    const cx<T> J = a.J ? a.J[off + n] : cx<T>{T(0), T(0)};
+    const cx<T> E = a.E[eoff + n];
+    const cx<T> R = a.R[boff + n];
+    const cx<T> s = R * E - beta * J;
+    const cx<T> gs = ws * s;
+    cx<T> gE = cmul_conj_a(R, gs);
+    cx<T> gJ = (-beta) * gs + wd * a.h[off + n];
+    if (a.gR) {
+      const cx<T> g = a.gR[boff + n];
+      const T inv = T(1) / a.den[boff + n];
+      const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
+      gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
+      gJ = gJ + (beta * inv) * (g * E);
+    }
+    gJ = gJ + beta * gE;
+    buf[(n / M) * C::LD + (n % M)] = gE;
+    gj[q] = gJ;
+  }
+  __syncthreads();
+  conv_core<T, M>(buf, tw, a.ghat, true);
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    cx<T>& x = buf[(n / M) * C::LD + (n % M)];
+    x = x + gj[q];
+  }
+  __syncthreads();
+  LdsFft<T, M, C::EPT_M, -1, C::U_SYN>{buf, M, C::LD, 1, tw, C::P / M}.run();
+  LdsFft<T, M, C::EPT_M, -1, C::U_SYN>{buf, M, 1, C::LD, tw, C::P / M}.run();
+  const int K = a.K, kmin = -(K / 2);
+  const bool upd = a.alpha && !(a.frozen && a.frozen[b]);
+  double bc1 = 1.0, bc2 = 1.0;
+  if (upd) {
+    const int t = a.tstep[b];
+    bc1 = 1.0 - pow(a.b1, double(t));
+    bc2 = 1.0 - pow(a.b2, double(t));
+  }
+  for (int e = tid; e < K * K; e += C::NT) {
+    const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
+    const cx<T> g = buf[iy * C::LD + ix];
+    const size_t idx = size_t(bp) * K * K + e;
+    if (a.galpha) a.galpha[idx] = g;
+    if (upd) {
+      const T b1 = T(a.b1), b2 = T(a.b2);
+      T m0 = b1 * a.m[2 * idx] + (T(1) - b1) * g.x;
+      T m1 = b1 * a.m[2 * idx + 1] + (T(1) - b1) * g.y;
+      T v0 = b2 * a.v[2 * idx] + (T(1) - b2) * g.x * g.x;
+      T v1 = b2 * a.v[2 * idx + 1] + (T(1) - b2) * g.y * g.y;
+      a.m[2 * idx] = m0;
+      a.m[2 * idx + 1] = m1;
+      a.v[2 * idx] = v0;
+      a.v[2 * idx + 1] = v1;
+      const T lr1 = T(a.lr / bc1), ic2 = T(1.0 / bc2), eps = T(a.eps);
+      cx<T> al = a.alpha[idx];
+      al.x -= lr1 * m0 / (sqrt(v0 * ic2) + eps);
+      al.y -= lr1 * m1 / (sqrt(v1 * ic2) + eps);
+      a.alpha[idx] = al;
+    }
+  }
+}
+
+}  // namespace pdfk

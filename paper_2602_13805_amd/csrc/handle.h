@@ -1,0 +1,50 @@
+// Internal state of a pdf_handle and shared host helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/pdf.h"
+
+struct pdf_handle {
+  int prec = PDF_FP32;
+  int M = 0, N = 0, P = 0, K = 0, Ni = 0, Ns = 0, B = 0;
+  int tile = 256, ntiles = 0;
+  pdf_params prm{};
+  hipStream_t stream = nullptr;
+  // operator tables (handle precision)
+  void* ghat = nullptr;   // [P][P] spectrum / P^2
+  void* tw = nullptr;     // [P] exp(-2 pi i k / P)
+  void* gs = nullptr;     // [Ns][N]
+  void* einc = nullptr;   // [Ni][N]
+  double* Ss = nullptr;   // device scalar ||E_inc||^2
+  double* Sd = nullptr;   // device [B] ||E_sca||^2
+  void* esca = nullptr;   // [B][Ni][Ns]
+  bool data_set = false;
+  // per-iteration scratch
+  void* J = nullptr;      // [B][Ni][N]
+  void* E = nullptr;      // [B][Ni][N]
+  void* h = nullptr;      // [B][Ni][N]
+  void* R = nullptr;      // [B][N]
+  void* den = nullptr;    // [B][N] real
+  void* chi = nullptr;    // [B][N]
+  void* gR = nullptr;     // [B][N]
+  void* Dpart = nullptr;  // [B][ntiles][Ni][Ns]
+  void* dres = nullptr;   // [B][Ni][Ns]
+  double* lsp = nullptr;  // [B][ntiles]
+  // start-value and reconstruction scratch
+  void* R0 = nullptr;     // [B][N]
+  void* g0 = nullptr;     // [B][Ni][K][K]
+  double* gnorm = nullptr;   // [B]
+  double* err = nullptr;     // [B]
+  int* frozen = nullptr;     // [B]
+  int* tstep = nullptr;      // [B]
+  void* m = nullptr;         // [B][Ni][K][K][2] real
+  void* v = nullptr;
+  double* loss = nullptr;    // [B][8]
+  std::string err_msg;
+};
+
+// Message returned by pdf_last_error(NULL).
+void pdf_set_global_error(const std::string& msg);

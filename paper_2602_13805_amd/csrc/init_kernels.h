@@ -1,0 +1,125 @@
+// Kernels of the start value (Sec. 3.1) and of the reconstruction loop.
+#pragma once
+
+#include "cplx.h"
+#include "pixel_kernels.h"
+
+namespace pdfk {
+
+// Back-propagation scalar of one (instance, incidence) pair (grid: B * Ni):
+//   v = G_S u (reduced here from the split-K parts), gamma = (v^H e)/(v^H v),
+//   u <- gamma u, so that J_BP = gamma G_S^H e.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bp_gamma(const cx<T>* Dpart, int ntiles, const cx<T>* esca,
+                                                  cx<T>* u, int Ni, int Ns, int N) {
+  __shared__ double red[16];
+  __shared__ double gam[2];
+  const int bp = blockIdx.x, b = bp / Ni, p = bp % Ni, tid = threadIdx.x;
+  double nr = 0, ni = 0, dd = 0;
+  for (int q = tid; q < Ns; q += blockDim.x) {
+    double vr = 0, vi = 0;
+    for (int t = 0; t < ntiles; ++t) {
+      const cx<T> x = Dpart[((size_t(b) * ntiles + t) * Ni + p) * Ns + q];
+      vr += x.x;
+      vi += x.y;
+    }
+    const cx<T> e = esca[(size_t(b) * Ni + p) * Ns + q];
+    nr += vr * e.x + vi * e.y;  // conj(v) e
+    ni += vr * e.y - vi * e.x;
+    dd += vr * vr + vi * vi;
+  }
+  const double snr = block_sum(nr, red);
+  const double sni = block_sum(ni, red);
+  const double sdd = block_sum(dd, red);
+  if (tid == 0) {
+    gam[0] = sdd > 0 ? snr / sdd : 0.0;
+    gam[1] = sdd > 0 ? sni / sdd : 0.0;
+  }
+  __syncthreads();
+  const cx<T> g{T(gam[0]), T(gam[1])};
+  cx<T>* row = u + size_t(bp) * N;
+  for (int n = tid; n < N; n += blockDim.x) row[n] = g * row[n];
+}
+
+// chi_0 = sum_p J conj(E) / sum_p |E|^2 and R_0 = beta chi_0 / (beta chi_0 + 1) (Eq. 7).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bp_contrast(const cx<T>* J, const cx<T>* E, cx<T>* R0, int Ni, int N,
+                                                     double beta) {
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double nr = 0, ni = 0, dd = 0;
+  for (int p = 0; p < Ni; ++p) {
+    const size_t idx = (size_t(b) * Ni + p) * N + n;
+    const cx<T> j = J[idx], e = E[idx];
+    nr += double(j.x) * e.x + double(j.y) * e.y;
+    ni += double(j.y) * e.x - double(j.x) * e.y;
+    dd += double(e.x) * e.x + double(e.y) * e.y;
+  }
+  const double cr = nr / dd, ci = ni / dd;
+  // R0 = beta chi / (beta chi + 1)
+  const double ar = beta * cr, ai = beta * ci;
+  const double br = ar + 1.0, bi = ai;
+  const double q = br * br + bi * bi;
+  R0[size_t(b) * N + n] = cx<T>{T((ar * br + ai * bi) / q), T((ai * br - ar * bi) / q)};
+}
+
+// Exact line search of the quadratic L^CSI along -g (grid: B):
+//   t* = (||g||^2 / 2) / (||A_d g||^2 / S_d + ||A_s g||^2 / S_s),  alpha_0 = -t* g.
+template <typename T>
+__global__ __launch_bounds__(256) void k_line_search(const double* lsp, const cx<T>* Dpart, int ntiles, int Ni,
+                                                     int Ns, const double* gnorm, const double* Ss,
+                                                     const double* Sd, const cx<T>* g0, cx<T>* alpha, int KK) {
+  __shared__ double red[16];
+  __shared__ double tstar;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int NO = Ni * Ns;
+  double dsum = 0.0;
+  for (int o = tid; o < NO; o += blockDim.x) {
+    double xr = 0, xi = 0;
+    for (int t = 0; t < ntiles; ++t) {
+      const cx<T> v = Dpart[(size_t(b) * ntiles + t) * NO + o];
+      xr += v.x;
+      xi += v.y;
+    }
+    dsum += xr * xr + xi * xi;
+  }
+  const double sd = block_sum(dsum, red);
+  if (tid == 0) {
+    double ss = 0.0;
+    for (int t = 0; t < ntiles; ++t) ss += lsp[size_t(b) * ntiles + t];
+    const double q = sd / Sd[b] + ss / Ss[0];
+    tstar = q > 0 ? 0.5 * gnorm[b] / q : 0.0;
+  }
+  __syncthreads();
+  const T t = T(tstar);
+  const size_t len = size_t(Ni) * KK;
+  for (size_t e = tid; e < len; e += blockDim.x) {
+    const cx<T> g = g0[size_t(b) * len + e];
+    alpha[size_t(b) * len + e] = cx<T>{-t * g.x, -t * g.y};
+  }
+}
+
+// Stop updating an instance once its image error reaches its target.
+__global__ void k_check_target(const double* err, const double* target, int* frozen, int* reached,
+                               const int* tstep, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (!frozen[b] && err[b] <= target[b]) {
+    frozen[b] = 1;
+    if (reached) reached[b] = tstep[b];
+  }
+}
+
+__global__ void k_fill_int(int* x, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* x, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = T(0);
+}
+
+}  // namespace pdfk

@@ -1,0 +1,400 @@
+// Per-pixel and per-instance kernels: the reduction over incidences that
+// yields the CIE contrast and the state loss, the receiver GEMMs, the
+// regularisers with their gradient, the CCO image, and small reductions.
+#pragma once
+
+#include "cplx.h"
+
+namespace pdfk {
+
+// Deterministic sum over a block (fixed tree).  red: >= blockDim.x/64 doubles of LDS.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  return s;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double x, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_down(x, o, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s = fmax(s, red[i]);
+  }
+  return s;
+}
+
+template <typename T>
+struct ReduceArgs {
+  const cx<T>* J;       // [B][Ni][N]
+  const cx<T>* E;       // [B][Ni][N]
+  const cx<T>* gs;      // [Ns][N]
+  const cx<T>* Rfix;    // [B][N] fixed contrast, or null (least squares)
+  cx<T>* R;             // [B][N] out (least squares only)
+  T* den;               // [B][N] out
+  cx<T>* chi;           // [B][N] out
+  double* lsp;          // [B][ntiles] out: partial sum_p |R E_p - beta J_p|^2
+  cx<T>* Dpart;         // [B][ntiles][Ni][Ns] out: partial G_S J over the tile
+  int Ni, Ns, N, ntiles;
+  T beta;
+};
+
+// Tile of pixels x all incidences of one instance (grid: ntiles x B).
+//   num = sum_p J conj(E), den = sum_p |E|^2 (FP64 accumulation)
+//   R = beta num / den (Eq. 6 solved per pixel), chi = R / (beta (1 - R)) (Eq. 7)
+//   sum_p |R E - beta J|^2 = |R|^2 den - 2 beta Re(R conj(num)) + beta^2 sum |J|^2
+//   Dpart[p][q] = sum_{n in tile} G_S[q][n] J_p[n]   (split-K part of Eq. 16)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pixel_reduce(ReduceArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TILE = blockDim.x;
+  cx<T>* Jt = reinterpret_cast<cx<T>*>(smem_raw);  // [Ni][TILE]
+  double* red = reinterpret_cast<double*>(Jt + size_t(a.Ni) * TILE);
+  const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int n = tile * TILE + tid;
+  const bool valid = n < a.N;
+  double nr = 0, ni = 0, dd = 0, jj = 0;
+  for (int p = 0; p < a.Ni; ++p) {
+    cx<T> J{T(0), T(0)}, E{T(0), T(0)};
+    if (valid) {
+      const size_t idx = (size_t(b) * a.Ni + p) * a.N + n;
+      J = a.J[idx];
+      E = a.E[idx];
+    }
+    nr += double(J.x) * E.x + double(J.y) * E.y;
+    ni += double(J.y) * E.x - double(J.x) * E.y;
+    dd += double(E.x) * E.x + double(E.y) * E.y;
+    jj += double(J.x) * J.x + double(J.y) * J.y;
+    Jt[size_t(p) * TILE + tid] = J;
+  }
+  double lpix = 0.0;
+  if (valid) {
+    const double beta = a.beta;
+    double rr, ri;
+    if (a.Rfix) {
+      const cx<T> r = a.Rfix[size_t(b) * a.N + n];
+      rr = r.x;
+      ri = r.y;
+    } else {
+      rr = beta * nr / dd;
+      ri = beta * ni / dd;
+      a.R[size_t(b) * a.N + n] = cx<T>{T(rr), T(ri)};
+    }
+    // sum_p |R E_p - beta J_p|^2
+    lpix = (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
+    a.den[size_t(b) * a.N + n] = T(dd);
+    // chi = R / (beta (1 - R))
+    const double xr = 1.0 - rr, xi = -ri;
+    const double q = beta * (xr * xr + xi * xi);
+    a.chi[size_t(b) * a.N + n] = cx<T>{T((rr * xr + ri * xi) / q), T((ri * xr - rr * xi) / q)};
+  }
+  const double s = block_sum(lpix, red);
+  if (tid == 0) a.lsp[size_t(b) * a.ntiles + tile] = s;
+  __syncthreads();
+  const int tile0 = tile * TILE;
+  const int kmax = min(TILE, a.N - tile0);
+  for (int o = tid; o < a.Ni * a.Ns; o += TILE) {
+    const int p = o / a.Ns, q = o % a.Ns;
+    const cx<T>* g = a.gs + size_t(q) * a.N + tile0;
+    const cx<T>* jt = Jt + size_t(p) * TILE;
+    cx<T> acc{T(0), T(0)};
+    for (int k = 0; k < kmax; ++k) acc = acc + g[k] * jt[k];
+    a.Dpart[((size_t(b) * a.ntiles + tile) * a.Ni + p) * a.Ns + q] = acc;
+  }
+}
+
+template <typename T>
+struct RegArgs {
+  const cx<T>* chi;     // [B][N]
+  const cx<T>* R;       // [B][N]
+  const cx<T>* Dpart;   // [B][ntiles][Ni][Ns]
+  const double* lsp;    // [B][ntiles]
+  const cx<T>* esca;    // [B][Ni][Ns]
+  const double* Ss;     // scalar
+  const double* Sd;     // [B]
+  cx<T>* d;             // [B][Ni][Ns] out: G_S J - E_sca
+  cx<T>* gR;            // [B][N] out
+  double* loss;         // [B][8] out, or null
+  int* tstep;           // [B] incremented when non-null
+  const int* frozen;    // [B] or null
+  int M, Ni, Ns, ntiles;
+  double beta, lam_bound, lam_tv, lam_bridge, tau_b, eps_tv, eps_abs;
+  int r_stopgrad;
+};
+
+template <typename T>
+__device__ __forceinline__ T sigm(T x) { return T(1) / (T(1) + exp(-x)); }
+
+// Regulariser terms anchored at pixel (i, j): value and the partial
+// gradients with respect to chi(i,j), chi(i,j+1), chi(i+1,j) (Eqs. 17-19).
+template <typename T>
+struct RegTerm {
+  double val_bound, val_tv, val_bridge;
+  cx<T> g_self, g_right, g_down;  // weighted by the lambdas
+};
+
+template <typename T>
+__device__ __forceinline__ RegTerm<T> reg_term(const cx<T>* c, int i, int j, int M, const RegArgs<T>& a) {
+  RegTerm<T> r;
+  const cx<T> z = c[i * M + j];
+  const bool hr = j + 1 < M, hd = i + 1 < M;
+  const cx<T> zr = hr ? c[i * M + j + 1] : z;
+  const cx<T> zd = hd ? c[(i + 1) * M + j] : z;
+  // bound
+  const T neg = z.x < T(0) ? -z.x : T(0);
+  r.val_bound = double(neg) * neg;
+  cx<T> gs{T(-2 * a.lam_bound) * neg, T(0)};
+  // total variation
+  const cx<T> dx = zr - z, dy = zd - z;
+  const T t = sqrt(norm2(dx) + norm2(dy) + T(a.eps_tv));
+  r.val_tv = t;
+  const T wt = T(a.lam_tv) / t;
+  cx<T> gr = wt * dx, gd = wt * dy;
+  gs = gs - wt * (dx + dy);
+  // bridge, on the smoothed modulus a = sqrt(|chi|^2 + eps_abs)
+  const T e = T(a.eps_abs), tb = T(a.tau_b);
+  const T az = sqrt(norm2(z) + e), ar = sqrt(norm2(zr) + e), ad = sqrt(norm2(zd) + e);
+  const T ax = hr ? ar - az : T(0), ay = hd ? ad - az : T(0);
+  const T sg = sigm((az - tb) / tb);
+  const T ex = exp(-ax * ax - ay * ay);
+  r.val_bridge = double(sg) * ex;
+  const T lb = T(a.lam_bridge);
+  const T ga = lb * (sg * (T(1) - sg) / tb * ex + T(2) * sg * ex * (ax + ay));
+  gs = gs + (ga / az) * z;
+  if (hr) gr = gr + (lb * T(-2) * ax * sg * ex / ar) * zr;
+  if (hd) gd = gd + (lb * T(-2) * ay * sg * ex / ad) * zd;
+  r.g_self = gs;
+  r.g_right = gr;
+  r.g_down = gd;
+  return r;
+}
+
+// One instance per block: data residual and L^Data from the split-K parts,
+// L^State from its partial sums, the three regularisers on chi with their
+// gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int M = a.M, N = M * M;
+  cx<T>* c = reinterpret_cast<cx<T>*>(smem_raw);   // chi [M][M]
+  double* red = reinterpret_cast<double*>(c + N);
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) a.tstep[b] += 1;
+  double dsum = 0.0;
+  const int NO = a.Ni * a.Ns;
+  for (int o = tid; o < NO; o += nt) {
+    double xr = 0.0, xi = 0.0;
+    for (int t = 0; t < a.ntiles; ++t) {
+      const cx<T> v = a.Dpart[(size_t(b) * a.ntiles + t) * NO + o];
+      xr += v.x;
+      xi += v.y;
+    }
+    const cx<T> e = a.esca[size_t(b) * NO + o];
+    const double rr = xr - e.x, ri = xi - e.y;
+    dsum += rr * rr + ri * ri;
+    a.d[size_t(b) * NO + o] = cx<T>{T(rr), T(ri)};
+  }
+  for (int n = tid; n < N; n += nt) c[n] = a.chi[size_t(b) * N + n];
+  __syncthreads();
+  double vb = 0, vt = 0, vr = 0, rmax = 0;
+  bool bad = false;
+  for (int n = tid; n < N; n += nt) {
+    const int i = n / M, j = n % M;
+    RegTerm<T> t0 = reg_term<T>(c, i, j, M, a);
+    vb += t0.val_bound;
+    vt += t0.val_tv;
+    vr += t0.val_bridge;
+    cx<T> g = t0.g_self;
+    if (j > 0) g = g + reg_term<T>(c, i, j - 1, M, a).g_right;
+    if (i > 0) g = g + reg_term<T>(c, i - 1, j, M, a).g_down;
+    const cx<T> R = a.R[size_t(b) * N + n];
+    rmax = fmax(rmax, sqrt(double(norm2(R))));
+    cx<T> gR{T(0), T(0)};
+    if (!a.r_stopgrad) {
+      // conj(1 / (beta (1 - R)^2)) * g
+      const cx<T> om{T(1) - R.x, -R.y};
+      const cx<T> w = om * om;
+      const T den = T(a.beta) * norm2(w);
+      gR = cx<T>{(w.x * g.x - w.y * g.y) / den, (w.x * g.y + w.y * g.x) / den};
+    }
+    if (!(isfinite(gR.x) && isfinite(gR.y))) bad = true;
+    a.gR[size_t(b) * N + n] = gR;
+  }
+  const double Sd = block_sum(dsum, red);
+  const double Sb = block_sum(vb, red);
+  const double St = block_sum(vt, red);
+  const double Sr = block_sum(vr, red);
+  const double Rm = block_max(rmax, red);
+  const double nb = block_sum(bad ? 1.0 : 0.0, red);
+  if (tid == 0 && a.loss) {
+    double ls = 0.0;
+    for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
+    ls /= a.Ss[0];
+    const double ld = Sd / a.Sd[b];
+    const double tot = ls + ld + a.lam_bound * Sb + a.lam_tv * St + a.lam_bridge * Sr;
+    double* L = a.loss + size_t(b) * 8;
+    L[0] = ls;
+    L[1] = ld;
+    L[2] = Sb;
+    L[3] = St;
+    L[4] = Sr;
+    L[5] = tot;
+    L[6] = Rm;
+    L[7] = (isfinite(tot) && nb == 0.0) ? 0.0 : 1.0;
+  }
+}
+
+// h[b][p][n] = s * sum_q conj(G_S[q][n]) x[b][p][q]   (G_S^H applied to Ns-vectors)
+// Grid: (ceil(N / 256), B), block 256; the G_S column of a pixel sits in registers.
+template <typename T, int NSMAX>
+__global__ __launch_bounds__(256) void k_adj_gemm(const cx<T>* __restrict__ gs, const cx<T>* __restrict__ x,
+                                                  cx<T>* __restrict__ h, int Ni, int Ns, int N) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* xs = reinterpret_cast<cx<T>*>(smem_raw);  // [Ni][Ns]
+  const int b = blockIdx.y, tid = threadIdx.x;
+  for (int o = tid; o < Ni * Ns; o += blockDim.x) xs[o] = x[size_t(b) * Ni * Ns + o];
+  __syncthreads();
+  const int n = blockIdx.x * blockDim.x + tid;
+  if (n >= N) return;
+  cx<T> g[NSMAX];
+#pragma unroll
+  for (int q = 0; q < NSMAX; ++q) g[q] = q < Ns ? gs[size_t(q) * N + n] : cx<T>{T(0), T(0)};
+  for (int p = 0; p < Ni; ++p) {
+    cx<T> acc{T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < NSMAX; ++q) {
+      if (q < Ns) acc = acc + cmul_conj_a(g[q], xs[p * Ns + q]);
+    }
+    h[(size_t(b) * Ni + p) * N + n] = acc;
+  }
+}
+
+// s[b] = sum |x[b][*]|^2 over len entries (grid: B blocks).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq(const cx<T>* x, size_t len, double* s) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const cx<T> v = x[size_t(b) * len + i];
+    acc += double(v.x) * v.x + double(v.y) * v.y;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) s[b] = t;
+}
+
+// Count-normalised (2r+1)^2 box mean of an M x M array in LDS.
+template <typename T>
+__device__ __forceinline__ T box_mean(const T* x, int i, int j, int M, int r) {
+  T s = T(0);
+  int cnt = 0;
+  for (int di = -r; di <= r; ++di) {
+    const int ii = i + di;
+    if (ii < 0 || ii >= M) continue;
+    for (int dj = -r; dj <= r; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= M) continue;
+      s += x[ii * M + jj];
+      ++cnt;
+    }
+  }
+  return s / T(cnt);
+}
+
+template <typename T>
+struct CcoArgs {
+  const cx<T>* chi;        // [B][N]
+  cx<T>* out;              // [B][N] CCO image, or null
+  const cx<T>* eps_true;   // [B][N] or null
+  double* err;             // [B] or null
+  int M, r;
+  double gf_eps, tau, eta_max, delta;
+};
+
+// CCO (Sec. 2.4, Eqs. 10-11): chi_cco = (1 + eta) G(chi|chi) + eta chi with the
+// self-guided filter G on Re and Im separately and
+// eta = eta_max sigmoid((|chi| - tau) / delta); optional relative error of
+// 1 + chi_cco against the true permittivity.  One instance per block.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cco(CcoArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int M = a.M, N = M * M;
+  T* pr = reinterpret_cast<T*>(smem_raw);  // Re chi, Im chi, A_re, b_re, A_im, b_im
+  T* pi = pr + N;
+  T* Ar = pi + N;
+  T* br = Ar + N;
+  T* Ai = br + N;
+  T* bi = Ai + N;
+  double* red = reinterpret_cast<double*>(bi + N);
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  for (int n = tid; n < N; n += nt) {
+    const cx<T> z = a.chi[size_t(b) * N + n];
+    pr[n] = z.x;
+    pi[n] = z.y;
+  }
+  __syncthreads();
+  const T ge = T(a.gf_eps);
+  for (int n = tid; n < N; n += nt) {
+    const int i = n / M, j = n % M;
+    for (int part = 0; part < 2; ++part) {
+      const T* p = part ? pi : pr;
+      T s = 0, s2 = 0;
+      int cnt = 0;
+      for (int di = -a.r; di <= a.r; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= M) continue;
+        for (int dj = -a.r; dj <= a.r; ++dj) {
+          const int jj = j + dj;
+          if (jj < 0 || jj >= M) continue;
+          const T v = p[ii * M + jj];
+          s += v;
+          s2 += v * v;
+          ++cnt;
+        }
+      }
+      const T mu = s / T(cnt);
+      const T var = s2 / T(cnt) - mu * mu;
+      const T A = var / (var + ge);
+      (part ? Ai : Ar)[n] = A;
+      (part ? bi : br)[n] = (T(1) - A) * mu;
+    }
+  }
+  __syncthreads();
+  double enum_ = 0, eden = 0;
+  for (int n = tid; n < N; n += nt) {
+    const int i = n / M, j = n % M;
+    const T gr = box_mean(Ar, i, j, M, a.r) * pr[n] + box_mean(br, i, j, M, a.r);
+    const T gi = box_mean(Ai, i, j, M, a.r) * pi[n] + box_mean(bi, i, j, M, a.r);
+    const T mag = sqrt(pr[n] * pr[n] + pi[n] * pi[n]);
+    const T eta = T(a.eta_max) / (T(1) + exp(-(mag - T(a.tau)) / T(a.delta)));
+    const cx<T> o{(T(1) + eta) * gr + eta * pr[n], (T(1) + eta) * gi + eta * pi[n]};
+    if (a.out) a.out[size_t(b) * N + n] = o;
+    if (a.eps_true) {
+      const cx<T> e = a.eps_true[size_t(b) * N + n];
+      const double dr = double(T(1) + o.x) - e.x, di = double(o.y) - e.y;
+      enum_ += dr * dr + di * di;
+      eden += double(e.x) * e.x + double(e.y) * e.y;
+    }
+  }
+  if (a.err) {
+    const double s1 = block_sum(enum_, red);
+    const double s2 = block_sum(eden, red);
+    if (tid == 0) a.err[b] = sqrt(s1 / s2);
+  }
+}
+
+}  // namespace pdfk

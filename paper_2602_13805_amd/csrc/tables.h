@@ -1,0 +1,30 @@
+// Host FP64 operator tables (see tables.cpp).
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+namespace pdfh {
+
+struct Geometry {
+  int M;
+  double side, cx, cy, freq;
+  int ni, ns;
+  const double* tx;  // [ni][2]
+  const double* rx;  // [ns][2]
+};
+
+struct Tables {
+  bool want_ghat = true, want_gs = true, want_einc = true;
+  std::vector<std::complex<double>> ghat;  // [2M][2M], unscaled FFT of the embedded kernel
+  std::vector<std::complex<double>> gs;    // [ns][M*M]
+  std::vector<std::complex<double>> einc;  // [ni][M*M]
+  double k0 = 0.0;
+  std::complex<double> cell, self;
+};
+
+int build_tables(const Geometry& g, Tables* t, std::string* err);
+void offset_kernel(int M, double h, double k0, std::vector<std::complex<double>>* ker);
+
+}  // namespace pdfh

@@ -1,0 +1,259 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP32 arithmetic on the device against FP64 on the host: loss terms
+and gradients within 1e-4 relative (norm-wise, and every gradient entry within
+1e-4 of the largest); the FP64 instantiation within 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from oracle import adam as oadam, cco as occo, forward, init as oinit, loss as oloss, solver as osolver
+from oracle import operators as ops
+from tests.common import geometry, make_case, rand_alpha, rel
+
+pytestmark = pytest.mark.gpu
+
+pdf = pytest.importorskip("paper_2602_13805_amd")
+DEV = "cuda:0"
+
+
+def solver_for(case, precision, batch=None, **kw):
+    wl = case["wl"]
+    B = batch or len(case["cases"])
+    params = pdf.default_params(precision, **kw)
+    s = pdf.Solver(case["M"], wl.side, wl.freq_hz, case["tx"], case["rx"], case["K"], batch=B, params=params,
+                   precision=precision, device=DEV)
+    es = np.stack([c["esca"] for c in case["cases"]])[:B]
+    s.set_data(torch.tensor(es, dtype=s.cdtype, device=DEV))
+    return s
+
+
+def oracle_terms(out):
+    return np.array([out["L_state"], out["L_data"], out["L_bound"], out["L_tv"], out["L_bridge"], out["L"]])
+
+
+def check_grad(g_dev, g_ref, tol):
+    g_dev = np.asarray(g_dev)
+    assert rel(g_dev, g_ref) < tol, rel(g_dev, g_ref)
+    assert np.max(np.abs(g_dev - g_ref)) < tol * np.max(np.abs(g_ref))
+
+
+CASES = [
+    # (M, K, Ni, Ns, batch, precision, tol)
+    (8, 5, 4, 6, 2, "fp32", 1e-4),
+    (16, 7, 6, 8, 2, "fp32", 1e-4),
+    (32, 9, 16, 32, 3, "fp32", 1e-4),
+    (64, 15, 32, 32, 1, "fp32", 1e-4),
+    (16, 7, 6, 8, 2, "fp64", 1e-9),
+    (32, 9, 16, 32, 2, "fp64", 1e-9),
+    (16, 16, 3, 5, 1, "fp32", 1e-4),   # full basis, even K (corner blocks)
+    (32, 14, 5, 7, 1, "fp64", 1e-9),   # paper's corner set M_F = 7
+    (16, 1, 1, 1, 1, "fp32", 1e-4),    # degenerate: one mode, one antenna each
+]
+
+
+@pytest.mark.parametrize("M,K,Ni,Ns,B,prec,tol", CASES)
+def test_loss_grad_parity(M, K, Ni, Ns, B, prec, tol):
+    print(f"case M={M} K={K} Ni={Ni} Ns={Ns} B={B} {prec}", flush=True)
+    case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+    s = solver_for(case, prec)
+    alpha = np.stack([rand_alpha((Ni, K, K), seed=10 + b) for b in range(B)])
+    loss, g = s.loss_grad(torch.tensor(alpha, dtype=s.cdtype, device=DEV))
+    loss = loss.cpu().numpy()
+    g = g.cpu().numpy()
+    for b, c in enumerate(case["cases"]):
+        ref = oloss.evaluate(alpha[b], c["prob"])
+        want = oracle_terms(ref)
+        got = loss[b, :6]
+        assert np.all(np.abs(got - want) <= tol * np.abs(want) + tol * 1e-3 * abs(want[5])), (b, got, want)
+        assert loss[b, 7] == 0.0
+        check_grad(g[b], ref["g_alpha"], tol)
+    s.close()
+
+
+def test_cfg2_full_size_parity():
+    # 64 x 64, 32 Tx / 32 Rx, K = 15, data from a 128 x 128 MoM with noise and jitter
+    wl = si.WORKLOADS["cfg2"]
+    print("case cfg2 full size", flush=True)
+    jt, jr = si.draw_jitter(0, wl.n_tx, wl.n_rx, wl.jitter_deg)
+    txj = si.antenna_positions(wl.n_tx, wl.radius, angle_offsets=jt)
+    rxj = si.antenna_positions(wl.n_rx, wl.radius, angle_offsets=jr)
+    shapes = si.draw_profile(wl, 0)
+    es, _ = forward.mom_solve(si.rasterize(shapes, wl.M_fine, wl.side), wl.side, ops.wavenumber(wl.freq_hz),
+                              txj, rxj)
+    n1, n2 = si.draw_noise(0, es.shape)
+    es = forward.add_noise(es, wl.noise, n1, n2)
+    tx, rx = geometry(wl.n_tx, wl.n_rx)
+    prob = oloss.build_problem(wl.M, wl.K, wl.side, [wl.freq_hz], tx, rx, es)
+    a0 = oinit.alpha0(prob)[0][0]
+    s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=1, device=DEV)
+    s.set_data(torch.tensor(es[None], dtype=s.cdtype, device=DEV))
+    for alpha in (a0, a0 + rand_alpha(a0.shape, 0.02, 3)):
+        loss, g = s.loss_grad(torch.tensor(alpha[None], dtype=s.cdtype, device=DEV))
+        ref = oloss.evaluate(alpha, prob)
+        want = oracle_terms(ref)
+        got = loss.cpu().numpy()[0, :6]
+        assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-7 * abs(want[5])), (got, want)
+        check_grad(g.cpu().numpy()[0], ref["g_alpha"], 1e-4)
+    # start value on the device against the oracle's
+    a_dev = s.init_alpha().cpu().numpy()[0]
+    assert rel(a_dev, a0) < 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-4), ("fp64", 1e-9)])
+def test_init_alpha_parity(prec, tol):
+    case = make_case(32, 9, 8, 12, seeds=(0, 1))
+    s = solver_for(case, prec)
+    a = s.init_alpha().cpu().numpy()
+    for b, c in enumerate(case["cases"]):
+        ref, info = oinit.alpha0(c["prob"])
+        assert rel(a[b], ref[0]) < tol, rel(a[b], ref[0])
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-10)])
+def test_image_and_cco_parity(prec, tol):
+    case = make_case(32, 9, 8, 12, seeds=(0, 1))
+    s = solver_for(case, prec)
+    alpha = np.stack([oinit.alpha0(c["prob"])[0][0] for c in case["cases"]])
+    eps = np.stack([c["eps"] for c in case["cases"]])
+    chi, cco, err = s.image(torch.tensor(alpha, dtype=s.cdtype, device=DEV),
+                            torch.tensor(eps, dtype=s.cdtype, device=DEV))
+    for b, c in enumerate(case["cases"]):
+        ref = oloss.evaluate(alpha[b], c["prob"], grad=False)
+        assert rel(chi[b].cpu().numpy(), ref["chi"]) < tol
+        ref_cco = occo.cco(ref["chi"])
+        assert rel(cco[b].cpu().numpy(), ref_cco) < tol
+        assert abs(err[b].item() - occo.image_error(ref_cco, c["eps"])) < tol
+    s.close()
+
+
+def test_adam_steps_fp64_match_oracle():
+    case = make_case(16, 7, 6, 8, seeds=(0, 1))
+    s = solver_for(case, "fp64")
+    alpha0 = np.stack([rand_alpha((6, 7, 7), seed=20 + b) for b in range(2)])
+    a = torch.tensor(alpha0, dtype=s.cdtype, device=DEV)
+    m, v, t = s.new_state()
+    loss = torch.empty((2, 8), dtype=torch.float64, device=DEV)
+    for _ in range(12):
+        s.step(a, m, v, t, loss)
+    assert t.cpu().tolist() == [12, 12]
+    for b, c in enumerate(case["cases"]):
+        x = alpha0[b].copy()
+        mm = np.zeros(x.shape + (2,))
+        vv = np.zeros(x.shape + (2,))
+        for k in range(1, 13):
+            last = oloss.evaluate(x, c["prob"])
+            x, mm, vv = oadam.adam_step(x, last["g_alpha"], mm, vv, k)
+        assert rel(a[b].cpu().numpy(), x) < 1e-9
+        assert abs(loss[b, 5].item() - last["L"]) < 1e-9 * last["L"]
+    s.close()
+
+
+def test_reconstruct_fp64_matches_oracle_and_graph_replay():
+    # cfg1-shaped FP64 reconstruction: 32 x 32, 16 Tx / 32 Rx, K = 9, 100 Adam steps
+    print("case cfg1 reconstruct", flush=True)
+    wl = si.WORKLOADS["cfg1"]
+    case = make_case(wl.M, wl.K, wl.n_tx, wl.n_rx, seeds=(0, 1))
+    s = solver_for(case, "fp64")
+    res = s.reconstruct(100, n_check=25)
+    assert res["iters_run"] == 100
+    a_dev = res["alpha"].cpu().numpy()
+    for b, c in enumerate(case["cases"]):
+        ref = osolver.reconstruct(c["prob"], 100)
+        assert rel(a_dev[b], ref["alpha"][0]) < 1e-8, rel(a_dev[b], ref["alpha"][0])
+        assert rel(res["chi_cco"][b].cpu().numpy(), ref["chi_cco"]) < 1e-8
+    # the same steps issued one by one (no graph) give the same bits
+    a = s.init_alpha()
+    m, v, t = s.new_state()
+    for _ in range(100):
+        s.step(a, m, v, t)
+    assert torch.equal(a, res["alpha"])
+    s.close()
+
+
+def test_batched_equals_single_and_deterministic():
+    case = make_case(32, 9, 8, 12, seeds=(0, 1, 2))
+    sb = solver_for(case, "fp32")
+    alpha = np.stack([rand_alpha((8, 9, 9), seed=30 + b) for b in range(3)])
+    at = torch.tensor(alpha, dtype=sb.cdtype, device=DEV)
+    l1, g1 = sb.loss_grad(at)
+    l2, g2 = sb.loss_grad(at)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    for b in range(3):
+        one = dict(case)
+        one["cases"] = [case["cases"][b]]
+        s1 = solver_for(one, "fp32")
+        l, g = s1.loss_grad(at[b:b + 1].contiguous())
+        assert torch.equal(l[0], l1[b]) and torch.equal(g[0], g1[b])
+        s1.close()
+    sb.close()
+
+
+def test_gradient_fd_on_device_fp64():
+    # the device adjoint against central differences of the device loss
+    case = make_case(16, 7, 4, 6, seeds=(3,))
+    s = solver_for(case, "fp64")
+    alpha = rand_alpha((1, 4, 7, 7), seed=5)
+    at = torch.tensor(alpha, dtype=s.cdtype, device=DEV)
+    _, g = s.loss_grad(at)
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for _ in range(8):
+        idx = tuple(int(rng.integers(0, n)) for n in alpha.shape)
+        for d in (1.0, 1j):
+            h = 1e-7
+            ap, am = alpha.copy(), alpha.copy()
+            ap[idx] += h * d
+            am[idx] -= h * d
+            lp = s.loss_grad(torch.tensor(ap, dtype=s.cdtype, device=DEV), grad=False)[0][0, 5].item()
+            lm = s.loss_grad(torch.tensor(am, dtype=s.cdtype, device=DEV), grad=False)[0][0, 5].item()
+            fd = (lp - lm) / (2 * h)
+            an = g[idx].real if d == 1.0 else g[idx].imag
+            assert abs(fd - an) < 1e-6 * np.max(np.abs(g)), (idx, d, fd, an)
+    s.close()
+
+
+def test_autograd_function_and_checkpoint():
+    case = make_case(16, 7, 4, 6, seeds=(0, 1))
+    s = solver_for(case, "fp32")
+    alpha = torch.tensor(np.stack([rand_alpha((4, 7, 7), seed=b) for b in range(2)]), dtype=s.cdtype,
+                         device=DEV, requires_grad=True)
+    w = torch.tensor([1.0, 0.5], dtype=torch.float64, device=DEV)
+    (pdf.PdfLoss.apply(alpha, s, False) * w).sum().backward()
+    g1 = alpha.grad.clone()
+    alpha.grad = None
+    (pdf.PdfLoss.apply(alpha, s, True) * w).sum().backward()
+    assert torch.equal(alpha.grad, g1)
+    _, g = s.loss_grad(alpha.detach().contiguous())
+    assert torch.allclose(g1[1], 0.5 * g[1])
+    s.close()
+
+
+def test_synthesize_matches_oracle_mom():
+    wl = si.WORKLOADS["cfg1"]
+    tx, rx = geometry(8, 12)
+    shapes = si.draw_profile(wl, 4)
+    eps = si.rasterize(shapes, 64, wl.side)
+    got = pdf.synthesize(64, wl.side, wl.freq_hz, tx, rx, eps, tol=1e-11, device=DEV)
+    ref, _ = forward.mom_solve(eps, wl.side, ops.wavenumber(wl.freq_hz), tx, rx)
+    assert rel(got, ref) < 1e-9, rel(got, ref)
+    # empty support: zero field
+    z = pdf.synthesize(16, wl.side, wl.freq_hz, tx, rx, np.ones((16, 16)), device=DEV)
+    assert np.all(z == 0)
+
+
+def test_error_paths_on_device():
+    case = make_case(16, 7, 4, 6, seeds=(0,))
+    wl = case["wl"]
+    s = pdf.Solver(16, wl.side, wl.freq_hz, case["tx"], case["rx"], 7, device=DEV)
+    with pytest.raises(pdf.PdfError) as e:
+        s.loss_grad(s.zeros_alpha())   # no data yet
+    assert e.value.code == -1
+    with pytest.raises(pdf.PdfError) as e:
+        s.set_data(torch.zeros((1, 4, 6), dtype=s.cdtype, device=DEV))  # ||E_sca|| = 0
+    assert e.value.code == -4
+    s.close()
