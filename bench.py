@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Throughput of the PDF hot path on one MI355X.
+
+Workload (cfg2): 64 x 64 inversion grid over a 2-wavelength domain, 32
+transmitters and 32 receivers on a 3-wavelength circle, K = 15 Fourier modes
+per axis, FP32.  Each of the `batch` instances has its own random profile
+(1-3 discs / ellipses, eps_r in [2, 4]) whose measured fields come from the
+library's FP64 method-of-moments solve on a 128 x 128 grid with +-2 degree
+antenna-angle jitter, plus 10 % complex AWGN.
+
+One step = one loss + gradient + Adam iteration of every instance in the
+batch (all hot-path kernels).  `value` = instance-iterations per second over
+the timed steps, inputs resident in HBM.  Also reported: per-kernel times
+(HIP events on the library's stream), the roofline of the dominant kernel,
+reconstructions per second to a fixed image error, single-instance numbers,
+and the FP64 oracle timed on the host (`cpu_baseline`).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDF loss+grad iters/s and reconstructions/s at 64² to fixed rel. image error"
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP32_PEAK = 157.3e12       # flop/s, MI355X FP32 vector (= FP32 matrix)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_cost(wl, B, ntiles):
+    """Algorithmic HBM bytes and flops per launch of each kernel (FP32, 8-byte complex).
+
+    Bytes count what a kernel must move at least: per-instance arrays once,
+    tables shared by the batch once.  Flops count 5 n log2 n per length-n FFT,
+    8 per complex multiply-add, 6 per complex multiply."""
+    M, K, Ni, Ns = wl.M, wl.K, wl.n_tx, wl.n_rx
+    N, P, c = M * M, 2 * M, 8
+    lg = lambda n: math.log2(n)
+    fft = lambda n: 5 * n * lg(n)
+    conv = (M + P + P + M) * fft(P) + 6 * P * P
+    synth = (K + M) * fft(M)
+    bytes_ = {
+        "fwd_conv": B * Ni * K * K * c + Ni * N * c + P * P * c + 2 * B * Ni * N * c,
+        "pixel_reduce": 2 * B * Ni * N * c + Ns * N * c + B * N * (8 + 4 + 8) + B * ntiles * (Ni * Ns * c + 8),
+        "image_reg": B * N * 16 + B * ntiles * Ni * Ns * c + 2 * B * Ni * Ns * c + B * N * c,
+        "adj_gemm": Ns * N * c + B * Ni * Ns * c + B * Ni * N * c,
+        "adj_conv": 3 * B * Ni * N * c + B * N * (8 + 4 + 8) + P * P * c + B * Ni * K * K * 48,
+    }
+    flops = {
+        "fwd_conv": B * Ni * (synth + conv + 6 * N),
+        "pixel_reduce": B * Ni * N * (8 * Ns + 16),
+        "image_reg": B * N * 150,
+        "adj_gemm": B * Ni * N * 8 * Ns,
+        "adj_conv": B * Ni * (conv + (M + K) * fft(M) + 60 * N),
+    }
+    return bytes_, flops
+
+
+def synthesize_batch(pdf, si, wl, B, dev):
+    import numpy as np
+    Ni, Ns, M = wl.n_tx, wl.n_rx, wl.M
+    esca = np.zeros((B, Ni, Ns), np.complex128)
+    eps = np.zeros((B, M, M), np.complex128)
+    for b in range(B):
+        shapes = si.draw_profile(wl, b)
+        jt, jr = si.draw_jitter(b, Ni, Ns, wl.jitter_deg)
+        txj = si.antenna_positions(Ni, wl.radius, angle_offsets=jt)
+        rxj = si.antenna_positions(Ns, wl.radius, angle_offsets=jr)
+        e = pdf.synthesize(wl.M_fine, wl.side, wl.freq_hz, txj, rxj, si.rasterize(shapes, wl.M_fine, wl.side),
+                           tol=1e-10, device=dev)
+        n1, n2 = si.draw_noise(b, e.shape)
+        esca[b] = si.add_noise(e, wl.noise, n1, n2)
+        eps[b] = si.rasterize(shapes, M, wl.side)
+        if (b + 1) % 16 == 0:
+            log(f"  synthesised {b + 1}/{B}")
+    return esca, eps
+
+
+def cpu_baseline(si, wl, esca0, seconds):
+    """The FP64 oracle's loss + gradient + Adam on one cfg2 instance, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import adam, init, loss
+    tx = si.antenna_positions(wl.n_tx, wl.radius)
+    rx = si.antenna_positions(wl.n_rx, wl.radius)
+    with threadpool_limits(limits=1):
+        prob = loss.build_problem(wl.M, wl.K, wl.side, [wl.freq_hz], tx, rx, esca0)
+        a, _ = init.alpha0(prob)
+        m = np.zeros(a.shape + (2,))
+        v = np.zeros(a.shape + (2,))
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            out = loss.evaluate(a, prob)
+            a, m, v = adam.adam_step(a, out["g_alpha"], m, v, n + 1)
+            n += 1
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="instance-iters/s", cores=1, kind="oracle",
+                sample=f"{n} loss+grad+Adam iterations of one cfg2 instance (64x64, 32/32, K=15, FP64 "
+                       f"NumPy/SciPy, 1 thread) in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--recon-iters", type=int, default=1000)
+    ap.add_argument("--no-recon", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: instances are independent, so N GPUs would each run their own "
+              "batch with no communication; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_13805_amd as pdf
+    import seeded_inputs as si
+
+    dev = "cuda:0"
+    wl = si.WORKLOADS["cfg2"]
+    B = args.batch
+    t0 = time.time()
+    esca, eps = synthesize_batch(pdf, si, wl, B, dev)
+    synth_s = time.time() - t0
+    log(f"synthesised {B} instances in {synth_s:.1f} s")
+
+    tx = si.antenna_positions(wl.n_tx, wl.radius)
+    rx = si.antenna_positions(wl.n_rx, wl.radius)
+    s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=B, device=dev)
+    s.set_data(torch.tensor(esca, dtype=s.cdtype, device=dev))
+    alpha = s.init_alpha()
+    m, v, t = s.new_state()
+    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        s.step(alpha, m, v, t, loss)
+    torch.cuda.synchronize()
+    s.timing(True, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(alpha, m, v, t, loss)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, nrec = s.timing_read()
+    s.timing(False)
+    value = B * args.steps / dt
+    log(f"{args.steps} steps x {B} instances in {dt:.3f} s: {value:.1f} instance-iters/s; kernels {kern_ms}")
+    if not np.all(np.isfinite(loss.cpu().numpy()[:, 5])):
+        raise RuntimeError("non-finite loss in the timed steps")
+
+    bytes_, flops = workload_cost(wl, B, s_ntiles(wl.M))
+    dom = max(kern_ms, key=kern_ms.get)
+    dur = kern_ms[dom] * 1e-3
+    t_hbm, t_alu = bytes_[dom] / HBM_PEAK, flops[dom] / FP32_PEAK
+    if t_alu > t_hbm:
+        roof = dict(bound="alu", achieved=flops[dom] / dur / 1e12, peak=FP32_PEAK / 1e12, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=bytes_[dom] / dur / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["algorithmic_bytes"] = bytes_[dom]
+    roof["algorithmic_flops"] = flops[dom]
+    roof["hbm_frac"] = bytes_[dom] / dur / HBM_PEAK
+    roof["alu_frac"] = flops[dom] / dur / FP32_PEAK
+    per_kernel = {k: dict(ms=kern_ms[k], GBps=bytes_[k] / (kern_ms[k] * 1e-3) / 1e9,
+                          TFLOPs=flops[k] / (kern_ms[k] * 1e-3) / 1e12) for k in kern_ms}
+
+    extra = {}
+    if not args.no_recon:
+        # Reference trajectory: each instance's lowest image error over R iterations (checked every
+        # 10); the timed run then stops each instance once it is within 5 % of that error.
+        R = args.recon_iters
+        eps_t = torch.tensor(eps, dtype=s.cdtype, device=dev)
+        ref = s.reconstruct(R, n_check=10, eps_true=eps_t)
+        target = (1.05 * ref["best_err"]).contiguous()
+        torch.cuda.synchronize()
+        res = s.reconstruct(R, n_check=10, eps_true=eps_t, target=target)
+        reached = res["reached"].cpu().numpy()
+        start_err = si_start_error(s, eps_t)
+        best = ref["best_err"].cpu().numpy()
+        extra["reconstructions"] = dict(
+            per_s=B / res["seconds"], seconds=res["seconds"], batch=B, n_reached=res["n_reached"],
+            mean_iters_to_target=float(np.mean(reached[reached >= 0])) if np.any(reached >= 0) else None,
+            target=f"1.05 x the lowest image error the same solver reaches within {R} iterations "
+                   "(checked every 10)",
+            mean_best_image_error=float(best.mean()), mean_start_image_error=float(start_err.mean()),
+            frac_improved_on_start=float(np.mean(best < start_err - 1e-6)))
+        # one instance alone: latency of a reconstruction and graph-replayed iterations
+        s1 = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=1, device=dev)
+        s1.set_data(torch.tensor(esca[:1], dtype=s1.cdtype, device=dev))
+        s1.reconstruct(50, n_check=50)
+        one = s1.reconstruct(R, n_check=R)
+        one_t = s1.reconstruct(R, n_check=10, eps_true=eps_t[:1].contiguous(), target=target[:1].contiguous())
+        extra["single_instance"] = dict(
+            iters_per_s=R / one["seconds"], seconds_per_reconstruction=one_t["seconds"],
+            iters_to_target=int(one_t["reached"].item()))
+        s1.close()
+        log(f"reconstructions: {extra}")
+    s.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "instance-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cfg2: 64x64 grid over 2 wavelengths, 32 Tx / 32 Rx on a 3-wavelength circle, "
+                               "K=15, FP32; fields from FP64 MoM on 128x128 with +-2 deg jitter and 10% AWGN",
+                   "batch": B, "M": wl.M, "K": wl.K, "n_tx": wl.n_tx, "n_rx": wl.n_rx,
+                   "freq_hz": wl.freq_hz, "parallelism": "none (one GPU, independent instances)"},
+        "roofline": roof, "kernels": per_kernel, "timed_kernel_steps": nrec, "synthesis_seconds": synth_s,
+        "paper_context": {"seconds_per_reconstruction": 0.88, "hardware": "1x RTX 4090",
+                          "note": "Table 1; 64x64, 36/36 antennas at 20 wavelengths, iteration count not stated"},
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(si, wl, esca[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def si_start_error(s, eps_t):
+    """Image error of each instance at the start value."""
+    _, _, err = s.image(s.init_alpha(), eps_t)
+    return err.cpu().numpy()
+
+
+def s_ntiles(M):
+    N = M * M
+    return (N + 255) // 256
+
+
+if __name__ == "__main__":
+    main()

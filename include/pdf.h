@@ -154,17 +154,23 @@ typedef struct {
 
 /* A full reconstruction of every instance (Sec. 3, Fig. 3): alpha_0 (or the
  * caller's start), up to n_iter Adam steps replayed from a captured HIP graph
- * of n_check steps, the image error checked every n_check steps against
- * target_err_dev[b] (instances stop updating once they reach it), then the
- * CCO image.  Synchronous.
+ * of n_check steps, then the CCO image.  With eps_true_dev, the image error
+ * ||(1 + chi_cco) - eps|| / ||eps|| is evaluated at the start and every
+ * n_check steps; with target_err_dev an instance stops updating once its
+ * error is <= its target, and the call returns when all have stopped.
+ * Synchronous.
  *   alpha_dev: [B][Ni][K][K] in/out (in: start if start_given != 0).
- *   eps_true_dev, target_err_dev (device double [B]): may be NULL (no early stop).
- *   reached_iter_dev: device int32 [B], first checked step at which the
- *   target was met (-1 if never), may be NULL.
+ *   eps_true_dev: [B][M][M] complex, may be NULL (no error checks).
+ *   target_err_dev: device double [B], may be NULL (no early stop).
+ *   reached_iter_dev: device int32 [B] out, step at which the target was met
+ *     (-1 if never), may be NULL.
+ *   best_err_dev / best_iter_dev: device double / int32 [B] out, lowest
+ *     checked error and its step, may be NULL.
  *   chi_cco_dev: [B][M][M] output, may be NULL. */
 int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t start_given,
                     void* alpha_dev, const void* eps_true_dev, const double* target_err_dev,
-                    int32_t* reached_iter_dev, void* chi_cco_dev, pdf_report* rep);
+                    int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
+                    void* chi_cco_dev, pdf_report* rep);
 
 /* FP64 method-of-moments synthesis of measured fields (Sec. 2.1, Eqs. 3-4):
  * solves (I - G_D X) E = E_inc on the support of chi = eps - 1 of a fine grid
@@ -176,6 +182,17 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
 int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
                    const pdf_array* rx, const double* eps_host, double tol,
                    double* esca_host, void* stream);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * each kernel of pdf_loss_grad / pdf_step (for benchmarks).  enable != 0
+ * clears the record and starts recording up to max_steps iterations; 0 stops.
+ * pdf_timing_read synchronises the stream and writes, for each of the
+ * PDF_NKERNELS kernels of one iteration, the average duration in ms
+ * (avg_ms[k]) over the recorded iterations; *n_steps gets their count.
+ * Kernel order: 0 fwd_conv, 1 pixel_reduce, 2 image_reg, 3 adj_gemm, 4 adj_conv. */
+#define PDF_NKERNELS 5
+int pdf_timing(pdf_handle* h, int32_t enable, int32_t max_steps);
+int pdf_timing_read(pdf_handle* h, double* avg_ms, int32_t* n_steps);
 
 /* Release everything the handle owns (waits for its stream).  NULL is a no-op. */
 void pdf_destroy(pdf_handle* h);

@@ -9,8 +9,7 @@ is what the default path solves (dense LU).  A full-grid dense LU and a
 GMRES solve with FFT matvecs are kept for cross-checks.
 
 Also here: the Mie (Bessel-series) field of a homogeneous circular cylinder
-under the same line source, and the additive noise of the workloads
-(Sec. 4.2 uses AWGN at a stated SNR).
+under the same line source.
 """
 from __future__ import annotations
 
@@ -18,6 +17,8 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse.linalg as spla
 from scipy import special
+
+import seeded_inputs as si
 
 from . import operators as ops
 
@@ -103,11 +104,5 @@ def mie_scattered(eps_r: complex, rho_c: float, centre, tx_xy: np.ndarray,
     return ct[:, None] * np.sum(a[None, None, :] * Ht[:, None, :] * Hr[None, :, :] * phase, axis=-1)
 
 
-def add_noise(esca: np.ndarray, nu: float, n1: np.ndarray, n2: np.ndarray) -> np.ndarray:
-    """e + nu * (||e||_F / sqrt(size)) * (n1 + i n2) / sqrt(2).
-
-    With n1, n2 standard normal, the noise norm is about nu * ||e||_F.  An SNR
-    in dB maps to nu = 10^(-SNR/20).
-    """
-    scale = nu * np.linalg.norm(esca) / np.sqrt(esca.size)
-    return esca + scale * (n1 + 1j * n2) / np.sqrt(2.0)
+# Noise is part of the synthetic-data recipe, shared with the GPU side.
+add_noise = si.add_noise

@@ -21,6 +21,8 @@ PDF_OK, PDF_EINVAL, PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE, PDF_EUNSUPPORTED = 0, 
 FP32, FP64 = 0, 1
 PARAMS_VERSION = 1
 LOSS_STRIDE = 8
+NKERNELS = 5
+KERNEL_NAMES = ("fwd_conv", "pixel_reduce", "image_reg", "adj_gemm", "adj_conv")
 LOSS_NAMES = ("state", "data", "bound", "tv", "bridge", "total", "max_abs_R", "nonfinite")
 
 c_i32, c_f64, c_vp = ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
@@ -60,10 +62,12 @@ SIGNATURES = {
     "pdf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_init_alpha": (c_i32, [c_vp, c_vp]),
     "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
-    "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,
+    "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                 ctypes.POINTER(Report)]),
     "pdf_synthesize": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array),
                                c_vp, c_f64, c_vp, c_vp]),
+    "pdf_timing": (c_i32, [c_vp, c_i32, c_i32]),
+    "pdf_timing_read": (c_i32, [c_vp, c_vp, c_vp]),
     "pdf_destroy": (None, [c_vp]),
     "pdf_last_error": (ctypes.c_char_p, [c_vp]),
 }
@@ -249,19 +253,37 @@ class Solver:
 
     def reconstruct(self, n_iter: int, n_check: int = 10, alpha: Optional[torch.Tensor] = None,
                     eps_true: Optional[torch.Tensor] = None, target: Optional[torch.Tensor] = None):
+        """Start value (unless alpha is given), n_iter Adam steps from a captured
+        graph, CCO image; with eps_true the image error is tracked every n_check
+        steps, and with target an instance stops once its error <= target."""
         start_given = alpha is not None
         a = alpha if start_given else self.zeros_alpha()
         self._want(a, self.alpha_shape, self.cdtype, "alpha", inplace=True)
+        if eps_true is not None:
+            eps_true = self._want(eps_true, (self.B, self.M, self.M), self.cdtype, "eps_true")
         if target is not None:
             target = self._want(target, (self.B,), torch.float64, "target")
-            eps_true = self._want(eps_true, (self.B, self.M, self.M), self.cdtype, "eps_true")
+        track = eps_true is not None
         reached = torch.full((self.B,), -1, dtype=torch.int32, device=self.device)
+        best_err = torch.empty(self.B, dtype=torch.float64, device=self.device) if track else None
+        best_iter = torch.empty(self.B, dtype=torch.int32, device=self.device) if track else None
         cco = torch.empty((self.B, self.M, self.M), dtype=self.cdtype, device=self.device)
         rep = Report()
         self._call(load().pdf_reconstruct, n_iter, n_check, int(start_given), _ptr(a), _ptr(eps_true),
-                   _ptr(target), _ptr(reached), _ptr(cco), ctypes.byref(rep))
-        return dict(alpha=a, chi_cco=cco, reached=reached, iters_run=rep.iters_run,
-                    n_reached=rep.n_reached, seconds=rep.seconds)
+                   _ptr(target), _ptr(reached), _ptr(best_err), _ptr(best_iter), _ptr(cco), ctypes.byref(rep))
+        return dict(alpha=a, chi_cco=cco, reached=reached, best_err=best_err, best_iter=best_iter,
+                    iters_run=rep.iters_run, n_reached=rep.n_reached, seconds=rep.seconds)
+
+    def timing(self, enable: bool, max_steps: int = 1000):
+        """Start (or stop) recording per-kernel HIP events on the library stream."""
+        _check(load().pdf_timing(self.h, int(enable), max_steps), self.h)
+
+    def timing_read(self):
+        """Average ms per kernel of the recorded iterations and their count."""
+        avg = np.zeros(NKERNELS, np.float64)
+        n = ctypes.c_int32()
+        _check(load().pdf_timing_read(self.h, avg.ctypes.data, ctypes.byref(n)), self.h)
+        return dict(zip(KERNEL_NAMES, avg.tolist())), n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -211,6 +211,15 @@ static int launch_adj_gemm(pdf_handle* h, const cx<T>* x, cx<T>* out) {
   return check_launch(h, "k_adj_gemm");
 }
 
+// Records the next timing event on the handle's stream (no-op unless timing).
+static int mark(pdf_handle* h) {
+  // the pool holds whole steps, so a step is either recorded fully or not at all
+  if (!h->timing || h->ev_used >= int(h->events.size())) return PDF_OK;
+  HIP_TRY(hipEventRecord(h->events[h->ev_used], h->stream));
+  h->ev_used++;
+  return PDF_OK;
+}
+
 // One evaluation of loss and gradient; with Adam buffers, also the update.
 template <typename T>
 static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
@@ -226,10 +235,15 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   f.Ni = h->Ni;
   f.K = h->K;
   f.beta = T(h->prm.beta);
+  if ((rc = mark(h))) return rc;
   if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = mark(h))) return rc;
   if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  if ((rc = mark(h))) return rc;
   if ((rc = launch_reg<T>(h, loss, tstep, frozen))) return rc;
+  if ((rc = mark(h))) return rc;
   if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
+  if ((rc = mark(h))) return rc;
   AdjArgs<T> a;
   a.J = (const cx<T>*)h->J;
   a.E = (const cx<T>*)h->E;
@@ -256,7 +270,8 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   a.Ni = h->Ni;
   a.K = h->K;
   a.beta = T(h->prm.beta);
-  return launch_adj<T>(h, a);
+  if ((rc = launch_adj<T>(h, a))) return rc;
+  return mark(h);
 }
 
 template <typename T>
@@ -451,9 +466,44 @@ extern "C" int pdf_tables_host(const pdf_grid* grid, double freq_hz, const pdf_a
   return PDF_OK;
 }
 
+extern "C" int pdf_timing(pdf_handle* h, int32_t enable, int32_t max_steps) {
+  if (!h) return fail(h, PDF_EINVAL, "null handle");
+  h->timing = false;
+  h->ev_used = 0;
+  if (!enable) return PDF_OK;
+  if (max_steps < 1 || max_steps > 100000) return fail(h, PDF_EINVAL, "max_steps out of range");
+  const size_t need = size_t(max_steps) * (PDF_NKERNELS + 1);
+  while (h->events.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    h->events.push_back(e);
+  }
+  h->timing_max = max_steps;
+  h->timing = true;
+  return PDF_OK;
+}
+
+extern "C" int pdf_timing_read(pdf_handle* h, double* avg_ms, int32_t* n_steps) {
+  if (!h || !avg_ms || !n_steps) return fail(h, PDF_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int per_step = PDF_NKERNELS + 1;
+  const int steps = h->ev_used / per_step;
+  for (int k = 0; k < PDF_NKERNELS; ++k) avg_ms[k] = 0.0;
+  for (int s = 0; s < steps; ++s)
+    for (int k = 0; k < PDF_NKERNELS; ++k) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->events[s * per_step + k], h->events[s * per_step + k + 1]));
+      avg_ms[k] += ms;
+    }
+  for (int k = 0; k < PDF_NKERNELS; ++k) avg_ms[k] = steps ? avg_ms[k] / steps : 0.0;
+  *n_steps = steps;
+  return PDF_OK;
+}
+
 extern "C" void pdf_destroy(pdf_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   void* ptrs[] = {h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
@@ -576,26 +626,47 @@ extern "C" int pdf_image(pdf_handle* h, const void* alpha_dev, void* chi_dev, vo
 
 template <typename T>
 static int reconstruct_impl(pdf_handle* h, int n_iter, int n_check, int start_given, void* alpha,
-                            const void* eps_true, const double* target, int* reached, void* cco_out,
-                            pdf_report* rep) {
+                            const void* eps_true, const double* target, int* reached, double* best_err,
+                            int* best_iter, void* cco_out, pdf_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   int rc;
   const size_t KK = size_t(h->K) * h->K;
   const size_t nre = 2 * size_t(h->B) * h->Ni * KK;
   if (!start_given && (rc = run_init<T>(h, alpha))) return rc;
   const int tb = 256;
+  const dim3 gb((h->B + tb - 1) / tb);
   hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->m, nre);
   hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->v, nre);
-  hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->tstep, 0, h->B);
-  hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->frozen, 0, h->B);
-  if (reached) hipLaunchKernelGGL(k_fill_int, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, reached, -1, h->B);
+  hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->tstep, 0, h->B);
+  hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->frozen, 0, h->B);
+  if (reached) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, reached, -1, h->B);
+  if (best_iter) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, best_iter, -1, h->B);
+  if (best_err) hipLaunchKernelGGL(k_fill_double, gb, dim3(tb), 0, h->stream, best_err, HUGE_VAL, h->B);
   if ((rc = check_launch(h, "fill"))) return rc;
-  const bool checking = eps_true && target;
+  const bool checking = eps_true != nullptr;
+  std::vector<int> fz(h->B);
+  // image error at the current iterate; returns the number of stopped instances
+  auto check = [&](int* nfrozen) -> int {
+    int r = run_image<T>(h, alpha, nullptr, nullptr, eps_true, h->err);
+    if (r) return r;
+    hipLaunchKernelGGL(k_track_error, gb, dim3(tb), 0, h->stream, h->err, target, h->frozen, reached, best_err,
+                       best_iter, h->tstep, h->B);
+    if ((r = check_launch(h, "k_track_error"))) return r;
+    *nfrozen = 0;
+    if (target) {
+      HIP_TRY(hipMemcpyAsync(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      for (int x : fz) *nfrozen += x;
+    }
+    return PDF_OK;
+  };
+  int nf = 0;
+  if (checking && (rc = check(&nf))) return rc;
   if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int done = 0;
-  if (n_iter > 0) {
+  if (n_iter > 0 && nf < h->B) {
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     int crc = PDF_OK;
     for (int s = 0; s < n_check && crc == PDF_OK; ++s)
@@ -606,42 +677,36 @@ static int reconstruct_impl(pdf_handle* h, int n_iter, int n_check, int start_gi
       return crc;
     }
     if (ce != hipSuccess) return fail(h, PDF_EHIP, std::string("capture: ") + hipGetErrorString(ce));
-    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(h, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
   }
-  std::vector<int> fz(h->B);
-  while (done < n_iter) {
+  while (done < n_iter && nf < h->B) {
     const int chunk = (n_iter - done < n_check) ? n_iter - done : n_check;
     if (chunk == n_check) {
-      HIP_TRY(hipGraphLaunch(exec, h->stream));
+      hipError_t le = hipGraphLaunch(exec, h->stream);
+      if (le != hipSuccess) {
+        rc = fail(h, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+        break;
+      }
     } else {
-      for (int s = 0; s < chunk; ++s)
-        if ((rc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen))) return rc;
+      for (int s = 0; s < chunk && !rc; ++s)
+        rc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen);
+      if (rc) break;
     }
     done += chunk;
-    if (checking) {
-      if ((rc = run_image<T>(h, alpha, nullptr, nullptr, eps_true, h->err))) return rc;
-      hipLaunchKernelGGL(k_check_target, dim3((h->B + tb - 1) / tb), dim3(tb), 0, h->stream, h->err, target,
-                         h->frozen, reached, h->tstep, h->B);
-      if ((rc = check_launch(h, "k_check_target"))) return rc;
-      HIP_TRY(hipMemcpyAsync(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost, h->stream));
-      HIP_TRY(hipStreamSynchronize(h->stream));
-      int nf = 0;
-      for (int x : fz) nf += x;
-      if (nf == h->B) break;
-    }
+    if (checking && (rc = check(&nf))) break;
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
+  if (rc) return rc;
   if (cco_out && (rc = run_image<T>(h, alpha, nullptr, cco_out, nullptr, nullptr))) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (rep) {
     rep->iters_run = done;
-    int nf = 0;
-    if (checking) {
-      HIP_TRY(hipMemcpy(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost));
-      for (int x : fz) nf += x;
-    }
-    rep->n_reached = nf;
+    rep->n_reached = target ? nf : 0;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return PDF_OK;
@@ -649,15 +714,18 @@ static int reconstruct_impl(pdf_handle* h, int n_iter, int n_check, int start_gi
 
 extern "C" int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t start_given,
                                void* alpha_dev, const void* eps_true_dev, const double* target_err_dev,
-                               int32_t* reached_iter_dev, void* chi_cco_dev, pdf_report* rep) {
+                               int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
+                               void* chi_cco_dev, pdf_report* rep) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
   if (n_iter < 0) return fail(h, PDF_EINVAL, "n_iter < 0");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  if ((target_err_dev || best_err_dev) && !eps_true_dev)
+    return fail(h, PDF_EINVAL, "error tracking needs eps_true_dev");
   return h->prec == PDF_FP32
              ? reconstruct_impl<float>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
-                                       reached_iter_dev, chi_cco_dev, rep)
+                                       reached_iter_dev, best_err_dev, best_iter_dev, chi_cco_dev, rep)
              : reconstruct_impl<double>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
-                                        reached_iter_dev, chi_cco_dev, rep);
+                                        reached_iter_dev, best_err_dev, best_iter_dev, chi_cco_dev, rep);
 }
 
 extern "C" const char* pdf_last_error(const pdf_handle* h) {

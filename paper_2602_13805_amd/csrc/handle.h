@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/pdf.h"
 
@@ -43,6 +44,11 @@ struct pdf_handle {
   void* m = nullptr;         // [B][Ni][K][K][2] real
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]
+  // optional per-kernel event timing
+  bool timing = false;
+  int timing_max = 0;
+  std::vector<hipEvent_t> events;   // pool
+  int ev_used = 0;
   std::string err_msg;
 };
 

@@ -100,15 +100,25 @@ __global__ __launch_bounds__(256) void k_line_search(const double* lsp, const cx
   }
 }
 
-// Stop updating an instance once its image error reaches its target.
-__global__ void k_check_target(const double* err, const double* target, int* frozen, int* reached,
-                               const int* tstep, int B) {
+// Error bookkeeping of the reconstruction loop: lowest error so far, and
+// stop updating an instance once its image error reaches its target.
+__global__ void k_track_error(const double* err, const double* target, int* frozen, int* reached,
+                              double* best_err, int* best_iter, const int* tstep, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  if (!frozen[b] && err[b] <= target[b]) {
+  if (best_err && err[b] < best_err[b]) {
+    best_err[b] = err[b];
+    if (best_iter) best_iter[b] = tstep[b];
+  }
+  if (target && !frozen[b] && err[b] <= target[b]) {
     frozen[b] = 1;
     if (reached) reached[b] = tstep[b];
   }
+}
+
+__global__ void k_fill_double(double* x, double v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
 }
 
 __global__ void k_fill_int(int* x, int v, int n) {

@@ -171,27 +171,33 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
     pdf_set_global_error("support larger than 20000 pixels");
     return PDF_EUNSUPPORTED;
   }
-  pdfh::Geometry g{M, grid->side, grid->cx, grid->cy, freq_hz, ni, ns, tx->xy, rx->xy};
-  pdfh::Tables t;
-  t.want_ghat = false;
-  std::string err;
-  if (pdfh::build_tables(g, &t, &err)) {
-    pdf_set_global_error(err);
-    return PDF_EINVAL;
-  }
+  const double k0 = 2.0 * M_PI * freq_hz / 299792458.0;
+  const double h = grid->side / M;
+  const double a = h / std::sqrt(M_PI);
+  const cd cell = cd(0.0, M_PI * k0 * a / 2.0) * std::cyl_bessel_j(1.0, k0 * a);
   std::vector<cd> ker;
-  pdfh::offset_kernel(M, grid->side / M, t.k0, &ker);
+  pdfh::offset_kernel(M, h, k0, &ker);
   std::vector<int> si(nS), sj(nS);
   std::vector<cd> chi(nS), einc(size_t(ni) * nS), gsS(size_t(ns) * nS);
+  std::vector<double> xs(nS), ys(nS);
   for (int c = 0; c < nS; ++c) {
     si[c] = S[c] / M;
     sj[c] = S[c] % M;
     chi[c] = eps[S[c]] - 1.0;
+    xs[c] = grid->cx - grid->side / 2.0 + (sj[c] + 0.5) * h;
+    ys[c] = grid->cy - grid->side / 2.0 + (si[c] + 0.5) * h;
   }
-  for (int p = 0; p < ni; ++p)
-    for (int c = 0; c < nS; ++c) einc[size_t(p) * nS + c] = t.einc[size_t(p) * N + S[c]];
-  for (int q = 0; q < ns; ++q)
-    for (int c = 0; c < nS; ++c) gsS[size_t(q) * nS + c] = t.gs[size_t(q) * N + S[c]];
+  // incident fields and receiver operator on the support only
+  pdfh::parallel_for(ni + ns, [&](int b0, int b1) {
+    for (int r = b0; r < b1; ++r) {
+      const bool is_tx = r < ni;
+      const double* xy = is_tx ? tx->xy + 2 * r : rx->xy + 2 * (r - ni);
+      cd scale = cell;
+      if (is_tx) scale = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(xy[0] - grid->cx, xy[1] - grid->cy)));
+      cd* dst = is_tx ? &einc[size_t(r) * nS] : &gsS[size_t(r - ni) * nS];
+      for (int c = 0; c < nS; ++c) dst[c] = scale * pdfh::hankel1(0, k0 * std::hypot(xy[0] - xs[c], xy[1] - ys[c]));
+    }
+  });
 
   Dev d;
   cx<double> *dA, *dker, *dchi, *db, *dgs, *x, *r, *rh, *p, *v, *s, *tt, *dots, *sc1, *sc2, *dout;

@@ -11,6 +11,9 @@
 #include <cmath>
 #include <complex>
 #include <string>
+#include <algorithm>
+#include <functional>
+#include <thread>
 #include <vector>
 
 #include "tables.h"
@@ -19,8 +22,23 @@ namespace pdfh {
 
 using cd = std::complex<double>;
 
-static cd hankel1(int n, double x) {
-  return cd(std::cyl_bessel_j(double(n), x), std::cyl_neumann(double(n), x));
+cd hankel1(int n, double x) { return cd(std::cyl_bessel_j(double(n), x), std::cyl_neumann(double(n), x)); }
+
+void parallel_for(int n, const std::function<void(int, int)>& fn) {
+  int nt = int(std::thread::hardware_concurrency());
+  nt = std::max(1, std::min(nt, 16));
+  nt = std::min(nt, std::max(1, n / 64));
+  if (nt <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int a = t * chunk, b = std::min(n, a + chunk);
+    if (a < b) th.emplace_back(fn, a, b);
+  }
+  for (auto& x : th) x.join();
 }
 
 // In-place radix-2 FFT (forward, exp(-2 pi i jk / n)) of length n = 2^m, stride s.
@@ -96,24 +114,29 @@ int build_tables(const Geometry& g, Tables* t, std::string* err) {
   }
   if (t->want_gs) {
     t->gs.assign(size_t(g.ns) * N, cd());
-    for (int q = 0; q < g.ns; ++q)
-      for (int i = 0; i < M; ++i)
+    parallel_for(g.ns * M, [&](int a, int b) {
+      for (int r = a; r < b; ++r) {
+        const int q = r / M, i = r % M;
         for (int j = 0; j < M; ++j) {
           const double d = std::hypot(g.rx[2 * q] - px(j), g.rx[2 * q + 1] - py(i));
           t->gs[size_t(q) * N + i * M + j] = cell * hankel1(0, k0 * d);
         }
+      }
+    });
   }
   if (t->want_einc) {
     t->einc.assign(size_t(g.ni) * N, cd());
-    for (int p = 0; p < g.ni; ++p) {
-      const double rc = std::hypot(g.tx[2 * p] - g.cx, g.tx[2 * p + 1] - g.cy);
-      const double c = 1.0 / std::abs(hankel1(0, k0 * rc));
-      for (int i = 0; i < M; ++i)
+    parallel_for(g.ni * M, [&](int a, int b) {
+      for (int r = a; r < b; ++r) {
+        const int p = r / M, i = r % M;
+        const double rc = std::hypot(g.tx[2 * p] - g.cx, g.tx[2 * p + 1] - g.cy);
+        const double c = 1.0 / std::abs(hankel1(0, k0 * rc));
         for (int j = 0; j < M; ++j) {
           const double d = std::hypot(g.tx[2 * p] - px(j), g.tx[2 * p + 1] - py(i));
           t->einc[size_t(p) * N + i * M + j] = c * hankel1(0, k0 * d);
         }
-    }
+      }
+    });
   }
   t->k0 = k0;
   t->cell = cell;
@@ -128,12 +151,16 @@ void offset_kernel(int M, double h, double k0, std::vector<cd>* ker) {
   const cd self = cd(0.0, M_PI * k0 * a / 2.0) * hankel1(1, k0 * a) - 1.0;
   const int W = 2 * M - 1;
   ker->assign(size_t(W) * W, cd());
-  for (int di = -(M - 1); di <= M - 1; ++di)
-    for (int dj = -(M - 1); dj <= M - 1; ++dj) {
-      cd v = self;
-      if (di != 0 || dj != 0) v = cell * hankel1(0, k0 * h * std::sqrt(double(di) * di + double(dj) * dj));
-      (*ker)[size_t(di + M - 1) * W + (dj + M - 1)] = v;
-    }
+  // the kernel depends on |offset| only: evaluate one quadrant and mirror it
+  parallel_for(M, [&](int a, int b) {
+    for (int di = a; di < b; ++di)
+      for (int dj = 0; dj < M; ++dj) {
+        cd v = self;
+        if (di != 0 || dj != 0) v = cell * hankel1(0, k0 * h * std::sqrt(double(di) * di + double(dj) * dj));
+        for (int si : {-1, 1})
+          for (int sj : {-1, 1}) (*ker)[size_t(si * di + M - 1) * W + (sj * dj + M - 1)] = v;
+      }
+  });
 }
 
 }  // namespace pdfh

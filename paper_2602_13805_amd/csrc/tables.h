@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,9 @@ struct Tables {
 };
 
 int build_tables(const Geometry& g, Tables* t, std::string* err);
+std::complex<double> hankel1(int n, double x);
+// Runs fn(begin, end) over [0, n) split across host threads.
+void parallel_for(int n, const std::function<void(int, int)>& fn);
 void offset_kernel(int M, double h, double k0, std::vector<std::complex<double>>* ker);
 
 }  // namespace pdfh

@@ -233,3 +233,12 @@ def draw_noise(seed: int, shape) -> tuple:
 def truth_eps(workload: Workload, seed: int, M: Optional[int] = None) -> np.ndarray:
     """True relative permittivity of a seed's profile on an M x M grid."""
     return rasterize(draw_profile(workload, seed), M or workload.M, workload.side)
+
+
+def add_noise(esca: np.ndarray, nu: float, n1: np.ndarray, n2: np.ndarray) -> np.ndarray:
+    """Complex AWGN of relative level nu (Sec. 4.2 adds AWGN at a stated SNR):
+    e + nu * (||e||_F / sqrt(size)) * (n1 + i n2) / sqrt(2), with n1, n2 the
+    standard-normal draws of draw_noise, so that ||noise|| is about nu ||e||.
+    An SNR in dB maps to nu = 10^(-SNR/20)."""
+    scale = nu * np.linalg.norm(esca) / np.sqrt(esca.size)
+    return esca + scale * (n1 + 1j * n2) / np.sqrt(2.0)
