@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--no-recon", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the steps, as a "
+                         "reference of known traffic for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: instances are independent, so N GPUs would each run their own "
@@ -141,6 +144,12 @@ def main():
     synth_s = time.time() - t0
     log(f"synthesised {B} instances in {synth_s:.1f} s")
 
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tx = si.antenna_positions(wl.n_tx, wl.radius)
     rx = si.antenna_positions(wl.n_rx, wl.radius)
     s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=B, device=dev)

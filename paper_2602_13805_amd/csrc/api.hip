@@ -138,12 +138,20 @@ static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
 }
 
+template <int NRT, int NCT>
+static void launch_reduce_mfma(pdf_handle* h, const ReduceArgs<float>& a) {
+  const size_t lds = sizeof(float) * 2 * 256 * (32 * NCT + 1) + 16 * sizeof(double);
+  set_lds(k_pixel_reduce_mfma<NRT, NCT>, lds);
+  hipLaunchKernelGGL((k_pixel_reduce_mfma<NRT, NCT>), dim3(h->ntiles, h->B), dim3(256), lds, h->stream, a);
+}
+
 template <typename T>
 static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx<T>* Rfix) {
   ReduceArgs<T> a;
   a.J = J;
   a.E = E;
   a.gs = (const cx<T>*)h->gs;
+  a.gsT = (const cx<T>*)h->gsT;
   a.Rfix = Rfix;
   a.R = (cx<T>*)h->R;
   a.den = (T*)h->den;
@@ -155,10 +163,26 @@ static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx
   a.N = h->N;
   a.ntiles = h->ntiles;
   a.beta = T(h->prm.beta);
-  const size_t lds = sizeof(cx<T>) * size_t(h->Ni) * h->tile + 16 * sizeof(double);
-  set_lds(k_pixel_reduce<T>, lds);
-  hipLaunchKernelGGL(k_pixel_reduce<T>, dim3(h->ntiles, h->B), dim3(h->tile), lds, h->stream, a);
-  return check_launch(h, "k_pixel_reduce");
+  if constexpr (sizeof(T) == 4) {
+    const int nrt = (h->Ns + 15) / 16, nct = (h->Ni + 31) / 32;
+    switch (nct * 8 + nrt) {
+      case 9: launch_reduce_mfma<1, 1>(h, a); break;
+      case 10: launch_reduce_mfma<2, 1>(h, a); break;
+      case 11: launch_reduce_mfma<3, 1>(h, a); break;
+      case 12: launch_reduce_mfma<4, 1>(h, a); break;
+      case 17: launch_reduce_mfma<1, 2>(h, a); break;
+      case 18: launch_reduce_mfma<2, 2>(h, a); break;
+      case 19: launch_reduce_mfma<3, 2>(h, a); break;
+      case 20: launch_reduce_mfma<4, 2>(h, a); break;
+      default: return fail(h, PDF_EUNSUPPORTED, "incidence / receiver count out of range");
+    }
+    return check_launch(h, "k_pixel_reduce_mfma");
+  } else {
+    const size_t lds = sizeof(cx<T>) * size_t(h->Ni) * h->tile + 16 * sizeof(double);
+    set_lds(k_pixel_reduce<T>, lds);
+    hipLaunchKernelGGL(k_pixel_reduce<T>, dim3(h->ntiles, h->B), dim3(h->tile), lds, h->stream, a);
+    return check_launch(h, "k_pixel_reduce");
+  }
 }
 
 template <typename T>
@@ -401,6 +425,12 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   for (int k = 0; k < h->P; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * k / h->P);
   if ((rc = upload<T>(h, &h->tw, tw, 1.0))) return rc;
   if ((rc = upload<T>(h, &h->gs, t.gs, 1.0))) return rc;
+  {
+    std::vector<std::complex<double>> gst(t.gs.size());
+    for (int q = 0; q < h->Ns; ++q)
+      for (int n = 0; n < h->N; ++n) gst[size_t(n) * h->Ns + q] = t.gs[size_t(q) * h->N + n];
+    if ((rc = upload<T>(h, &h->gsT, gst, 1.0))) return rc;
+  }
   if ((rc = upload<T>(h, &h->einc, t.einc, 1.0))) return rc;
   // ||E_inc||^2 of the values actually used (after rounding to T)
   double ss = 0.0;
@@ -504,7 +534,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
-  void* ptrs[] = {h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
+  void* ptrs[] = {h->gsT, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
                   h->v,    h->loss};
@@ -547,7 +577,11 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   h->stream = (hipStream_t)stream;
   const size_t csz = prm.precision == PDF_FP32 ? 8 : 16;
   int tile = 256;
-  while (tile > 64 && size_t(h->Ni) * tile * csz > 64 * 1024) tile >>= 1;
+  if (prm.precision == PDF_FP32 && h->Ni > 64) {
+    delete h;
+    return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 incidences");
+  }
+  while (prm.precision == PDF_FP64 && tile > 64 && size_t(h->Ni) * tile * csz > 64 * 1024) tile >>= 1;
   if (size_t(h->Ni) * tile * csz > 64 * 1024) {
     delete h;
     return fail(nullptr, PDF_EUNSUPPORTED, "too many incidences for the pixel-reduction tile");

@@ -14,35 +14,80 @@ struct ConvCfg {
   static constexpr int M = M_;
   static constexpr int P = 2 * M;
   static constexpr int N = M * M;
-  static constexpr int LD = P + 1;  // padded row stride of the LDS tile (complex units)
+  using TileL = Tile<P>;             // P x P tile in LDS, row stride P + 1
   static constexpr int NT = M >= 64 ? 1024 : (M >= 32 ? 256 : 64);
-  static constexpr int EPT_M = 8;                 // length-M transforms (basis)
-  static constexpr int EPT_R = 8;                 // length-P transforms along rows
-  static constexpr int EPT_C = P >= 16 ? 16 : P;  // length-P transforms along columns
+  static constexpr int EPT_M = 8;                 // length-M transforms (basis), workgroup-wide
+  static constexpr int EPT_R = 8;                 // length-P transforms along rows, workgroup-wide
+  static constexpr int EPT_C = 16;                // length-P transforms along columns, wave-local
   static constexpr int PPT = N / NT;              // pixels owned per thread
-  static constexpr int U_SYN = CeilDiv<M*(M / EPT_M), NT>::value;
-  static constexpr int U_ROW = CeilDiv<M*(P / EPT_R), NT>::value;
-  static constexpr int U_COL = CeilDiv<P*(P / EPT_C), NT>::value;
   static_assert(N % NT == 0, "pixel ownership must be exact");
-  static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(P) * LD + P);
+  static_assert(P >= 16, "the column pass needs P >= 16");
+  static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(P) * TileL::LD + P);
+  using Rows = Vecs<P, M, true>;                 // the M nonzero rows, elements along a row
+  using Cols = Vecs<P, P, false, false, true>;   // all P columns, wave-local
+  using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
+  using ColsM = Vecs<P, M, false>;
+  using ModeRows = Vecs<P, M, true, true>;       // the K rows / columns of the kept modes
+  using ModeCols = Vecs<P, M, false, true>;
 };
 
-template <typename T>
-struct GhatLoad {
-  const cx<T>* g;
-  int P;
-  bool cj;
-  __device__ __forceinline__ cx<T> operator()(int vec, int k, cx<T> x) const {
-    cx<T> w = g[k * P + vec];
-    if (cj) w.y = -w.y;
-    return x * w;
+// Column phase of the convolution, in place on all P columns: forward FFT
+// (rows >= M are zero), multiplication by the spectrum, inverse FFT, rows
+// < M kept.  Each wavefront owns whole columns, so the phase needs no
+// workgroup barrier until its end.  The forward transform's last pass and the
+// inverse transform's first pass share their registers (both radix R2 on the
+// elements j + R1 r of butterfly j), so the spectrum is multiplied in
+// registers and one LDS round trip is saved.
+template <typename T, int M>
+__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+  using C = ConvCfg<T, M>;
+  constexpr int P = C::P;
+  using F = Fft<T, P, C::EPT_C, C::NT, typename C::Cols, 1>;
+  constexpr int R1 = F::radix(1), R2 = P / R1;  // forward radices R1 then R2, inverse R2 then R1
+  static_assert(R2 <= 16 && R2 <= C::EPT_C, "column transform must take two passes");
+  const F f{buf, tw, typename C::Cols{}};
+  // spectrum multiply on the registers of a pass whose butterfly j holds elements j + NSOUT r
+  auto mul_ghat = [&](typename F::Regs& g, auto rc, int NSOUT) {
+    constexpr int R = decltype(rc)::value;
+#pragma unroll
+    for (int q = 0; q < F::UPT; ++q) {
+      if (!g.act[q]) continue;
+#pragma unroll
+      for (int u = 0; u < C::EPT_C / R; ++u) {
+        const int j = g.t[q] + u * F::TPV;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cx<T> w = ghat[(j + r * NSOUT) * P + g.vec[q]];
+          if (adjoint) w.y = -w.y;
+          g.v[q][u * R + r] = g.v[q][u * R + r] * w;
+        }
+      }
+    }
+  };
+  if constexpr (R2 == 1) {
+    typename F::Regs g;
+    f.assign(g);
+    f.template load<R1, 1, -1, R1 / 2>(g, NoLoad());
+    F::sync();
+    f.template compute<R1, -1, R1 / 2, R1>(g);
+    mul_ghat(g, std::integral_constant<int, R1>{}, 1);
+    f.template compute<R1, +1, R1, R1 / 2>(g);
+    f.template store<R1, 1, R1 / 2>(g);
+  } else {
+    f.template pass<R1, 1, -1, R1 / 2, R1>(NoLoad());
+    typename F::Regs g;
+    f.assign(g);
+    f.template load<R2, R1, -1, R2>(g, NoLoad());
+    F::sync();
+    f.template compute<R2, -1, R2, R2>(g);
+    mul_ghat(g, std::integral_constant<int, R2>{}, R1);
+    f.template compute<R2, +1, R2, R2>(g);
+    f.template store<R2, 1, R2>(g);
+    F::sync();
+    f.template pass<R1, R2, +1, R1, M / R2>(NoLoad());
   }
-};
-
-struct KeepBelow {
-  int lim;
-  __device__ __forceinline__ bool operator()(int, int k) const { return k < lim; }
-};
+  __syncthreads();  // the row pass that follows reads every column
+}
 
 // In place on the top-left M x M of the LDS tile: x -> G_D x (or G_D^H x),
 // where the spectrum ghat is pre-scaled by 1/P^2.  Entries outside the
@@ -50,11 +95,13 @@ struct KeepBelow {
 template <typename T, int M>
 __device__ __forceinline__ void conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
   using C = ConvCfg<T, M>;
-  LdsFft<T, C::P, C::EPT_R, -1, C::U_ROW>{buf, M, C::LD, 1, tw, 1}.run(M);
-  LdsFft<T, C::P, C::EPT_C, -1, C::U_COL>{buf, C::P, 1, C::LD, tw, 1}.run(M);
-  LdsFft<T, C::P, C::EPT_C, +1, C::U_COL>{buf, C::P, 1, C::LD, tw, 1}.run(
-      C::P, GhatLoad<T>{ghat, C::P, adjoint}, KeepBelow{M});
-  LdsFft<T, C::P, C::EPT_R, +1, C::U_ROW>{buf, M, C::LD, 1, tw, 1}.run(C::P, NoLoad(), KeepBelow{M});
+  constexpr int P = C::P;
+  // every row pass begins and ends with a workgroup barrier; the column phase
+  // is wave-local and ends with one
+  const Fft<T, P, C::EPT_R, C::NT, typename C::Rows, 1> rows{buf, tw, typename C::Rows{}};
+  rows.template run<-1, M, P>();
+  col_conv<T, M>(buf, tw, ghat, adjoint);
+  rows.template run<+1, P, M>();
 }
 
 __device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
@@ -78,7 +125,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
   using C = ConvCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::P * C::LD;
+  cx<T>* tw = buf + C::P * C::TileL::LD;
   const int bp = blockIdx.x;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
@@ -86,21 +133,24 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
   const size_t off = size_t(bp) * C::N;
   cx<T> jr[C::PPT];
   if constexpr (FROM_ALPHA) {
-    for (int e = tid; e < C::N; e += C::NT) buf[(e / M) * C::LD + (e % M)] = cx<T>{T(0), T(0)};
+    for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
     __syncthreads();
     const int K = a.K, kmin = -(K / 2);
     const cx<T>* al = a.in + size_t(bp) * K * K;
     for (int e = tid; e < K * K; e += C::NT) {
       const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
-      buf[iy * C::LD + ix] = al[e];
+      buf[C::TileL::at(iy, ix)] = al[e];
     }
     __syncthreads();
-    LdsFft<T, M, C::EPT_M, +1, C::U_SYN>{buf, M, C::LD, 1, tw, C::P / M}.run();
-    LdsFft<T, M, C::EPT_M, +1, C::U_SYN>{buf, M, 1, C::LD, tw, C::P / M}.run();
+    typename C::ModeRows mr;
+    mr.nv = K;
+    mr.kmin = kmin;
+    Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
+    Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = buf[(n / M) * C::LD + (n % M)];
+      jr[q] = buf[C::TileL::at(n / M, n % M)];
       if (a.J) a.J[off + n] = jr[q];
     }
   } else {
@@ -108,7 +158,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
       jr[q] = a.in[off + n];
-      buf[(n / M) * C::LD + (n % M)] = jr[q];
+      buf[C::TileL::at(n / M, n % M)] = jr[q];
     }
     __syncthreads();
   }
@@ -116,7 +166,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    cx<T> e = buf[(n / M) * C::LD + (n % M)] + a.beta * jr[q];
+    cx<T> e = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q];
     if (a.einc) e = e + a.einc[size_t(p) * C::N + n];
     a.E[off + n] = e;
   }
@@ -159,7 +209,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
   using C = ConvCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::P * C::LD;
+  cx<T>* tw = buf + C::P * C::TileL::LD;
   const int bp = blockIdx.x;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
@@ -189,7 +239,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
       gJ = gJ + (beta * inv) * (g * E);
     }
     gJ = gJ + beta * gE;
-    buf[(n / M) * C::LD + (n % M)] = gE;
+    buf[C::TileL::at(n / M, n % M)] = gE;
     gj[q] = gJ;
   }
   __syncthreads();
@@ -197,13 +247,16 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    cx<T>& x = buf[(n / M) * C::LD + (n % M)];
+    cx<T>& x = buf[C::TileL::at(n / M, n % M)];
     x = x + gj[q];
   }
   __syncthreads();
-  LdsFft<T, M, C::EPT_M, -1, C::U_SYN>{buf, M, C::LD, 1, tw, C::P / M}.run();
-  LdsFft<T, M, C::EPT_M, -1, C::U_SYN>{buf, M, 1, C::LD, tw, C::P / M}.run();
   const int K = a.K, kmin = -(K / 2);
+  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>();
+  typename C::ModeCols mc;
+  mc.nv = K;
+  mc.kmin = kmin;
+  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>();
   const bool upd = a.alpha && !(a.frozen && a.frozen[b]);
   double bc1 = 1.0, bc2 = 1.0;
   if (upd) {
@@ -213,7 +266,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
   }
   for (int e = tid; e < K * K; e += C::NT) {
     const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
-    const cx<T> g = buf[iy * C::LD + ix];
+    const cx<T> g = buf[C::TileL::at(iy, ix)];
     const size_t idx = size_t(bp) * K * K + e;
     if (a.galpha) a.galpha[idx] = g;
     if (upd) {

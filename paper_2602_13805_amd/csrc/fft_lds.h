@@ -4,13 +4,17 @@
 // vector in registers, does EPT/R radix-R butterflies per pass with the
 // in-register FFTs below, and exchanges through LDS between passes (load all,
 // barrier, store all, barrier), so the transform is in place and needs no
-// bit reversal.  Vectors are rows or columns of a 2-D tile: element k of
-// vector v sits at buf[v * vstride + k * estride].  Threads are assigned
-// vector-fastest, so neighbouring lanes touch neighbouring rows / columns.
+// bit reversal.  Vectors are rows or columns of a 2-D tile.  Threads are
+// assigned vector-fastest, so neighbouring lanes touch neighbouring rows or
+// columns.  Zero-padded inputs and cropped outputs are known at compile time
+// and their butterflies are skipped.
 //
 // Forward transforms use exp(-2 pi i jk/L) (DIR = -1), inverse ones
 // exp(+2 pi i jk/L) (DIR = +1); neither is normalised.
 #pragma once
+
+#include <type_traits>
+#include <utility>
 
 #include "cplx.h"
 
@@ -48,34 +52,115 @@ __host__ __device__ constexpr int bitrev(int i) {
   return r;
 }
 
-// In-register FFT of R points (R = 1, 2, 4, 8, 16), natural order in and out.
-template <typename T, int R, int DIR>
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [0, N).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// v * exp(DIR 2 pi i E / 16) with the trivial and 45-degree rotations spelled
+// out (IEEE rules forbid the compiler from folding multiplications by 0 or 1).
+template <typename T, int E, int DIR>
+__device__ __forceinline__ cx<T> rot16(cx<T> v) {
+  constexpr int e = ((E % 16) + 16) % 16;
+  constexpr T h = T(0.70710678118654752440);
+  if constexpr (e == 0) {
+    return v;
+  } else if constexpr (e == 8) {
+    return {-v.x, -v.y};
+  } else if constexpr (e == 4) {          // exp(DIR i pi/2) = DIR i
+    return DIR > 0 ? cx<T>{-v.y, v.x} : cx<T>{v.y, -v.x};
+  } else if constexpr (e == 12) {         // -DIR i
+    return DIR > 0 ? cx<T>{v.y, -v.x} : cx<T>{-v.y, v.x};
+  } else if constexpr (e % 4 == 2) {      // odd multiples of 45 degrees
+    constexpr T c = T(cos16(e)), sn = T(DIR * cos16(e - 4));
+    // c, sn = +-h: (c x - sn y, sn x + c y) with one add and one multiply per part
+    constexpr T sa = c > 0 ? h : -h;
+    constexpr T sb = sn > 0 ? h : -h;
+    if constexpr (c > 0 && sn > 0) return {h * (v.x - v.y), h * (v.x + v.y)};
+    else if constexpr (c > 0 && sn < 0) return {h * (v.x + v.y), h * (v.y - v.x)};
+    else if constexpr (c < 0 && sn > 0) return {-h * (v.x + v.y), h * (v.x - v.y)};
+    else return {h * (v.y - v.x), -h * (v.x + v.y)};
+    (void)sa;
+    (void)sb;
+  } else {
+    constexpr T c = T(cos16(e)), sn = T(DIR * cos16(e - 4));
+    return {c * v.x - sn * v.y, sn * v.x + c * v.y};
+  }
+}
+
+template <int R>
+__host__ __device__ constexpr int ilog2(int n) {
+  return n <= 1 ? 0 : 1 + ilog2<R>(n / 2);
+}
+
+// Zero pattern of the register file before radix-2 stage `st` of fft_reg,
+// when inputs r >= ZR are known zeros: bit i set = register i holds zero.
+template <int R>
+__host__ __device__ constexpr unsigned zero_mask(int ZR, int st) {
+  unsigned m = 0;
+  for (int i = 0; i < R; ++i)
+    if (bitrev<R>(i) >= ZR) m |= 1u << i;
+  for (int t = 0; t < st; ++t) {
+    const int s = 1 << t;
+    unsigned o = m;
+    for (int k = 0; k < R; k += 2 * s)
+      for (int j = 0; j < s; ++j) {
+        const bool z = ((m >> (k + j)) & 1u) && ((m >> (k + j + s)) & 1u);
+        o = z ? (o | (1u << (k + j)) | (1u << (k + j + s))) : (o & ~((1u << (k + j)) | (1u << (k + j + s))));
+      }
+    m = o;
+  }
+  return m;
+}
+
+// In-register FFT of R points (R = 1, 2, 4, 8, 16), natural order in and out:
+// bit reversal, then radix-2 decimation-in-time stages, all indices and
+// twiddles resolved at compile time.  Inputs r >= ZR are known to be zero
+// (their butterflies are skipped) and only outputs r < KR are needed.
+template <typename T, int R, int DIR, int ZR = R, int KR = R>
 __device__ __forceinline__ void fft_reg(cx<T>* v) {
   if constexpr (R > 1) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int j = bitrev<R>(i);
-      if (j > i) {
+    static_for<R>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      constexpr int j = bitrev<R>(i);
+      if constexpr (j > i) {
         cx<T> t = v[i];
         v[i] = v[j];
         v[j] = t;
       }
-    }
-#pragma unroll
-    for (int s = 1; s < R; s <<= 1) {
-#pragma unroll
-      for (int k = 0; k < R; k += 2 * s) {
-#pragma unroll
-        for (int j = 0; j < s; ++j) {
-          const int e = j * (16 / (2 * s));  // twiddle exp(DIR 2 pi i j / 2s) in 16ths
-          const cx<T> w = {T(cos16(e)), T(DIR * cos16(e - 4))};
-          cx<T> a = v[k + j];
-          cx<T> b = (j == 0) ? v[k + j + s] : v[k + j + s] * w;
-          v[k + j] = a + b;
-          v[k + j + s] = a - b;
+    });
+    constexpr int L2 = ilog2<R>(R);
+    static_for<L2>([&](auto stc) {
+      constexpr int st = decltype(stc)::value;
+      constexpr int s = 1 << st;
+      constexpr unsigned zm = zero_mask<R>(ZR, st);
+      constexpr bool last = st == L2 - 1;
+      static_for<R / 2>([&](auto bc) {
+        constexpr int bidx = decltype(bc)::value;
+        constexpr int k = (bidx / s) * 2 * s, j = bidx % s;
+        constexpr bool za = (zm >> (k + j)) & 1u, zb = (zm >> (k + j + s)) & 1u;
+        constexpr bool lo = !last || (k + j) < KR, hi = !last || (k + j + s) < KR;
+        if constexpr (za && zb) {
+          // both inputs are zero registers: so are both outputs
+        } else if constexpr (zb) {
+          if constexpr (hi) v[k + j + s] = v[k + j];
+        } else if constexpr (za) {
+          const cx<T> b = rot16<T, j * (16 / (2 * s)), DIR>(v[k + j + s]);
+          if constexpr (lo) v[k + j] = b;
+          if constexpr (hi) v[k + j + s] = cx<T>{-b.x, -b.y};
+        } else {
+          const cx<T> a = v[k + j];
+          const cx<T> b = rot16<T, j * (16 / (2 * s)), DIR>(v[k + j + s]);
+          if constexpr (lo) v[k + j] = a + b;
+          if constexpr (hi) v[k + j + s] = a - b;
         }
-      }
-    }
+      });
+    });
   }
 }
 
@@ -83,96 +168,180 @@ struct NoLoad {
   template <typename C>
   __device__ __forceinline__ C operator()(int, int, C v) const { return v; }
 };
-struct KeepAll {
-  __device__ __forceinline__ bool operator()(int, int) const { return true; }
+
+// Orders LDS accesses of one wavefront (its lanes exchange data through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Layout of a P-wide complex tile in LDS: element (i, c) at i * (P + 1) + c.
+// LDS serves 16 lanes of an 8-byte access per cycle from 32 four-byte banks;
+// the odd row stride sends 16 consecutive rows at one column, and 16
+// consecutive columns of one row, to 16 different bank pairs.
+template <int P>
+struct Tile {
+  static constexpr int LD = P + 1;
+  __device__ __forceinline__ static int at(int i, int c) { return i * LD + c; }
 };
 
-// One workgroup transforms nvec vectors of length L.  NT = blockDim.x,
-// UPT = ceil(nvec * L / EPT / NT) work units per thread.
-//   tw[k * twstep] = exp(-2 pi i k / L), k in [0, L)
-//   nzero: input elements k >= nzero are taken as zero without reading LDS
-//   ld(v, k, x): applied to every input element read in the first pass
-//   keep(v, k): output element k of vector v is stored only if true
-template <typename T, int L, int EPT, int DIR, int UPT>
-struct LdsFft {
-  static_assert(EPT <= 16 && (EPT & (EPT - 1)) == 0, "EPT must be a power of two <= 16");
+// Vectors of a tile: rows (element k = column k) or columns (element k = row
+// k).  NV is the compile-time vector count; a mapped set holds nv <= NV
+// vectors, vector v being row / column (kmin + v) mod NV (the kept Fourier
+// modes of a centred or corner set).
+template <int P, int NV_, bool ROWS, bool MAPPED = false, bool WAVE_LOCAL = false>
+struct Vecs {
+  static constexpr int NV = NV_;
+  // wave-local: a vector's threads sit in one wavefront (numbered
+  // vector-fastest inside it) and passes synchronise only the wavefront;
+  // otherwise threads are numbered vector-fastest across the workgroup and
+  // passes use workgroup barriers
+  static constexpr bool WL = WAVE_LOCAL;
+  int nv = NV_;
+  int kmin = 0;
+  __device__ __forceinline__ int addr(int v, int k) const {
+    const int x = MAPPED ? ((kmin + v) & (NV - 1)) : v;
+    return ROWS ? Tile<P>::at(x, k) : Tile<P>::at(k, x);
+  }
+};
+
+// Radix-R Stockham passes (R <= 16) over the vectors of a Vecs set, L points
+// each, EPT elements per thread, NT threads.  tw[k * TWS] = exp(-2 pi i k / L).
+// After a wave-local transform, callers put a workgroup barrier before any
+// phase that reads another wavefront's vectors.
+template <typename T, int L, int EPT, int NT, class V, int TWS>
+struct Fft {
+  static_assert(EPT <= 32 && (EPT & (EPT - 1)) == 0, "EPT must be a power of two <= 32");
   static_assert(L >= EPT && L % EPT == 0, "bad FFT length");
   static constexpr int TPV = L / EPT;
+  static constexpr int UPT = (V::NV * TPV + NT - 1) / NT;
+  static_assert(!V::WL || (64 % TPV == 0 && NT % 64 == 0), "a vector's threads must sit in one wavefront");
+  static constexpr int VPW = 64 / TPV;  // vectors per wavefront (wave-local sets)
+
+  __device__ __forceinline__ static void sync() {
+    if constexpr (V::WL)
+      wave_sync();
+    else
+      __syncthreads();
+  }
 
   cx<T>* buf;
-  int nvec, vstride, estride;
   const cx<T>* tw;
-  int twstep;
+  V vs;
 
-  template <int R, int NS, class LoadOp, class KeepOp>
-  __device__ __forceinline__ void pass(int nzero, const LoadOp& ld, const KeepOp& keep) {
-    constexpr bool FIRST = (NS == 1);
-    constexpr bool LAST = (NS * R == L);
-    constexpr int BPT = EPT / R;
-    constexpr int LR = L / R;
+  // radix of the pass at stride NS: as large as the registers allow, at most 16
+  __host__ __device__ static constexpr int radix(int NS) {
+    return (L / NS < EPT ? L / NS : EPT) < 16 ? (L / NS < EPT ? L / NS : EPT) : 16;
+  }
+
+  struct Regs {
     cx<T> v[UPT][EPT];
-    int vec[UPT], tt[UPT];
+    int vec[UPT], t[UPT];
+    bool act[UPT];
+  };
+
+  __device__ __forceinline__ void assign(Regs& g) const {
 #pragma unroll
     for (int q = 0; q < UPT; ++q) {
-      const int unit = threadIdx.x + q * blockDim.x;
-      vec[q] = unit % nvec;
-      tt[q] = unit / nvec;
-      if (tt[q] < TPV) {
+      const int unit = threadIdx.x + q * NT;
+      if constexpr (V::WL) {
+        const int lane = unit & 63;
+        g.vec[q] = (unit >> 6) * VPW + lane % VPW;
+        g.t[q] = lane / VPW;
+      } else {
+        g.vec[q] = unit % V::NV;
+        g.t[q] = unit / V::NV;
+      }
+      g.act[q] = g.vec[q] < vs.nv && g.t[q] < TPV;
+    }
+  }
+
+  // Load of a pass: element j + r L/R of the butterflies j = t + u TPV, with
+  // the pass twiddle.  In a first pass (NS = 1) inputs r >= ZR are zero and
+  // ld(v, k, x) is applied to every element read.
+  template <int R, int NS, int DIR, int ZR, class LoadOp>
+  __device__ __forceinline__ void load(Regs& g, const LoadOp& ld) const {
+    constexpr int BPT = EPT / R, LR = L / R;
 #pragma unroll
-        for (int u = 0; u < BPT; ++u) {
-          const int j = tt[q] + u * TPV;
+    for (int q = 0; q < UPT; ++q) {
+      if (!g.act[q]) continue;
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
+      for (int u = 0; u < BPT; ++u) {
+        const int j = g.t[q] + u * TPV;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cx<T> x{T(0), T(0)};
+          if (r < ZR) {
             const int k = j + r * LR;
-            cx<T> x;
-            if (FIRST && k >= nzero) {
-              x = cx<T>{T(0), T(0)};
-            } else {
-              x = buf[vec[q] * vstride + k * estride];
-              if (FIRST) x = ld(vec[q], k, x);
+            x = buf[vs.addr(g.vec[q], k)];
+            if constexpr (NS == 1) x = ld(g.vec[q], k, x);
+            if constexpr (NS > 1) {
+              if (r > 0) {
+                cx<T> w = tw[((j % NS) * r * (L / (NS * R))) * TWS];
+                if (DIR > 0) w.y = -w.y;
+                x = x * w;
+              }
             }
-            if (NS > 1 && r > 0) {
-              const int idx = (j % NS) * r * (L / (NS * R));
-              cx<T> w = tw[idx * twstep];
-              if (DIR > 0) w.y = -w.y;
-              x = x * w;
-            }
-            v[q][u * R + r] = x;
           }
+          g.v[q][u * R + r] = x;
         }
       }
     }
-    __syncthreads();
+  }
+
+  template <int R, int DIR, int ZR, int KR>
+  __device__ __forceinline__ void compute(Regs& g) const {
 #pragma unroll
     for (int q = 0; q < UPT; ++q) {
-      if (tt[q] < TPV) {
+      if (!g.act[q]) continue;
 #pragma unroll
-        for (int u = 0; u < BPT; ++u) {
-          fft_reg<T, R, DIR>(&v[q][u * R]);
-          const int j = tt[q] + u * TPV;
-          const int base = (j / NS) * NS * R + (j % NS);
+      for (int u = 0; u < EPT / R; ++u) fft_reg<T, R, DIR, ZR, KR>(&g.v[q][u * R]);
+    }
+  }
+
+  // Store of a pass: output r of butterfly j goes to (j / NS) NS R + j % NS + r NS;
+  // only outputs r < KR are written.
+  template <int R, int NS, int KR>
+  __device__ __forceinline__ void store(const Regs& g) const {
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int k = base + r * NS;
-            if (!LAST || keep(vec[q], k)) buf[vec[q] * vstride + k * estride] = v[q][u * R + r];
-          }
-        }
+    for (int q = 0; q < UPT; ++q) {
+      if (!g.act[q]) continue;
+#pragma unroll
+      for (int u = 0; u < EPT / R; ++u) {
+        const int j = g.t[q] + u * TPV;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < KR; ++r) buf[vs.addr(g.vec[q], base + r * NS)] = g.v[q][u * R + r];
       }
     }
-    __syncthreads();
   }
 
-  template <int NS, class LoadOp, class KeepOp>
-  __device__ __forceinline__ void run_from(int nzero, const LoadOp& ld, const KeepOp& keep) {
-    constexpr int R = (L / NS < EPT) ? (L / NS) : EPT;
-    pass<R, NS>(nzero, ld, keep);
-    if constexpr (NS * R < L) run_from<NS * R>(nzero, ld, keep);
+  // One full pass: load, barrier, butterflies, store, barrier.
+  template <int R, int NS, int DIR, int ZR, int KR, class LoadOp>
+  __device__ __forceinline__ void pass(const LoadOp& ld) const {
+    Regs g;
+    assign(g);
+    load<R, NS, DIR, ZR>(g, ld);
+    sync();
+    compute<R, DIR, ZR, KR>(g);
+    store<R, NS, KR>(g);
+    sync();
   }
 
-  template <class LoadOp = NoLoad, class KeepOp = KeepAll>
-  __device__ __forceinline__ void run(int nzero = L, const LoadOp& ld = LoadOp(),
-                                      const KeepOp& keep = KeepOp()) {
-    run_from<1>(nzero, ld, keep);
+  // The whole transform with radices EPT, EPT, ..., remainder.  NZ: inputs
+  // k >= NZ are zero; KEEP: only outputs k < KEEP are stored (both must be
+  // multiples of the stride they apply at, e.g. L/2).
+  template <int DIR, int NZ = L, int KEEP = L, int NS = 1, class LoadOp = NoLoad>
+  __device__ __forceinline__ void run(const LoadOp& ld = LoadOp()) const {
+    constexpr int R = radix(NS);
+    constexpr bool first = NS == 1, last = NS * R == L;
+    constexpr int ZR = first ? (NZ * R + L - 1) / L : R;
+    constexpr int KR = last ? (KEEP + NS - 1) / NS : R;
+    static_assert(!first || (NZ * R) % L == 0, "zero prefix must align with the first pass");
+    static_assert(!last || KEEP % NS == 0, "kept prefix must align with the last pass");
+    pass<R, NS, DIR, ZR, KR>(ld);
+    if constexpr (!last) run<DIR, NZ, KEEP, NS * R>(ld);
   }
 };
 

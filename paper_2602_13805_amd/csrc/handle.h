@@ -18,6 +18,7 @@ struct pdf_handle {
   void* ghat = nullptr;   // [P][P] spectrum / P^2
   void* tw = nullptr;     // [P] exp(-2 pi i k / P)
   void* gs = nullptr;     // [Ns][N]
+  void* gsT = nullptr;    // [N][Ns] (transposed copy for the MFMA receiver GEMM)
   void* einc = nullptr;   // [Ni][N]
   double* Ss = nullptr;   // device scalar ||E_inc||^2
   double* Sd = nullptr;   // device [B] ||E_sca||^2

@@ -8,6 +8,7 @@
 // is a tiled complex FP64 GEMM on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <string>
@@ -39,28 +40,31 @@ __global__ void k_mom_build(cx<double>* A, const cx<double>* ker, const int* si,
   A[idx] = v;
 }
 
-// Y[p][a] = sum_c A[a][c] X[p][c], A [n][n] row-major, X, Y [nrhs][n].
-// Block: 64 rows x 64 right-hand sides, 256 threads, each 4 x 4 outputs.
+// Partial products of Y[p][a] = sum_c A[a][c] X[p][c] (A [n][n] row-major,
+// X, Y [nrhs][n]) over the column slice s of the grid's y dimension:
+// part[s][p][a].  Block: 64 rows x 64 right-hand sides, 256 threads, each
+// 4 x 4 outputs; the slices are summed in fixed order by k_zsum.
 constexpr int TBM = 64, TBN = 64, TBK = 16;
 __global__ __launch_bounds__(256) void k_zgemm(const cx<double>* __restrict__ A, const cx<double>* __restrict__ X,
-                                               cx<double>* __restrict__ Y, int n, int nrhs) {
+                                               cx<double>* __restrict__ part, int n, int nrhs, int kslice) {
   __shared__ cx<double> As[TBK][TBM + 1];
   __shared__ cx<double> Xs[TBK][TBN + 1];
-  const int a0 = blockIdx.x * TBM, p0 = blockIdx.y * TBN;
+  const int a0 = blockIdx.x * TBM, s = blockIdx.y;
+  const int c_begin = s * kslice, c_end = min(n, c_begin + kslice);
   const int tid = threadIdx.x, ta = tid % 16, tp = tid / 16;
   cx<double> acc[4][4];
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) acc[i][j] = cx<double>{0.0, 0.0};
-  for (int c0 = 0; c0 < n; c0 += TBK) {
+  for (int c0 = c_begin; c0 < c_end; c0 += TBK) {
     for (int e = tid; e < TBM * TBK; e += 256) {
       const int r = e / TBK, k = e % TBK;
       const int a = a0 + r, c = c0 + k;
-      As[k][r] = (a < n && c < n) ? A[size_t(a) * n + c] : cx<double>{0.0, 0.0};
+      As[k][r] = (a < n && c < c_end) ? A[size_t(a) * n + c] : cx<double>{0.0, 0.0};
     }
     for (int e = tid; e < TBN * TBK; e += 256) {
       const int r = e / TBK, k = e % TBK;
-      const int p = p0 + r, c = c0 + k;
-      Xs[k][r] = (p < nrhs && c < n) ? X[size_t(p) * n + c] : cx<double>{0.0, 0.0};
+      const int c = c0 + k;
+      Xs[k][r] = (r < nrhs && c < c_end) ? X[size_t(r) * n + c] : cx<double>{0.0, 0.0};
     }
     __syncthreads();
     for (int k = 0; k < TBK; ++k) {
@@ -72,11 +76,21 @@ __global__ __launch_bounds__(256) void k_zgemm(const cx<double>* __restrict__ A,
     }
     __syncthreads();
   }
+  cx<double>* out = part + size_t(s) * nrhs * n;
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
-      const int a = a0 + ta + 16 * i, p = p0 + tp + 16 * j;
-      if (a < n && p < nrhs) Y[size_t(p) * n + a] = acc[i][j];
+      const int a = a0 + ta + 16 * i, p = tp + 16 * j;
+      if (a < n && p < nrhs) out[size_t(p) * n + a] = acc[i][j];
     }
+}
+
+// Y = sum over the S slices of part, in slice order.
+__global__ void k_zsum(const cx<double>* part, cx<double>* Y, size_t len, int S) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  cx<double> s = part[i];
+  for (int k = 1; k < S; ++k) s = s + part[size_t(k) * len + i];
+  Y[i] = s;
 }
 
 // out[p] = sum_c conj(X[p][c]) Y[p][c]   (one block per right-hand side)
@@ -225,11 +239,20 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
   hipLaunchKernelGGL(k_mom_build, dim3((nA + 255) / 256), dim3(256), 0, st, dA, dker, dsi, dsj, dchi, nS, M);
   MOM_TRY(hipGetLastError());
 
-  const dim3 ggrid((nS + TBM - 1) / TBM, (ni + TBN - 1) / TBN);
+  // split the inner dimension so that about a thousand workgroups run
+  const int rblocks = (nS + TBM - 1) / TBM;
+  int nsplit = (1024 + rblocks - 1) / rblocks;
+  nsplit = std::max(1, std::min(nsplit, (nS + TBK - 1) / TBK));
+  const int kslice = (((nS + nsplit - 1) / nsplit) + TBK - 1) / TBK * TBK;
+  nsplit = (nS + kslice - 1) / kslice;
+  const dim3 ggrid(rblocks, nsplit);
   const size_t nv = size_t(ni) * nS;
   const dim3 vgrid((nv + 255) / 256);
+  cx<double>* dpart;
+  MOM_TRY(d.alloc(&dpart, sizeof(cx<double>) * nv * nsplit));
   auto matvec = [&](const cx<double>* in, cx<double>* o) {
-    hipLaunchKernelGGL(k_zgemm, ggrid, dim3(256), 0, st, dA, in, o, nS, ni);
+    hipLaunchKernelGGL(k_zgemm, ggrid, dim3(256), 0, st, dA, in, dpart, nS, ni, kslice);
+    hipLaunchKernelGGL(k_zsum, vgrid, dim3(256), 0, st, dpart, o, nv, nsplit);
   };
   auto dot = [&](const cx<double>* a, const cx<double>* b, int slot, std::vector<cd>& h) -> hipError_t {
     hipLaunchKernelGGL(k_zdot, dim3(ni), dim3(256), 0, st, a, b, dots + slot * ni, nS);

@@ -43,6 +43,7 @@ struct ReduceArgs {
   const cx<T>* J;       // [B][Ni][N]
   const cx<T>* E;       // [B][Ni][N]
   const cx<T>* gs;      // [Ns][N]
+  const cx<T>* gsT;     // [N][Ns] (the same operator, receiver-contiguous)
   const cx<T>* Rfix;    // [B][N] fixed contrast, or null (least squares)
   cx<T>* R;             // [B][N] out (least squares only)
   T* den;               // [B][N] out
@@ -115,6 +116,138 @@ __global__ __launch_bounds__(256) void k_pixel_reduce(ReduceArgs<T> a) {
     for (int k = 0; k < kmax; ++k) acc = acc + g[k] * jt[k];
     a.Dpart[((size_t(b) * a.ntiles + tile) * a.Ni + p) * a.Ns + q] = acc;
   }
+}
+
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// FP32 version of k_pixel_reduce with the split-K receiver GEMM on MFMA.
+// Block: 256 threads, one pixel each for the reduction over incidences;
+// then the complex GEMM D[p][q] = sum_k G_S[q][k] J_p[k] over the tile as a
+// real GEMM C = A B with A the 2x2-block real form of G_S (rows 2q+c: c = 0
+// real, 1 imaginary part of D) and B the (Re, Im) rows of J:
+//   A[2q][2k] = Re G, A[2q][2k+1] = -Im G, A[2q+1][2k] = Im G, A[2q+1][2k+1] = Re G.
+// One v_mfma_f32_32x32x2f32 consumes one complex pixel for a 32 x 32 output
+// tile (16 receivers x 32 incidences).  Each wave takes a quarter of the
+// pixels; the four partial tiles are summed through LDS in fixed order.
+// NRT = ceil(Ns / 16) row tiles, NCT = ceil(Ni / 32) column tiles.
+template <int NRT, int NCT>
+__global__ __launch_bounds__(256) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
+  constexpr int TILE = 256;
+  constexpr int LDJ = 32 * NCT + 1;  // padded row of the staged currents (floats)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* Jr = reinterpret_cast<float*>(smem_raw);   // [TILE][LDJ]
+  float* Ji = Jr + TILE * LDJ;                       // [TILE][LDJ]
+  double* red = reinterpret_cast<double*>(Ji + TILE * LDJ);
+  const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int n = tile * TILE + tid;
+  const bool valid = n < a.N;
+  const int Ni = a.Ni, Ns = a.Ns, N = a.N;
+  double nr = 0, ni = 0, dd = 0, jj = 0;
+  const cx<float>* Jb = a.J + size_t(b) * Ni * N + n;
+  const cx<float>* Eb = a.E + size_t(b) * Ni * N + n;
+#pragma unroll 4
+  for (int p = 0; p < Ni; ++p) {
+    cx<float> J{0.f, 0.f}, E{0.f, 0.f};
+    if (valid) {
+      J = Jb[size_t(p) * N];
+      E = Eb[size_t(p) * N];
+    }
+    nr += double(J.x) * E.x + double(J.y) * E.y;
+    ni += double(J.y) * E.x - double(J.x) * E.y;
+    dd += double(E.x) * E.x + double(E.y) * E.y;
+    jj += double(J.x) * J.x + double(J.y) * J.y;
+    Jr[tid * LDJ + p] = J.x;
+    Ji[tid * LDJ + p] = J.y;
+  }
+  for (int p = Ni; p < 32 * NCT; ++p) {
+    Jr[tid * LDJ + p] = 0.f;
+    Ji[tid * LDJ + p] = 0.f;
+  }
+  double lpix = 0.0;
+  if (valid) {
+    const double beta = a.beta;
+    double rr, ri;
+    if (a.Rfix) {
+      const cx<float> r = a.Rfix[size_t(b) * N + n];
+      rr = r.x;
+      ri = r.y;
+    } else {
+      rr = beta * nr / dd;
+      ri = beta * ni / dd;
+      a.R[size_t(b) * N + n] = cx<float>{float(rr), float(ri)};
+    }
+    lpix = (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
+    a.den[size_t(b) * N + n] = float(dd);
+    const double xr = 1.0 - rr, xi = -ri;
+    const double q = beta * (xr * xr + xi * xi);
+    a.chi[size_t(b) * N + n] = cx<float>{float((rr * xr + ri * xi) / q), float((ri * xr - rr * xi) / q)};
+  }
+  const double s = block_sum(lpix, red);  // contains barriers: Jr / Ji are complete after it
+  if (tid == 0) a.lsp[size_t(b) * a.ntiles + tile] = s;
+  __syncthreads();
+
+  const int lane = tid & 63, w = tid >> 6;
+  const int m = lane & 31, cp = lane >> 5;    // A row within the tile / k component (0 Re J, 1 Im J)
+  const int c = m & 1, comp = c ^ cp;         // D part (0 Re, 1 Im) / which part of G
+  const float sgn = (c == 0 && cp == 1) ? -1.f : 1.f;
+  const int tile0 = tile * TILE;
+  const int kmax = min(TILE, N - tile0);
+  const int k0 = w * (TILE / 4), k1 = min(k0 + TILE / 4, kmax);
+  const float* G = reinterpret_cast<const float*>(a.gsT);
+  const float* Jsrc = cp ? Ji : Jr;
+  floatx16 acc[NRT][NCT];
+#pragma unroll
+  for (int h = 0; h < NRT; ++h)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[h][t][r] = 0.f;
+  // operands of KC pixels are loaded before their MFMAs so that the L2
+  // latency of the G_S rows overlaps
+  constexpr int KC = 8;
+  for (int kb = k0; kb < k1; kb += KC) {
+    float av[KC][NRT], bv[KC][NCT];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = kb + kk;
+      const bool in = k < k1;
+      const float* grow = G + size_t(tile0 + (in ? k : k0)) * 2 * Ns;
+#pragma unroll
+      for (int h = 0; h < NRT; ++h) {
+        const int q = 16 * h + (m >> 1);
+        av[kk][h] = (in && q < Ns) ? sgn * grow[2 * q + comp] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) bv[kk][t] = in ? Jsrc[k * LDJ + 32 * t + m] : 0.f;
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int h = 0; h < NRT; ++h)
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+          acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][h], bv[kk][t], acc[h][t], 0, 0, 0);
+  }
+  // sum the four waves' partial tiles (reusing the staging LDS) and store
+  float* W = Jr;  // [4][16][64] floats per output tile
+  cx<float>* Dout = a.Dpart + (size_t(b) * a.ntiles + tile) * Ni * Ns;
+#pragma unroll
+  for (int h = 0; h < NRT; ++h)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) W[(w * 16 + r) * 64 + lane] = acc[h][t][r];
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const float v = W[e] + W[1024 + e] + W[2048 + e] + W[3072 + e];
+        const int r = e >> 6, l = e & 63;
+        const int i = (r & 3) + 8 * (r >> 2) + 4 * (l >> 5);   // row of the 32 x 32 tile
+        const int q = 16 * h + (i >> 1), p = 32 * t + (l & 31);
+        if (q < Ns && p < Ni) reinterpret_cast<float*>(Dout + p * Ns + q)[i & 1] = v;
+      }
+    }
 }
 
 template <typename T>
