@@ -145,9 +145,10 @@ def main():
     log(f"synthesised {B} instances in {synth_s:.1f} s")
 
     if args.copy_calibration_mib:
+        # an elementwise kernel (not a DMA copy): reads and writes exactly this many MiB each
         src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     tx = si.antenna_positions(wl.n_tx, wl.radius)

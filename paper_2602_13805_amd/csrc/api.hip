@@ -140,7 +140,7 @@ static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
 
 template <int NRT, int NCT>
 static void launch_reduce_mfma(pdf_handle* h, const ReduceArgs<float>& a) {
-  const size_t lds = sizeof(float) * 2 * 256 * (32 * NCT + 1) + 16 * sizeof(double);
+  const size_t lds = reduce_mfma_lds<NCT>();
   set_lds(k_pixel_reduce_mfma<NRT, NCT>, lds);
   hipLaunchKernelGGL((k_pixel_reduce_mfma<NRT, NCT>), dim3(h->ntiles, h->B), dim3(256), lds, h->stream, a);
 }
@@ -219,8 +219,28 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
   return check_launch(h, "k_image_reg");
 }
 
+template <int NRT>
+static void launch_adj_gemm_mfma(pdf_handle* h, const cx<float>* x, cx<float>* out) {
+  const size_t lds = sizeof(cx<float>) * size_t(h->Ns) * 16 * NRT;
+  dim3 grid((h->N + 255) / 256, h->B);
+  hipLaunchKernelGGL((k_adj_gemm_mfma<NRT>), grid, dim3(256), lds, h->stream, (const cx<float>*)h->gs, x, out,
+                     h->Ni, h->Ns, h->N);
+}
+
 template <typename T>
 static int launch_adj_gemm(pdf_handle* h, const cx<T>* x, cx<T>* out) {
+  if constexpr (sizeof(T) == 4) {
+    if (h->N % 32 == 0) {
+      switch ((h->Ni + 15) / 16) {
+        case 1: launch_adj_gemm_mfma<1>(h, x, out); break;
+        case 2: launch_adj_gemm_mfma<2>(h, x, out); break;
+        case 3: launch_adj_gemm_mfma<3>(h, x, out); break;
+        case 4: launch_adj_gemm_mfma<4>(h, x, out); break;
+        default: return fail(h, PDF_EUNSUPPORTED, "incidence count out of range");
+      }
+      return check_launch(h, "k_adj_gemm_mfma");
+    }
+  }
   const size_t lds = sizeof(cx<T>) * size_t(h->Ni) * h->Ns;
   dim3 grid((h->N + 255) / 256, h->B);
   if (h->Ns <= 16)
@@ -581,8 +601,10 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
     delete h;
     return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 incidences");
   }
+  // the FP64 reduction stages [Ni][tile] currents in LDS; the FP32 one has a fixed
+  // 256-pixel tile staged in 128-pixel halves (any Ni <= 64)
   while (prm.precision == PDF_FP64 && tile > 64 && size_t(h->Ni) * tile * csz > 64 * 1024) tile >>= 1;
-  if (size_t(h->Ni) * tile * csz > 64 * 1024) {
+  if (prm.precision == PDF_FP64 && size_t(h->Ni) * tile * csz > 64 * 1024) {
     delete h;
     return fail(nullptr, PDF_EUNSUPPORTED, "too many incidences for the pixel-reduction tile");
   }

@@ -122,80 +122,49 @@ __global__ __launch_bounds__(256) void k_pixel_reduce(ReduceArgs<T> a) {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // FP32 version of k_pixel_reduce with the split-K receiver GEMM on MFMA.
-// Block: 256 threads, one pixel each for the reduction over incidences;
-// then the complex GEMM D[p][q] = sum_k G_S[q][k] J_p[k] over the tile as a
-// real GEMM C = A B with A the 2x2-block real form of G_S (rows 2q+c: c = 0
-// real, 1 imaginary part of D) and B the (Re, Im) rows of J:
-//   A[2q][2k] = Re G, A[2q][2k+1] = -Im G, A[2q+1][2k] = Im G, A[2q+1][2k+1] = Re G.
-// One v_mfma_f32_32x32x2f32 consumes one complex pixel for a 32 x 32 output
-// tile (16 receivers x 32 incidences).  Each wave takes a quarter of the
-// pixels; the four partial tiles are summed through LDS in fixed order.
+// Block: 256 threads over a tile of 256 pixels, taken as two sub-tiles of
+// 128 so that the staging LDS stays near 34 KB and four blocks share a CU.
+// Per sub-tile:
+//  1. the reduction over incidences: thread (pixel, half) loads the
+//     incidences p = half, half + 2, ... of its pixel in batches of four
+//     (loads issued before use), accumulates num / den / sum |J|^2 in FP64
+//     and stages J in LDS; the two halves are added in fixed order;
+//  2. the complex GEMM D[p][q] += sum_k G_S[q][k] J_p[k] over the sub-tile
+//     as a real GEMM C = A B with A the 2x2-block real form of G_S (rows
+//     2q+c: c = 0 real, 1 imaginary part of D) and B the (Re, Im) rows of J:
+//       A[2q][2k] = Re G, A[2q][2k+1] = -Im G, A[2q+1][2k] = Im G, A[2q+1][2k+1] = Re G.
+//     One v_mfma_f32_32x32x2f32 consumes one complex pixel for a 32 x 32
+//     output tile (16 receivers x 32 incidences); each wave takes a quarter
+//     of the sub-tile.
+// The four waves' partial tiles are summed through LDS in fixed order.
 // NRT = ceil(Ns / 16) row tiles, NCT = ceil(Ni / 32) column tiles.
-template <int NRT, int NCT>
-__global__ __launch_bounds__(256) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
-  constexpr int TILE = 256;
-  constexpr int LDJ = 32 * NCT + 1;  // padded row of the staged currents (floats)
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* Jr = reinterpret_cast<float*>(smem_raw);   // [TILE][LDJ]
-  float* Ji = Jr + TILE * LDJ;                       // [TILE][LDJ]
-  double* red = reinterpret_cast<double*>(Ji + TILE * LDJ);
-  const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-  const int n = tile * TILE + tid;
-  const bool valid = n < a.N;
-  const int Ni = a.Ni, Ns = a.Ns, N = a.N;
-  double nr = 0, ni = 0, dd = 0, jj = 0;
-  const cx<float>* Jb = a.J + size_t(b) * Ni * N + n;
-  const cx<float>* Eb = a.E + size_t(b) * Ni * N + n;
-#pragma unroll 4
-  for (int p = 0; p < Ni; ++p) {
-    cx<float> J{0.f, 0.f}, E{0.f, 0.f};
-    if (valid) {
-      J = Jb[size_t(p) * N];
-      E = Eb[size_t(p) * N];
-    }
-    nr += double(J.x) * E.x + double(J.y) * E.y;
-    ni += double(J.y) * E.x - double(J.x) * E.y;
-    dd += double(E.x) * E.x + double(E.y) * E.y;
-    jj += double(J.x) * J.x + double(J.y) * J.y;
-    Jr[tid * LDJ + p] = J.x;
-    Ji[tid * LDJ + p] = J.y;
-  }
-  for (int p = Ni; p < 32 * NCT; ++p) {
-    Jr[tid * LDJ + p] = 0.f;
-    Ji[tid * LDJ + p] = 0.f;
-  }
-  double lpix = 0.0;
-  if (valid) {
-    const double beta = a.beta;
-    double rr, ri;
-    if (a.Rfix) {
-      const cx<float> r = a.Rfix[size_t(b) * N + n];
-      rr = r.x;
-      ri = r.y;
-    } else {
-      rr = beta * nr / dd;
-      ri = beta * ni / dd;
-      a.R[size_t(b) * N + n] = cx<float>{float(rr), float(ri)};
-    }
-    lpix = (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
-    a.den[size_t(b) * N + n] = float(dd);
-    const double xr = 1.0 - rr, xi = -ri;
-    const double q = beta * (xr * xr + xi * xi);
-    a.chi[size_t(b) * N + n] = cx<float>{float((rr * xr + ri * xi) / q), float((ri * xr - rr * xi) / q)};
-  }
-  const double s = block_sum(lpix, red);  // contains barriers: Jr / Ji are complete after it
-  if (tid == 0) a.lsp[size_t(b) * a.ntiles + tile] = s;
-  __syncthreads();
+constexpr int kReduceTile = 256, kReduceSub = 128;
 
+template <int NCT>
+constexpr size_t reduce_mfma_lds() {
+  return sizeof(float) * 2 * kReduceSub * (32 * NCT + 1) + sizeof(double) * 4 * kReduceSub + 16 * sizeof(double);
+}
+
+template <int NRT, int NCT>
+__global__ __launch_bounds__(256, (NRT * NCT <= 2 ? 4 : 2)) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
+  constexpr int SUB = kReduceSub, NSUB = kReduceTile / kReduceSub;
+  constexpr int LDJ = 32 * NCT + 1;  // padded row of the staged currents (floats)
+  constexpr int PB = 4;              // incidences per load batch
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* Jr = reinterpret_cast<float*>(smem_raw);         // [SUB][LDJ]
+  float* Ji = Jr + SUB * LDJ;                               // [SUB][LDJ]
+  double* part = reinterpret_cast<double*>(Ji + SUB * LDJ);  // [4][SUB] sums of the second half
+  double* red = part + 4 * SUB;
+  const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int Ni = a.Ni, Ns = a.Ns, N = a.N;
+  const int px = tid & (SUB - 1), half = tid / SUB;
   const int lane = tid & 63, w = tid >> 6;
   const int m = lane & 31, cp = lane >> 5;    // A row within the tile / k component (0 Re J, 1 Im J)
   const int c = m & 1, comp = c ^ cp;         // D part (0 Re, 1 Im) / which part of G
   const float sgn = (c == 0 && cp == 1) ? -1.f : 1.f;
-  const int tile0 = tile * TILE;
-  const int kmax = min(TILE, N - tile0);
-  const int k0 = w * (TILE / 4), k1 = min(k0 + TILE / 4, kmax);
   const float* G = reinterpret_cast<const float*>(a.gsT);
   const float* Jsrc = cp ? Ji : Jr;
+  const double beta = a.beta;
   floatx16 acc[NRT][NCT];
 #pragma unroll
   for (int h = 0; h < NRT; ++h)
@@ -203,32 +172,110 @@ __global__ __launch_bounds__(256) void k_pixel_reduce_mfma(ReduceArgs<float> a) 
     for (int t = 0; t < NCT; ++t)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[h][t][r] = 0.f;
-  // operands of KC pixels are loaded before their MFMAs so that the L2
-  // latency of the G_S rows overlaps
-  constexpr int KC = 8;
-  for (int kb = k0; kb < k1; kb += KC) {
-    float av[KC][NRT], bv[KC][NCT];
+  double lpix = 0.0;
+
+  for (int sub = 0; sub < NSUB; ++sub) {
+    const int sub0 = tile * kReduceTile + sub * SUB;
+    if (sub0 >= N) break;  // block-uniform
+    const int n = sub0 + px;
+    const bool valid = n < N;
+    // 1. reduction over this thread's incidences
+    double nr = 0, ni = 0, dd = 0, jj = 0;
+    const int nc = min(n, N - 1);
+    const cx<float>* Jb = a.J + size_t(b) * Ni * N + nc;
+    const cx<float>* Eb = a.E + size_t(b) * Ni * N + nc;
+    // Loaded values are used unconditionally (a pixel past the end is masked
+    // by a multiplication): a load whose value feeds only one arm of a select
+    // is moved under a branch by the compiler and waited for on its own.
+    const float vm = valid ? 1.f : 0.f;
+    auto accumulate = [&](int p, cx<float> J, cx<float> E) {
+      J = cx<float>{vm * J.x, vm * J.y};
+      E = cx<float>{vm * E.x, vm * E.y};
+      nr += double(J.x) * E.x + double(J.y) * E.y;
+      ni += double(J.y) * E.x - double(J.x) * E.y;
+      dd += double(E.x) * E.x + double(E.y) * E.y;
+      jj += double(J.x) * J.x + double(J.y) * J.y;
+      Jr[px * LDJ + p] = J.x;
+      Ji[px * LDJ + p] = J.y;
+    };
+    int p0 = half;
+    for (; p0 + 2 * (PB - 1) < Ni; p0 += 2 * PB) {  // whole batches: loads issued before use
+      cx<float> Jv[PB], Ev[PB];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int k = kb + kk;
-      const bool in = k < k1;
-      const float* grow = G + size_t(tile0 + (in ? k : k0)) * 2 * Ns;
-#pragma unroll
-      for (int h = 0; h < NRT; ++h) {
-        const int q = 16 * h + (m >> 1);
-        av[kk][h] = (in && q < Ns) ? sgn * grow[2 * q + comp] : 0.f;
+      for (int u = 0; u < PB; ++u) {
+        Jv[u] = Jb[size_t(p0 + 2 * u) * N];
+        Ev[u] = Eb[size_t(p0 + 2 * u) * N];
       }
 #pragma unroll
-      for (int t = 0; t < NCT; ++t) bv[kk][t] = in ? Jsrc[k * LDJ + 32 * t + m] : 0.f;
+      for (int u = 0; u < PB; ++u) accumulate(p0 + 2 * u, Jv[u], Ev[u]);
     }
+    for (; p0 < Ni; p0 += 2) accumulate(p0, Jb[size_t(p0) * N], Eb[size_t(p0) * N]);
+    for (; p0 < 32 * NCT; p0 += 2) {  // zero incidences pad the MFMA tile
+      Jr[px * LDJ + p0] = 0.f;
+      Ji[px * LDJ + p0] = 0.f;
+    }
+    if (half == 1) {
+      part[px] = nr;
+      part[SUB + px] = ni;
+      part[2 * SUB + px] = dd;
+      part[3 * SUB + px] = jj;
+    }
+    __syncthreads();  // staged J and the second half's sums are complete
+    if (half == 0 && valid) {
+      nr += part[px];
+      ni += part[SUB + px];
+      dd += part[2 * SUB + px];
+      jj += part[3 * SUB + px];
+      double rr, ri;
+      if (a.Rfix) {
+        const cx<float> r = a.Rfix[size_t(b) * N + n];
+        rr = r.x;
+        ri = r.y;
+      } else {
+        rr = beta * nr / dd;
+        ri = beta * ni / dd;
+        a.R[size_t(b) * N + n] = cx<float>{float(rr), float(ri)};
+      }
+      lpix += (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
+      a.den[size_t(b) * N + n] = float(dd);
+      const double xr = 1.0 - rr, xi = -ri;
+      const double q = beta * (xr * xr + xi * xi);
+      a.chi[size_t(b) * N + n] = cx<float>{float((rr * xr + ri * xi) / q), float((ri * xr - rr * xi) / q)};
+    }
+    // 2. receiver GEMM over this sub-tile; operands of KC pixels are loaded
+    // before their MFMAs so that the L2 latency of the G_S rows overlaps
+    const int kmax = min(SUB, N - sub0);
+    const int k0 = w * (SUB / 4), k1 = min(k0 + SUB / 4, kmax);
+    constexpr int KC = 4;
+    for (int kb = k0; kb < k1; kb += KC) {
+      float av[KC][NRT], bv[KC][NCT];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk)
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = kb + kk;
+        const bool in = k < k1;
+        const float* grow = G + size_t(sub0 + (in ? k : k0)) * 2 * Ns;
 #pragma unroll
-      for (int h = 0; h < NRT; ++h)
+        for (int h = 0; h < NRT; ++h) {
+          // a zero A operand masks pixels past the range and padding receivers
+          const int q = 16 * h + (m >> 1);
+          av[kk][h] = ((in && q < Ns) ? sgn : 0.f) * grow[2 * min(q, Ns - 1) + comp];
+        }
 #pragma unroll
-        for (int t = 0; t < NCT; ++t)
-          acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][h], bv[kk][t], acc[h][t], 0, 0, 0);
+        for (int t = 0; t < NCT; ++t) bv[kk][t] = Jsrc[(in ? k : k0) * LDJ + 32 * t + m];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+        for (int h = 0; h < NRT; ++h)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t)
+            acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][h], bv[kk][t], acc[h][t], 0, 0, 0);
+    }
+    __syncthreads();  // the staging buffers are rewritten by the next sub-tile
   }
+  const double s = block_sum(lpix, red);
+  if (tid == 0) a.lsp[size_t(b) * a.ntiles + tile] = s;
+
   // sum the four waves' partial tiles (reusing the staging LDS) and store
   float* W = Jr;  // [4][16][64] floats per output tile
   cx<float>* Dout = a.Dpart + (size_t(b) * a.ntiles + tile) * Ni * Ns;
@@ -414,6 +461,85 @@ __global__ __launch_bounds__(256) void k_adj_gemm(const cx<T>* __restrict__ gs, 
     }
     h[(size_t(b) * Ni + p) * N + n] = acc;
   }
+}
+
+// FP32 version of k_adj_gemm on MFMA: for one instance, the real-expanded
+// GEMM D = A B with rows i = 2p + c (c = 0 real, 1 imaginary part of h_p),
+// columns the pixels and one receiver q per K step of two:
+//   A[2p][2q] = Re x, A[2p][2q+1] = Im x, A[2p+1][2q] = Im x, A[2p+1][2q+1] = -Re x,
+//   B[2q][n] = Re G_S[q][n], B[2q+1][n] = Im G_S[q][n],
+// so that D[2p][n] + i D[2p+1][n] = sum_q conj(G_S[q][n]) x[p][q].
+// Block: 4 waves x CT column tiles of 32 pixels; x^T is staged in LDS
+// (incidence-contiguous, conflict-free reads); each lane of a finished tile
+// holds (Re, Im) of h_p at one pixel, so stores are 256-byte rows.
+// Requires N % 32 == 0.  NRT = ceil(Ni / 16) row tiles.
+template <int NRT>
+__global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restrict__ gs,
+                                                       const cx<float>* __restrict__ x, cx<float>* __restrict__ h,
+                                                       int Ni, int Ns, int N) {
+  constexpr int CT = 2, KC = 8, LDX = 16 * NRT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<float>* xs = reinterpret_cast<cx<float>*>(smem_raw);  // [Ns][LDX]: xs[q][p] = x[p][q]
+  const int b = blockIdx.y, tid = threadIdx.x;
+  for (int o = tid; o < Ns * LDX; o += blockDim.x) {
+    const int q = o / LDX, p = o % LDX;
+    xs[o] = p < Ni ? x[(size_t(b) * Ni + p) * Ns + q] : cx<float>{0.f, 0.f};
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int m = lane & 31, cp = lane >> 5;
+  const int c = m & 1;
+  const int n0 = (blockIdx.x * 4 + w) * 32 * CT;
+  if (n0 >= N) return;  // wave-uniform; no barrier follows
+  int nct = (N - n0) / 32;
+  nct = nct < CT ? nct : CT;
+  const float* Gf = reinterpret_cast<const float*>(gs);
+  floatx16 acc[NRT][CT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[r][t][e] = 0.f;
+  for (int qb = 0; qb < Ns; qb += KC) {
+    float av[KC][NRT], bv[KC][CT];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int q = qb + kk;
+      const bool in = q < Ns;
+      // unconditional loads from clamped (in-bounds) addresses, then a select
+      // (a zero A operand masks receivers past Ns; tiles past nct are not stored)
+      const int qc = min(q, Ns - 1);
+#pragma unroll
+      for (int t = 0; t < CT; ++t) bv[kk][t] = Gf[(size_t(qc) * N + n0 + 32 * (t < nct ? t : 0) + m) * 2 + cp];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        const cx<float> d = xs[qc * LDX + 16 * r + (m >> 1)];
+        av[kk][r] = (in ? 1.f : 0.f) * (c == 0 ? (cp == 0 ? d.x : d.y) : (cp == 0 ? d.y : -d.x));
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+          acc[r][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][r], bv[kk][t], acc[r][t], 0, 0, 0);
+  }
+  // lane (l % 32 = pixel, l / 32) holds rows i = (e % 4) + 8 (e / 4) + 4 (l / 32): pairs (e, e + 1)
+  // with e even are (Re, Im) of incidence p = 16 r + i / 2
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      if (t >= nct) continue;
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        const int i = (e & 3) + 8 * (e >> 2) + 4 * cp;
+        const int p = 16 * r + (i >> 1);
+        if (p < Ni) h[(size_t(b) * Ni + p) * N + n0 + 32 * t + m] = cx<float>{acc[r][t][e], acc[r][t][e + 1]};
+      }
+    }
 }
 
 // s[b] = sum |x[b][*]|^2 over len entries (grid: B blocks).

@@ -51,6 +51,9 @@ CASES = [
     (16, 16, 3, 5, 1, "fp32", 1e-4),   # full basis, even K (corner blocks)
     (32, 14, 5, 7, 1, "fp64", 1e-9),   # paper's corner set M_F = 7
     (16, 1, 1, 1, 1, "fp32", 1e-4),    # degenerate: one mode, one antenna each
+    (32, 9, 36, 36, 2, "fp32", 1e-4),  # the paper's 36 / 36 antennas: ragged 2nd incidence / receiver tiles
+    (16, 7, 64, 64, 1, "fp32", 1e-4),  # largest antenna counts of the FP32 path
+    (8, 5, 33, 17, 2, "fp32", 1e-4),   # ragged tiles on a grid smaller than one pixel sub-tile
 ]
 
 
