@@ -38,6 +38,116 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# kernel names in the library's timing order, and how they appear in profiler output
+KERNEL_SYMBOLS = {
+    "fwd_conv": "k_fwd_conv<float, 64, true>",
+    "pixel_reduce": "k_pixel_reduce_mfma<",
+    "image_reg": "k_image_reg<float>",
+    "adj_gemm": "k_adj_gemm_mfma<",
+    "adj_conv": "k_adj_conv<float, 64>",
+}
+CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")
+
+
+# the sources the step kernels and their launches are built from
+STEP_SOURCES = ("api.hip", "conv_kernels.h", "cplx.h", "fft_lds.h", "handle.h", "init_kernels.h",
+                "pixel_kernels.h")
+
+
+def kernel_source_hash():
+    """SHA-256 over the step kernels' sources: traffic counts are valid only for the code they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2602_13805_amd", "csrc")
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short_kernel(name):
+    for k, sym in KERNEL_SYMBOLS.items():
+        if sym in name:
+            return k
+    if CALIBRATION_SYMBOL in name:
+        return "calibration_copy"
+    return None
+
+
+def summarize_rocprof(dirs, kind, copy_mib):
+    """Text summary of rocprofv3 CSV output (kernel-trace stats, or FETCH_SIZE / WRITE_SIZE passes)."""
+    import csv
+    import glob
+    lines = []
+    if kind == "stats":
+        rows = []
+        for d in dirs:
+            for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+                with open(f) as fh:
+                    rows += list(csv.DictReader(fh))
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines.append("| kernel | calls | total ms | average us | min us | max us | % |")
+        lines.append("|---|---|---|---|---|---|---|")
+        for r in rows[:16]:
+            lines.append(f"| {r['Name'][:80]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                         f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                         f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+        return "\n".join(lines)
+    acc = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    k = _short_kernel(r["Kernel_Name"])
+                    if k is None:
+                        continue
+                    acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    cal = avg.get("calibration_copy", {})
+    if "FETCH_SIZE" not in cal or "WRITE_SIZE" not in cal:
+        raise SystemExit("the calibration copy kernel is missing from the counter output")
+    cbytes = copy_mib * 2 ** 20
+    f_scale = cbytes / (cal["FETCH_SIZE"] * 1024.0)
+    w_scale = cbytes / (cal["WRITE_SIZE"] * 1024.0)
+    lines.append(f"source_sha256: {kernel_source_hash()}")
+    lines.append(f"calibration_bytes: {cbytes}")
+    lines.append(f"calibration_fetch_kib: {cal['FETCH_SIZE']:.1f}")
+    lines.append(f"calibration_write_kib: {cal['WRITE_SIZE']:.1f}")
+    lines.append(f"fetch_scale: {f_scale:.4f}")
+    lines.append(f"write_scale: {w_scale:.4f}")
+    for k in KERNEL_SYMBOLS:
+        if k not in avg or "FETCH_SIZE" not in avg[k] or "WRITE_SIZE" not in avg[k]:
+            continue
+        fb = avg[k]["FETCH_SIZE"] * 1024.0 * f_scale
+        wb = avg[k]["WRITE_SIZE"] * 1024.0 * w_scale
+        lines.append(f"kernel {k} fetch_kib={avg[k]['FETCH_SIZE']:.1f} write_kib={avg[k]['WRITE_SIZE']:.1f} "
+                     f"bytes={fb + wb:.0f}")
+    return "\n".join(lines)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if taken on these sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    meta, per = {}, {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("kernel "):
+                parts = line.split()
+                per[parts[1]] = dict(kv.split("=") for kv in parts[2:])
+            elif ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                meta[k.strip()] = v.strip()
+    if meta.get("source_sha256") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    if kernel not in per:
+        return None, "kernel not in the counter summary"
+    return float(per[kernel]["bytes"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size"
+
+
 def workload_cost(wl, B, ntiles):
     """Algorithmic HBM bytes and flops per launch of each kernel (FP32, 8-byte complex).
 
@@ -68,22 +178,23 @@ def workload_cost(wl, B, ntiles):
 
 
 def synthesize_batch(pdf, si, wl, B, dev):
+    """Measured fields of B random instances: FP64 MoM on the fine grid with jittered antennas, plus noise."""
     import numpy as np
     Ni, Ns, M = wl.n_tx, wl.n_rx, wl.M
-    esca = np.zeros((B, Ni, Ns), np.complex128)
+    txs, rxs, eps_f = [], [], np.zeros((B, wl.M_fine, wl.M_fine), np.complex128)
     eps = np.zeros((B, M, M), np.complex128)
     for b in range(B):
         shapes = si.draw_profile(wl, b)
         jt, jr = si.draw_jitter(b, Ni, Ns, wl.jitter_deg)
-        txj = si.antenna_positions(Ni, wl.radius, angle_offsets=jt)
-        rxj = si.antenna_positions(Ns, wl.radius, angle_offsets=jr)
-        e = pdf.synthesize(wl.M_fine, wl.side, wl.freq_hz, txj, rxj, si.rasterize(shapes, wl.M_fine, wl.side),
-                           tol=1e-10, device=dev)
-        n1, n2 = si.draw_noise(b, e.shape)
-        esca[b] = si.add_noise(e, wl.noise, n1, n2)
+        txs.append(si.antenna_positions(Ni, wl.radius, angle_offsets=jt))
+        rxs.append(si.antenna_positions(Ns, wl.radius, angle_offsets=jr))
+        eps_f[b] = si.rasterize(shapes, wl.M_fine, wl.side)
         eps[b] = si.rasterize(shapes, M, wl.side)
-        if (b + 1) % 16 == 0:
-            log(f"  synthesised {b + 1}/{B}")
+    e = pdf.synthesize_batch(wl.M_fine, wl.side, wl.freq_hz, txs, rxs, eps_f, tol=1e-10, device=dev)
+    esca = np.zeros((B, Ni, Ns), np.complex128)
+    for b in range(B):
+        n1, n2 = si.draw_noise(b, e[b].shape)
+        esca[b] = si.add_noise(e[b], wl.noise, n1, n2)
     return esca, eps
 
 
@@ -124,7 +235,13 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the steps, as a "
                          "reference of known traffic for hardware byte counters")
+    ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
+                    help="print a summary of rocprofv3 CSV output in these directories and exit")
+    ap.add_argument("--summary-kind", choices=["stats", "pmc"], default="stats")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        print(summarize_rocprof(args.summarize_rocprof, args.summary_kind, args.copy_calibration_mib or 256))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: instances are independent, so N GPUs would each run their own "
               "batch with no communication; run with --gpus 1.", file=sys.stderr)
@@ -184,7 +301,7 @@ def main():
     else:
         roof = dict(bound="hbm", achieved=bytes_[dom] / dur / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"], roof["traffic_source"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["algorithmic_bytes"] = bytes_[dom]
     roof["algorithmic_flops"] = flops[dom]

@@ -183,6 +183,22 @@ int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
                    const pdf_array* rx, const double* eps_host, double tol,
                    double* esca_host, void* stream);
 
+/* pdf_synthesize for n instances on one fine grid and frequency, each with its
+ * own antenna positions (e.g. jittered), solved concurrently by `workers`
+ * host threads (0: 8; at most 16) on streams of their own.  Synchronous.
+ *   tx, rx: host arrays of n pdf_array each; every instance has the same
+ *     Ni = tx[0].n and Ns = rx[0].n.
+ *   eps_host: host complex128 [n][M][M]; esca_host: host complex128 [n][Ni][Ns].
+ *   coarse: 0, or a divisor d of M: then jc_host (host complex128
+ *     [n][Ni][M/d][M/d]) receives the induced currents chi E of the solution
+ *     averaged over d x d pixel blocks (the currents on a d-times coarser grid).
+ *   stream: used only for the shared tables (synchronised).
+ * Errors as pdf_synthesize; the message names the first failing instance. */
+int pdf_synthesize_batch(const pdf_grid* grid, double freq_hz, int32_t n, const pdf_array* tx,
+                         const pdf_array* rx, const double* eps_host, double tol,
+                         double* esca_host, int32_t coarse, double* jc_host, int32_t workers,
+                         void* stream);
+
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * each kernel of pdf_loss_grad / pdf_step (for benchmarks).  enable != 0
  * clears the record and starts recording up to max_steps iterations; 0 stops.

@@ -66,6 +66,8 @@ SIGNATURES = {
                                 ctypes.POINTER(Report)]),
     "pdf_synthesize": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array),
                                c_vp, c_f64, c_vp, c_vp]),
+    "pdf_synthesize_batch": (c_i32, [ctypes.POINTER(Grid), c_f64, c_i32, ctypes.POINTER(Array),
+                                     ctypes.POINTER(Array), c_vp, c_f64, c_vp, c_i32, c_vp, c_i32, c_vp]),
     "pdf_timing": (c_i32, [c_vp, c_i32, c_i32]),
     "pdf_timing_read": (c_i32, [c_vp, c_vp, c_vp]),
     "pdf_destroy": (None, [c_vp]),
@@ -150,6 +152,37 @@ def synthesize(M: int, side: float, freq_hz: float, tx, rx, eps: np.ndarray, tol
     _check(load().pdf_synthesize(ctypes.byref(g), freq_hz, ctypes.byref(ta), ctypes.byref(ra),
                                  eps.ctypes.data, tol, out.ctypes.data, ctypes.c_void_p(stream.cuda_stream)))
     return out
+
+
+def synthesize_batch(M: int, side: float, freq_hz: float, tx_list, rx_list, eps: np.ndarray, tol: float = 1e-10,
+                     coarse: int = 0, workers: int = 0, device: str = "cuda:0", cx: float = 0.0,
+                     cy: float = 0.0):
+    """FP64 MoM for n instances (each with its own antenna positions) solved concurrently.
+
+    eps: [n, M, M].  Returns E_sca [n, Ni, Ns], and with coarse = d > 0 also the
+    induced currents averaged over d x d blocks, [n, Ni, M/d, M/d]."""
+    g = Grid(M, side, cx, cy)
+    n = len(tx_list)
+    if len(rx_list) != n:
+        raise ValueError("one rx array per instance is required")
+    eps = np.ascontiguousarray(np.asarray(eps, dtype=np.complex128))
+    if eps.shape != (n, M, M):
+        raise ValueError("eps must be [n, M, M]")
+    keep = [_array(t) for t in tx_list] + [_array(r) for r in rx_list]
+    ta = (Array * max(n, 1))(*[k[0] for k in keep[:n]])
+    ra = (Array * max(n, 1))(*[k[0] for k in keep[n:]])
+    ni = len(tx_list[0]) if n else 0
+    ns = len(rx_list[0]) if n else 0
+    out = np.zeros((n, ni, ns), np.complex128)
+    mc = M // coarse if coarse > 0 else 0
+    jc = np.zeros((n, ni, mc, mc), np.complex128) if coarse > 0 else None
+    stream = torch.cuda.Stream(device)
+    torch.cuda.current_stream(device).synchronize()
+    _check(load().pdf_synthesize_batch(ctypes.byref(g), freq_hz, n, ta, ra, eps.ctypes.data, tol, out.ctypes.data,
+                                       coarse, jc.ctypes.data if jc is not None else None, workers,
+                                       ctypes.c_void_p(stream.cuda_stream)))
+    del keep
+    return (out, jc) if coarse > 0 else out
 
 
 class Solver:

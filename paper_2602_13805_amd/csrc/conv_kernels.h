@@ -129,17 +129,22 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
   const int bp = blockIdx.x;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
-  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
   const size_t off = size_t(bp) * C::N;
   cx<T> jr[C::PPT];
   if constexpr (FROM_ALPHA) {
+    // the coefficients (K^2 <= N) are loaded with the twiddles in one round trip
+    const int K = a.K, KK = K * K, kmin = -(K / 2);
+    const cx<T>* al = a.in + size_t(bp) * KK;
+    cx<T> av[C::PPT];
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) av[q] = al[min(tid + q * C::NT, KK - 1)];
+    for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
     for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
     __syncthreads();
-    const int K = a.K, kmin = -(K / 2);
-    const cx<T>* al = a.in + size_t(bp) * K * K;
-    for (int e = tid; e < K * K; e += C::NT) {
-      const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
-      buf[C::TileL::at(iy, ix)] = al[e];
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int e = tid + q * C::NT;
+      if (e < KK) buf[C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))] = av[q];
     }
     __syncthreads();
     typename C::ModeRows mr;
@@ -155,20 +160,30 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
     }
   } else {
 #pragma unroll
+    for (int q = 0; q < C::PPT; ++q) jr[q] = a.in[off + tid + q * C::NT];
+    for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
+#pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = a.in[off + n];
       buf[C::TileL::at(n / M, n % M)] = jr[q];
     }
     __syncthreads();
   }
   conv_core<T, M>(buf, tw, a.ghat, false);
+  // all loads of the epilogue are issued before their use (the workgroup
+  // fills its CU, so nothing else hides their latency)
+  cx<T> ei[C::PPT];
+  if (a.einc) {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) ei[q] = a.einc[size_t(p) * C::N + tid + q * C::NT];
+  } else {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) ei[q] = cx<T>{T(0), T(0)};
+  }
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    cx<T> e = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q];
-    if (a.einc) e = e + a.einc[size_t(p) * C::N + n];
-    a.E[off + n] = e;
+    a.E[off + n] = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
   }
 }
 
@@ -213,27 +228,52 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
   const int bp = blockIdx.x;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
-  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
   const size_t off = size_t(bp) * C::N;
   const size_t eoff = size_t(a.e_shared ? p : bp) * C::N;
   const size_t boff = size_t(b) * C::N;
   const T ws = T(2.0 / a.Ss[0]);
   const T wd = T(a.hsign * 2.0 / a.Sd[b]);
   const T beta = a.beta;
+  // all loads of the prologue are issued before their use (the workgroup
+  // fills its CU, so nothing else hides their latency); optional inputs are
+  // uniform branches around whole groups of loads
+  cx<T> Jv[C::PPT], Ev[C::PPT], Rv[C::PPT], Hv[C::PPT], Gv[C::PPT];
+  T Dv[C::PPT];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    Ev[q] = a.E[eoff + n];
+    Rv[q] = a.R[boff + n];
+    Hv[q] = a.h[off + n];
+  }
+  if (a.J) {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) Jv[q] = a.J[off + tid + q * C::NT];
+  } else {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) Jv[q] = cx<T>{T(0), T(0)};
+  }
+  const bool has_gr = a.gR != nullptr;
+  if (has_gr) {
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      Gv[q] = a.gR[boff + tid + q * C::NT];
+      Dv[q] = a.den[boff + tid + q * C::NT];
+    }
+  }
+  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
   cx<T> gj[C::PPT];
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    const cx<T> J = a.J ? a.J[off + n] : cx<T>{T(0), T(0)};
-    const cx<T> E = a.E[eoff + n];
-    const cx<T> R = a.R[boff + n];
+    const cx<T> J = Jv[q], E = Ev[q], R = Rv[q];
     const cx<T> s = R * E - beta * J;
     const cx<T> gs = ws * s;
     cx<T> gE = cmul_conj_a(R, gs);
-    cx<T> gJ = (-beta) * gs + wd * a.h[off + n];
-    if (a.gR) {
-      const cx<T> g = a.gR[boff + n];
-      const T inv = T(1) / a.den[boff + n];
+    cx<T> gJ = (-beta) * gs + wd * Hv[q];
+    if (has_gr) {
+      const cx<T> g = Gv[q];
+      const T inv = T(1) / Dv[q];
       const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
       gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
       gJ = gJ + (beta * inv) * (g * E);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <complex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pdf.h"
@@ -135,62 +136,61 @@ __global__ __launch_bounds__(256) void k_scatter_out(const cx<double>* gsS, cons
   if (threadIdx.x == 0) out[blockIdx.x] = cx<double>{sr, si};
 }
 
+// Device allocations of one solve, stream-ordered so that concurrent solves
+// on other streams are not serialised by allocation or release.
 struct Dev {
+  hipStream_t st;
   std::vector<void*> ptrs;
+  explicit Dev(hipStream_t s) : st(s) {}
   ~Dev() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)hipFreeAsync(p, st);
   }
   template <typename T>
   hipError_t alloc(T** p, size_t bytes) {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), bytes, st);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;
   }
 };
 
-}  // namespace
+// What every solve of one grid and frequency shares.
+struct Shared {
+  int M = 0;
+  double side = 0, gx = 0, gy = 0, k0 = 0, h = 0;  // grid side and centre
+  cd cell;
+  std::vector<cd> ker;               // offset kernel [(2M-1)^2]
+  const cx<double>* dker = nullptr;  // its device copy
+};
 
-#define MOM_TRY(call)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (call);                                                        \
-    if (e_ != hipSuccess) {                                                        \
-      pdf_set_global_error(std::string(#call) + ": " + hipGetErrorString(e_));     \
-      return PDF_EHIP;                                                             \
-    }                                                                              \
+#define MOM_TRY(call)                                                  \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) {                                            \
+      *err = std::string(#call) + ": " + hipGetErrorString(e_);        \
+      return PDF_EHIP;                                                 \
+    }                                                                  \
   } while (0)
 
-extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_array* tx, const pdf_array* rx,
-                              const double* eps_host, double tol, double* esca_host, void* stream_v) {
-  if (!grid || !tx || !rx || !tx->xy || !rx->xy || !eps_host || !esca_host || !stream_v) {
-    pdf_set_global_error("null argument");
-    return PDF_EINVAL;
-  }
-  if (grid->M < 1 || !(grid->side > 0) || !(freq_hz > 0) || tx->n < 1 || rx->n < 1 || !(tol > 0)) {
-    pdf_set_global_error("invalid sizes");
-    return PDF_EINVAL;
-  }
-  hipStream_t st = (hipStream_t)stream_v;
-  const int M = grid->M, N = M * M, ni = tx->n, ns = rx->n;
-  const cd* eps = reinterpret_cast<const cd*>(eps_host);
+// One solve: E_sca [Ni][Ns] into out; with d > 0 also the induced currents
+// chi E averaged over d x d pixel blocks, [Ni][M/d][M/d], into jc.
+int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const cd* eps, double tol, cd* out,
+              int d, cd* jc, hipStream_t st, int host_threads, std::string* err) {
+  const int M = sh.M, N = M * M, ni = tx->n, ns = rx->n;
   std::vector<int> S;
   for (int n = 0; n < N; ++n)
     if (eps[n] != cd(1.0, 0.0)) S.push_back(n);
-  cd* out = reinterpret_cast<cd*>(esca_host);
   const int nS = int(S.size());
+  const int Mc = d > 0 ? M / d : 0;
+  if (jc) std::fill(jc, jc + size_t(ni) * Mc * Mc, cd(0.0));
   if (nS == 0) {
     for (int i = 0; i < ni * ns; ++i) out[i] = 0.0;
     return PDF_OK;
   }
   if (nS > 20000) {
-    pdf_set_global_error("support larger than 20000 pixels");
+    *err = "support larger than 20000 pixels";
     return PDF_EUNSUPPORTED;
   }
-  const double k0 = 2.0 * M_PI * freq_hz / 299792458.0;
-  const double h = grid->side / M;
-  const double a = h / std::sqrt(M_PI);
-  const cd cell = cd(0.0, M_PI * k0 * a / 2.0) * std::cyl_bessel_j(1.0, k0 * a);
-  std::vector<cd> ker;
-  pdfh::offset_kernel(M, h, k0, &ker);
+  const double k0 = sh.k0, h = sh.h;
   std::vector<int> si(nS), sj(nS);
   std::vector<cd> chi(nS), einc(size_t(ni) * nS), gsS(size_t(ns) * nS);
   std::vector<double> xs(nS), ys(nS);
@@ -198,45 +198,43 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
     si[c] = S[c] / M;
     sj[c] = S[c] % M;
     chi[c] = eps[S[c]] - 1.0;
-    xs[c] = grid->cx - grid->side / 2.0 + (sj[c] + 0.5) * h;
-    ys[c] = grid->cy - grid->side / 2.0 + (si[c] + 0.5) * h;
+    xs[c] = sh.gx - sh.side / 2.0 + (sj[c] + 0.5) * h;
+    ys[c] = sh.gy - sh.side / 2.0 + (si[c] + 0.5) * h;
   }
   // incident fields and receiver operator on the support only
-  pdfh::parallel_for(ni + ns, [&](int b0, int b1) {
+  pdfh::parallel_for(ni + ns, host_threads, [&](int b0, int b1) {
     for (int r = b0; r < b1; ++r) {
       const bool is_tx = r < ni;
       const double* xy = is_tx ? tx->xy + 2 * r : rx->xy + 2 * (r - ni);
-      cd scale = cell;
-      if (is_tx) scale = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(xy[0] - grid->cx, xy[1] - grid->cy)));
+      cd scale = sh.cell;
+      if (is_tx) scale = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(xy[0] - sh.gx, xy[1] - sh.gy)));
       cd* dst = is_tx ? &einc[size_t(r) * nS] : &gsS[size_t(r - ni) * nS];
       for (int c = 0; c < nS; ++c) dst[c] = scale * pdfh::hankel1(0, k0 * std::hypot(xy[0] - xs[c], xy[1] - ys[c]));
     }
   });
 
-  Dev d;
-  cx<double> *dA, *dker, *dchi, *db, *dgs, *x, *r, *rh, *p, *v, *s, *tt, *dots, *sc1, *sc2, *dout;
+  Dev dv(st);
+  cx<double> *dA, *dchi, *db, *dgs, *x, *r, *rh, *p, *v, *s, *tt, *dots, *sc1, *sc2, *dout;
   int *dsi, *dsj;
   const size_t vb = sizeof(cx<double>) * size_t(ni) * nS;
-  MOM_TRY(d.alloc(&dA, sizeof(cx<double>) * size_t(nS) * nS));
-  MOM_TRY(d.alloc(&dker, sizeof(cx<double>) * ker.size()));
-  MOM_TRY(d.alloc(&dchi, sizeof(cx<double>) * nS));
-  MOM_TRY(d.alloc(&dsi, sizeof(int) * nS));
-  MOM_TRY(d.alloc(&dsj, sizeof(int) * nS));
-  MOM_TRY(d.alloc(&db, vb));
-  MOM_TRY(d.alloc(&dgs, sizeof(cx<double>) * gsS.size()));
-  for (auto** q : {&x, &r, &rh, &p, &v, &s, &tt}) MOM_TRY(d.alloc(q, vb));
-  MOM_TRY(d.alloc(&dots, sizeof(cx<double>) * ni * 3));
-  MOM_TRY(d.alloc(&sc1, sizeof(cx<double>) * ni));
-  MOM_TRY(d.alloc(&sc2, sizeof(cx<double>) * ni));
-  MOM_TRY(d.alloc(&dout, sizeof(cx<double>) * ni * ns));
-  MOM_TRY(hipMemcpyAsync(dker, ker.data(), sizeof(cd) * ker.size(), hipMemcpyHostToDevice, st));
+  MOM_TRY(dv.alloc(&dA, sizeof(cx<double>) * size_t(nS) * nS));
+  MOM_TRY(dv.alloc(&dchi, sizeof(cx<double>) * nS));
+  MOM_TRY(dv.alloc(&dsi, sizeof(int) * nS));
+  MOM_TRY(dv.alloc(&dsj, sizeof(int) * nS));
+  MOM_TRY(dv.alloc(&db, vb));
+  MOM_TRY(dv.alloc(&dgs, sizeof(cx<double>) * gsS.size()));
+  for (auto** q : {&x, &r, &rh, &p, &v, &s, &tt}) MOM_TRY(dv.alloc(q, vb));
+  MOM_TRY(dv.alloc(&dots, sizeof(cx<double>) * ni * 3));
+  MOM_TRY(dv.alloc(&sc1, sizeof(cx<double>) * ni));
+  MOM_TRY(dv.alloc(&sc2, sizeof(cx<double>) * ni));
+  MOM_TRY(dv.alloc(&dout, sizeof(cx<double>) * ni * ns));
   MOM_TRY(hipMemcpyAsync(dchi, chi.data(), sizeof(cd) * nS, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(dsi, si.data(), sizeof(int) * nS, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(dsj, sj.data(), sizeof(int) * nS, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(db, einc.data(), vb, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(dgs, gsS.data(), sizeof(cd) * gsS.size(), hipMemcpyHostToDevice, st));
   const size_t nA = size_t(nS) * nS;
-  hipLaunchKernelGGL(k_mom_build, dim3((nA + 255) / 256), dim3(256), 0, st, dA, dker, dsi, dsj, dchi, nS, M);
+  hipLaunchKernelGGL(k_mom_build, dim3((nA + 255) / 256), dim3(256), 0, st, dA, sh.dker, dsi, dsj, dchi, nS, M);
   MOM_TRY(hipGetLastError());
 
   // split the inner dimension so that about a thousand workgroups run
@@ -249,14 +247,14 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
   const size_t nv = size_t(ni) * nS;
   const dim3 vgrid((nv + 255) / 256);
   cx<double>* dpart;
-  MOM_TRY(d.alloc(&dpart, sizeof(cx<double>) * nv * nsplit));
+  MOM_TRY(dv.alloc(&dpart, sizeof(cx<double>) * nv * nsplit));
   auto matvec = [&](const cx<double>* in, cx<double>* o) {
     hipLaunchKernelGGL(k_zgemm, ggrid, dim3(256), 0, st, dA, in, dpart, nS, ni, kslice);
     hipLaunchKernelGGL(k_zsum, vgrid, dim3(256), 0, st, dpart, o, nv, nsplit);
   };
-  auto dot = [&](const cx<double>* a, const cx<double>* b, int slot, std::vector<cd>& h) -> hipError_t {
+  auto dot = [&](const cx<double>* a, const cx<double>* b, int slot, std::vector<cd>& hv) -> hipError_t {
     hipLaunchKernelGGL(k_zdot, dim3(ni), dim3(256), 0, st, a, b, dots + slot * ni, nS);
-    hipError_t e = hipMemcpyAsync(h.data(), dots + slot * ni, sizeof(cd) * ni, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(hv.data(), dots + slot * ni, sizeof(cd) * ni, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
   };
@@ -271,7 +269,7 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
     hipLaunchKernelGGL(k_zaxpy2, vgrid, dim3(256), 0, st, z, a, b, sc1, w, sc2, nS, ni);
     return hipGetLastError();
   };
-  std::vector<cd> one(ni, 1.0), mone(ni, -1.0), bnorm(ni), rho(ni), rho_old(ni, 1.0), alpha(ni, 1.0),
+  std::vector<cd> mone(ni, -1.0), bnorm(ni), rho(ni), rho_old(ni, 1.0), alpha(ni, 1.0),
       omega(ni, 1.0), tmp(ni), tmp2(ni), beta(ni), nalpha(ni), nomega(ni);
   std::vector<bool> conv(ni, false);
   // x0 = E_inc, r0 = b - A x0, r_hat = r0
@@ -322,17 +320,147 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
     if (all) break;
     for (int q = 0; q < ni; ++q)
       if (!conv[q] && std::abs(omega[q]) == 0.0) {
-        pdf_set_global_error("BiCGSTAB breakdown");
+        *err = "BiCGSTAB breakdown";
         return PDF_ENONFINITE;
       }
   }
   if (it >= max_it) {
-    pdf_set_global_error("BiCGSTAB did not converge, residual " + std::to_string(worst));
+    *err = "BiCGSTAB did not converge, residual " + std::to_string(worst);
     return PDF_ENONFINITE;
   }
   hipLaunchKernelGGL(k_scatter_out, dim3(ni * ns), dim3(256), 0, st, dgs, dchi, x, dout, nS, ns);
   MOM_TRY(hipGetLastError());
   MOM_TRY(hipMemcpyAsync(out, dout, sizeof(cd) * ni * ns, hipMemcpyDeviceToHost, st));
+  std::vector<cd> xh;
+  if (jc) {
+    xh.resize(size_t(ni) * nS);
+    MOM_TRY(hipMemcpyAsync(xh.data(), x, vb, hipMemcpyDeviceToHost, st));
+  }
   MOM_TRY(hipStreamSynchronize(st));
+  if (jc) {
+    // induced current chi E per fine pixel, averaged over each d x d block
+    const double w = 1.0 / (double(d) * d);
+    for (int q = 0; q < ni; ++q)
+      for (int c = 0; c < nS; ++c)
+        jc[(size_t(q) * Mc + si[c] / d) * Mc + sj[c] / d] += w * chi[c] * xh[size_t(q) * nS + c];
+  }
+  return PDF_OK;
+}
+
+int check_args(const pdf_grid* grid, double freq_hz, double tol) {
+  if (grid->M < 1 || !(grid->side > 0) || !(freq_hz > 0) || !(tol > 0)) {
+    pdf_set_global_error("invalid sizes");
+    return PDF_EINVAL;
+  }
+  return PDF_OK;
+}
+
+// Host offset kernel and its device copy (uploaded on st, which is synchronised).
+int make_shared(const pdf_grid* grid, double freq_hz, hipStream_t st, Shared* sh, cx<double>** dker,
+                std::string* err) {
+  sh->M = grid->M;
+  sh->side = grid->side;
+  sh->gx = grid->cx;
+  sh->gy = grid->cy;
+  sh->k0 = 2.0 * M_PI * freq_hz / 299792458.0;
+  sh->h = grid->side / grid->M;
+  const double a = sh->h / std::sqrt(M_PI);
+  sh->cell = cd(0.0, M_PI * sh->k0 * a / 2.0) * std::cyl_bessel_j(1.0, sh->k0 * a);
+  pdfh::offset_kernel(sh->M, sh->h, sh->k0, &sh->ker);
+  MOM_TRY(hipMalloc(reinterpret_cast<void**>(dker), sizeof(cx<double>) * sh->ker.size()));
+  MOM_TRY(hipMemcpyAsync(*dker, sh->ker.data(), sizeof(cd) * sh->ker.size(), hipMemcpyHostToDevice, st));
+  MOM_TRY(hipStreamSynchronize(st));
+  sh->dker = *dker;
+  return PDF_OK;
+}
+
+}  // namespace
+
+extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_array* tx, const pdf_array* rx,
+                              const double* eps_host, double tol, double* esca_host, void* stream_v) {
+  if (!grid || !tx || !rx || !tx->xy || !rx->xy || !eps_host || !esca_host || !stream_v) {
+    pdf_set_global_error("null argument");
+    return PDF_EINVAL;
+  }
+  if (int rc = check_args(grid, freq_hz, tol)) return rc;
+  if (tx->n < 1 || rx->n < 1) {
+    pdf_set_global_error("invalid sizes");
+    return PDF_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream_v;
+  Shared sh;
+  cx<double>* dker = nullptr;
+  std::string err;
+  int rc = make_shared(grid, freq_hz, st, &sh, &dker, &err);
+  if (rc == PDF_OK)
+    rc = solve_one(sh, tx, rx, reinterpret_cast<const cd*>(eps_host), tol, reinterpret_cast<cd*>(esca_host), 0,
+                   nullptr, st, 16, &err);
+  if (dker) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(dker);
+  }
+  if (rc) pdf_set_global_error(err);
+  return rc;
+}
+
+extern "C" int pdf_synthesize_batch(const pdf_grid* grid, double freq_hz, int32_t n, const pdf_array* tx,
+                                    const pdf_array* rx, const double* eps_host, double tol, double* esca_host,
+                                    int32_t coarse, double* jc_host, int32_t workers, void* stream_v) {
+  if (!grid || !tx || !rx || !eps_host || !esca_host || !stream_v || (coarse > 0 && !jc_host)) {
+    pdf_set_global_error("null argument");
+    return PDF_EINVAL;
+  }
+  if (int rc = check_args(grid, freq_hz, tol)) return rc;
+  if (n < 0 || coarse < 0 || (coarse > 0 && grid->M % coarse != 0)) {
+    pdf_set_global_error("invalid sizes (coarse must divide M)");
+    return PDF_EINVAL;
+  }
+  if (n == 0) return PDF_OK;
+  const int ni = tx[0].n, ns = rx[0].n;
+  for (int i = 0; i < n; ++i)
+    if (tx[i].n != ni || rx[i].n != ns || ni < 1 || ns < 1 || !tx[i].xy || !rx[i].xy) {
+      pdf_set_global_error("every instance needs the same, nonzero antenna counts");
+      return PDF_EINVAL;
+    }
+  hipStream_t st0 = (hipStream_t)stream_v;
+  Shared sh;
+  cx<double>* dker = nullptr;
+  std::string err0;
+  if (int rc = make_shared(grid, freq_hz, st0, &sh, &dker, &err0)) {
+    pdf_set_global_error(err0);
+    return rc;
+  }
+  const int W = std::max(1, std::min({int(workers > 0 ? workers : 8), int(n), 16}));
+  const int host_threads = std::max(1, 16 / W);
+  const size_t N = size_t(grid->M) * grid->M;
+  const int Mc = coarse > 0 ? grid->M / coarse : 0;
+  std::vector<int> rcs(W, PDF_OK);
+  std::vector<std::string> errs(W);
+  std::vector<std::thread> th;
+  for (int w = 0; w < W; ++w)
+    th.emplace_back([&, w]() {
+      hipStream_t st;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        rcs[w] = PDF_EHIP;
+        errs[w] = "hipStreamCreateWithFlags failed";
+        return;
+      }
+      for (int i = w; i < n && rcs[w] == PDF_OK; i += W) {
+        rcs[w] = solve_one(sh, &tx[i], &rx[i], reinterpret_cast<const cd*>(eps_host) + size_t(i) * N, tol,
+                           reinterpret_cast<cd*>(esca_host) + size_t(i) * ni * ns, coarse,
+                           coarse > 0 ? reinterpret_cast<cd*>(jc_host) + size_t(i) * ni * Mc * Mc : nullptr,
+                           st, host_threads, &errs[w]);
+        if (rcs[w]) errs[w] = "instance " + std::to_string(i) + ": " + errs[w];
+      }
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    });
+  for (auto& t : th) t.join();
+  (void)hipFree(dker);
+  for (int w = 0; w < W; ++w)
+    if (rcs[w]) {
+      pdf_set_global_error(errs[w]);
+      return rcs[w];
+    }
   return PDF_OK;
 }

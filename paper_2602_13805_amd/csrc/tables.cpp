@@ -24,9 +24,11 @@ using cd = std::complex<double>;
 
 cd hankel1(int n, double x) { return cd(std::cyl_bessel_j(double(n), x), std::cyl_neumann(double(n), x)); }
 
-void parallel_for(int n, const std::function<void(int, int)>& fn) {
+void parallel_for(int n, const std::function<void(int, int)>& fn) { parallel_for(n, 16, fn); }
+
+void parallel_for(int n, int max_threads, const std::function<void(int, int)>& fn) {
   int nt = int(std::thread::hardware_concurrency());
-  nt = std::max(1, std::min(nt, 16));
+  nt = std::max(1, std::min(nt, std::min(16, max_threads)));
   nt = std::min(nt, std::max(1, n / 64));
   if (nt <= 1) {
     fn(0, n);

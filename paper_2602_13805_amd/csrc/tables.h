@@ -29,6 +29,8 @@ int build_tables(const Geometry& g, Tables* t, std::string* err);
 std::complex<double> hankel1(int n, double x);
 // Runs fn(begin, end) over [0, n) split across host threads.
 void parallel_for(int n, const std::function<void(int, int)>& fn);
+// The same with at most max_threads threads (at most 16 in any case).
+void parallel_for(int n, int max_threads, const std::function<void(int, int)>& fn);
 void offset_kernel(int M, double h, double k0, std::vector<std::complex<double>>* ker);
 
 }  // namespace pdfh

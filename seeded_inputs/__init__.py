@@ -199,12 +199,20 @@ def rasterize(shapes: Sequence[Shape], M: int, side: float, cx: float = 0.0,
     base = -side / 2.0 + np.arange(M) * h
     xs = (cx + base[:, None] + off[None, :]).reshape(-1)   # M*sub
     ys = (cy + base[:, None] + off[None, :]).reshape(-1)
-    X, Y = np.meshgrid(xs, ys)                              # [M*sub, M*sub], Y rows
     eps = np.ones((M, M), dtype=np.complex128)
     for s in shapes:
+        # only the pixels of the shape's bounding square (plus one) can hold a sample inside it
+        r = s.bound_radius
+        j0 = max(0, int(math.floor((s.cx - r - cx + side / 2.0) / h)) - 1)
+        j1 = min(M, int(math.ceil((s.cx + r - cx + side / 2.0) / h)) + 1)
+        i0 = max(0, int(math.floor((s.cy - r - cy + side / 2.0) / h)) - 1)
+        i1 = min(M, int(math.ceil((s.cy + r - cy + side / 2.0) / h)) + 1)
+        if i0 >= i1 or j0 >= j1:
+            continue
+        X, Y = np.meshgrid(xs[j0 * sub:j1 * sub], ys[i0 * sub:i1 * sub])
         inside = s.contains(X, Y).astype(np.float64)
-        frac = inside.reshape(M, sub, M, sub).mean(axis=(1, 3))
-        eps += (s.eps_r - 1.0) * frac
+        frac = inside.reshape(i1 - i0, sub, j1 - j0, sub).mean(axis=(1, 3))
+        eps[i0:i1, j0:j1] += (s.eps_r - 1.0) * frac
     return eps
 
 

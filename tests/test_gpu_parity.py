@@ -249,6 +249,33 @@ def test_synthesize_matches_oracle_mom():
     assert np.all(z == 0)
 
 
+def test_synthesize_batch_matches_single_and_oracle_currents():
+    wl = si.WORKLOADS["cfg1"]
+    n, Ni, Ns, M = 5, 8, 12, 32
+    txs, rxs, eps = [], [], np.zeros((n, M, M), np.complex128)
+    for b in range(n):
+        jt, jr = si.draw_jitter(b, Ni, Ns, 2.0)
+        txs.append(si.antenna_positions(Ni, 3 * wl.wavelength, angle_offsets=jt))
+        rxs.append(si.antenna_positions(Ns, 3 * wl.wavelength, angle_offsets=jr))
+        eps[b] = si.rasterize(si.draw_profile(wl, b), M, wl.side)
+    eps[3] = 1.0  # an empty instance in the middle of the batch
+    print(f"synthesize_batch n={n} M={M}", flush=True)
+    es, jc = pdf.synthesize_batch(M, wl.side, wl.freq_hz, txs, rxs, eps, tol=1e-11, coarse=2, workers=3,
+                                  device=DEV)
+    assert jc.shape == (n, Ni, M // 2, M // 2)
+    k0 = ops.wavenumber(wl.freq_hz)
+    for b in range(n):
+        one = pdf.synthesize(M, wl.side, wl.freq_hz, txs[b], rxs[b], eps[b], tol=1e-11, device=DEV)
+        assert np.array_equal(one, es[b]), b          # same solve, whichever thread ran it
+        ref, etot = forward.mom_solve(eps[b], wl.side, k0, txs[b], rxs[b])
+        if b == 3:
+            assert np.all(es[b] == 0) and np.all(jc[b] == 0)
+            continue
+        assert rel(es[b], ref) < 1e-9, (b, rel(es[b], ref))
+        jref = ((eps[b].reshape(-1) - 1.0)[None, :] * etot).reshape(Ni, M // 2, 2, M // 2, 2).mean(axis=(2, 4))
+        assert rel(jc[b], jref) < 1e-9, (b, rel(jc[b], jref))
+
+
 def test_error_paths_on_device():
     case = make_case(16, 7, 4, 6, seeds=(0,))
     wl = case["wl"]
