@@ -199,6 +199,66 @@ int pdf_synthesize_batch(const pdf_grid* grid, double freq_hz, int32_t n, const 
                          double* esca_host, int32_t coarse, double* jc_host, int32_t workers,
                          void* stream);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network: an addition to the method (the paper has none).  A
+ * fully connected network with exact GELU between its affine layers predicts
+ * the start coefficients alpha_0 from the measured fields; it is trained on
+ * pairs made by the FP64 MoM (pdf_synthesize_batch with coarse currents, then
+ * pdf_analyze).  GEMM operands are bfloat16 (round to nearest even), with FP32
+ * accumulation, biases, pre-activations, gradients, master weights and Adam
+ * state (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ *   Layer l (0 <= l < n_layers): z = h W_l^T + b_l with W_l FP32 [sizes[l+1]][sizes[l]]
+ *   row-major, h_0 = s_in * x, h_{l+1} = gelu(z) for hidden layers, output
+ *   y = s_out * z of the last layer.  All device arrays are row-major FP32.
+ * The handle owns its buffers (sized for batch_max rows) and uses `stream`;
+ * calls are asynchronous on it unless stated.  Errors: PDF_EINVAL, PDF_ENOMEM,
+ * PDF_EHIP; the message is in pdf_last_error(NULL). */
+typedef struct pdf_mlp pdf_mlp;
+
+/* sizes: n_layers + 1 widths (input, hidden..., output).  Weights start at 0:
+ * set every layer with pdf_mlp_set_layer.  Synchronous. */
+int pdf_mlp_create(int32_t n_layers, const int32_t* sizes, int32_t batch_max, void* stream,
+                   pdf_mlp** out);
+/* Host FP32 weights and bias of layer l in; resets that layer's Adam state and
+ * the step count.  Synchronous. */
+int pdf_mlp_set_layer(pdf_mlp* net, int32_t l, const float* W_host, const float* b_host);
+/* Layer l out to host FP32: what = 0 weights and bias, 1 their gradients from
+ * the last pdf_mlp_train_step.  Synchronous. */
+int pdf_mlp_get_layer(pdf_mlp* net, int32_t l, int32_t what, float* W_host, float* b_host);
+/* y_dev [B][n_out] = s_out * net(s_in * x_dev [B][n_in]), 1 <= B <= batch_max. */
+int pdf_mlp_forward(pdf_mlp* net, const float* x_dev, float s_in, float s_out, int32_t B,
+                    float* y_dev);
+/* One Adam step on the mean squared error over the B rows idx_dev[0..B) (device
+ * int32, or NULL for rows 0..B) of x_dev [n_rows][n_in] against t_dev
+ * [n_rows][n_out] (targets in the network's output units, i.e. before s_out).
+ * Indices outside [0, n_rows) are clamped into it (callers should not pass
+ * them).  loss_dev: device double, the batch MSE before the step (may be NULL). */
+int pdf_mlp_train_step(pdf_mlp* net, const float* x_dev, const float* t_dev, int32_t n_rows,
+                       const int32_t* idx_dev, float s_in, int32_t B, double lr,
+                       double* loss_dev);
+int pdf_mlp_widths(const pdf_mlp* net, int32_t* n_in, int32_t* n_out, int32_t* batch_max);
+void pdf_mlp_destroy(pdf_mlp* net);
+
+/* Start values of every instance of h (FP32 handles): the back-propagation
+ * start of pdf_init_alpha (Sec. 3.1) and the network's prediction
+ * s_out * net(s_in * E_sca) are both evaluated with the physics loss, and each
+ * instance keeps the one with the lower total loss (so the network can only
+ * replace a worse start).  The network maps the handle's E_sca [Ni][Ns]
+ * (interleaved Re, Im: n_in = 2 Ni Ns) to alpha [Ni][K][K] (n_out = 2 Ni K^2).
+ *   alpha_dev: [B][Ni][K][K] out.  chosen_dev: device int32 [B] out, 1 where
+ *   the network's start was kept (may be NULL).  loss_dev: device double
+ *   [B][2] out, total loss of the two starts (back-propagation, network), may
+ *   be NULL.  Requires pdf_set_data. */
+int pdf_warm_start(pdf_handle* h, pdf_mlp* net, float s_in, float s_out, void* alpha_dev,
+                   int32_t* chosen_dev, double* loss_dev);
+
+/* Kept Fourier coefficients of pixel currents (Sec. 2.3, Eq. 9): for n sets
+ * of Ni currents J [n][Ni][M][M] on the handle's grid, alpha = F_T(J)
+ * [n][Ni][K][K] with F_T the forward DFT divided by M^2 (so that the synthesis
+ * F_T^* of alpha is the band-limited J).  Any n >= 1, independent of the
+ * handle's batch. */
+int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev);
+
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * each kernel of pdf_loss_grad / pdf_step (for benchmarks).  enable != 0
  * clears the record and starts recording up to max_steps iterations; 0 stops.

@@ -68,6 +68,15 @@ SIGNATURES = {
                                c_vp, c_f64, c_vp, c_vp]),
     "pdf_synthesize_batch": (c_i32, [ctypes.POINTER(Grid), c_f64, c_i32, ctypes.POINTER(Array),
                                      ctypes.POINTER(Array), c_vp, c_f64, c_vp, c_i32, c_vp, c_i32, c_vp]),
+    "pdf_mlp_create": (c_i32, [c_i32, c_vp, c_i32, c_vp, ctypes.POINTER(c_vp)]),
+    "pdf_mlp_set_layer": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "pdf_mlp_get_layer": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp]),
+    "pdf_mlp_forward": (c_i32, [c_vp, c_vp, ctypes.c_float, ctypes.c_float, c_i32, c_vp]),
+    "pdf_mlp_train_step": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, ctypes.c_float, c_i32, c_f64, c_vp]),
+    "pdf_mlp_widths": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "pdf_mlp_destroy": (None, [c_vp]),
+    "pdf_warm_start": (c_i32, [c_vp, c_vp, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp]),
+    "pdf_analyze": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "pdf_timing": (c_i32, [c_vp, c_i32, c_i32]),
     "pdf_timing_read": (c_i32, [c_vp, c_vp, c_vp]),
     "pdf_destroy": (None, [c_vp]),
@@ -273,6 +282,26 @@ class Solver:
         self._call(load().pdf_init_alpha, _ptr(a))
         return a
 
+    def warm_start(self, net: "Mlp", s_in: float, s_out: float):
+        """Start values: the network's prediction where its loss beats the back-propagation start.
+
+        Returns alpha [B, Ni, K, K], chosen [B] int32 (1 = network) and the two
+        starts' total losses [B, 2] (back-propagation, network)."""
+        a = self.zeros_alpha()
+        chosen = torch.zeros(self.B, dtype=torch.int32, device=self.device)
+        losses = torch.zeros((self.B, 2), dtype=torch.float64, device=self.device)
+        self._call(load().pdf_warm_start, net.h, ctypes.c_float(s_in), ctypes.c_float(s_out), _ptr(a),
+                   _ptr(chosen), _ptr(losses))
+        return a, chosen, losses
+
+    def analyze(self, J: torch.Tensor):
+        """Kept Fourier coefficients F_T(J) [n, Ni, K, K] of pixel currents J [n, Ni, M, M]."""
+        n = J.shape[0]
+        J = self._want(J, (n, self.Ni, self.M, self.M), self.cdtype, "J")
+        a = torch.empty((n, self.Ni, self.K, self.K), dtype=self.cdtype, device=self.device)
+        self._call(load().pdf_analyze, n, _ptr(J), _ptr(a))
+        return a
+
     def image(self, alpha, eps_true: Optional[torch.Tensor] = None):
         alpha = self._want(alpha, self.alpha_shape, self.cdtype, "alpha")
         chi = torch.empty((self.B, self.M, self.M), dtype=self.cdtype, device=self.device)
@@ -321,6 +350,110 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             load().pdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """Warm-start network on one GPU: affine layers of the given widths with GELU between them.
+
+    Weights start at zero; call init_weights or set_layer before use."""
+
+    def __init__(self, sizes, batch_max: int, device: str = "cuda:0"):
+        self.device = torch.device(device)
+        self.sizes = [int(x) for x in sizes]
+        self.L = len(self.sizes) - 1
+        self.batch_max = int(batch_max)
+        self.stream = torch.cuda.Stream(self.device)
+        arr = (c_i32 * len(self.sizes))(*self.sizes)
+        h = c_vp()
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(load().pdf_mlp_create(self.L, arr, self.batch_max, c_vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def init_weights(self, seed: int):
+        """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases from a seeded PCG64 stream."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        for l in range(self.L):
+            bound = 1.0 / np.sqrt(self.sizes[l])
+            W = rng.uniform(-bound, bound, size=(self.sizes[l + 1], self.sizes[l])).astype(np.float32)
+            b = rng.uniform(-bound, bound, size=self.sizes[l + 1]).astype(np.float32)
+            self.set_layer(l, W, b)
+
+    def set_layer(self, l: int, W: np.ndarray, b: np.ndarray):
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        if W.shape != (self.sizes[l + 1], self.sizes[l]) or b.shape != (self.sizes[l + 1],):
+            raise ValueError(f"layer {l}: expected W {(self.sizes[l + 1], self.sizes[l])} and b {(self.sizes[l + 1],)}")
+        self._enter()
+        _check(load().pdf_mlp_set_layer(self.h, l, W.ctypes.data, b.ctypes.data))
+
+    def get_layer(self, l: int, grad: bool = False):
+        W = np.zeros((self.sizes[l + 1], self.sizes[l]), np.float32)
+        b = np.zeros(self.sizes[l + 1], np.float32)
+        self._enter()
+        _check(load().pdf_mlp_get_layer(self.h, l, 1 if grad else 0, W.ctypes.data, b.ctypes.data))
+        return W, b
+
+    def _rows(self, x, n, name):
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float32 and x.device == self.device
+                and x.dim() == 2 and x.shape[1] == n):
+            raise ValueError(f"{name}: expected float32 [rows, {n}] on {self.device}")
+        return x.contiguous()
+
+    def forward(self, x: torch.Tensor, s_in: float = 1.0, s_out: float = 1.0):
+        x = self._rows(x, self.sizes[0], "x")
+        B = x.shape[0]
+        if not 1 <= B <= self.batch_max:
+            raise ValueError(f"batch {B} outside 1..{self.batch_max}")
+        y = torch.empty((B, self.sizes[-1]), dtype=torch.float32, device=self.device)
+        self._enter()
+        rc = load().pdf_mlp_forward(self.h, _ptr(x), ctypes.c_float(s_in), ctypes.c_float(s_out), B, _ptr(y))
+        self._leave()
+        _check(rc)
+        return y
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, idx: Optional[torch.Tensor], s_in: float, lr: float,
+                   loss: Optional[torch.Tensor] = None):
+        """One Adam step on the MSE over rows idx of (x, t) (all rows if idx is None)."""
+        x = self._rows(x, self.sizes[0], "x")
+        t = self._rows(t, self.sizes[-1], "t")
+        if t.shape[0] != x.shape[0]:
+            raise ValueError("x and t need the same number of rows")
+        if idx is not None:
+            if idx.dtype != torch.int32 or idx.device != self.device or idx.dim() != 1 or idx.numel() < 1:
+                raise ValueError("idx: expected int32 [B] on the network's device")
+            lo, hi = int(idx.min()), int(idx.max())
+            if lo < 0 or hi >= x.shape[0]:
+                raise ValueError(f"idx values must lie in [0, {x.shape[0]})")
+            idx = idx.contiguous()
+            B = idx.shape[0]
+        else:
+            B = x.shape[0]
+        if not 1 <= B <= self.batch_max:
+            raise ValueError(f"batch {B} outside 1..{self.batch_max}")
+        if loss is not None and (loss.dtype != torch.float64 or loss.numel() < 1 or not loss.is_contiguous()):
+            raise ValueError("loss: expected a contiguous float64 tensor")
+        self._enter()
+        rc = load().pdf_mlp_train_step(self.h, _ptr(x), _ptr(t), x.shape[0], _ptr(idx), ctypes.c_float(s_in), B,
+                                       float(lr), _ptr(loss))
+        self._leave()
+        _check(rc)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pdf_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdf.so")
-SOURCES = ["api.hip", "mom.hip", "tables.cpp"]
+SOURCES = ["api.hip", "mom.hip", "mlp.hip", "tables.cpp"]
 ARCH = "gfx950"
 
 

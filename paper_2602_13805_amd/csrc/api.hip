@@ -318,6 +318,25 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   return mark(h);
 }
 
+// Loss only (no adjoint): forward kernels and the image / regulariser pass.
+template <typename T>
+static int run_loss(pdf_handle* h, const void* alpha, double* loss) {
+  int rc;
+  FwdArgs<T> f;
+  f.in = (const cx<T>*)alpha;
+  f.einc = (const cx<T>*)h->einc;
+  f.ghat = (const cx<T>*)h->ghat;
+  f.tw = (const cx<T>*)h->tw;
+  f.J = (cx<T>*)h->J;
+  f.E = (cx<T>*)h->E;
+  f.Ni = h->Ni;
+  f.K = h->K;
+  f.beta = T(h->prm.beta);
+  if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  return launch_reg<T>(h, loss, nullptr, nullptr);
+}
+
 template <typename T>
 static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_out, const void* eps_true,
                      double* err) {
@@ -484,6 +503,7 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   HIP_TRY(hipMalloc(&h->m, 2 * sizeof(T) * B * Ni * KK));
   HIP_TRY(hipMalloc(&h->v, 2 * sizeof(T) * B * Ni * KK));
   HIP_TRY(hipMalloc(&h->loss, sizeof(double) * 8 * B));
+  HIP_TRY(hipMalloc(&h->loss_w, sizeof(double) * 8 * B));
   return PDF_OK;
 }
 
@@ -557,7 +577,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   void* ptrs[] = {h->gsT, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
-                  h->v,    h->loss};
+                  h->v,    h->loss, h->loss_w};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -670,6 +690,75 @@ extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
   return h->prec == PDF_FP32 ? run_init<float>(h, alpha_dev) : run_init<double>(h, alpha_dev);
+}
+
+extern "C" int pdf_warm_start(pdf_handle* h, pdf_mlp* net, float s_in, float s_out, void* alpha_dev,
+                              int32_t* chosen_dev, double* loss_dev) {
+  if (!h || !net || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  if (h->prec != PDF_FP32) return fail(h, PDF_EUNSUPPORTED, "the warm start serves FP32 handles");
+  int32_t n_in = 0, n_out = 0, bmax = 0;
+  pdf_mlp_widths(net, &n_in, &n_out, &bmax);
+  const int KK = h->K * h->K;
+  if (n_in != 2 * h->Ni * h->Ns || n_out != 2 * h->Ni * KK)
+    return fail(h, PDF_EINVAL, "network widths do not match 2 Ni Ns inputs and 2 Ni K^2 outputs");
+  int rc;
+  if ((rc = run_init<float>(h, alpha_dev))) return rc;
+  if ((rc = run_loss<float>(h, alpha_dev, h->loss))) return rc;
+  // the network's prediction into g0 (free after run_init), ordered between the two streams
+  hipStream_t ns = pdf_mlp_stream(net);
+  hipEvent_t ev;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  rc = PDF_OK;
+  if (hipEventRecord(ev, h->stream) != hipSuccess || hipStreamWaitEvent(ns, ev, 0) != hipSuccess)
+    rc = fail(h, PDF_EHIP, "stream ordering failed");
+  for (int b0 = 0; !rc && b0 < h->B; b0 += bmax) {
+    const int nb = std::min(bmax, h->B - b0);
+    if (pdf_mlp_forward(net, (const float*)h->esca + size_t(b0) * n_in, s_in, s_out, nb,
+                        (float*)h->g0 + size_t(b0) * n_out))
+      rc = fail(h, PDF_EHIP, std::string("network forward: ") + pdf_last_error(nullptr));
+  }
+  if (!rc && (hipEventRecord(ev, ns) != hipSuccess || hipStreamWaitEvent(h->stream, ev, 0) != hipSuccess))
+    rc = fail(h, PDF_EHIP, "stream ordering failed");
+  (void)hipEventDestroy(ev);
+  if (rc) return rc;
+  if ((rc = run_loss<float>(h, h->g0, h->loss_w))) return rc;
+  const int len = h->Ni * KK;
+  hipLaunchKernelGGL(k_pick_start<float>, dim3((len + 255) / 256, h->B), dim3(256), 0, h->stream,
+                     (cx<float>*)alpha_dev, (const cx<float>*)h->g0, h->loss, h->loss_w, len, chosen_dev, loss_dev);
+  return check_launch(h, "k_pick_start");
+}
+
+template <typename T, int M>
+static int launch_analyze_m(pdf_handle* h, int n, const void* J, void* alpha) {
+  using C = ConvCfg<T, M>;
+  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+    auto k = k_analyze<T, M>;
+    set_lds(k, C::LDS_BYTES);
+    hipLaunchKernelGGL(k, dim3(unsigned(n) * h->Ni), dim3(C::NT), C::LDS_BYTES, h->stream, (const cx<T>*)J,
+                       (const cx<T>*)h->tw, (cx<T>*)alpha, h->K);
+    return check_launch(h, "k_analyze");
+  } else {
+    return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident transform");
+  }
+}
+
+template <typename T>
+static int launch_analyze(pdf_handle* h, int n, const void* J, void* alpha) {
+  switch (h->M) {
+    case 8: return launch_analyze_m<T, 8>(h, n, J, alpha);
+    case 16: return launch_analyze_m<T, 16>(h, n, J, alpha);
+    case 32: return launch_analyze_m<T, 32>(h, n, J, alpha);
+    case 64: return launch_analyze_m<T, 64>(h, n, J, alpha);
+  }
+  return fail(h, PDF_EUNSUPPORTED, "unsupported M");
+}
+
+extern "C" int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev) {
+  if (!h || !J_dev || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (n < 1) return fail(h, PDF_EINVAL, "n must be >= 1");
+  return h->prec == PDF_FP32 ? launch_analyze<float>(h, n, J_dev, alpha_dev)
+                             : launch_analyze<double>(h, n, J_dev, alpha_dev);
 }
 
 extern "C" int pdf_image(pdf_handle* h, const void* alpha_dev, void* chi_dev, void* chi_cco_dev,

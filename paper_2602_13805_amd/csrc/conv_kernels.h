@@ -328,4 +328,38 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
   }
 }
 
+// alpha = F_T(J) on the kept modes (Sec. 2.3, Eq. 9): forward DFT of one
+// set of pixel currents divided by M^2 (grid: one workgroup per current).
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_analyze(const cx<T>* J, const cx<T>* twg, cx<T>* alpha,
+                                                                  int K) {
+  using C = ConvCfg<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + C::P * C::TileL::LD;
+  const size_t v = blockIdx.x;
+  const int tid = threadIdx.x;
+  cx<T> jv[C::PPT];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) jv[q] = J[v * C::N + tid + q * C::NT];
+  for (int k = tid; k < C::P; k += C::NT) tw[k] = twg[k];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    buf[C::TileL::at(n / M, n % M)] = jv[q];
+  }
+  __syncthreads();
+  const int kmin = -(K / 2);
+  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>();
+  typename C::ModeCols mc;
+  mc.nv = K;
+  mc.kmin = kmin;
+  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>();
+  const T s = T(1) / T(C::N);
+  for (int e = tid; e < K * K; e += C::NT) {
+    const cx<T> g = buf[C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))];
+    alpha[v * K * K + e] = cx<T>{s * g.x, s * g.y};
+  }
+}
+
 }  // namespace pdfk

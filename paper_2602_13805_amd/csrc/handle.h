@@ -45,6 +45,7 @@ struct pdf_handle {
   void* m = nullptr;         // [B][Ni][K][K][2] real
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]
+  double* loss_w = nullptr;  // [B][8] second loss record (start selection)
   // optional per-kernel event timing
   bool timing = false;
   int timing_max = 0;
@@ -55,3 +56,6 @@ struct pdf_handle {
 
 // Message returned by pdf_last_error(NULL).
 void pdf_set_global_error(const std::string& msg);
+
+// The stream a warm-start network was created on.
+hipStream_t pdf_mlp_stream(const pdf_mlp* net);

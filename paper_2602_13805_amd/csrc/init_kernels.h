@@ -116,6 +116,26 @@ __global__ void k_track_error(const double* err, const double* target, int* froz
   }
 }
 
+// Keeps, per instance, the start with the lower total loss (loss rows of 8,
+// total at index 5): alpha <- alt where loss_alt < loss_bp (grid: x over the
+// len values of an instance, y over instances).
+template <typename T>
+__global__ void k_pick_start(cx<T>* alpha, const cx<T>* alt, const double* loss_bp, const double* loss_alt,
+                             int len, int* chosen, double* loss_out) {
+  const int b = blockIdx.y;
+  const double lb = loss_bp[size_t(b) * 8 + 5], la = loss_alt[size_t(b) * 8 + 5];
+  const bool take = la < lb;  // false for a non-finite network start
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (take && e < len) alpha[size_t(b) * len + e] = alt[size_t(b) * len + e];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (chosen) chosen[b] = take ? 1 : 0;
+    if (loss_out) {
+      loss_out[2 * b] = lb;
+      loss_out[2 * b + 1] = la;
+    }
+  }
+}
+
 __global__ void k_fill_double(double* x, double v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;

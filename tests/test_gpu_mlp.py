@@ -1,0 +1,146 @@
+"""GPU parity of the warm-start network (an addition; the paper has none), of the Fourier
+analysis used for its targets, and of the start selection.  The network is compared with the
+FP64 oracle evaluated with the same bfloat16 rounding points (oracle.mlp, quant=True)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_13805_amd as pdf
+from oracle import fourier, mlp as omlp
+from tests.common import make_case, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def host_params(net):
+    return [tuple(np.asarray(a, np.float64) for a in net.get_layer(l)) for l in range(net.L)]
+
+
+# ragged widths: partial 128-wide tiles in every dimension, batch not a multiple of 32
+SIZES = [72, 130, 100, 44]
+
+
+def test_mlp_forward_gradients_adam_match_oracle():
+    print(f"mlp sizes={SIZES}", flush=True)
+    B = 37
+    net = pdf.Mlp(SIZES, batch_max=64, device=DEV)
+    net.init_weights(11)
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(B, SIZES[0])).astype(np.float32)
+    t = rng.normal(size=(B, SIZES[-1])).astype(np.float32)
+    xd, td = torch.tensor(x, device=DEV), torch.tensor(t, device=DEV)
+    s_in = 0.8
+    params = host_params(net)
+    y = net.forward(xd, s_in=s_in, s_out=1.0).cpu().numpy()
+    yo, cache = omlp.forward(params, x, s_in=s_in, quant=True)
+    assert rel(y, yo) < 1e-4, rel(y, yo)
+    y2 = net.forward(xd, s_in=s_in, s_out=2.5).cpu().numpy()
+    assert rel(y2, 2.5 * yo) < 1e-4
+    # one training step: loss, gradients, Adam
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    lr = 1e-3
+    net.train_step(xd, td, None, s_in, lr, loss)
+    lo, dy = omlp.mse(yo, t)
+    assert abs(loss.item() - lo) < 1e-4 * lo
+    go = omlp.backward(params, cache, dy, quant=True)
+    new = host_params(net)
+    for l in range(net.L):
+        gW, gb = net.get_layer(l, grad=True)
+        assert rel(gW, go[l][0]) < 2e-3, (l, rel(gW, go[l][0]))
+        assert rel(gb, go[l][1]) < 2e-3, (l, rel(gb, go[l][1]))
+        # Adam from the device's own gradients: first step of the bias-corrected form
+        W1, _, _ = omlp.adam_update(params[l][0], gW.astype(np.float64), 0.0, 0.0, 1, lr)
+        b1, _, _ = omlp.adam_update(params[l][1], gb.astype(np.float64), 0.0, 0.0, 1, lr)
+        assert np.max(np.abs(new[l][0] - W1)) < 1e-6, l
+        assert np.max(np.abs(new[l][1] - b1)) < 1e-6, l
+    net.close()
+
+
+def test_mlp_row_gather_equals_gathered_rows():
+    B = 24
+    rng = np.random.default_rng(13)
+    x = torch.tensor(rng.normal(size=(50, SIZES[0])).astype(np.float32), device=DEV)
+    t = torch.tensor(rng.normal(size=(50, SIZES[-1])).astype(np.float32), device=DEV)
+    idx = torch.tensor(rng.permutation(50)[:B].astype(np.int32), device=DEV)
+    grads = []
+    for gathered in (False, True):
+        net = pdf.Mlp(SIZES, batch_max=32, device=DEV)
+        net.init_weights(14)
+        if gathered:
+            net.train_step(x[idx.long()].contiguous(), t[idx.long()].contiguous(), None, 1.0, 1e-3)
+        else:
+            net.train_step(x, t, idx, 1.0, 1e-3)
+        grads.append([net.get_layer(l, grad=True) for l in range(net.L)])
+        net.close()
+    for (a, b), (c, d) in zip(grads[0], grads[1]):
+        assert np.array_equal(a, c) and np.array_equal(b, d)
+
+
+def test_mlp_training_fits_a_linear_map():
+    sizes = [64, 128, 128, 32]
+    rng = np.random.default_rng(15)
+    A = rng.normal(size=(32, 64)) / 8.0
+    x = rng.normal(size=(256, 64)).astype(np.float32)
+    t = (x @ A.T).astype(np.float32)
+    xd, td = torch.tensor(x, device=DEV), torch.tensor(t, device=DEV)
+    net = pdf.Mlp(sizes, batch_max=256, device=DEV)
+    net.init_weights(16)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    hist = []
+    for step in range(300):
+        net.train_step(xd, td, None, 1.0, 3e-3, loss)
+        hist.append(loss.item())
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.05 * hist[0], (hist[0], hist[-1])
+    net.close()
+
+
+def test_analyze_matches_oracle():
+    for M, K, prec, tol in [(32, 9, "fp32", 1e-5), (64, 15, "fp32", 1e-5), (16, 7, "fp64", 1e-12),
+                            (16, 16, "fp32", 1e-5)]:
+        case = make_case(M, K, 3, 4, seeds=(0,))
+        wl = case["wl"]
+        s = pdf.Solver(M, wl.side, wl.freq_hz, case["tx"], case["rx"], K, batch=1,
+                       params=pdf.default_params(prec), device=DEV)
+        rng = np.random.default_rng(M + K)
+        J = rng.normal(size=(5, 3, M, M)) + 1j * rng.normal(size=(5, 3, M, M))
+        got = s.analyze(torch.tensor(J, dtype=s.cdtype, device=DEV)).cpu().numpy()
+        ref = fourier.analyze(J, K)
+        assert rel(got, ref) < tol, (M, K, prec, rel(got, ref))
+        s.close()
+
+
+def test_warm_start_keeps_the_lower_loss_start():
+    M, K, Ni, Ns, B = 32, 9, 6, 8, 4
+    case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+    wl = case["wl"]
+    s = pdf.Solver(M, wl.side, wl.freq_hz, case["tx"], case["rx"], K, batch=B, device=DEV)
+    esca = np.stack([c["esca"] for c in case["cases"]])
+    s.set_data(torch.tensor(esca, dtype=s.cdtype, device=DEV))
+    bp = s.init_alpha()
+    nin, nout = 2 * Ni * Ns, 2 * Ni * K * K
+    net = pdf.Mlp([nin, 16, nout], batch_max=3, device=DEV)  # batch_max < B: predictions in chunks
+    net.init_weights(17)
+    # a network whose output ignores its input: zero last weights, bias = a chosen alpha
+    target = (bp[1] * 0.5).cpu().numpy()
+    bias = np.stack([target.real, target.imag], axis=-1).reshape(-1).astype(np.float32)
+    net.set_layer(1, np.zeros((nout, 16), np.float32), bias)
+    alpha, chosen, losses = s.warm_start(net, 1.0, 1.0)
+    l_bp = s.loss_grad(bp, grad=False)[0][:, 5].cpu().numpy()
+    pred = torch.tensor(np.broadcast_to(target, (B, Ni, K, K)).copy(), dtype=s.cdtype, device=DEV)
+    l_net = s.loss_grad(pred, grad=False)[0][:, 5].cpu().numpy()
+    lo = losses.cpu().numpy()
+    assert np.allclose(lo[:, 0], l_bp, rtol=1e-12) and np.allclose(lo[:, 1], l_net, rtol=1e-12)
+    want = l_net < l_bp
+    assert np.array_equal(chosen.cpu().numpy() == 1, want)
+    for b in range(B):
+        ref = pred[b] if want[b] else bp[b]
+        assert torch.equal(alpha[b], ref), b
+    # widths that do not fit the handle are refused
+    bad = pdf.Mlp([nin + 2, 8, nout], batch_max=4, device=DEV)
+    with pytest.raises(pdf.PdfError):
+        s.warm_start(bad, 1.0, 1.0)
+    bad.close()
+    net.close()
+    s.close()
