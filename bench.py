@@ -13,7 +13,8 @@ batch (all hot-path kernels).  `value` = instance-iterations per second over
 the timed steps, inputs resident in HBM.  Also reported: per-kernel times
 (HIP events on the library's stream), the roofline of the dominant kernel,
 reconstructions per second to a fixed image error, single-instance numbers,
-and the FP64 oracle timed on the host (`cpu_baseline`).
+the warm-started reconstructions (network trained here on fresh MoM pairs)
+to the same errors, and the FP64 oracle timed on the host (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
 """
@@ -235,6 +236,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the steps, as a "
                          "reference of known traffic for hardware byte counters")
+    ap.add_argument("--warm-pairs", type=int, default=4096,
+                    help="training pairs of the warm-start network (0: skip the warm-start leg)")
+    ap.add_argument("--warm-epochs", type=int, default=40)
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
     ap.add_argument("--summary-kind", choices=["stats", "pmc"], default="stats")
@@ -341,6 +345,9 @@ def main():
             iters_to_target=int(one_t["reached"].item()))
         s1.close()
         log(f"reconstructions: {extra}")
+        if args.warm_pairs > 0:
+            extra["warm_start"] = warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev)
+            log(f"warm start: {extra['warm_start']}")
     s.close()
 
     out = {
@@ -359,6 +366,80 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(si, wl, esca[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev):
+    """Train the warm-start network on fresh MoM pairs, then reconstruct the same instances from its
+    start to the same per-instance targets (network, selection and iterations all timed)."""
+    import numpy as np
+    import torch
+    from paper_2602_13805_amd import warmstart as ws
+    B = s.B
+    t0 = time.time()
+    data = ws.make_dataset(si, wl, ws.TRAIN_SEED0 + np.arange(args.warm_pairs), dev, log=log)
+    data_s = time.time() - t0
+    tr = ws.train(data, epochs=args.warm_epochs, batch=256, lr=1e-3, seed=0, device=dev, log=log)
+    # forward throughput of the network on a full batch (bfloat16 MFMA)
+    x = data.x[:256].contiguous()
+    tr.net.forward(x, tr.s_in, tr.s_out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nf = 20
+    for _ in range(nf):
+        tr.net.forward(x, tr.s_in, tr.s_out)
+    torch.cuda.synchronize()
+    fwd_s = (time.perf_counter() - t1) / nf
+    sizes = tr.net.sizes
+    fwd_flops = 2.0 * 256 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    del data
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a_w, chosen, losses = s.warm_start(tr.net, tr.s_in, tr.s_out)
+    res = s.reconstruct(R, n_check=10, alpha=a_w.clone(), eps_true=eps_t, target=target)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t1
+    reached = res["reached"].cpu().numpy()
+    e_w = s.image(a_w, eps_t)[2].cpu().numpy()
+    a_bp = s.init_alpha()
+    e_bp = s.image(a_bp, eps_t)[2].cpu().numpy()
+    # lowest image error along R iterations from either start
+    best_w = s.reconstruct(R, n_check=10, alpha=a_w.clone(), eps_true=eps_t)["best_err"].cpu().numpy()
+    best_bp = s.reconstruct(R, n_check=10, alpha=a_bp.clone(), eps_true=eps_t)["best_err"].cpu().numpy()
+    # one fixed image error for every instance: fraction reaching it, iterations, time
+    fixed = {}
+    for e_star in (0.40, 0.30):
+        tgt = torch.full((B,), e_star, dtype=torch.float64, device=dev)
+        row = {}
+        for name, a in (("plain", a_bp), ("warm", a_w)):
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if name == "warm":
+                a, _, _ = s.warm_start(tr.net, tr.s_in, tr.s_out)
+            else:
+                a = s.init_alpha()
+            r = s.reconstruct(R, n_check=10, alpha=a, eps_true=eps_t, target=tgt)
+            torch.cuda.synchronize()
+            rr = r["reached"].cpu().numpy()
+            row[name] = dict(frac_reached=float(np.mean(rr >= 0)),
+                             mean_iters=float(np.mean(rr[rr >= 0])) if np.any(rr >= 0) else None,
+                             seconds=time.perf_counter() - t2)
+        fixed[f"{e_star:.2f}"] = row
+    tr.net.close()
+    return dict(
+        mean_best_image_error=float(best_w.mean()), mean_best_image_error_plain=float(best_bp.mean()),
+        fixed_error_targets=fixed,
+        per_s=B / sec, seconds=sec, batch=B, n_reached=res["n_reached"],
+        mean_iters_to_target=float(np.mean(reached[reached >= 0])) if np.any(reached >= 0) else None,
+        target="the same per-instance targets as the plain reconstructions",
+        mean_start_image_error=float(e_w.mean()), mean_start_image_error_plain=float(e_bp.mean()),
+        frac_network_start=float(chosen.float().mean()),
+        training=dict(pairs=args.warm_pairs, epochs=args.warm_epochs, steps=tr.steps, batch=256,
+                      seconds=tr.seconds, data_seconds=data_s, first_epoch_mse=tr.history[0],
+                      last_epoch_mse=tr.history[-1], widths=sizes,
+                      data="cfg2 profiles, seeds 1000000 + i, FP64 MoM on 128x128 with jitter and noise; "
+                           "targets F_T of the true induced currents on the 64x64 grid"),
+        network_forward=dict(rows=256, ms=fwd_s * 1e3, tflops=fwd_flops / fwd_s / 1e12,
+                             peak_tflops=2500.0, frac=fwd_flops / fwd_s / 2.5e15))
 
 
 def si_start_error(s, eps_t):
