@@ -172,6 +172,38 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
                     int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
                     void* chi_cco_dev, pdf_report* rep);
 
+/* Tile shapes of the FP32 MFMA kernels for this handle's shape, chosen by
+ * timing `reps` launches of each candidate on the handle's own buffers: the
+ * G_S^H GEMM's column tiles per wavefront (1, 2 or 4 tiles of 32 pixels) and
+ * the pixel reduction's load batch (4 incidences at four wavefronts per SIMD,
+ * or 8 at two).  Every candidate computes each result in the same order, so
+ * the choice changes timing only, never a value.  choice: host int32 [2]
+ * out (column tiles, load batch), may be NULL; ms: host double [5] out
+ * (the three GEMM and two reduction timings), may be NULL.  FP64 handles and
+ * grids with M*M not a multiple of 32 keep the defaults (2, 4).  Synchronous;
+ * overwrites the handle's scratch arrays (not alpha, data or Adam state). */
+int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms);
+/* Sets the tile choice directly (ct in {1, 2, 4}, pb in {4, 8}). */
+int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb);
+
+/* Uneven batching: the reconstructions of n handles (different grids, antenna
+ * counts, truncations, batch sizes and precisions) advanced together.  Every
+ * n_check steps of all still-running handles are one HIP graph made of one
+ * branch per handle (that handle's kernels, specialised for its shape) with no
+ * dependencies between branches, so the handles run concurrently on the GPU;
+ * the graph is rebuilt only when a handle stops.  Array arguments hold n
+ * entries with pdf_reconstruct's meaning for hs[i] (an array may be NULL
+ * where pdf_reconstruct allows NULL, meaning NULL for every handle).  Handles
+ * not tuned yet are first tuned by pdf_autotune (5 launches per candidate).  rep:
+ * steps taken, instances that reached their target (all handles), wall time.
+ * Each handle must appear once.  Synchronous. */
+int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n_iter, int32_t n_check,
+                          int32_t start_given, void* const* alpha_dev,
+                          const void* const* eps_true_dev, const double* const* target_err_dev,
+                          int32_t* const* reached_iter_dev, double* const* best_err_dev,
+                          int32_t* const* best_iter_dev, void* const* chi_cco_dev,
+                          pdf_report* rep);
+
 /* FP64 method-of-moments synthesis of measured fields (Sec. 2.1, Eqs. 3-4):
  * solves (I - G_D X) E = E_inc on the support of chi = eps - 1 of a fine grid
  * and returns E_sca = G_S X E.  Stand-alone (no handle); synchronous.

@@ -77,6 +77,10 @@ SIGNATURES = {
     "pdf_mlp_destroy": (None, [c_vp]),
     "pdf_warm_start": (c_i32, [c_vp, c_vp, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp]),
     "pdf_analyze": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "pdf_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "pdf_set_tiles": (c_i32, [c_vp, c_i32, c_i32]),
+    "pdf_reconstruct_multi": (c_i32, [c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                      c_vp]),
     "pdf_timing": (c_i32, [c_vp, c_i32, c_i32]),
     "pdf_timing_read": (c_i32, [c_vp, c_vp, c_vp]),
     "pdf_destroy": (None, [c_vp]),
@@ -336,6 +340,17 @@ class Solver:
         return dict(alpha=a, chi_cco=cco, reached=reached, best_err=best_err, best_iter=best_iter,
                     iters_run=rep.iters_run, n_reached=rep.n_reached, seconds=rep.seconds)
 
+    def autotune(self, reps: int = 5):
+        """Times the tile candidates of the MFMA kernels on this handle and keeps the fastest.
+        Returns ((column tiles, load batch), the five candidate timings in ms)."""
+        choice = (c_i32 * 2)()
+        ms = np.zeros(5, np.float64)
+        self._call(load().pdf_autotune, reps, ctypes.cast(choice, c_vp), ms.ctypes.data)
+        return (choice[0], choice[1]), ms
+
+    def set_tiles(self, ct: int, pb: int):
+        _check(load().pdf_set_tiles(self.h, ct, pb), self.h)
+
     def timing(self, enable: bool, max_steps: int = 1000):
         """Start (or stop) recording per-kernel HIP events on the library stream."""
         _check(load().pdf_timing(self.h, int(enable), max_steps), self.h)
@@ -357,6 +372,50 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def reconstruct_multi(solvers, n_iter: int, n_check: int = 10, alphas=None, eps_trues=None, targets=None):
+    """Reconstructions of several solvers (any grids, antenna counts, truncations, batches) advanced
+    together, one graph branch per solver.  Per-solver arguments are lists (or None); returns one
+    result dict per solver as Solver.reconstruct does, and the shared step count and wall time."""
+    n = len(solvers)
+    if n < 1:
+        raise ValueError("no solvers")
+    start_given = alphas is not None
+    res, keep = [], []
+    arr = lambda vals: (c_vp * n)(*[None if v is None else v.data_ptr() for v in vals])
+    A, E, T, RE, BE, BI, C = [], [], [], [], [], [], []
+    for i, s in enumerate(solvers):
+        a = alphas[i] if start_given else s.zeros_alpha()
+        s._want(a, s.alpha_shape, s.cdtype, f"alphas[{i}]", inplace=True)
+        et = eps_trues[i] if eps_trues is not None else None
+        if et is not None:
+            et = s._want(et, (s.B, s.M, s.M), s.cdtype, f"eps_trues[{i}]")
+        tg = targets[i] if targets is not None else None
+        if tg is not None:
+            if et is None:
+                raise ValueError("targets need eps_trues")
+            tg = s._want(tg, (s.B,), torch.float64, f"targets[{i}]")
+        track = et is not None
+        r = dict(alpha=a, chi_cco=torch.empty((s.B, s.M, s.M), dtype=s.cdtype, device=s.device),
+                 reached=torch.full((s.B,), -1, dtype=torch.int32, device=s.device),
+                 best_err=torch.empty(s.B, dtype=torch.float64, device=s.device) if track else None,
+                 best_iter=torch.empty(s.B, dtype=torch.int32, device=s.device) if track else None)
+        res.append(r)
+        A.append(a); E.append(et); T.append(tg); RE.append(r["reached"]); BE.append(r["best_err"])
+        BI.append(r["best_iter"]); C.append(r["chi_cco"])
+        s._enter()
+    hs = (c_vp * n)(*[s.h.value for s in solvers])
+    args = [arr(A), arr(E) if eps_trues is not None else None, arr(T) if targets is not None else None,
+            arr(RE), arr(BE) if eps_trues is not None else None, arr(BI) if eps_trues is not None else None, arr(C)]
+    rep = Report()
+    rc = load().pdf_reconstruct_multi(n, hs, n_iter, n_check, int(start_given), *args, ctypes.byref(rep))
+    for s in solvers:
+        s._leave()
+    _check(rc, solvers[0].h)
+    for r in res:
+        r.update(iters_run=rep.iters_run, seconds=rep.seconds)
+    return res, dict(iters_run=rep.iters_run, n_reached=rep.n_reached, seconds=rep.seconds)
 
 
 class Mlp:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -141,8 +142,13 @@ static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
 template <int NRT, int NCT>
 static void launch_reduce_mfma(pdf_handle* h, const ReduceArgs<float>& a) {
   const size_t lds = reduce_mfma_lds<NCT>();
-  set_lds(k_pixel_reduce_mfma<NRT, NCT>, lds);
-  hipLaunchKernelGGL((k_pixel_reduce_mfma<NRT, NCT>), dim3(h->ntiles, h->B), dim3(256), lds, h->stream, a);
+  if (h->tune_pb == 8) {
+    set_lds(k_pixel_reduce_mfma<NRT, NCT, 8>, lds);
+    hipLaunchKernelGGL((k_pixel_reduce_mfma<NRT, NCT, 8>), dim3(h->ntiles, h->B), dim3(256), lds, h->stream, a);
+  } else {
+    set_lds(k_pixel_reduce_mfma<NRT, NCT, 4>, lds);
+    hipLaunchKernelGGL((k_pixel_reduce_mfma<NRT, NCT, 4>), dim3(h->ntiles, h->B), dim3(256), lds, h->stream, a);
+  }
 }
 
 template <typename T>
@@ -219,12 +225,22 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
   return check_launch(h, "k_image_reg");
 }
 
+template <int NRT, int CT>
+static void launch_adj_gemm_ct(pdf_handle* h, const cx<float>* x, cx<float>* out) {
+  const size_t lds = sizeof(cx<float>) * size_t(h->Ns) * 16 * NRT;
+  constexpr int px = 4 * 32 * CT;  // pixels per workgroup
+  dim3 grid((h->N + px - 1) / px, h->B);
+  hipLaunchKernelGGL((k_adj_gemm_mfma<NRT, CT>), grid, dim3(256), lds, h->stream, (const cx<float>*)h->gs, x, out,
+                     h->Ni, h->Ns, h->N);
+}
+
 template <int NRT>
 static void launch_adj_gemm_mfma(pdf_handle* h, const cx<float>* x, cx<float>* out) {
-  const size_t lds = sizeof(cx<float>) * size_t(h->Ns) * 16 * NRT;
-  dim3 grid((h->N + 255) / 256, h->B);
-  hipLaunchKernelGGL((k_adj_gemm_mfma<NRT>), grid, dim3(256), lds, h->stream, (const cx<float>*)h->gs, x, out,
-                     h->Ni, h->Ns, h->N);
+  switch (h->tune_ct) {
+    case 1: launch_adj_gemm_ct<NRT, 1>(h, x, out); break;
+    case 4: launch_adj_gemm_ct<NRT, 4>(h, x, out); break;
+    default: launch_adj_gemm_ct<NRT, 2>(h, x, out); break;
+  }
 }
 
 template <typename T>
@@ -692,6 +708,71 @@ extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {
   return h->prec == PDF_FP32 ? run_init<float>(h, alpha_dev) : run_init<double>(h, alpha_dev);
 }
 
+// Average duration (ms) of `reps` launches of fn on the handle's stream.
+template <class F>
+static int time_launches(pdf_handle* h, int reps, F fn, double* ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(h, PDF_EHIP, "hipEventCreate");
+  }
+  int rc = fn();  // warm-up (and first-launch set-up) outside the timed range
+  if (!rc && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, PDF_EHIP, "hipEventRecord");
+  for (int i = 0; i < reps && !rc; ++i) rc = fn();
+  float t = 0.f;
+  if (!rc && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    rc = fail(h, PDF_EHIP, "event timing failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = double(t) / reps;
+  return rc;
+}
+
+extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms) {
+  if (!h || reps < 1) return fail(h, PDF_EINVAL, "bad argument");
+  if (h->prec != PDF_FP32 || h->N % 32 != 0) {  // only the FP32 MFMA kernels have tile choices
+    h->tuned = true;
+    if (choice) choice[0] = h->tune_ct, choice[1] = h->tune_pb;
+    return PDF_OK;
+  }
+  int rc;
+  double t[5];
+  const int cts[3] = {1, 2, 4}, pbs[2] = {4, 8};
+  int best_ct = h->tune_ct, best_pb = h->tune_pb;
+  for (int i = 0; i < 3; ++i) {
+    h->tune_ct = cts[i];
+    if ((rc = time_launches(h, reps, [&]() { return launch_adj_gemm<float>(h, (const cx<float>*)h->dres,
+                                                                           (cx<float>*)h->h); }, &t[i])))
+      return rc;
+  }
+  for (int i = 0; i < 2; ++i) {
+    h->tune_pb = pbs[i];
+    if ((rc = time_launches(h, reps, [&]() { return launch_reduce<float>(h, (const cx<float>*)h->J,
+                                                                         (const cx<float>*)h->E, nullptr); },
+                            &t[3 + i])))
+      return rc;
+  }
+  best_ct = cts[t[0] <= t[1] ? (t[0] <= t[2] ? 0 : 2) : (t[1] <= t[2] ? 1 : 2)];
+  best_pb = pbs[t[3] <= t[4] ? 0 : 1];
+  h->tune_ct = best_ct;
+  h->tune_pb = best_pb;
+  h->tuned = true;
+  if (choice) choice[0] = best_ct, choice[1] = best_pb;
+  if (ms)
+    for (int i = 0; i < 5; ++i) ms[i] = t[i];
+  return PDF_OK;
+}
+
+extern "C" int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb) {
+  if (!h || (ct != 1 && ct != 2 && ct != 4) || (pb != 4 && pb != 8)) return fail(h, PDF_EINVAL, "bad tile choice");
+  h->tune_ct = ct;
+  h->tune_pb = pb;
+  h->tuned = true;
+  return PDF_OK;
+}
+
 extern "C" int pdf_warm_start(pdf_handle* h, pdf_mlp* net, float s_in, float s_out, void* alpha_dev,
                               int32_t* chosen_dev, double* loss_dev) {
   if (!h || !net || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
@@ -769,91 +850,206 @@ extern "C" int pdf_image(pdf_handle* h, const void* alpha_dev, void* chi_dev, vo
                              : run_image<double>(h, alpha_dev, chi_dev, chi_cco_dev, eps_true_dev, err_dev);
 }
 
+// One handle's part of a reconstruction: start value, counters, error checks,
+// n_check captured iterations, final image.  Handles of either precision
+// share the interface, so several can be advanced together.
+struct Recon {
+  virtual ~Recon() = default;
+  virtual int prepare(int start_given) = 0;        // start value and counters; first error check
+  virtual int check() = 0;                         // error check after a chunk (updates nf)
+  virtual int iterate(int k) = 0;                  // k iterations on the handle's stream (capturable)
+  virtual int finish() = 0;                        // final image, synchronise
+  pdf_handle* h = nullptr;
+  bool has_target = false;
+  int nf = 0;                                      // instances that reached their target
+  bool active() const { return nf < h->B; }
+};
+
 template <typename T>
-static int reconstruct_impl(pdf_handle* h, int n_iter, int n_check, int start_given, void* alpha,
-                            const void* eps_true, const double* target, int* reached, double* best_err,
-                            int* best_iter, void* cco_out, pdf_report* rep) {
-  auto t0 = std::chrono::steady_clock::now();
-  int rc;
-  const size_t KK = size_t(h->K) * h->K;
-  const size_t nre = 2 * size_t(h->B) * h->Ni * KK;
-  if (!start_given && (rc = run_init<T>(h, alpha))) return rc;
-  const int tb = 256;
-  const dim3 gb((h->B + tb - 1) / tb);
-  hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->m, nre);
-  hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->v, nre);
-  hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->tstep, 0, h->B);
-  hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->frozen, 0, h->B);
-  if (reached) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, reached, -1, h->B);
-  if (best_iter) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, best_iter, -1, h->B);
-  if (best_err) hipLaunchKernelGGL(k_fill_double, gb, dim3(tb), 0, h->stream, best_err, HUGE_VAL, h->B);
-  if ((rc = check_launch(h, "fill"))) return rc;
-  const bool checking = eps_true != nullptr;
-  std::vector<int> fz(h->B);
-  // image error at the current iterate; returns the number of stopped instances
-  auto check = [&](int* nfrozen) -> int {
+struct ReconT : Recon {
+  void* alpha;
+  const void* eps_true;
+  const double* target;
+  int *reached, *best_iter;
+  double* best_err;
+  void* cco_out;
+  std::vector<int> fz;
+  ReconT(pdf_handle* hh, void* a, const void* et, const double* tg, int* re, double* be, int* bi, void* co)
+      : alpha(a), eps_true(et), target(tg), reached(re), best_iter(bi), best_err(be), cco_out(co) {
+    h = hh;
+    has_target = tg != nullptr;
+    fz.resize(hh->B);
+  }
+  int prepare(int start_given) override {
+    int rc;
+    const size_t KK = size_t(h->K) * h->K;
+    const size_t nre = 2 * size_t(h->B) * h->Ni * KK;
+    if (!start_given && (rc = run_init<T>(h, alpha))) return rc;
+    const int tb = 256;
+    const dim3 gb((h->B + tb - 1) / tb);
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->m, nre);
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3((nre + tb - 1) / tb), dim3(tb), 0, h->stream, (T*)h->v, nre);
+    hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->tstep, 0, h->B);
+    hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, h->frozen, 0, h->B);
+    if (reached) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, reached, -1, h->B);
+    if (best_iter) hipLaunchKernelGGL(k_fill_int, gb, dim3(tb), 0, h->stream, best_iter, -1, h->B);
+    if (best_err) hipLaunchKernelGGL(k_fill_double, gb, dim3(tb), 0, h->stream, best_err, HUGE_VAL, h->B);
+    if ((rc = check_launch(h, "fill"))) return rc;
+    nf = 0;
+    return eps_true ? check() : PDF_OK;
+  }
+  int check() override {
+    if (!eps_true) return PDF_OK;
+    const int tb = 256;
+    const dim3 gb((h->B + tb - 1) / tb);
     int r = run_image<T>(h, alpha, nullptr, nullptr, eps_true, h->err);
     if (r) return r;
     hipLaunchKernelGGL(k_track_error, gb, dim3(tb), 0, h->stream, h->err, target, h->frozen, reached, best_err,
                        best_iter, h->tstep, h->B);
     if ((r = check_launch(h, "k_track_error"))) return r;
-    *nfrozen = 0;
+    nf = 0;
     if (target) {
       HIP_TRY(hipMemcpyAsync(fz.data(), h->frozen, sizeof(int) * h->B, hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(hipStreamSynchronize(h->stream));
-      for (int x : fz) *nfrozen += x;
+      for (int x : fz) nf += x;
     }
     return PDF_OK;
-  };
-  int nf = 0;
-  if (checking && (rc = check(&nf))) return rc;
-  if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int done = 0;
-  if (n_iter > 0 && nf < h->B) {
-    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    int crc = PDF_OK;
-    for (int s = 0; s < n_check && crc == PDF_OK; ++s)
-      crc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen);
-    hipError_t ce = hipStreamEndCapture(h->stream, &graph);
-    if (crc) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return crc;
-    }
-    if (ce != hipSuccess) return fail(h, PDF_EHIP, std::string("capture: ") + hipGetErrorString(ce));
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return fail(h, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    }
   }
-  while (done < n_iter && nf < h->B) {
+  int iterate(int k) override {
+    for (int s = 0; s < k; ++s)
+      if (int rc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen)) return rc;
+    return PDF_OK;
+  }
+  int finish() override {
+    int rc;
+    if (cco_out && (rc = run_image<T>(h, alpha, nullptr, cco_out, nullptr, nullptr))) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PDF_OK;
+  }
+};
+
+// Captures k iterations of r on its handle's stream into a new graph.
+static int capture_iterations(Recon* r, int k, hipGraph_t* g) {
+  pdf_handle* h = r->h;
+  *g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  const int crc = r->iterate(k);
+  hipError_t ce = hipStreamEndCapture(h->stream, g);
+  if (crc) {
+    if (*g) (void)hipGraphDestroy(*g);
+    *g = nullptr;
+    return crc;
+  }
+  if (ce != hipSuccess) return fail(h, PDF_EHIP, std::string("capture: ") + hipGetErrorString(ce));
+  return PDF_OK;
+}
+
+// Advances every reconstruction in rs together: each n_check steps are one
+// graph launch whose branches (one child graph per active handle) have no
+// dependencies between them, so the handles' kernels run concurrently.
+static int reconstruct_all(std::vector<Recon*>& rs, int n_iter, int n_check, int start_given, pdf_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = PDF_OK;
+  for (Recon* r : rs)
+    if ((rc = r->prepare(start_given))) return rc;
+  if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
+  pdf_handle* lead = rs[0]->h;
+  hipGraph_t parent = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraph_t> children;
+  std::vector<Recon*> graphed;  // the active set the current graph was built for
+  std::vector<hipEvent_t> evs(rs.size() + 1, nullptr);
+  for (auto& e : evs)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = fail(lead, PDF_EHIP, "hipEventCreate");
+  auto drop_graph = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (parent) (void)hipGraphDestroy(parent);
+    for (hipGraph_t g : children) (void)hipGraphDestroy(g);
+    exec = nullptr;
+    parent = nullptr;
+    children.clear();
+    graphed.clear();
+  };
+  auto build_graph = [&](const std::vector<Recon*>& act) -> int {
+    pdf_handle* h = lead;  // errors are reported on the lead handle
+    drop_graph();
+    HIP_TRY(hipGraphCreate(&parent, 0));
+    for (Recon* r : act) {
+      hipGraph_t g;
+      if (int e = capture_iterations(r, n_check, &g)) return e;
+      children.push_back(g);
+      hipGraphNode_t node;
+      HIP_TRY(hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g));
+    }
+    hipError_t ie = hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0);
+    if (ie != hipSuccess) return fail(lead, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    graphed = act;
+    return PDF_OK;
+  };
+  int done = 0;
+  while (!rc && done < n_iter) {
+    std::vector<Recon*> act;
+    for (Recon* r : rs)
+      if (r->active()) act.push_back(r);
+    if (act.empty()) break;
     const int chunk = (n_iter - done < n_check) ? n_iter - done : n_check;
     if (chunk == n_check) {
-      hipError_t le = hipGraphLaunch(exec, h->stream);
+      if (graphed != act && (rc = build_graph(act))) break;
+      // join the handles' streams into the lead stream, launch, fork back
+      for (size_t i = 0; i < act.size() && !rc; ++i)
+        if (hipEventRecord(evs[i], act[i]->h->stream) != hipSuccess ||
+            hipStreamWaitEvent(lead->stream, evs[i], 0) != hipSuccess)
+          rc = fail(lead, PDF_EHIP, "stream join failed");
+      if (rc) break;
+      hipError_t le = hipGraphLaunch(exec, lead->stream);
       if (le != hipSuccess) {
-        rc = fail(h, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+        rc = fail(lead, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
         break;
       }
+      if (hipEventRecord(evs.back(), lead->stream) != hipSuccess) rc = fail(lead, PDF_EHIP, "hipEventRecord");
+      for (Recon* r : act)
+        if (!rc && hipStreamWaitEvent(r->h->stream, evs.back(), 0) != hipSuccess)
+          rc = fail(lead, PDF_EHIP, "stream fork failed");
     } else {
-      for (int s = 0; s < chunk && !rc; ++s)
-        rc = run_iteration<T>(h, alpha, nullptr, h->loss, alpha, h->m, h->v, h->tstep, h->frozen);
-      if (rc) break;
+      for (Recon* r : act)
+        if (!rc) rc = r->iterate(chunk);
     }
     done += chunk;
-    if (checking && (rc = check(&nf))) break;
+    for (Recon* r : act)
+      if (!rc) rc = r->check();
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  drop_graph();
+  for (auto& e : evs)
+    if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
-  if (cco_out && (rc = run_image<T>(h, alpha, nullptr, cco_out, nullptr, nullptr))) return rc;
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  int reached = 0;
+  bool any_target = false;
+  for (Recon* r : rs) {
+    if ((rc = r->finish())) return rc;
+    reached += r->nf;
+    any_target = any_target || r->has_target;
+  }
   if (rep) {
     rep->iters_run = done;
-    rep->n_reached = target ? nf : 0;
+    rep->n_reached = any_target ? reached : 0;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  return PDF_OK;
+}
+
+static Recon* make_recon(pdf_handle* h, void* alpha, const void* eps_true, const double* target, int* reached,
+                         double* best_err, int* best_iter, void* cco_out) {
+  if (h->prec == PDF_FP32) return new ReconT<float>(h, alpha, eps_true, target, reached, best_err, best_iter, cco_out);
+  return new ReconT<double>(h, alpha, eps_true, target, reached, best_err, best_iter, cco_out);
+}
+
+static int check_recon_args(pdf_handle* h, void* alpha_dev, int n_iter, const void* eps_true_dev,
+                            const double* target_err_dev, const double* best_err_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (n_iter < 0) return fail(h, PDF_EINVAL, "n_iter < 0");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  if ((target_err_dev || best_err_dev) && !eps_true_dev)
+    return fail(h, PDF_EINVAL, "error tracking needs eps_true_dev");
   return PDF_OK;
 }
 
@@ -861,16 +1057,35 @@ extern "C" int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, i
                                void* alpha_dev, const void* eps_true_dev, const double* target_err_dev,
                                int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
                                void* chi_cco_dev, pdf_report* rep) {
-  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
-  if (n_iter < 0) return fail(h, PDF_EINVAL, "n_iter < 0");
-  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
-  if ((target_err_dev || best_err_dev) && !eps_true_dev)
-    return fail(h, PDF_EINVAL, "error tracking needs eps_true_dev");
-  return h->prec == PDF_FP32
-             ? reconstruct_impl<float>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
-                                       reached_iter_dev, best_err_dev, best_iter_dev, chi_cco_dev, rep)
-             : reconstruct_impl<double>(h, n_iter, n_check, start_given, alpha_dev, eps_true_dev, target_err_dev,
-                                        reached_iter_dev, best_err_dev, best_iter_dev, chi_cco_dev, rep);
+  if (int rc = check_recon_args(h, alpha_dev, n_iter, eps_true_dev, target_err_dev, best_err_dev)) return rc;
+  std::unique_ptr<Recon> r(make_recon(h, alpha_dev, eps_true_dev, target_err_dev, reached_iter_dev, best_err_dev,
+                                      best_iter_dev, chi_cco_dev));
+  std::vector<Recon*> rs{r.get()};
+  return reconstruct_all(rs, n_iter, n_check, start_given, rep);
+}
+
+extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n_iter, int32_t n_check,
+                                     int32_t start_given, void* const* alpha_dev, const void* const* eps_true_dev,
+                                     const double* const* target_err_dev, int32_t* const* reached_iter_dev,
+                                     double* const* best_err_dev, int32_t* const* best_iter_dev,
+                                     void* const* chi_cco_dev, pdf_report* rep) {
+  if (n < 1 || !hs || !alpha_dev) return fail(nullptr, PDF_EINVAL, "pdf_reconstruct_multi: null argument");
+  std::vector<std::unique_ptr<Recon>> own;
+  std::vector<Recon*> rs;
+  for (int i = 0; i < n; ++i) {
+    const void* et = eps_true_dev ? eps_true_dev[i] : nullptr;
+    const double* tg = target_err_dev ? target_err_dev[i] : nullptr;
+    double* be = best_err_dev ? best_err_dev[i] : nullptr;
+    if (int rc = check_recon_args(hs[i], alpha_dev[i], n_iter, et, tg, be)) return rc;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i], PDF_EINVAL, "a handle appears twice");
+    if (!hs[i]->tuned)
+      if (int rc = pdf_autotune(hs[i], 5, nullptr, nullptr)) return rc;
+    own.emplace_back(make_recon(hs[i], alpha_dev[i], et, tg, reached_iter_dev ? reached_iter_dev[i] : nullptr, be,
+                                best_iter_dev ? best_iter_dev[i] : nullptr, chi_cco_dev ? chi_cco_dev[i] : nullptr));
+    rs.push_back(own.back().get());
+  }
+  return reconstruct_all(rs, n_iter, n_check, start_given, rep);
 }
 
 extern "C" const char* pdf_last_error(const pdf_handle* h) {

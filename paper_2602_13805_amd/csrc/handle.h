@@ -46,6 +46,10 @@ struct pdf_handle {
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]
   double* loss_w = nullptr;  // [B][8] second loss record (start selection)
+  // tile shapes of the FP32 MFMA kernels (chosen by pdf_autotune; results do not depend on them)
+  int tune_ct = 2;           // column tiles per wave of the G_S^H GEMM: 1, 2 or 4
+  int tune_pb = 4;           // load batch of the pixel reduction: 4 or 8
+  bool tuned = false;
   // optional per-kernel event timing
   bool timing = false;
   int timing_max = 0;

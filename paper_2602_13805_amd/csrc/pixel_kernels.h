@@ -126,7 +126,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // 128 so that the staging LDS stays near 34 KB and four blocks share a CU.
 // Per sub-tile:
 //  1. the reduction over incidences: thread (pixel, half) loads the
-//     incidences p = half, half + 2, ... of its pixel in batches of four
+//     incidences p = half, half + 2, ... of its pixel in batches of PB
 //     (loads issued before use), accumulates num / den / sum |J|^2 in FP64
 //     and stages J in LDS; the two halves are added in fixed order;
 //  2. the complex GEMM D[p][q] += sum_k G_S[q][k] J_p[k] over the sub-tile
@@ -145,11 +145,12 @@ constexpr size_t reduce_mfma_lds() {
   return sizeof(float) * 2 * kReduceSub * (32 * NCT + 1) + sizeof(double) * 4 * kReduceSub + 16 * sizeof(double);
 }
 
-template <int NRT, int NCT>
-__global__ __launch_bounds__(256, (NRT * NCT <= 2 ? 4 : 2)) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
+// PB: incidences per load batch (a tuning choice: the accumulation order does
+// not depend on it, so neither do the results).
+template <int NRT, int NCT, int PB>
+__global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
   constexpr int SUB = kReduceSub, NSUB = kReduceTile / kReduceSub;
   constexpr int LDJ = 32 * NCT + 1;  // padded row of the staged currents (floats)
-  constexpr int PB = 4;              // incidences per load batch
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* Jr = reinterpret_cast<float*>(smem_raw);         // [SUB][LDJ]
   float* Ji = Jr + SUB * LDJ;                               // [SUB][LDJ]
@@ -472,12 +473,14 @@ __global__ __launch_bounds__(256) void k_adj_gemm(const cx<T>* __restrict__ gs, 
 // Block: 4 waves x CT column tiles of 32 pixels; x^T is staged in LDS
 // (incidence-contiguous, conflict-free reads); each lane of a finished tile
 // holds (Re, Im) of h_p at one pixel, so stores are 256-byte rows.
-// Requires N % 32 == 0.  NRT = ceil(Ni / 16) row tiles.
-template <int NRT>
+// Requires N % 32 == 0.  NRT = ceil(Ni / 16) row tiles; CT column tiles of 32
+// pixels per wave (a tuning choice: every output is the same chain of MFMAs
+// over the receivers whatever CT is, so the results do not depend on it).
+template <int NRT, int CT>
 __global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restrict__ gs,
                                                        const cx<float>* __restrict__ x, cx<float>* __restrict__ h,
                                                        int Ni, int Ns, int N) {
-  constexpr int CT = 2, KC = 8, LDX = 16 * NRT;
+  constexpr int KC = 8, LDX = 16 * NRT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<float>* xs = reinterpret_cast<cx<float>*>(smem_raw);  // [Ns][LDX]: xs[q][p] = x[p][q]
   const int b = blockIdx.y, tid = threadIdx.x;

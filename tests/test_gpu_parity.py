@@ -276,6 +276,66 @@ def test_synthesize_batch_matches_single_and_oracle_currents():
         assert rel(jc[b], jref) < 1e-9, (b, rel(jc[b], jref))
 
 
+def test_tile_choices_do_not_change_results_and_autotune_picks_one():
+    for (M, K, Ni, Ns, B) in [(32, 9, 16, 32, 3), (8, 5, 33, 17, 2), (64, 15, 32, 32, 1)]:
+        case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+        s = solver_for(case, "fp32")
+        alpha = torch.tensor(rand_alpha(s.alpha_shape, seed=M), dtype=s.cdtype, device=DEV)
+        outs = []
+        for ct in (1, 2, 4):
+            for pb in (4, 8):
+                s.set_tiles(ct, pb)
+                loss, g = s.loss_grad(alpha)
+                outs.append((loss.clone(), g.clone()))
+        for loss, g in outs[1:]:
+            assert torch.equal(loss, outs[0][0]) and torch.equal(g, outs[0][1]), (M, Ni, Ns)
+        (ct, pb), ms = s.autotune(3)
+        print(f"autotune M={M} Ni={Ni} Ns={Ns} B={B}: ct={ct} pb={pb} ms={np.round(ms, 4).tolist()}", flush=True)
+        assert ct in (1, 2, 4) and pb in (4, 8) and np.all(ms > 0)
+        loss, g = s.loss_grad(alpha)
+        assert torch.equal(loss, outs[0][0]) and torch.equal(g, outs[0][1])
+        with pytest.raises(pdf.PdfError):
+            s.set_tiles(3, 4)
+        s.close()
+
+
+def test_reconstruct_multi_equals_separate_reconstructions():
+    """Uneven batching: handles of different grids, antenna counts, truncations, batches and
+    precisions advanced in one graph give exactly what each handle gives alone."""
+    shapes = [(16, 7, 6, 8, 2, "fp32"), (32, 9, 16, 32, 3, "fp32"), (16, 5, 4, 6, 2, "fp64"), (8, 5, 3, 5, 1, "fp32")]
+    sol, eps, datas = [], [], []
+    for (M, K, Ni, Ns, B, prec) in shapes:
+        case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+        s = solver_for(case, prec)
+        sol.append(s)
+        eps.append(torch.tensor(np.stack([c["eps"] for c in case["cases"]]), dtype=s.cdtype, device=DEV))
+    print("reconstruct_multi shapes", shapes, flush=True)
+    for with_target in (False, True):
+        targets = None
+        ref = []
+        for s, et in zip(sol, eps):
+            tg = None
+            if with_target:  # stop some instances early: the error after the first check
+                r0 = s.reconstruct(10, n_check=10, eps_true=et)
+                tg = (r0["best_err"] * 1.02).contiguous()
+            ref.append((s.reconstruct(40, n_check=10, eps_true=et, target=tg), tg))
+        if with_target:
+            targets = [tg for _, tg in ref]
+        got, info = pdf.reconstruct_multi(sol, 40, n_check=10, eps_trues=eps, targets=targets)
+        for (r, _), g in zip(ref, got):
+            assert torch.equal(r["alpha"], g["alpha"])
+            assert torch.equal(r["chi_cco"], g["chi_cco"])
+            assert torch.equal(r["best_err"], g["best_err"]) and torch.equal(r["best_iter"], g["best_iter"])
+            assert torch.equal(r["reached"], g["reached"])
+        if with_target:
+            assert info["n_reached"] == sum(int((r["reached"] >= 0).sum()) for r, _ in ref)
+    # a handle listed twice is refused
+    with pytest.raises(pdf.PdfError):
+        pdf.reconstruct_multi([sol[0], sol[0]], 10)
+    for s in sol:
+        s.close()
+
+
 def test_error_paths_on_device():
     case = make_case(16, 7, 4, 6, seeds=(0,))
     wl = case["wl"]
