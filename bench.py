@@ -239,6 +239,8 @@ def main():
     ap.add_argument("--warm-pairs", type=int, default=4096,
                     help="training pairs of the warm-start network (0: skip the warm-start leg)")
     ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--uneven", type=int, default=512,
+                    help="instances of the uneven-shape batch leg (0: skip it)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
     ap.add_argument("--summary-kind", choices=["stats", "pmc"], default="stats")
@@ -348,6 +350,9 @@ def main():
         if args.warm_pairs > 0:
             extra["warm_start"] = warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev)
             log(f"warm start: {extra['warm_start']}")
+    if args.uneven > 0:
+        extra["uneven_batch"] = uneven_leg(pdf, si, wl, args.uneven, 200, dev)
+        log(f"uneven batch: {extra['uneven_batch']}")
     s.close()
 
     out = {
@@ -440,6 +445,57 @@ def warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev):
                            "targets F_T of the true induced currents on the 64x64 grid"),
         network_forward=dict(rows=256, ms=fwd_s * 1e3, tflops=fwd_flops / fwd_s / 1e12,
                              peak_tflops=2500.0, frac=fwd_flops / fwd_s / 2.5e15))
+
+
+def uneven_leg(pdf, si, wl, n_inst, iters, dev):
+    """Instances of uneven shapes (cfg3-style draws on the GPU-supported grids): one handle per
+    shape, all advanced in one graph per 10 steps, against the same handles one after another."""
+    import dataclasses
+    import numpy as np
+    import torch
+    shapes = si.uneven_shapes(n_inst, seed=2026)
+    groups = {}
+    for i, key in enumerate(shapes):
+        groups.setdefault(key, []).append(i)
+    sols = []
+    t0 = time.time()
+    for (M, a, K), idx in sorted(groups.items()):
+        w = dataclasses.replace(wl, M=M, n_tx=a, n_rx=a, K=K, M_fine=2 * M)
+        txs, rxs, epsf = [], [], np.zeros((len(idx), 2 * M, 2 * M), np.complex128)
+        for j, seed in enumerate(idx):
+            jt, jr = si.draw_jitter(seed, a, a, w.jitter_deg)
+            txs.append(si.antenna_positions(a, w.radius, angle_offsets=jt))
+            rxs.append(si.antenna_positions(a, w.radius, angle_offsets=jr))
+            epsf[j] = si.rasterize(si.draw_profile(w, seed), 2 * M, w.side)
+        es = pdf.synthesize_batch(2 * M, w.side, w.freq_hz, txs, rxs, epsf, tol=1e-10, device=dev)
+        for j, seed in enumerate(idx):
+            n1, n2 = si.draw_noise(seed, es[j].shape)
+            es[j] = si.add_noise(es[j], w.noise, n1, n2)
+        s = pdf.Solver(M, w.side, w.freq_hz, si.antenna_positions(a, w.radius), si.antenna_positions(a, w.radius),
+                       K, batch=len(idx), device=dev)
+        s.set_data(torch.tensor(es, dtype=s.cdtype, device=dev))
+        sols.append(s)
+    setup_s = time.time() - t0
+    pdf.reconstruct_multi(sols, 10, n_check=10)   # tunes every handle, warms the graph path
+    torch.cuda.synchronize()
+    _, info = pdf.reconstruct_multi(sols, iters, n_check=10)
+    multi_s = info["seconds"]
+    seq_s = 0.0
+    for s in sols:
+        seq_s += s.reconstruct(iters, n_check=10)["seconds"]
+    tiles = {}
+    for s in sols:
+        ch, _ = s.autotune(3)
+        tiles[str(ch)] = tiles.get(str(ch), 0) + s.B
+    for s in sols:
+        s.close()
+    work = n_inst * iters
+    return dict(instances=n_inst, handles=len(sols), iterations=iters,
+                shapes="M from {32, 64}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), cfg2 profiles",
+                instance_iters_per_s=work / multi_s, seconds=multi_s,
+                sequential_instance_iters_per_s=work / seq_s, sequential_seconds=seq_s,
+                speedup_over_sequential=seq_s / multi_s, setup_seconds=setup_s,
+                tile_choices_by_instances=tiles)
 
 
 def si_start_error(s, eps_t):

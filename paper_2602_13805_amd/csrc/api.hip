@@ -944,83 +944,52 @@ static int capture_iterations(Recon* r, int k, hipGraph_t* g) {
   return PDF_OK;
 }
 
-// Advances every reconstruction in rs together: each n_check steps are one
-// graph launch whose branches (one child graph per active handle) have no
-// dependencies between them, so the handles' kernels run concurrently.
+// Advances every reconstruction in rs together.  Each handle's n_check steps
+// are captured once into a graph of its own and launched on the handle's own
+// stream, so the handles' kernels run concurrently on the hardware queues
+// (a graph whose independent branches are the handles ran them one after
+// another, no faster than separate calls); checks and early stop per handle.
 static int reconstruct_all(std::vector<Recon*>& rs, int n_iter, int n_check, int start_given, pdf_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = PDF_OK;
   for (Recon* r : rs)
     if ((rc = r->prepare(start_given))) return rc;
   if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
-  pdf_handle* lead = rs[0]->h;
-  hipGraph_t parent = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::vector<hipGraph_t> children;
-  std::vector<Recon*> graphed;  // the active set the current graph was built for
-  std::vector<hipEvent_t> evs(rs.size() + 1, nullptr);
-  for (auto& e : evs)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = fail(lead, PDF_EHIP, "hipEventCreate");
-  auto drop_graph = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (parent) (void)hipGraphDestroy(parent);
-    for (hipGraph_t g : children) (void)hipGraphDestroy(g);
-    exec = nullptr;
-    parent = nullptr;
-    children.clear();
-    graphed.clear();
-  };
-  auto build_graph = [&](const std::vector<Recon*>& act) -> int {
-    pdf_handle* h = lead;  // errors are reported on the lead handle
-    drop_graph();
-    HIP_TRY(hipGraphCreate(&parent, 0));
-    for (Recon* r : act) {
-      hipGraph_t g;
-      if (int e = capture_iterations(r, n_check, &g)) return e;
-      children.push_back(g);
-      hipGraphNode_t node;
-      HIP_TRY(hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g));
-    }
-    hipError_t ie = hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0);
-    if (ie != hipSuccess) return fail(lead, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    graphed = act;
-    return PDF_OK;
-  };
+  const size_t n = rs.size();
+  std::vector<hipGraph_t> graphs(n, nullptr);
+  std::vector<hipGraphExec_t> execs(n, nullptr);
   int done = 0;
   while (!rc && done < n_iter) {
-    std::vector<Recon*> act;
-    for (Recon* r : rs)
-      if (r->active()) act.push_back(r);
-    if (act.empty()) break;
+    bool any = false;
     const int chunk = (n_iter - done < n_check) ? n_iter - done : n_check;
-    if (chunk == n_check) {
-      if (graphed != act && (rc = build_graph(act))) break;
-      // join the handles' streams into the lead stream, launch, fork back
-      for (size_t i = 0; i < act.size() && !rc; ++i)
-        if (hipEventRecord(evs[i], act[i]->h->stream) != hipSuccess ||
-            hipStreamWaitEvent(lead->stream, evs[i], 0) != hipSuccess)
-          rc = fail(lead, PDF_EHIP, "stream join failed");
-      if (rc) break;
-      hipError_t le = hipGraphLaunch(exec, lead->stream);
-      if (le != hipSuccess) {
-        rc = fail(lead, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
-        break;
+    for (size_t i = 0; i < n && !rc; ++i) {
+      Recon* r = rs[i];
+      if (!r->active()) continue;
+      any = true;
+      if (chunk == n_check) {
+        if (!execs[i]) {
+          if ((rc = capture_iterations(r, n_check, &graphs[i]))) break;
+          hipError_t ie = hipGraphInstantiate(&execs[i], graphs[i], nullptr, nullptr, 0);
+          if (ie != hipSuccess) {
+            rc = fail(r->h, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            break;
+          }
+        }
+        hipError_t le = hipGraphLaunch(execs[i], r->h->stream);
+        if (le != hipSuccess) rc = fail(r->h, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+      } else {
+        rc = r->iterate(chunk);
       }
-      if (hipEventRecord(evs.back(), lead->stream) != hipSuccess) rc = fail(lead, PDF_EHIP, "hipEventRecord");
-      for (Recon* r : act)
-        if (!rc && hipStreamWaitEvent(r->h->stream, evs.back(), 0) != hipSuccess)
-          rc = fail(lead, PDF_EHIP, "stream fork failed");
-    } else {
-      for (Recon* r : act)
-        if (!rc) rc = r->iterate(chunk);
     }
+    if (!any) break;
     done += chunk;
-    for (Recon* r : act)
-      if (!rc) rc = r->check();
+    for (Recon* r : rs)
+      if (!rc && r->active()) rc = r->check();
   }
-  drop_graph();
-  for (auto& e : evs)
-    if (e) (void)hipEventDestroy(e);
+  for (size_t i = 0; i < n; ++i) {
+    if (execs[i]) (void)hipGraphExecDestroy(execs[i]);
+    if (graphs[i]) (void)hipGraphDestroy(graphs[i]);
+  }
   if (rc) return rc;
   int reached = 0;
   bool any_target = false;

@@ -216,6 +216,22 @@ def rasterize(shapes: Sequence[Shape], M: int, side: float, cx: float = 0.0,
     return eps
 
 
+def uneven_shapes(n: int, seed: int, grids=(32, 64), antennas=(16, 24, 32, 48, 64),
+                  truncations=(7, 9, 11, 13, 15, 17, 19, 21)):
+    """Per-instance (M, N_i = N_s, K) of an uneven batch, drawn uniformly from the given sets
+    (K <= M is kept by redrawing K)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        M = int(rng.choice(grids))
+        a = int(rng.choice(antennas))
+        K = int(rng.choice(truncations))
+        while K > M:
+            K = int(rng.choice(truncations))
+        out.append((M, a, K))
+    return out
+
+
 def antenna_positions(n: int, radius: float, cx: float = 0.0, cy: float = 0.0,
                       angle_offsets: Optional[np.ndarray] = None) -> np.ndarray:
     """n antennas equally spaced on a circle, the first at angle 0; [n, 2] (x, y)."""
