@@ -39,7 +39,7 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-constexpr int GT = 128, GK = 32, LDK = GK + 8;  // tile, K step, padded LDS row (bf16)
+constexpr int GK = 32, LDK = GK + 8;  // K step, padded LDS row (bf16)
 
 enum Epi { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_GELU_GRAD = 3 };
 
@@ -58,13 +58,14 @@ struct GemmArgs {
 };
 
 // Loads an operand tile of GT rows (m or n) x GK k into LDS as [row][k].
-template <bool KCONTIG>
+template <int GT, bool KCONTIG>
 __device__ __forceinline__ void stage(u16* S, const u16* src, int ld, int row0, int nrows, int k0, int K,
                                       int tid) {
+  constexpr int IT = GT * GK / 8 / 256;  // vectors of 8 per thread
   if constexpr (KCONTIG) {
-    // 128 rows x 32 k = 512 vectors of 8; two per thread
+    // GT rows x 32 k = GT * 4 vectors of 8
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < IT; ++it) {
       const int v = tid + it * 256;
       const int r = v >> 2, kq = (v & 3) * 8;
       const int row = row0 + r, k = k0 + kq;
@@ -84,11 +85,11 @@ __device__ __forceinline__ void stage(u16* S, const u16* src, int ld, int row0, 
       *reinterpret_cast<uint4*>(S + r * LDK + kq) = val;
     }
   } else {
-    // 32 k-rows x 128 rows: each thread takes 8 consecutive rows of two k
+    // 32 k-rows x GT rows: each vector is 8 consecutive rows of one k
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < IT; ++it) {
       const int v = tid + it * 256;
-      const int kk = v >> 4, rq = (v & 15) * 8;
+      const int kk = v / (GT / 8), rq = (v % (GT / 8)) * 8;
       const int k = k0 + kk, row = row0 + rq;
       u16 e[8];
       if (k < K && row + 8 <= nrows) {
@@ -111,45 +112,50 @@ __device__ __forceinline__ void stage(u16* S, const u16* src, int ld, int row0, 
   }
 }
 
-template <bool AK, bool BK, int EPI>
+// GT x GT output tile per workgroup (GT = 128: each wave 2 x 2 MFMA tiles of
+// 32 x 32; GT = 64: one tile each, for products too small to fill the chip
+// with 128-wide tiles).
+template <int GT, bool AK, bool BK, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int WT = GT / 64;  // MFMA tiles per wave and dimension
   __shared__ __align__(16) u16 sA[GT * LDK];
   __shared__ __align__(16) u16 sB[GT * LDK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  floatx16 acc[2][2];
+  const int wm = (w >> 1) * (GT / 2), wn = (w & 1) * (GT / 2);
+  floatx16 acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   for (int k0 = 0; k0 < g.K; k0 += GK) {
-    stage<AK>(sA, g.A, g.lda, m0, g.Mr, k0, g.K, tid);
-    stage<BK>(sB, g.B, g.ldb, n0, g.Nc, k0, g.K, tid);
+    stage<GT, AK>(sA, g.A, g.lda, m0, g.Mr, k0, g.K, tid);
+    stage<GT, BK>(sB, g.B, g.ldb, n0, g.Nc, k0, g.K, tid);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[WT], b[WT];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < WT; ++i) {
         // lane (l % 32, l / 32) holds A[m = l % 32][k = 8 (l / 32) + j], likewise B[n][k]
         a[i] = *reinterpret_cast<const bf16x8*>(sA + (wm + 32 * i + (lane & 31)) * LDK + ks + 8 * (lane >> 5));
         b[i] = *reinterpret_cast<const bf16x8*>(sB + (wn + 32 * i + (lane & 31)) * LDK + ks + 8 * (lane >> 5));
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < WT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   // D[m][n]: lane l holds n = l % 32 and rows m = (r % 4) + 8 (r / 4) + 4 (l / 32)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm + 32 * i + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
@@ -287,10 +293,17 @@ int mcheck(pdf_mlp* n, const char* what) {
   return PDF_OK;
 }
 
+// 128-wide tiles when they give at least two workgroups per CU, else 64-wide.
 template <bool AK, bool BK, int EPI>
 void launch_gemm(pdf_mlp* n, const GemmArgs& g) {
-  dim3 grid((g.Nc + GT - 1) / GT, (g.Mr + GT - 1) / GT);
-  hipLaunchKernelGGL((k_gemm_bf16<AK, BK, EPI>), grid, dim3(256), 0, n->stream, g);
+  const long big = long((g.Nc + 127) / 128) * ((g.Mr + 127) / 128);
+  if (big >= 512) {
+    dim3 grid((g.Nc + 127) / 128, (g.Mr + 127) / 128);
+    hipLaunchKernelGGL((k_gemm_bf16<128, AK, BK, EPI>), grid, dim3(256), 0, n->stream, g);
+  } else {
+    dim3 grid((g.Nc + 63) / 64, (g.Mr + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_bf16<64, AK, BK, EPI>), grid, dim3(256), 0, n->stream, g);
+  }
 }
 
 // forward of B rows from the bfloat16 input a[0] (already staged); y = out_scale * output

@@ -138,6 +138,29 @@ __global__ __launch_bounds__(256) void k_scatter_out(const cx<double>* gsS, cons
 
 // Device allocations of one solve, stream-ordered so that concurrent solves
 // on other streams are not serialised by allocation or release.
+// Values of c_a H0(k0 |r_a - r_c|) for antennas a and support pixels c by
+// cubic Hermite interpolation of H0^(1) between samples at multiples of dx
+// (tab[2i] = H0(x_i), tab[2i+1] = H1(x_i), x_i = (i0 + i) dx, H0' = -H1).
+// The nodes depend on dx only, not on the table's extent, so every value is
+// the same whatever other antennas shared the table.
+__global__ void k_antenna_field(const double* axy, const cx<double>* ascale, int na, const double* px,
+                                const double* py, int nS, double k0, const cx<double>* tab, int i0, int nt,
+                                double dx, cx<double>* out) {
+  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= size_t(na) * nS) return;
+  const int a = int(idx / nS), c = int(idx % nS);
+  const double x = k0 * hypot(axy[2 * a] - px[c], axy[2 * a + 1] - py[c]);
+  const double xs = x / dx, fl = floor(xs), t = xs - fl;
+  const int i = min(max(int(fl) - i0, 0), nt - 2);
+  const cx<double> f0 = tab[2 * i], f1 = tab[2 * i + 2];
+  const cx<double> d0{-dx * tab[2 * i + 1].x, -dx * tab[2 * i + 1].y};
+  const cx<double> d1{-dx * tab[2 * i + 3].x, -dx * tab[2 * i + 3].y};
+  const double u = 1.0 - t;
+  const double h00 = (1.0 + 2.0 * t) * u * u, h10 = t * u * u, h01 = t * t * (3.0 - 2.0 * t), h11 = -t * t * u;
+  const cx<double> v{h00 * f0.x + h10 * d0.x + h01 * f1.x + h11 * d1.x, h00 * f0.y + h10 * d0.y + h01 * f1.y + h11 * d1.y};
+  out[idx] = ascale[a] * v;
+}
+
 struct Dev {
   hipStream_t st;
   std::vector<void*> ptrs;
@@ -160,7 +183,15 @@ struct Shared {
   cd cell;
   std::vector<cd> ker;               // offset kernel [(2M-1)^2]
   const cx<double>* dker = nullptr;  // its device copy
+  // Hankel samples for the antenna fields (null: evaluate on the host)
+  const cx<double>* dtab = nullptr;  // [nt][2] H0, H1 at (i0 + i) dx
+  int i0 = 0, nt = 0;
+  double dx = 0.0;
 };
+
+// Hermite error about dx^4 / 384 times the fourth derivative of H0: below 1e-13 for x >= 1
+constexpr double kTabDx = 2e-3;
+constexpr double kTabMinX = 1.0;  // closer antennas (larger derivatives) use the host path
 
 #define MOM_TRY(call)                                                  \
   do {                                                                 \
@@ -192,7 +223,11 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   }
   const double k0 = sh.k0, h = sh.h;
   std::vector<int> si(nS), sj(nS);
-  std::vector<cd> chi(nS), einc(size_t(ni) * nS), gsS(size_t(ns) * nS);
+  std::vector<cd> chi(nS), einc, gsS;
+  if (!sh.dtab) {
+    einc.resize(size_t(ni) * nS);
+    gsS.resize(size_t(ns) * nS);
+  }
   std::vector<double> xs(nS), ys(nS);
   for (int c = 0; c < nS; ++c) {
     si[c] = S[c] / M;
@@ -201,17 +236,22 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
     xs[c] = sh.gx - sh.side / 2.0 + (sj[c] + 0.5) * h;
     ys[c] = sh.gy - sh.side / 2.0 + (si[c] + 0.5) * h;
   }
-  // incident fields and receiver operator on the support only
-  pdfh::parallel_for(ni + ns, host_threads, [&](int b0, int b1) {
-    for (int r = b0; r < b1; ++r) {
-      const bool is_tx = r < ni;
-      const double* xy = is_tx ? tx->xy + 2 * r : rx->xy + 2 * (r - ni);
-      cd scale = sh.cell;
-      if (is_tx) scale = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(xy[0] - sh.gx, xy[1] - sh.gy)));
-      cd* dst = is_tx ? &einc[size_t(r) * nS] : &gsS[size_t(r - ni) * nS];
-      for (int c = 0; c < nS; ++c) dst[c] = scale * pdfh::hankel1(0, k0 * std::hypot(xy[0] - xs[c], xy[1] - ys[c]));
-    }
-  });
+  // incident fields and receiver operator on the support only: on the device
+  // from the shared Hankel samples, else on the host
+  const bool dev_fields = sh.dtab != nullptr;
+  std::vector<cd> tscale(ni);
+  for (int p = 0; p < ni; ++p)
+    tscale[p] = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(tx->xy[2 * p] - sh.gx, tx->xy[2 * p + 1] - sh.gy)));
+  if (!dev_fields)
+    pdfh::parallel_for(ni + ns, host_threads, [&](int b0, int b1) {
+      for (int r = b0; r < b1; ++r) {
+        const bool is_tx = r < ni;
+        const double* xy = is_tx ? tx->xy + 2 * r : rx->xy + 2 * (r - ni);
+        const cd scale = is_tx ? tscale[r] : sh.cell;
+        cd* dst = is_tx ? &einc[size_t(r) * nS] : &gsS[size_t(r - ni) * nS];
+        for (int c = 0; c < nS; ++c) dst[c] = scale * pdfh::hankel1(0, k0 * std::hypot(xy[0] - xs[c], xy[1] - ys[c]));
+      }
+    });
 
   Dev dv(st);
   cx<double> *dA, *dchi, *db, *dgs, *x, *r, *rh, *p, *v, *s, *tt, *dots, *sc1, *sc2, *dout;
@@ -222,7 +262,7 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   MOM_TRY(dv.alloc(&dsi, sizeof(int) * nS));
   MOM_TRY(dv.alloc(&dsj, sizeof(int) * nS));
   MOM_TRY(dv.alloc(&db, vb));
-  MOM_TRY(dv.alloc(&dgs, sizeof(cx<double>) * gsS.size()));
+  MOM_TRY(dv.alloc(&dgs, sizeof(cx<double>) * size_t(ns) * nS));
   for (auto** q : {&x, &r, &rh, &p, &v, &s, &tt}) MOM_TRY(dv.alloc(q, vb));
   MOM_TRY(dv.alloc(&dots, sizeof(cx<double>) * ni * 3));
   MOM_TRY(dv.alloc(&sc1, sizeof(cx<double>) * ni));
@@ -231,8 +271,30 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   MOM_TRY(hipMemcpyAsync(dchi, chi.data(), sizeof(cd) * nS, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(dsi, si.data(), sizeof(int) * nS, hipMemcpyHostToDevice, st));
   MOM_TRY(hipMemcpyAsync(dsj, sj.data(), sizeof(int) * nS, hipMemcpyHostToDevice, st));
-  MOM_TRY(hipMemcpyAsync(db, einc.data(), vb, hipMemcpyHostToDevice, st));
-  MOM_TRY(hipMemcpyAsync(dgs, gsS.data(), sizeof(cd) * gsS.size(), hipMemcpyHostToDevice, st));
+  if (dev_fields) {
+    double *dpx, *dpy, *daxy;
+    cx<double>* dsc;
+    const std::vector<cd> rscale(ns, sh.cell);
+    MOM_TRY(dv.alloc(&dpx, sizeof(double) * nS));
+    MOM_TRY(dv.alloc(&dpy, sizeof(double) * nS));
+    MOM_TRY(dv.alloc(&daxy, sizeof(double) * 2 * (ni + ns)));
+    MOM_TRY(dv.alloc(&dsc, sizeof(cx<double>) * (ni + ns)));
+    MOM_TRY(hipMemcpyAsync(dpx, xs.data(), sizeof(double) * nS, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(dpy, ys.data(), sizeof(double) * nS, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(daxy, tx->xy, sizeof(double) * 2 * ni, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(daxy + 2 * ni, rx->xy, sizeof(double) * 2 * ns, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(dsc, tscale.data(), sizeof(cd) * ni, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(dsc + ni, rscale.data(), sizeof(cd) * ns, hipMemcpyHostToDevice, st));
+    const size_t ne = size_t(ni) * nS, nr = size_t(ns) * nS;
+    hipLaunchKernelGGL(k_antenna_field, dim3((ne + 255) / 256), dim3(256), 0, st, daxy, dsc, ni, dpx, dpy, nS, k0,
+                       sh.dtab, sh.i0, sh.nt, sh.dx, db);
+    hipLaunchKernelGGL(k_antenna_field, dim3((nr + 255) / 256), dim3(256), 0, st, daxy + 2 * ni, dsc + ni, ns, dpx,
+                       dpy, nS, k0, sh.dtab, sh.i0, sh.nt, sh.dx, dgs);
+    MOM_TRY(hipGetLastError());
+  } else {
+    MOM_TRY(hipMemcpyAsync(db, einc.data(), vb, hipMemcpyHostToDevice, st));
+    MOM_TRY(hipMemcpyAsync(dgs, gsS.data(), sizeof(cd) * gsS.size(), hipMemcpyHostToDevice, st));
+  }
   const size_t nA = size_t(nS) * nS;
   hipLaunchKernelGGL(k_mom_build, dim3((nA + 255) / 256), dim3(256), 0, st, dA, sh.dker, dsi, dsj, dchi, nS, M);
   MOM_TRY(hipGetLastError());
@@ -356,8 +418,8 @@ int check_args(const pdf_grid* grid, double freq_hz, double tol) {
 }
 
 // Host offset kernel and its device copy (uploaded on st, which is synchronised).
-int make_shared(const pdf_grid* grid, double freq_hz, hipStream_t st, Shared* sh, cx<double>** dker,
-                std::string* err) {
+int make_shared(const pdf_grid* grid, double freq_hz, int n, const pdf_array* tx, const pdf_array* rx,
+                hipStream_t st, Shared* sh, cx<double>** dker, cx<double>** dtab, std::string* err) {
   sh->M = grid->M;
   sh->side = grid->side;
   sh->gx = grid->cx;
@@ -369,8 +431,34 @@ int make_shared(const pdf_grid* grid, double freq_hz, hipStream_t st, Shared* sh
   pdfh::offset_kernel(sh->M, sh->h, sh->k0, &sh->ker);
   MOM_TRY(hipMalloc(reinterpret_cast<void**>(dker), sizeof(cx<double>) * sh->ker.size()));
   MOM_TRY(hipMemcpyAsync(*dker, sh->ker.data(), sizeof(cd) * sh->ker.size(), hipMemcpyHostToDevice, st));
-  MOM_TRY(hipStreamSynchronize(st));
   sh->dker = *dker;
+  // Hankel samples covering k0 |r_a - r_c| for every antenna a and pixel centre c
+  const double hd = grid->side / std::sqrt(2.0);
+  double xmin = HUGE_VAL, xmax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (const pdf_array* arr : {&tx[i], &rx[i]})
+      for (int a = 0; a < arr->n; ++a) {
+        const double r = std::hypot(arr->xy[2 * a] - grid->cx, arr->xy[2 * a + 1] - grid->cy);
+        xmin = std::min(xmin, sh->k0 * (r - hd));
+        xmax = std::max(xmax, sh->k0 * (r + hd));
+      }
+  if (xmin >= kTabMinX && std::isfinite(xmax)) {
+    sh->dx = kTabDx;
+    sh->i0 = int(std::floor(xmin / kTabDx)) - 2;
+    sh->nt = int(std::ceil(xmax / kTabDx)) + 3 - sh->i0;
+    std::vector<cd> tab(2 * size_t(sh->nt));
+    pdfh::parallel_for(sh->nt, [&](int b0, int b1) {
+      for (int i = b0; i < b1; ++i) {
+        const double x = (sh->i0 + i) * kTabDx;
+        tab[2 * size_t(i)] = pdfh::hankel1(0, x);
+        tab[2 * size_t(i) + 1] = pdfh::hankel1(1, x);
+      }
+    });
+    MOM_TRY(hipMalloc(reinterpret_cast<void**>(dtab), sizeof(cx<double>) * tab.size()));
+    MOM_TRY(hipMemcpyAsync(*dtab, tab.data(), sizeof(cd) * tab.size(), hipMemcpyHostToDevice, st));
+    sh->dtab = *dtab;
+  }
+  MOM_TRY(hipStreamSynchronize(st));
   return PDF_OK;
 }
 
@@ -390,15 +478,15 @@ extern "C" int pdf_synthesize(const pdf_grid* grid, double freq_hz, const pdf_ar
   hipStream_t st = (hipStream_t)stream_v;
   Shared sh;
   cx<double>* dker = nullptr;
+  cx<double>* dtab = nullptr;
   std::string err;
-  int rc = make_shared(grid, freq_hz, st, &sh, &dker, &err);
+  int rc = make_shared(grid, freq_hz, 1, tx, rx, st, &sh, &dker, &dtab, &err);
   if (rc == PDF_OK)
     rc = solve_one(sh, tx, rx, reinterpret_cast<const cd*>(eps_host), tol, reinterpret_cast<cd*>(esca_host), 0,
                    nullptr, st, 16, &err);
-  if (dker) {
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(dker);
-  }
+  (void)hipStreamSynchronize(st);
+  if (dker) (void)hipFree(dker);
+  if (dtab) (void)hipFree(dtab);
   if (rc) pdf_set_global_error(err);
   return rc;
 }
@@ -425,9 +513,12 @@ extern "C" int pdf_synthesize_batch(const pdf_grid* grid, double freq_hz, int32_
   hipStream_t st0 = (hipStream_t)stream_v;
   Shared sh;
   cx<double>* dker = nullptr;
+  cx<double>* dtab = nullptr;
   std::string err0;
-  if (int rc = make_shared(grid, freq_hz, st0, &sh, &dker, &err0)) {
+  if (int rc = make_shared(grid, freq_hz, n, tx, rx, st0, &sh, &dker, &dtab, &err0)) {
     pdf_set_global_error(err0);
+    if (dker) (void)hipFree(dker);
+    if (dtab) (void)hipFree(dtab);
     return rc;
   }
   const int W = std::max(1, std::min({int(workers > 0 ? workers : 8), int(n), 16}));
@@ -457,6 +548,7 @@ extern "C" int pdf_synthesize_batch(const pdf_grid* grid, double freq_hz, int32_
     });
   for (auto& t : th) t.join();
   (void)hipFree(dker);
+  if (dtab) (void)hipFree(dtab);
   for (int w = 0; w < W; ++w)
     if (rcs[w]) {
       pdf_set_global_error(errs[w]);

@@ -244,6 +244,12 @@ def test_synthesize_matches_oracle_mom():
     got = pdf.synthesize(64, wl.side, wl.freq_hz, tx, rx, eps, tol=1e-11, device=DEV)
     ref, _ = forward.mom_solve(eps, wl.side, ops.wavenumber(wl.freq_hz), tx, rx)
     assert rel(got, ref) < 1e-9, rel(got, ref)
+    # antennas 1.5 wavelengths from the centre of a 2-wavelength domain: too close for the
+    # interpolated Hankel samples, so the host evaluates the antenna fields
+    txn, rxn = geometry(6, 7, radius_wl=1.5)
+    got = pdf.synthesize(64, wl.side, wl.freq_hz, txn, rxn, eps, tol=1e-11, device=DEV)
+    ref, _ = forward.mom_solve(eps, wl.side, ops.wavenumber(wl.freq_hz), txn, rxn)
+    assert rel(got, ref) < 1e-9, rel(got, ref)
     # empty support: zero field
     z = pdf.synthesize(16, wl.side, wl.freq_hz, tx, rx, np.ones((16, 16)), device=DEV)
     assert np.all(z == 0)
