@@ -182,15 +182,21 @@ def synthesize_batch(pdf, si, wl, B, dev):
     """Measured fields of B random instances: FP64 MoM on the fine grid with jittered antennas, plus noise."""
     import numpy as np
     Ni, Ns, M = wl.n_tx, wl.n_rx, wl.M
-    txs, rxs, eps_f = [], [], np.zeros((B, wl.M_fine, wl.M_fine), np.complex128)
-    eps = np.zeros((B, M, M), np.complex128)
-    for b in range(B):
+    from concurrent.futures import ThreadPoolExecutor
+
+    def draw(b):
         shapes = si.draw_profile(wl, b)
         jt, jr = si.draw_jitter(b, Ni, Ns, wl.jitter_deg)
-        txs.append(si.antenna_positions(Ni, wl.radius, angle_offsets=jt))
-        rxs.append(si.antenna_positions(Ns, wl.radius, angle_offsets=jr))
-        eps_f[b] = si.rasterize(shapes, wl.M_fine, wl.side)
-        eps[b] = si.rasterize(shapes, M, wl.side)
+        return (si.antenna_positions(Ni, wl.radius, angle_offsets=jt),
+                si.antenna_positions(Ns, wl.radius, angle_offsets=jr),
+                si.rasterize(shapes, wl.M_fine, wl.side), si.rasterize(shapes, M, wl.side))
+
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        drawn = list(pool.map(draw, range(B)))
+    txs = [d[0] for d in drawn]
+    rxs = [d[1] for d in drawn]
+    eps_f = np.stack([d[2] for d in drawn])
+    eps = np.stack([d[3] for d in drawn])
     e = pdf.synthesize_batch(wl.M_fine, wl.side, wl.freq_hz, txs, rxs, eps_f, tol=1e-10, device=dev)
     esca = np.zeros((B, Ni, Ns), np.complex128)
     for b in range(B):
@@ -236,7 +242,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the steps, as a "
                          "reference of known traffic for hardware byte counters")
-    ap.add_argument("--warm-pairs", type=int, default=4096,
+    ap.add_argument("--warm-pairs", type=int, default=20000,
                     help="training pairs of the warm-start network (0: skip the warm-start leg)")
     ap.add_argument("--warm-epochs", type=int, default=40)
     ap.add_argument("--uneven", type=int, default=512,

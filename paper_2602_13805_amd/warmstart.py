@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import dataclasses
 import time
+from concurrent.futures import ThreadPoolExecutor
 from typing import Optional, Sequence
 
 import numpy as np
@@ -49,17 +50,21 @@ def make_dataset(si, wl, seeds: Sequence[int], device: str = "cuda:0", chunk: in
     xs, ts, eps_all = [], [], []
     seeds = np.asarray(seeds, dtype=np.int64)
     t0 = time.time()
+    def draw(s):
+        shapes = si.draw_profile(wl, int(s))
+        jt, jr = si.draw_jitter(int(s), Ni, Ns, wl.jitter_deg)
+        return (si.antenna_positions(Ni, wl.radius, angle_offsets=jt),
+                si.antenna_positions(Ns, wl.radius, angle_offsets=jr),
+                si.rasterize(shapes, wl.M_fine, wl.side), si.rasterize(shapes, M, wl.side))
+
+    pool = ThreadPoolExecutor(max_workers=8)
     for c0 in range(0, len(seeds), chunk):
         cs = seeds[c0:c0 + chunk]
-        txs, rxs = [], []
-        epsf = np.zeros((len(cs), wl.M_fine, wl.M_fine), np.complex128)
-        for i, s in enumerate(cs):
-            shapes = si.draw_profile(wl, int(s))
-            jt, jr = si.draw_jitter(int(s), Ni, Ns, wl.jitter_deg)
-            txs.append(si.antenna_positions(Ni, wl.radius, angle_offsets=jt))
-            rxs.append(si.antenna_positions(Ns, wl.radius, angle_offsets=jr))
-            epsf[i] = si.rasterize(shapes, wl.M_fine, wl.side)
-            eps_all.append(si.rasterize(shapes, M, wl.side))
+        drawn = list(pool.map(draw, cs))   # seeded per instance: the order of completion does not matter
+        txs = [d[0] for d in drawn]
+        rxs = [d[1] for d in drawn]
+        epsf = np.stack([d[2] for d in drawn])
+        eps_all.extend(d[3] for d in drawn)
         es, jc = _b.synthesize_batch(wl.M_fine, wl.side, wl.freq_hz, txs, rxs, epsf, tol=1e-10, coarse=d,
                                      device=device)
         for i, s in enumerate(cs):
@@ -71,6 +76,7 @@ def make_dataset(si, wl, seeds: Sequence[int], device: str = "cuda:0", chunk: in
         ts.append(torch.view_as_real(alpha).reshape(len(cs), -1).contiguous())
         if log:
             log(f"  warm-start data {c0 + len(cs)}/{len(seeds)} ({time.time() - t0:.1f} s)")
+    pool.shutdown()
     sv.close()
     return Dataset(torch.cat(xs), torch.cat(ts), np.stack(eps_all), seeds)
 
