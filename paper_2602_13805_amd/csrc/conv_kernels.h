@@ -23,6 +23,7 @@ struct ConvCfg {
   static_assert(N % NT == 0, "pixel ownership must be exact");
   static_assert(P >= 16, "the column pass needs P >= 16");
   static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(P) * TileL::LD + P);
+  static constexpr int BOT = M * TileL::LD;       // offset of rows M..2M-1: the second region
   using Rows = Vecs<P, M, true>;                 // the M nonzero rows, elements along a row
   using Cols = Vecs<P, P, false, false, true>;   // all P columns, wave-local
   using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
@@ -38,8 +39,10 @@ struct ConvCfg {
 // inverse transform's first pass share their registers (both radix R2 on the
 // elements j + R1 r of butterfly j), so the spectrum is multiplied in
 // registers and one LDS round trip is saved.
+// The input column (rows < M) is read from the region at element offset
+// src; the result is in rows < M of the tile (offset 0).
 template <typename T, int M>
-__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
   using C = ConvCfg<T, M>;
   constexpr int P = C::P;
   using F = Fft<T, P, C::EPT_C, C::NT, typename C::Cols, 1>;
@@ -67,14 +70,22 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
   if constexpr (R2 == 1) {
     typename F::Regs g;
     f.assign(g);
-    f.template load<R1, 1, -1, R1 / 2>(g, NoLoad());
+    f.template load<R1, 1, -1, R1 / 2>(g, NoLoad(), src);
     F::sync();
     f.template compute<R1, -1, R1 / 2, R1>(g);
     mul_ghat(g, std::integral_constant<int, R1>{}, 1);
     f.template compute<R1, +1, R1, R1 / 2>(g);
     f.template store<R1, 1, R1 / 2>(g);
   } else {
-    f.template pass<R1, 1, -1, R1 / 2, R1>(NoLoad());
+    {  // first pass: from the source region into the whole column (they overlap: wave sync between)
+      typename F::Regs g1;
+      f.assign(g1);
+      f.template load<R1, 1, -1, R1 / 2>(g1, NoLoad(), src);
+      F::sync();
+      f.template compute<R1, -1, R1 / 2, R1>(g1);
+      f.template store<R1, 1, R1>(g1);
+      F::sync();
+    }
     typename F::Regs g;
     f.assign(g);
     f.template load<R2, R1, -1, R2>(g, NoLoad());
@@ -89,19 +100,28 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
   __syncthreads();  // the row pass that follows reads every column
 }
 
-// In place on the top-left M x M of the LDS tile: x -> G_D x (or G_D^H x),
-// where the spectrum ghat is pre-scaled by 1/P^2.  Entries outside the
-// M x M block are never read before being written.
-template <typename T, int M>
-__device__ __forceinline__ void conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+// x -> G_D x (or G_D^H x) for x on the M x M block of region `src` (element
+// offset 0: rows 0..M-1 of the tile, or BOT: rows M..2M-1); returns the
+// offset of the region holding the result.  The spectrum ghat is pre-scaled
+// by 1/P^2.  With PP the row passes alternate between the two regions (one
+// barrier each), else they run in place (two barriers each): measured, the
+// first is faster in the forward kernel and the second in the adjoint one.
+// The column phase is wave-local and ends with a workgroup barrier.
+template <typename T, int M, bool PP>
+__device__ __forceinline__ int conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
   using C = ConvCfg<T, M>;
-  constexpr int P = C::P;
-  // every row pass begins and ends with a workgroup barrier; the column phase
-  // is wave-local and ends with one
+  constexpr int P = C::P, BOT = C::BOT;
   const Fft<T, P, C::EPT_R, C::NT, typename C::Rows, 1> rows{buf, tw, typename C::Rows{}};
-  rows.template run<-1, M, P>();
-  col_conv<T, M>(buf, tw, ghat, adjoint);
-  rows.template run<+1, P, M>();
+  if constexpr (PP) {
+    const int r = rows.template run_pp<-1, M, P>(src, src == 0 ? BOT : 0);
+    col_conv<T, M>(buf, tw, ghat, adjoint, r);
+    return rows.template run_pp<+1, P, M>(0, BOT);
+  } else {
+    rows.template run<-1, M, P>(NoLoad(), src);
+    col_conv<T, M>(buf, tw, ghat, adjoint, src);
+    rows.template run<+1, P, M>(NoLoad(), 0);
+    return 0;
+  }
 }
 
 __device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
@@ -131,6 +151,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
   cx<T> jr[C::PPT];
+  int src = 0;  // region holding J
   if constexpr (FROM_ALPHA) {
     // the coefficients (K^2 <= N) are loaded with the twiddles in one round trip
     const int K = a.K, KK = K * K, kmin = -(K / 2);
@@ -139,7 +160,11 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) av[q] = al[min(tid + q * C::NT, KK - 1)];
     for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
-    for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+    // both regions start at zero: the mode passes write only the K kept rows
+    for (int e = tid; e < C::N; e += C::NT) {
+      buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+      buf[C::BOT + C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
@@ -150,12 +175,14 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
     typename C::ModeRows mr;
     mr.nv = K;
     mr.kmin = kmin;
-    Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
-    Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
+    int r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run_pp<+1>(0, C::BOT);
+    r = Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run_pp<+1>(
+        r, r == 0 ? C::BOT : 0);
+    src = r;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = buf[C::TileL::at(n / M, n % M)];
+      jr[q] = buf[r + C::TileL::at(n / M, n % M)];
       if (a.J) a.J[off + n] = jr[q];
     }
   } else {
@@ -169,7 +196,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
     }
     __syncthreads();
   }
-  conv_core<T, M>(buf, tw, a.ghat, false);
+  const int res = conv_core<T, M, true>(buf, tw, a.ghat, false, src);
   // all loads of the epilogue are issued before their use (the workgroup
   // fills its CU, so nothing else hides their latency)
   cx<T> ei[C::PPT];
@@ -183,7 +210,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    a.E[off + n] = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
+    a.E[off + n] = buf[res + C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
   }
 }
 
@@ -283,20 +310,20 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
     gj[q] = gJ;
   }
   __syncthreads();
-  conv_core<T, M>(buf, tw, a.ghat, true);
+  int r = conv_core<T, M, false>(buf, tw, a.ghat, true, 0);
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    cx<T>& x = buf[C::TileL::at(n / M, n % M)];
+    cx<T>& x = buf[r + C::TileL::at(n / M, n % M)];
     x = x + gj[q];
   }
   __syncthreads();
   const int K = a.K, kmin = -(K / 2);
-  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>();
+  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>(NoLoad(), r);
   typename C::ModeCols mc;
   mc.nv = K;
   mc.kmin = kmin;
-  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>();
+  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(NoLoad(), r);
   const bool upd = a.alpha && !(a.frozen && a.frozen[b]);
   double bc1 = 1.0, bc2 = 1.0;
   if (upd) {
@@ -306,7 +333,7 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
   }
   for (int e = tid; e < K * K; e += C::NT) {
     const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
-    const cx<T> g = buf[C::TileL::at(iy, ix)];
+    const cx<T> g = buf[r + C::TileL::at(iy, ix)];
     const size_t idx = size_t(bp) * K * K + e;
     if (a.galpha) a.galpha[idx] = g;
     if (upd) {
@@ -350,14 +377,15 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_analyze(const cx<T>* J,
   }
   __syncthreads();
   const int kmin = -(K / 2);
-  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>();
+  int r = Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run_pp<-1>(
+      0, C::BOT);
   typename C::ModeCols mc;
   mc.nv = K;
   mc.kmin = kmin;
-  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>();
+  r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run_pp<-1>(r, r == 0 ? C::BOT : 0);
   const T s = T(1) / T(C::N);
   for (int e = tid; e < K * K; e += C::NT) {
-    const cx<T> g = buf[C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))];
+    const cx<T> g = buf[r + C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))];
     alpha[v * K * K + e] = cx<T>{s * g.x, s * g.y};
   }
 }

@@ -2,9 +2,9 @@
 //
 // Radix-R Stockham autosort passes: each thread holds EPT elements of one
 // vector in registers, does EPT/R radix-R butterflies per pass with the
-// in-register FFTs below, and exchanges through LDS between passes (load all,
-// barrier, store all, barrier), so the transform is in place and needs no
-// bit reversal.  Vectors are rows or columns of a 2-D tile.  Threads are
+// in-register FFTs below, and exchanges through LDS between passes, either in
+// place (load all, barrier, store all, barrier) or between two disjoint
+// regions of the tile (load, store, one barrier); no bit reversal is needed.  Vectors are rows or columns of a 2-D tile.  Threads are
 // assigned vector-fastest, so neighbouring lanes touch neighbouring rows or
 // columns.  Zero-padded inputs and cropped outputs are known at compile time
 // and their butterflies are skipped.
@@ -261,7 +261,7 @@ struct Fft {
   // the pass twiddle.  In a first pass (NS = 1) inputs r >= ZR are zero and
   // ld(v, k, x) is applied to every element read.
   template <int R, int NS, int DIR, int ZR, class LoadOp>
-  __device__ __forceinline__ void load(Regs& g, const LoadOp& ld) const {
+  __device__ __forceinline__ void load(Regs& g, const LoadOp& ld, int off = 0) const {
     constexpr int BPT = EPT / R, LR = L / R;
 #pragma unroll
     for (int q = 0; q < UPT; ++q) {
@@ -274,7 +274,7 @@ struct Fft {
           cx<T> x{T(0), T(0)};
           if (r < ZR) {
             const int k = j + r * LR;
-            x = buf[vs.addr(g.vec[q], k)];
+            x = buf[off + vs.addr(g.vec[q], k)];
             if constexpr (NS == 1) x = ld(g.vec[q], k, x);
             if constexpr (NS > 1) {
               if (r > 0) {
@@ -303,7 +303,7 @@ struct Fft {
   // Store of a pass: output r of butterfly j goes to (j / NS) NS R + j % NS + r NS;
   // only outputs r < KR are written.
   template <int R, int NS, int KR>
-  __device__ __forceinline__ void store(const Regs& g) const {
+  __device__ __forceinline__ void store(const Regs& g, int off = 0) const {
 #pragma unroll
     for (int q = 0; q < UPT; ++q) {
       if (!g.act[q]) continue;
@@ -312,36 +312,67 @@ struct Fft {
         const int j = g.t[q] + u * TPV;
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int r = 0; r < KR; ++r) buf[vs.addr(g.vec[q], base + r * NS)] = g.v[q][u * R + r];
+        for (int r = 0; r < KR; ++r) buf[off + vs.addr(g.vec[q], base + r * NS)] = g.v[q][u * R + r];
       }
     }
   }
 
-  // One full pass: load, barrier, butterflies, store, barrier.
+  // One full pass in place on the region at element offset off: load,
+  // barrier, butterflies, store, barrier.
   template <int R, int NS, int DIR, int ZR, int KR, class LoadOp>
-  __device__ __forceinline__ void pass(const LoadOp& ld) const {
+  __device__ __forceinline__ void pass(const LoadOp& ld, int off = 0) const {
     Regs g;
     assign(g);
-    load<R, NS, DIR, ZR>(g, ld);
+    load<R, NS, DIR, ZR>(g, ld, off);
     sync();
     compute<R, DIR, ZR, KR>(g);
-    store<R, NS, KR>(g);
+    store<R, NS, KR>(g, off);
     sync();
   }
 
-  // The whole transform with radices EPT, EPT, ..., remainder.  NZ: inputs
-  // k >= NZ are zero; KEEP: only outputs k < KEEP are stored (both must be
-  // multiples of the stride they apply at, e.g. L/2).
+  // One pass from region src to the disjoint region dst (element offsets into
+  // the tile): loads, butterflies, stores, then one barrier; no barrier is
+  // needed between the loads and the stores.
+  template <int R, int NS, int DIR, int ZR, int KR, class LoadOp>
+  __device__ __forceinline__ void pass_oop(const LoadOp& ld, int src, int dst) const {
+    Regs g;
+    assign(g);
+    load<R, NS, DIR, ZR>(g, ld, src);
+    compute<R, DIR, ZR, KR>(g);
+    store<R, NS, KR>(g, dst);
+    sync();
+  }
+
+  // The whole transform alternating between the disjoint regions a and b (the
+  // first pass reads a); returns the offset of the region holding the result.
   template <int DIR, int NZ = L, int KEEP = L, int NS = 1, class LoadOp = NoLoad>
-  __device__ __forceinline__ void run(const LoadOp& ld = LoadOp()) const {
+  __device__ __forceinline__ int run_pp(int a, int b, const LoadOp& ld = LoadOp()) const {
     constexpr int R = radix(NS);
     constexpr bool first = NS == 1, last = NS * R == L;
     constexpr int ZR = first ? (NZ * R + L - 1) / L : R;
     constexpr int KR = last ? (KEEP + NS - 1) / NS : R;
     static_assert(!first || (NZ * R) % L == 0, "zero prefix must align with the first pass");
     static_assert(!last || KEEP % NS == 0, "kept prefix must align with the last pass");
-    pass<R, NS, DIR, ZR, KR>(ld);
-    if constexpr (!last) run<DIR, NZ, KEEP, NS * R>(ld);
+    pass_oop<R, NS, DIR, ZR, KR>(ld, a, b);
+    if constexpr (!last)
+      return run_pp<DIR, NZ, KEEP, NS * R>(b, a, ld);
+    else
+      return b;
+  }
+
+  // The whole transform with radices EPT, EPT, ..., remainder.  NZ: inputs
+  // k >= NZ are zero; KEEP: only outputs k < KEEP are stored (both must be
+  // multiples of the stride they apply at, e.g. L/2).
+  template <int DIR, int NZ = L, int KEEP = L, int NS = 1, class LoadOp = NoLoad>
+  __device__ __forceinline__ void run(const LoadOp& ld = LoadOp(), int off = 0) const {
+    constexpr int R = radix(NS);
+    constexpr bool first = NS == 1, last = NS * R == L;
+    constexpr int ZR = first ? (NZ * R + L - 1) / L : R;
+    constexpr int KR = last ? (KEEP + NS - 1) / NS : R;
+    static_assert(!first || (NZ * R) % L == 0, "zero prefix must align with the first pass");
+    static_assert(!last || KEEP % NS == 0, "kept prefix must align with the last pass");
+    pass<R, NS, DIR, ZR, KR>(ld, off);
+    if constexpr (!last) run<DIR, NZ, KEEP, NS * R>(ld, off);
   }
 };
 
