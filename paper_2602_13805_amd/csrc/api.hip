@@ -2,7 +2,9 @@
 // the start value, images and the reconstruction loop.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <chrono>
+#include <map>
 #include <memory>
 #include <cmath>
 #include <complex>
@@ -152,7 +154,7 @@ static void launch_reduce_mfma(pdf_handle* h, const ReduceArgs<float>& a) {
 }
 
 template <typename T>
-static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx<T>* Rfix) {
+static ReduceArgs<T> reduce_args(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx<T>* Rfix) {
   ReduceArgs<T> a;
   a.J = J;
   a.E = E;
@@ -169,6 +171,12 @@ static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx
   a.N = h->N;
   a.ntiles = h->ntiles;
   a.beta = T(h->prm.beta);
+  return a;
+}
+
+template <typename T>
+static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx<T>* Rfix) {
+  const ReduceArgs<T> a = reduce_args<T>(h, J, E, Rfix);
   if constexpr (sizeof(T) == 4) {
     const int nrt = (h->Ns + 15) / 16, nct = (h->Ni + 31) / 32;
     switch (nct * 8 + nrt) {
@@ -192,7 +200,7 @@ static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx
 }
 
 template <typename T>
-static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
+static RegArgs<T> reg_args(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
   RegArgs<T> a;
   a.chi = (const cx<T>*)h->chi;
   a.R = (const cx<T>*)h->R;
@@ -218,6 +226,12 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
   a.eps_tv = h->prm.eps_tv;
   a.eps_abs = h->prm.eps_abs;
   a.r_stopgrad = h->prm.r_stopgrad;
+  return a;
+}
+
+template <typename T>
+static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
+  const RegArgs<T> a = reg_args<T>(h, loss, tstep, frozen);
   const int nt = h->N < 1024 ? h->N : 1024;
   const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
   set_lds(k_image_reg<T>, lds);
@@ -280,11 +294,8 @@ static int mark(pdf_handle* h) {
   return PDF_OK;
 }
 
-// One evaluation of loss and gradient; with Adam buffers, also the update.
 template <typename T>
-static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
-                         void* v, int* tstep, const int* frozen) {
-  int rc;
+static FwdArgs<T> fwd_args(pdf_handle* h, const void* alpha) {
   FwdArgs<T> f;
   f.in = (const cx<T>*)alpha;
   f.einc = (const cx<T>*)h->einc;
@@ -295,15 +306,12 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   f.Ni = h->Ni;
   f.K = h->K;
   f.beta = T(h->prm.beta);
-  if ((rc = mark(h))) return rc;
-  if ((rc = launch_fwd<T>(h, f, true))) return rc;
-  if ((rc = mark(h))) return rc;
-  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
-  if ((rc = mark(h))) return rc;
-  if ((rc = launch_reg<T>(h, loss, tstep, frozen))) return rc;
-  if ((rc = mark(h))) return rc;
-  if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
-  if ((rc = mark(h))) return rc;
+  return f;
+}
+
+template <typename T>
+static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, void* v, int* tstep,
+                           const int* frozen) {
   AdjArgs<T> a;
   a.J = (const cx<T>*)h->J;
   a.E = (const cx<T>*)h->E;
@@ -330,8 +338,201 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   a.Ni = h->Ni;
   a.K = h->K;
   a.beta = T(h->prm.beta);
-  if ((rc = launch_adj<T>(h, a))) return rc;
+  return a;
+}
+
+// One evaluation of loss and gradient; with Adam buffers, also the update.
+template <typename T>
+static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
+                         void* v, int* tstep, const int* frozen) {
+  int rc;
+  const FwdArgs<T> f = fwd_args<T>(h, alpha);
+  if ((rc = mark(h))) return rc;
+  if ((rc = launch_fwd<T>(h, f, true))) return rc;
+  if ((rc = mark(h))) return rc;
+  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  if ((rc = mark(h))) return rc;
+  if ((rc = launch_reg<T>(h, loss, tstep, frozen))) return rc;
+  if ((rc = mark(h))) return rc;
+  if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
+  if ((rc = mark(h))) return rc;
+  if ((rc = launch_adj<T>(h, adj_args<T>(h, grad, alpha_upd, m, v, tstep, frozen)))) return rc;
   return mark(h);
+}
+
+// ------------------------------------------------------------------ grouped launches
+
+// FP32 handles of one shape class (grid M, receiver tiles ceil(Ns/16),
+// incidence tiles ceil(Ni/32) and ceil(Ni/16), tile choice) advanced by one
+// launch per kernel: each launch reads a table of the handles' argument sets
+// and the first workgroup of each set.  The handles may differ in N_i, N_s,
+// K and batch within the class.
+struct Group {
+  std::vector<pdf_handle*> hs;
+  void* dmem = nullptr;
+  const FwdArgs<float>* fwd = nullptr;
+  const ReduceArgs<float>* red = nullptr;
+  const RegArgs<float>* reg = nullptr;
+  const AdjGemmArgs* ag = nullptr;
+  const AdjArgs<float>* adj = nullptr;
+  const int* st[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // [n + 1] workgroup starts per kernel
+  int tot[5] = {0, 0, 0, 0, 0};
+  int n = 0, M = 0, ntiles = 0, nbx = 0, nt_reg = 0, nrt = 0, nct = 0, nrta = 0, ct = 2, pb = 4;
+  size_t lds_reg = 0, lds_ag = 0;
+  ~Group() {
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::vector<void*>& alphas) {
+  pdf_handle* h0 = hs[0];
+  g->hs = hs;
+  g->n = int(hs.size());
+  g->M = h0->M;
+  g->ntiles = h0->ntiles;
+  g->nrt = (h0->Ns + 15) / 16;
+  g->nct = (h0->Ni + 31) / 32;
+  g->nrta = (h0->Ni + 15) / 16;
+  g->ct = h0->tune_ct;
+  g->pb = h0->tune_pb;
+  g->nbx = (h0->N + 128 * g->ct - 1) / (128 * g->ct);
+  g->nt_reg = h0->N < 1024 ? h0->N : 1024;
+  g->lds_reg = sizeof(cx<float>) * size_t(h0->N) + 16 * sizeof(double);
+  int max_ns = 0;
+  for (pdf_handle* h : hs) max_ns = std::max(max_ns, h->Ns);
+  g->lds_ag = sizeof(cx<float>) * size_t(max_ns) * 16 * g->nrta;
+  const int n = g->n;
+  std::vector<FwdArgs<float>> fwd(n);
+  std::vector<ReduceArgs<float>> red(n);
+  std::vector<RegArgs<float>> reg(n);
+  std::vector<AdjGemmArgs> ag(n);
+  std::vector<AdjArgs<float>> adj(n);
+  std::vector<int> st(5 * size_t(n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    pdf_handle* h = hs[i];
+    fwd[i] = fwd_args<float>(h, alphas[i]);
+    red[i] = reduce_args<float>(h, (const cx<float>*)h->J, (const cx<float>*)h->E, nullptr);
+    reg[i] = reg_args<float>(h, h->loss, h->tstep, h->frozen);
+    ag[i] = AdjGemmArgs{(const cx<float>*)h->gs, (const cx<float>*)h->dres, (cx<float>*)h->h, h->Ni, h->Ns, h->N};
+    adj[i] = adj_args<float>(h, nullptr, alphas[i], h->m, h->v, h->tstep, h->frozen);
+    const int cnt[5] = {h->B * h->Ni, h->ntiles * h->B, h->B, g->nbx * h->B, h->B * h->Ni};
+    for (int k = 0; k < 5; ++k) st[k * size_t(n + 1) + i + 1] = st[k * size_t(n + 1) + i] + cnt[k];
+  }
+  for (int k = 0; k < 5; ++k) g->tot[k] = st[k * size_t(n + 1) + n];
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o1 = al(sizeof(FwdArgs<float>) * n), o2 = o1 + al(sizeof(ReduceArgs<float>) * n),
+               o3 = o2 + al(sizeof(RegArgs<float>) * n), o4 = o3 + al(sizeof(AdjGemmArgs) * n),
+               o5 = o4 + al(sizeof(AdjArgs<float>) * n), total = o5 + sizeof(int) * st.size();
+  std::vector<unsigned char> hostbuf(total, 0);
+  std::memcpy(hostbuf.data(), fwd.data(), sizeof(FwdArgs<float>) * n);
+  std::memcpy(hostbuf.data() + o1, red.data(), sizeof(ReduceArgs<float>) * n);
+  std::memcpy(hostbuf.data() + o2, reg.data(), sizeof(RegArgs<float>) * n);
+  std::memcpy(hostbuf.data() + o3, ag.data(), sizeof(AdjGemmArgs) * n);
+  std::memcpy(hostbuf.data() + o4, adj.data(), sizeof(AdjArgs<float>) * n);
+  std::memcpy(hostbuf.data() + o5, st.data(), sizeof(int) * st.size());
+  pdf_handle* h = h0;
+  HIP_TRY(hipMalloc(&g->dmem, total));
+  HIP_TRY(hipMemcpy(g->dmem, hostbuf.data(), total, hipMemcpyHostToDevice));
+  unsigned char* d = static_cast<unsigned char*>(g->dmem);
+  g->fwd = reinterpret_cast<const FwdArgs<float>*>(d);
+  g->red = reinterpret_cast<const ReduceArgs<float>*>(d + o1);
+  g->reg = reinterpret_cast<const RegArgs<float>*>(d + o2);
+  g->ag = reinterpret_cast<const AdjGemmArgs*>(d + o3);
+  g->adj = reinterpret_cast<const AdjArgs<float>*>(d + o4);
+  for (int k = 0; k < 5; ++k) g->st[k] = reinterpret_cast<const int*>(d + o5) + k * size_t(n + 1);
+  return PDF_OK;
+}
+
+template <int M>
+static void group_conv_m(const Group* g, hipStream_t st, bool adjoint) {
+  using C = ConvCfg<float, M>;
+  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+    if (!adjoint) {
+      auto k = k_fwd_conv_group<float, M, true>;
+      set_lds(k, C::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::LDS_BYTES, st, g->fwd, g->st[0], g->n);
+    } else {
+      auto k = k_adj_conv_group<float, M>;
+      set_lds(k, C::LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(g->tot[4]), dim3(C::NT), C::LDS_BYTES, st, g->adj, g->st[4], g->n);
+    }
+  }
+}
+
+static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
+  switch (g->M) {
+    case 8: group_conv_m<8>(g, st, adjoint); break;
+    case 16: group_conv_m<16>(g, st, adjoint); break;
+    case 32: group_conv_m<32>(g, st, adjoint); break;
+    case 64: group_conv_m<64>(g, st, adjoint); break;
+  }
+}
+
+template <int NRT, int NCT>
+static void group_reduce_t(const Group* g, hipStream_t st) {
+  const size_t lds = reduce_mfma_lds<NCT>();
+  if (g->pb == 8) {
+    set_lds(k_pixel_reduce_mfma_group<NRT, NCT, 8>, lds);
+    hipLaunchKernelGGL((k_pixel_reduce_mfma_group<NRT, NCT, 8>), dim3(g->tot[1]), dim3(256), lds, st, g->red,
+                       g->st[1], g->n, g->ntiles);
+  } else {
+    set_lds(k_pixel_reduce_mfma_group<NRT, NCT, 4>, lds);
+    hipLaunchKernelGGL((k_pixel_reduce_mfma_group<NRT, NCT, 4>), dim3(g->tot[1]), dim3(256), lds, st, g->red,
+                       g->st[1], g->n, g->ntiles);
+  }
+}
+
+static void group_reduce(const Group* g, hipStream_t st) {
+  switch (g->nct * 8 + g->nrt) {
+    case 9: group_reduce_t<1, 1>(g, st); break;
+    case 10: group_reduce_t<2, 1>(g, st); break;
+    case 11: group_reduce_t<3, 1>(g, st); break;
+    case 12: group_reduce_t<4, 1>(g, st); break;
+    case 17: group_reduce_t<1, 2>(g, st); break;
+    case 18: group_reduce_t<2, 2>(g, st); break;
+    case 19: group_reduce_t<3, 2>(g, st); break;
+    case 20: group_reduce_t<4, 2>(g, st); break;
+  }
+}
+
+template <int NRT, int CT>
+static void group_adj_gemm_t(const Group* g, hipStream_t st) {
+  hipLaunchKernelGGL((k_adj_gemm_mfma_group<NRT, CT>), dim3(g->tot[3]), dim3(256), g->lds_ag, st, g->ag, g->st[3],
+                     g->n, g->nbx);
+}
+
+template <int NRT>
+static void group_adj_gemm_n(const Group* g, hipStream_t st) {
+  switch (g->ct) {
+    case 1: group_adj_gemm_t<NRT, 1>(g, st); break;
+    case 4: group_adj_gemm_t<NRT, 4>(g, st); break;
+    default: group_adj_gemm_t<NRT, 2>(g, st); break;
+  }
+}
+
+static void group_adj_gemm(const Group* g, hipStream_t st) {
+  switch (g->nrta) {
+    case 1: group_adj_gemm_n<1>(g, st); break;
+    case 2: group_adj_gemm_n<2>(g, st); break;
+    case 3: group_adj_gemm_n<3>(g, st); break;
+    case 4: group_adj_gemm_n<4>(g, st); break;
+  }
+}
+
+// k grouped iterations (loss, gradient, Adam) on the first handle's stream.
+static int group_iterate(const Group* g, int k) {
+  pdf_handle* h = g->hs[0];
+  hipStream_t st = h->stream;
+  set_lds(k_image_reg_group<float>, g->lds_reg);
+  for (int s = 0; s < k; ++s) {
+    group_conv(g, st, false);
+    group_reduce(g, st);
+    hipLaunchKernelGGL(k_image_reg_group<float>, dim3(g->tot[2]), dim3(g->nt_reg), g->lds_reg, st, g->reg,
+                       g->st[2], g->n);
+    group_adj_gemm(g, st);
+    group_conv(g, st, true);
+  }
+  return check_launch(h, "grouped iteration");
 }
 
 // Loss only (no adjoint): forward kernels and the image / regulariser pass.
@@ -928,12 +1129,52 @@ struct ReconT : Recon {
   }
 };
 
-// Captures k iterations of r on its handle's stream into a new graph.
-static int capture_iterations(Recon* r, int k, hipGraph_t* g) {
-  pdf_handle* h = r->h;
+// A unit advances one handle, or a shape class of handles by grouped launches.
+struct Unit {
+  std::vector<Recon*> rs;
+  std::unique_ptr<Group> grp;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> evs;  // one per member: joins and forks of the members' streams
+  ~Unit() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+  pdf_handle* lead() const { return rs[0]->h; }
+  bool active() const {
+    for (Recon* r : rs)
+      if (r->active()) return true;
+    return false;
+  }
+  int iterate(int k) { return grp ? group_iterate(grp.get(), k) : rs[0]->iterate(k); }
+  // the lead stream waits for every member's stream (before), or every member for the lead (after)
+  int join(bool before) {
+    pdf_handle* h = lead();
+    if (rs.size() < 2) return PDF_OK;
+    if (evs.empty()) {
+      evs.resize(rs.size(), nullptr);
+      for (auto& e : evs) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    if (before) {
+      for (size_t i = 1; i < rs.size(); ++i) {
+        HIP_TRY(hipEventRecord(evs[i], rs[i]->h->stream));
+        HIP_TRY(hipStreamWaitEvent(h->stream, evs[i], 0));
+      }
+    } else {
+      HIP_TRY(hipEventRecord(evs[0], h->stream));
+      for (size_t i = 1; i < rs.size(); ++i) HIP_TRY(hipStreamWaitEvent(rs[i]->h->stream, evs[0], 0));
+    }
+    return PDF_OK;
+  }
+};
+
+// Captures k iterations of a unit on its lead stream into a new graph.
+static int capture_unit(Unit& u, int k, hipGraph_t* g) {
+  pdf_handle* h = u.lead();
   *g = nullptr;
   HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  const int crc = r->iterate(k);
+  const int crc = u.iterate(k);
   hipError_t ce = hipStreamEndCapture(h->stream, g);
   if (crc) {
     if (*g) (void)hipGraphDestroy(*g);
@@ -944,60 +1185,59 @@ static int capture_iterations(Recon* r, int k, hipGraph_t* g) {
   return PDF_OK;
 }
 
-// Advances every reconstruction in rs together.  Each handle's n_check steps
-// are captured once into a graph of its own and launched on the handle's own
-// stream, so the handles' kernels run concurrently on the hardware queues
-// (a graph whose independent branches are the handles ran them one after
-// another, no faster than separate calls); checks and early stop per handle.
-static int reconstruct_all(std::vector<Recon*>& rs, int n_iter, int n_check, int start_given, pdf_report* rep) {
+// Advances every unit together.  Each unit's n_check steps are captured once
+// into a graph of its own and launched on its lead handle's stream, so
+// different units overlap on the hardware queues while a unit's grouped
+// launches fill the GPU with all of its handles' work; checks and early stop
+// are per handle.
+static int reconstruct_all(std::vector<std::unique_ptr<Unit>>& units, int n_iter, int n_check, int start_given,
+                           pdf_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = PDF_OK;
-  for (Recon* r : rs)
-    if ((rc = r->prepare(start_given))) return rc;
+  for (auto& u : units)
+    for (Recon* r : u->rs)
+      if ((rc = r->prepare(start_given))) return rc;
   if (n_check < 1 || n_check > n_iter) n_check = n_iter > 0 ? n_iter : 1;
-  const size_t n = rs.size();
-  std::vector<hipGraph_t> graphs(n, nullptr);
-  std::vector<hipGraphExec_t> execs(n, nullptr);
   int done = 0;
   while (!rc && done < n_iter) {
     bool any = false;
     const int chunk = (n_iter - done < n_check) ? n_iter - done : n_check;
-    for (size_t i = 0; i < n && !rc; ++i) {
-      Recon* r = rs[i];
-      if (!r->active()) continue;
+    for (auto& up : units) {
+      Unit& u = *up;
+      if (rc || !u.active()) continue;
       any = true;
+      if ((rc = u.join(true))) break;
       if (chunk == n_check) {
-        if (!execs[i]) {
-          if ((rc = capture_iterations(r, n_check, &graphs[i]))) break;
-          hipError_t ie = hipGraphInstantiate(&execs[i], graphs[i], nullptr, nullptr, 0);
+        if (!u.exec) {
+          if ((rc = capture_unit(u, n_check, &u.graph))) break;
+          hipError_t ie = hipGraphInstantiate(&u.exec, u.graph, nullptr, nullptr, 0);
           if (ie != hipSuccess) {
-            rc = fail(r->h, PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            rc = fail(u.lead(), PDF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
             break;
           }
         }
-        hipError_t le = hipGraphLaunch(execs[i], r->h->stream);
-        if (le != hipSuccess) rc = fail(r->h, PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+        hipError_t le = hipGraphLaunch(u.exec, u.lead()->stream);
+        if (le != hipSuccess) rc = fail(u.lead(), PDF_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
       } else {
-        rc = r->iterate(chunk);
+        rc = u.iterate(chunk);
       }
+      if (!rc) rc = u.join(false);
     }
     if (!any) break;
     done += chunk;
-    for (Recon* r : rs)
-      if (!rc && r->active()) rc = r->check();
-  }
-  for (size_t i = 0; i < n; ++i) {
-    if (execs[i]) (void)hipGraphExecDestroy(execs[i]);
-    if (graphs[i]) (void)hipGraphDestroy(graphs[i]);
+    for (auto& u : units)
+      for (Recon* r : u->rs)
+        if (!rc && r->active()) rc = r->check();
   }
   if (rc) return rc;
   int reached = 0;
   bool any_target = false;
-  for (Recon* r : rs) {
-    if ((rc = r->finish())) return rc;
-    reached += r->nf;
-    any_target = any_target || r->has_target;
-  }
+  for (auto& u : units)
+    for (Recon* r : u->rs) {
+      if ((rc = r->finish())) return rc;
+      reached += r->nf;
+      any_target = any_target || r->has_target;
+    }
   if (rep) {
     rep->iters_run = done;
     rep->n_reached = any_target ? reached : 0;
@@ -1029,8 +1269,10 @@ extern "C" int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, i
   if (int rc = check_recon_args(h, alpha_dev, n_iter, eps_true_dev, target_err_dev, best_err_dev)) return rc;
   std::unique_ptr<Recon> r(make_recon(h, alpha_dev, eps_true_dev, target_err_dev, reached_iter_dev, best_err_dev,
                                       best_iter_dev, chi_cco_dev));
-  std::vector<Recon*> rs{r.get()};
-  return reconstruct_all(rs, n_iter, n_check, start_given, rep);
+  std::vector<std::unique_ptr<Unit>> units;
+  units.emplace_back(new Unit());
+  units[0]->rs.push_back(r.get());
+  return reconstruct_all(units, n_iter, n_check, start_given, rep);
 }
 
 extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n_iter, int32_t n_check,
@@ -1048,13 +1290,45 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
     if (int rc = check_recon_args(hs[i], alpha_dev[i], n_iter, et, tg, be)) return rc;
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i], PDF_EINVAL, "a handle appears twice");
-    if (!hs[i]->tuned)
-      if (int rc = pdf_autotune(hs[i], 5, nullptr, nullptr)) return rc;
     own.emplace_back(make_recon(hs[i], alpha_dev[i], et, tg, reached_iter_dev ? reached_iter_dev[i] : nullptr, be,
                                 best_iter_dev ? best_iter_dev[i] : nullptr, chi_cco_dev ? chi_cco_dev[i] : nullptr));
     rs.push_back(own.back().get());
   }
-  return reconstruct_all(rs, n_iter, n_check, start_given, rep);
+  // shape classes of FP32 handles: one tile choice each (tuned on the member with the largest batch)
+  std::map<std::array<int, 4>, std::vector<int>> classes;
+  std::vector<std::unique_ptr<Unit>> units;
+  for (int i = 0; i < n; ++i) {
+    pdf_handle* h = hs[i];
+    if (h->prec == PDF_FP32 && h->N % 32 == 0)
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
+    else {
+      units.emplace_back(new Unit());
+      units.back()->rs.push_back(rs[i]);
+    }
+  }
+  for (auto& kv : classes) {
+    const std::vector<int>& idx = kv.second;
+    int best = idx[0];
+    for (int i : idx)
+      if (hs[i]->B > hs[best]->B) best = i;
+    if (!hs[best]->tuned)
+      if (int rc = pdf_autotune(hs[best], 5, nullptr, nullptr)) return rc;
+    for (int i : idx) pdf_set_tiles(hs[i], hs[best]->tune_ct, hs[best]->tune_pb);
+    units.emplace_back(new Unit());
+    Unit& u = *units.back();
+    for (int i : idx) u.rs.push_back(rs[i]);
+    if (idx.size() >= 2) {
+      std::vector<pdf_handle*> gh;
+      std::vector<void*> ga;
+      for (int i : idx) {
+        gh.push_back(hs[i]);
+        ga.push_back(alpha_dev[i]);
+      }
+      u.grp.reset(new Group());
+      if (int rc = group_build(u.grp.get(), gh, ga)) return rc;
+    }
+  }
+  return reconstruct_all(units, n_iter, n_check, start_given, rep);
 }
 
 extern "C" const char* pdf_last_error(const pdf_handle* h) {

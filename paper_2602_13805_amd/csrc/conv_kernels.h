@@ -141,12 +141,10 @@ struct FwdArgs {
 // alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
 // E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
 template <typename T, int M, bool FROM_ALPHA>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) {
+__device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + C::P * C::TileL::LD;
-  const int bp = blockIdx.x;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
@@ -214,6 +212,21 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) 
   }
 }
 
+template <typename T, int M, bool FROM_ALPHA>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fwd_conv_body<T, M, FROM_ALPHA>(a, blockIdx.x, smem_raw);
+}
+
+// One launch over several argument sets (handles of one shape class).
+template <typename T, int M, bool FROM_ALPHA>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
+                                                                         const int* __restrict__ start, int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  fwd_conv_body<T, M, FROM_ALPHA>(a[g], blockIdx.x - start[g], smem_raw);
+}
+
 template <typename T>
 struct AdjArgs {
   const cx<T>* J;      // [BP][N] currents, or null (alpha = 0)
@@ -247,12 +260,10 @@ struct AdjArgs {
 // The state loss's own derivative in R vanishes because R is its per-pixel
 // least-squares minimiser, so only the regulariser part g_R reaches R.
 template <typename T, int M>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) {
+__device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + C::P * C::TileL::LD;
-  const int bp = blockIdx.x;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
@@ -353,6 +364,20 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) 
       a.alpha[idx] = al;
     }
   }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  adj_conv_body<T, M>(a, blockIdx.x, smem_raw);
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv_group(const AdjArgs<T>* __restrict__ a,
+                                                                        const int* __restrict__ start, int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  adj_conv_body<T, M>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 // alpha = F_T(J) on the kept modes (Sec. 2.3, Eq. 9): forward DFT of one

@@ -39,3 +39,18 @@ __host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
   T d = b.x * b.x + b.y * b.y;
   return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
 }
+
+// Grouped launches: one launch serves several argument sets, set g taking the
+// workgroups [start[g], start[g+1]).  Returns g for workgroup bx (the search
+// is uniform over the workgroup).
+__device__ __forceinline__ int group_of(const int* start, int n, int bx) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= bx)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}

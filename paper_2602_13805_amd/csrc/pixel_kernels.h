@@ -148,15 +148,15 @@ constexpr size_t reduce_mfma_lds() {
 // PB: incidences per load batch (a tuning choice: the accumulation order does
 // not depend on it, so neither do the results).
 template <int NRT, int NCT, int PB>
-__global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
+__device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& a, int tile, int b,
+                                                       unsigned char* smem_raw) {
   constexpr int SUB = kReduceSub, NSUB = kReduceTile / kReduceSub;
   constexpr int LDJ = 32 * NCT + 1;  // padded row of the staged currents (floats)
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   float* Jr = reinterpret_cast<float*>(smem_raw);         // [SUB][LDJ]
   float* Ji = Jr + SUB * LDJ;                               // [SUB][LDJ]
   double* part = reinterpret_cast<double*>(Ji + SUB * LDJ);  // [4][SUB] sums of the second half
   double* red = part + 4 * SUB;
-  const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int Ni = a.Ni, Ns = a.Ns, N = a.N;
   const int px = tid & (SUB - 1), half = tid / SUB;
   const int lane = tid & 63, w = tid >> 6;
@@ -298,6 +298,23 @@ __global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pi
     }
 }
 
+template <int NRT, int NCT, int PB>
+__global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pixel_reduce_mfma(ReduceArgs<float> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  pixel_reduce_mfma_body<NRT, NCT, PB>(a, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// One launch over several argument sets of one shape class (the same tile
+// count ntiles); set g's workgroup l is tile l % ntiles of instance l / ntiles.
+template <int NRT, int NCT, int PB>
+__global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pixel_reduce_mfma_group(
+    const ReduceArgs<float>* __restrict__ a, const int* __restrict__ start, int n, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  const int l = blockIdx.x - start[g];
+  pixel_reduce_mfma_body<NRT, NCT, PB>(a[g], l % ntiles, l / ntiles, smem_raw);
+}
+
 template <typename T>
 struct RegArgs {
   const cx<T>* chi;     // [B][N]
@@ -368,12 +385,11 @@ __device__ __forceinline__ RegTerm<T> reg_term(const cx<T>* c, int i, int j, int
 // L^State from its partial sums, the three regularisers on chi with their
 // gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsigned char* smem_raw) {
   const int M = a.M, N = M * M;
   cx<T>* c = reinterpret_cast<cx<T>*>(smem_raw);   // chi [M][M]
   double* red = reinterpret_cast<double*>(c + N);
-  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) a.tstep[b] += 1;
   double dsum = 0.0;
   const int NO = a.Ni * a.Ns;
@@ -439,6 +455,20 @@ __global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  image_reg_body<T>(a, blockIdx.x, smem_raw);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_image_reg_group(const RegArgs<T>* __restrict__ a,
+                                                          const int* __restrict__ start, int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  image_reg_body<T>(a[g], blockIdx.x - start[g], smem_raw);
+}
+
 // h[b][p][n] = s * sum_q conj(G_S[q][n]) x[b][p][q]   (G_S^H applied to Ns-vectors)
 // Grid: (ceil(N / 256), B), block 256; the G_S column of a pixel sits in registers.
 template <typename T, int NSMAX>
@@ -476,14 +506,22 @@ __global__ __launch_bounds__(256) void k_adj_gemm(const cx<T>* __restrict__ gs, 
 // Requires N % 32 == 0.  NRT = ceil(Ni / 16) row tiles; CT column tiles of 32
 // pixels per wave (a tuning choice: every output is the same chain of MFMAs
 // over the receivers whatever CT is, so the results do not depend on it).
+struct AdjGemmArgs {
+  const cx<float>* gs;  // [Ns][N]
+  const cx<float>* x;   // [B][Ni][Ns]
+  cx<float>* h;         // [B][Ni][N] out
+  int Ni, Ns, N;
+};
+
 template <int NRT, int CT>
-__global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restrict__ gs,
-                                                       const cx<float>* __restrict__ x, cx<float>* __restrict__ h,
-                                                       int Ni, int Ns, int N) {
+__device__ __forceinline__ void adj_gemm_mfma_body(const AdjGemmArgs& args, int bx, int b, unsigned char* smem_raw) {
   constexpr int KC = 8, LDX = 16 * NRT;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const cx<float>* __restrict__ gs = args.gs;
+  const cx<float>* __restrict__ x = args.x;
+  cx<float>* __restrict__ h = args.h;
+  const int Ni = args.Ni, Ns = args.Ns, N = args.N;
   cx<float>* xs = reinterpret_cast<cx<float>*>(smem_raw);  // [Ns][LDX]: xs[q][p] = x[p][q]
-  const int b = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   for (int o = tid; o < Ns * LDX; o += blockDim.x) {
     const int q = o / LDX, p = o % LDX;
     xs[o] = p < Ni ? x[(size_t(b) * Ni + p) * Ns + q] : cx<float>{0.f, 0.f};
@@ -492,7 +530,7 @@ __global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restri
   const int lane = tid & 63, w = tid >> 6;
   const int m = lane & 31, cp = lane >> 5;
   const int c = m & 1;
-  const int n0 = (blockIdx.x * 4 + w) * 32 * CT;
+  const int n0 = (bx * 4 + w) * 32 * CT;
   if (n0 >= N) return;  // wave-uniform; no barrier follows
   int nct = (N - n0) / 32;
   nct = nct < CT ? nct : CT;
@@ -543,6 +581,24 @@ __global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restri
         if (p < Ni) h[(size_t(b) * Ni + p) * N + n0 + 32 * t + m] = cx<float>{acc[r][t][e], acc[r][t][e + 1]};
       }
     }
+}
+
+template <int NRT, int CT>
+__global__ __launch_bounds__(256) void k_adj_gemm_mfma(const cx<float>* __restrict__ gs,
+                                                       const cx<float>* __restrict__ x, cx<float>* __restrict__ h,
+                                                       int Ni, int Ns, int N) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  adj_gemm_mfma_body<NRT, CT>(AdjGemmArgs{gs, x, h, Ni, Ns, N}, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// Grouped: set g's workgroup l is pixel block l % nbx of instance l / nbx.
+template <int NRT, int CT>
+__global__ __launch_bounds__(256) void k_adj_gemm_mfma_group(const AdjGemmArgs* __restrict__ a,
+                                                             const int* __restrict__ start, int n, int nbx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  const int l = blockIdx.x - start[g];
+  adj_gemm_mfma_body<NRT, CT>(a[g], l % nbx, l / nbx, smem_raw);
 }
 
 // s[b] = sum |x[b][*]|^2 over len entries (grid: B blocks).

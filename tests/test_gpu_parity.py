@@ -308,7 +308,10 @@ def test_tile_choices_do_not_change_results_and_autotune_picks_one():
 def test_reconstruct_multi_equals_separate_reconstructions():
     """Uneven batching: handles of different grids, antenna counts, truncations, batches and
     precisions advanced in one graph give exactly what each handle gives alone."""
-    shapes = [(16, 7, 6, 8, 2, "fp32"), (32, 9, 16, 32, 3, "fp32"), (16, 5, 4, 6, 2, "fp64"), (8, 5, 3, 5, 1, "fp32")]
+    # same-class pairs (one grid, the same receiver / incidence tile counts) run as grouped launches:
+    # M = 16 with N_s <= 16, N_i <= 16, and M = 32 with 16 < N_s <= 32, N_i <= 16
+    shapes = [(16, 7, 6, 8, 2, "fp32"), (32, 9, 16, 32, 3, "fp32"), (16, 5, 4, 6, 2, "fp64"), (8, 5, 3, 5, 1, "fp32"),
+              (16, 5, 5, 7, 3, "fp32"), (32, 11, 12, 20, 2, "fp32"), (16, 9, 9, 13, 1, "fp32")]
     sol, eps, datas = [], [], []
     for (M, K, Ni, Ns, B, prec) in shapes:
         case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
