@@ -104,9 +104,9 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
 // offset 0: rows 0..M-1 of the tile, or BOT: rows M..2M-1); returns the
 // offset of the region holding the result.  The spectrum ghat is pre-scaled
 // by 1/P^2.  With PP the row passes alternate between the two regions (one
-// barrier each), else they run in place (two barriers each): measured, the
-// first is faster in the forward kernel and the second in the adjoint one.
-// The column phase is wave-local and ends with a workgroup barrier.
+// barrier each), else they run in place (two barriers each); which is faster
+// depends on the kernel around it (the autotuner times both).  The column
+// phase is wave-local and ends with a workgroup barrier.
 template <typename T, int M, bool PP>
 __device__ __forceinline__ int conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
   using C = ConvCfg<T, M>;
@@ -140,7 +140,9 @@ struct FwdArgs {
 
 // alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
 // E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
-template <typename T, int M, bool FROM_ALPHA>
+// PP: the convolution's row passes alternate between the tile's halves (one
+// barrier each) or run in place; a tuning choice with identical results.
+template <typename T, int M, bool FROM_ALPHA, bool PP>
 __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -194,7 +196,7 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     }
     __syncthreads();
   }
-  const int res = conv_core<T, M, true>(buf, tw, a.ghat, false, src);
+  const int res = conv_core<T, M, PP>(buf, tw, a.ghat, false, src);
   // all loads of the epilogue are issued before their use (the workgroup
   // fills its CU, so nothing else hides their latency)
   cx<T> ei[C::PPT];
@@ -212,19 +214,19 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
   }
 }
 
-template <typename T, int M, bool FROM_ALPHA>
+template <typename T, int M, bool FROM_ALPHA, bool PP>
 __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fwd_conv_body<T, M, FROM_ALPHA>(a, blockIdx.x, smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA, PP>(a, blockIdx.x, smem_raw);
 }
 
 // One launch over several argument sets (handles of one shape class).
-template <typename T, int M, bool FROM_ALPHA>
+template <typename T, int M, bool FROM_ALPHA, bool PP>
 __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
                                                                          const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = group_of(start, n, blockIdx.x);
-  fwd_conv_body<T, M, FROM_ALPHA>(a[g], blockIdx.x - start[g], smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA, PP>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 template <typename T>
@@ -259,7 +261,7 @@ struct AdjArgs {
 //   g_alpha = B^H g_J  (unnormalised forward DFT on the kept modes)
 // The state loss's own derivative in R vanishes because R is its per-pixel
 // least-squares minimiser, so only the regulariser part g_R reaches R.
-template <typename T, int M>
+template <typename T, int M, bool PP>
 __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -321,7 +323,7 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
     gj[q] = gJ;
   }
   __syncthreads();
-  int r = conv_core<T, M, false>(buf, tw, a.ghat, true, 0);
+  int r = conv_core<T, M, PP>(buf, tw, a.ghat, true, 0);
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
@@ -366,18 +368,18 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   }
 }
 
-template <typename T, int M>
+template <typename T, int M, bool PP>
 __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  adj_conv_body<T, M>(a, blockIdx.x, smem_raw);
+  adj_conv_body<T, M, PP>(a, blockIdx.x, smem_raw);
 }
 
-template <typename T, int M>
+template <typename T, int M, bool PP>
 __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv_group(const AdjArgs<T>* __restrict__ a,
                                                                         const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = group_of(start, n, blockIdx.x);
-  adj_conv_body<T, M>(a[g], blockIdx.x - start[g], smem_raw);
+  adj_conv_body<T, M, PP>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 // alpha = F_T(J) on the kept modes (Sec. 2.3, Eq. 9): forward DFT of one
