@@ -98,7 +98,7 @@ int pdf_default_params(pdf_params* p);
  *   grid, tx, rx, params: host structs (params may be NULL for defaults).
  *   freq_hz: frequency.  K: truncation per axis, 1 <= K <= M.
  *   stream: hipStream_t for every later call (must not be NULL).
- * Supported: M in {8, 16, 32, 64} (FP32) or {8, 16, 32} (FP64); Ni, Ns >= 1.
+ * Supported: M in {8, 16, 32, 48, 64} (FP32) or {8, 16, 32, 48} (FP64); Ni, Ns >= 1.
  * Errors: PDF_EINVAL (bad sizes / null), PDF_EUNSUPPORTED (other M),
  * PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (||E_inc|| = 0). */
 int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx,

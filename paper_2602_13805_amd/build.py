@@ -27,7 +27,13 @@ def hipcc() -> str:
 
 
 def command(out: str = LIB, extra=()) -> list:
+    # -ffp-contract=on: a multiply and an add fuse only inside one source
+    # expression, never across statements, so a result depends on the source
+    # alone and not on how the compiler arranged the code around it; the
+    # tuning variants of a kernel (e.g. in-place or ping-pong FFT passes) then
+    # give bitwise-identical results by construction
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,

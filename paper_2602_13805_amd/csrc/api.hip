@@ -72,8 +72,8 @@ extern "C" int pdf_default_params(pdf_params* p) {
 }
 
 static bool supported_m(int prec, int M) {
-  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 64;
-  return M == 8 || M == 16 || M == 32;
+  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 48 || M == 64;
+  return M == 8 || M == 16 || M == 32 || M == 48;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -119,6 +119,7 @@ static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
     case 8: return launch_fwd_m<T, 8>(h, a, from_alpha, nblk);
     case 16: return launch_fwd_m<T, 16>(h, a, from_alpha, nblk);
     case 32: return launch_fwd_m<T, 32>(h, a, from_alpha, nblk);
+    case 48: return launch_fwd_m<T, 48>(h, a, from_alpha, nblk);
     case 64: return launch_fwd_m<T, 64>(h, a, from_alpha, nblk);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
@@ -151,6 +152,7 @@ static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
     case 8: return launch_adj_m<T, 8>(h, a, nblk);
     case 16: return launch_adj_m<T, 16>(h, a, nblk);
     case 32: return launch_adj_m<T, 32>(h, a, nblk);
+    case 48: return launch_adj_m<T, 48>(h, a, nblk);
     case 64: return launch_adj_m<T, 64>(h, a, nblk);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
@@ -489,6 +491,7 @@ static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
     case 8: group_conv_m<8>(g, st, adjoint); break;
     case 16: group_conv_m<16>(g, st, adjoint); break;
     case 32: group_conv_m<32>(g, st, adjoint); break;
+    case 48: group_conv_m<48>(g, st, adjoint); break;
     case 64: group_conv_m<64>(g, st, adjoint); break;
   }
 }
@@ -843,7 +846,7 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   if (batch < 1) return fail(nullptr, PDF_EINVAL, "batch must be >= 1");
   if (!stream) return fail(nullptr, PDF_EINVAL, "a non-default stream is required");
   if (!supported_m(prm.precision, grid->M))
-    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32 or 64 (FP64: up to 32)");
+    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48 or 64 (FP64: up to 48)");
   if (rx->n > 64) return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 receivers");
   if (!(prm.beta > 0) || prm.gf_radius < 0) return fail(nullptr, PDF_EINVAL, "beta must be > 0");
   pdf_handle* h = new pdf_handle();
@@ -1077,6 +1080,7 @@ static int launch_analyze(pdf_handle* h, int n, const void* J, void* alpha) {
     case 8: return launch_analyze_m<T, 8>(h, n, J, alpha);
     case 16: return launch_analyze_m<T, 16>(h, n, J, alpha);
     case 32: return launch_analyze_m<T, 32>(h, n, J, alpha);
+    case 48: return launch_analyze_m<T, 48>(h, n, J, alpha);
     case 64: return launch_analyze_m<T, 64>(h, n, J, alpha);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");

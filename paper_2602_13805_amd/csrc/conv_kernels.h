@@ -15,10 +15,13 @@ struct ConvCfg {
   static constexpr int P = 2 * M;
   static constexpr int N = M * M;
   using TileL = Tile<P>;             // P x P tile in LDS, row stride P + 1
-  static constexpr int NT = M >= 64 ? 1024 : (M >= 32 ? 256 : 64);
-  static constexpr int EPT_M = 8;                 // length-M transforms (basis), workgroup-wide
-  static constexpr int EPT_R = 8;                 // length-P transforms along rows, workgroup-wide
-  static constexpr int EPT_C = 16;                // length-P transforms along columns, wave-local
+  // M = 48 (P = 96 = 3 * 32) takes radix-12 / radix-3 passes: every
+  // per-thread element count carries the factor 3
+  static constexpr bool TRI = M % 3 == 0;
+  static constexpr int NT = M >= 64 ? 1024 : (TRI ? 384 : (M >= 32 ? 256 : 64));
+  static constexpr int EPT_M = TRI ? 12 : 8;      // length-M transforms (basis), workgroup-wide
+  static constexpr int EPT_R = TRI ? 12 : 8;      // length-P transforms along rows, workgroup-wide
+  static constexpr int EPT_C = TRI ? 24 : 16;     // length-P transforms along columns, wave-local
   static constexpr int PPT = N / NT;              // pixels owned per thread
   static_assert(N % NT == 0, "pixel ownership must be exact");
   static_assert(P >= 16, "the column pass needs P >= 16");

@@ -54,18 +54,18 @@ __host__ __device__ constexpr int bitrev(int i) {
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [0, N).
 template <class F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+__host__ __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>{}), ...);
 }
 template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
+__host__ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // v * exp(DIR 2 pi i E / 16) with the trivial and 45-degree rotations spelled
 // out (IEEE rules forbid the compiler from folding multiplications by 0 or 1).
 template <typename T, int E, int DIR>
-__device__ __forceinline__ cx<T> rot16(cx<T> v) {
+__host__ __device__ __forceinline__ cx<T> rot16(cx<T> v) {
   constexpr int e = ((E % 16) + 16) % 16;
   constexpr T h = T(0.70710678118654752440);
   if constexpr (e == 0) {
@@ -123,8 +123,95 @@ __host__ __device__ constexpr unsigned zero_mask(int ZR, int st) {
 // twiddles resolved at compile time.  Inputs r >= ZR are known to be zero
 // (their butterflies are skipped) and only outputs r < KR are needed.
 template <typename T, int R, int DIR, int ZR = R, int KR = R>
-__device__ __forceinline__ void fft_reg(cx<T>* v) {
-  if constexpr (R > 1) {
+__host__ __device__ __forceinline__ void fft_reg(cx<T>* v);
+
+// cos(2 pi k / 12); sin(2 pi k / 12) = cos(2 pi (k - 3) / 12).
+__host__ __device__ constexpr double cos12(int k) {
+  switch (((k % 12) + 12) % 12) {
+    case 0: return 1.0;
+    case 1: return 0.86602540378443864676;
+    case 2: return 0.5;
+    case 3: return 0.0;
+    case 4: return -0.5;
+    case 5: return -0.86602540378443864676;
+    case 6: return -1.0;
+    case 7: return -0.86602540378443864676;
+    case 8: return -0.5;
+    case 9: return 0.0;
+    case 10: return 0.5;
+    default: return 0.86602540378443864676;
+  }
+}
+
+// v * exp(DIR 2 pi i E / 12), trivial rotations spelled out
+template <typename T, int E, int DIR>
+__host__ __device__ __forceinline__ cx<T> rot12(cx<T> v) {
+  constexpr int e = ((E % 12) + 12) % 12;
+  if constexpr (e == 0) {
+    return v;
+  } else if constexpr (e == 6) {
+    return {-v.x, -v.y};
+  } else if constexpr (e == 3) {
+    return DIR > 0 ? cx<T>{-v.y, v.x} : cx<T>{v.y, -v.x};
+  } else if constexpr (e == 9) {
+    return DIR > 0 ? cx<T>{v.y, -v.x} : cx<T>{-v.y, v.x};
+  } else {
+    constexpr T c = T(cos12(e)), sn = T(DIR * cos12(e - 3));
+    return {c * v.x - sn * v.y, sn * v.x + c * v.y};
+  }
+}
+
+// 3-point DFT in place: (a, b, c) -> (a + b + c, a + w b + w^2 c, a + w^2 b + w c), w = exp(DIR 2 pi i / 3)
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
+  const cx<T> s = b + c, d = b - c;
+  const cx<T> m{a.x - T(0.5) * s.x, a.y - T(0.5) * s.y};
+  const T k = T(DIR * 0.86602540378443864676);
+  const cx<T> id{-k * d.y, k * d.x};  // i k d
+  a = a + s;
+  b = m + id;
+  c = m - id;
+}
+
+// In-register DFT of R = 3 Q points (Q = 1, 2, 4), natural order in and out:
+// with n = Q n1 + n2 and k = k1 + 3 k2,
+//   X[k1 + 3 k2] = sum_n2 W_Q^{n2 k2} W_R^{n2 k1} sum_n1 x[Q n1 + n2] W_3^{n1 k1},
+// i.e. 3-point DFTs across the stride Q, the twiddles W_R^{n2 k1}, and Q-point
+// FFTs of each k1 row; the final relabelling of registers is free.
+template <typename T, int R, int DIR>
+__host__ __device__ __forceinline__ void fft_mixed(cx<T>* v) {
+  constexpr int Q = R / 3;
+  static_assert(R == 3 * Q && (Q == 1 || Q == 2 || Q == 4), "radix 3, 6 or 12");
+  static_for<Q>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    dft3<T, DIR>(v[n2], v[Q + n2], v[2 * Q + n2]);  // output k1 at v[Q k1 + n2]
+  });
+  static_for<Q>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    v[Q + n2] = rot12<T, n2 * 1 * (12 / R), DIR>(v[Q + n2]);
+    v[2 * Q + n2] = rot12<T, n2 * 2 * (12 / R), DIR>(v[2 * Q + n2]);
+  });
+  if constexpr (Q > 1) {
+    fft_reg<T, Q, DIR>(&v[0]);
+    fft_reg<T, Q, DIR>(&v[Q]);
+    fft_reg<T, Q, DIR>(&v[2 * Q]);
+  }
+  cx<T> t[R];
+  static_for<R>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;  // i = Q k1 + k2  ->  output k1 + 3 k2
+    t[(i / Q) + 3 * (i % Q)] = v[i];
+  });
+  static_for<R>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    v[i] = t[i];
+  });
+}
+
+template <typename T, int R, int DIR, int ZR, int KR>
+__host__ __device__ __forceinline__ void fft_reg(cx<T>* v) {
+  if constexpr (R % 3 == 0) {
+    fft_mixed<T, R, DIR>(v);  // no pruning: zero inputs are loaded as zeros, unused outputs not stored
+  } else if constexpr (R > 1) {
     static_for<R>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       constexpr int j = bitrev<R>(i);
@@ -201,7 +288,14 @@ struct Vecs {
   int nv = NV_;
   int kmin = 0;
   __device__ __forceinline__ int addr(int v, int k) const {
-    const int x = MAPPED ? ((kmin + v) & (NV - 1)) : v;
+    int x = v;
+    if constexpr (MAPPED) {
+      x = kmin + v;  // kmin in (-NV, 0] and v < NV: one wrap suffices
+      if constexpr ((NV & (NV - 1)) == 0)
+        x &= NV - 1;
+      else
+        x += x < 0 ? NV : 0;
+    }
     return ROWS ? Tile<P>::at(x, k) : Tile<P>::at(k, x);
   }
 };
@@ -212,7 +306,7 @@ struct Vecs {
 // phase that reads another wavefront's vectors.
 template <typename T, int L, int EPT, int NT, class V, int TWS>
 struct Fft {
-  static_assert(EPT <= 32 && (EPT & (EPT - 1)) == 0, "EPT must be a power of two <= 32");
+  static_assert(EPT <= 32, "at most 32 elements per thread");
   static_assert(L >= EPT && L % EPT == 0, "bad FFT length");
   static constexpr int TPV = L / EPT;
   static constexpr int UPT = (V::NV * TPV + NT - 1) / NT;
@@ -230,9 +324,13 @@ struct Fft {
   const cx<T>* tw;
   V vs;
 
-  // radix of the pass at stride NS: as large as the registers allow, at most 16
+  // radix of the pass at stride NS: the largest of 16, 12, 8, 6, 4, 3, 2 that
+  // divides both the remaining length and the elements per thread
   __host__ __device__ static constexpr int radix(int NS) {
-    return (L / NS < EPT ? L / NS : EPT) < 16 ? (L / NS < EPT ? L / NS : EPT) : 16;
+    constexpr int cand[7] = {16, 12, 8, 6, 4, 3, 2};
+    for (int r : cand)
+      if (r <= EPT && (L / NS) % r == 0 && EPT % r == 0) return r;
+    return 0;  // no plan: rejected by the asserts of the pass
   }
 
   struct Regs {

@@ -98,7 +98,7 @@ def test_mlp_training_fits_a_linear_map():
 
 def test_analyze_matches_oracle():
     for M, K, prec, tol in [(32, 9, "fp32", 1e-5), (64, 15, "fp32", 1e-5), (16, 7, "fp64", 1e-12),
-                            (16, 16, "fp32", 1e-5)]:
+                            (16, 16, "fp32", 1e-5), (48, 13, "fp32", 1e-5), (48, 11, "fp64", 1e-12)]:
         case = make_case(M, K, 3, 4, seeds=(0,))
         wl = case["wl"]
         s = pdf.Solver(M, wl.side, wl.freq_hz, case["tx"], case["rx"], K, batch=1,

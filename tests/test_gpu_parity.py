@@ -2,7 +2,9 @@
 
 Tolerances: FP32 arithmetic on the device against FP64 on the host: loss terms
 and gradients within 1e-4 relative (norm-wise, and every gradient entry within
-1e-4 of the largest); the FP64 instantiation within 1e-9.
+1e-4 of the largest), or, for the terms that depend on chi = R / (beta (1 - R))
+and the gradient, 1e-6 times that map's condition number where it is larger;
+the FP64 instantiation within 1e-9.
 """
 import numpy as np
 import pytest
@@ -34,6 +36,21 @@ def oracle_terms(out):
     return np.array([out["L_state"], out["L_data"], out["L_bound"], out["L_tv"], out["L_bridge"], out["L"]])
 
 
+def chi_condition(ref):
+    """max |R| / |1 - R| over the pixels: the factor by which chi = R / (beta (1 - R)) amplifies a
+    relative error in R."""
+    R = np.asarray(ref["R"])
+    return float(np.max(np.abs(R) / np.abs(1.0 - R)))
+
+
+def term_tolerances(ref, prec, tol):
+    """Per-term tolerance of (state, data, bound, TV, bridge, total) and of the gradient.  In FP32
+    the device's R carries a relative error of about 1e-6 (two FFT convolutions and the incidence
+    sums); the chi-dependent terms see it times the condition number of chi(R)."""
+    tc = max(tol, 1e-6 * chi_condition(ref)) if prec == "fp32" else tol
+    return np.array([tol, tol, tc, tc, tc, tc]), tc
+
+
 def check_grad(g_dev, g_ref, tol):
     g_dev = np.asarray(g_dev)
     assert rel(g_dev, g_ref) < tol, rel(g_dev, g_ref)
@@ -54,6 +71,11 @@ CASES = [
     (32, 9, 36, 36, 2, "fp32", 1e-4),  # the paper's 36 / 36 antennas: ragged 2nd incidence / receiver tiles
     (16, 7, 64, 64, 1, "fp32", 1e-4),  # largest antenna counts of the FP32 path
     (8, 5, 33, 17, 2, "fp32", 1e-4),   # ragged tiles on a grid smaller than one pixel sub-tile
+    (48, 13, 12, 20, 2, "fp32", 1e-4),  # P = 96: radix-12 / radix-3 passes; chi(R) condition ~1400
+    (48, 13, 12, 20, 2, "fp64", 1e-9),  # the same instances in FP64: the arithmetic itself, strictly
+    (48, 11, 6, 9, 2, "fp64", 1e-9),
+    (48, 48, 3, 5, 1, "fp32", 1e-4),    # full basis on the radix-3 grid, even K (mapped wrap past 0)
+    (48, 21, 36, 36, 1, "fp32", 1e-4),  # largest truncation of the uneven draws, the paper's antenna count
 ]
 
 
@@ -70,9 +92,10 @@ def test_loss_grad_parity(M, K, Ni, Ns, B, prec, tol):
         ref = oloss.evaluate(alpha[b], c["prob"])
         want = oracle_terms(ref)
         got = loss[b, :6]
-        assert np.all(np.abs(got - want) <= tol * np.abs(want) + tol * 1e-3 * abs(want[5])), (b, got, want)
+        tt, tg = term_tolerances(ref, prec, tol)
+        assert np.all(np.abs(got - want) <= tt * np.abs(want) + tol * 1e-3 * abs(want[5])), (b, got, want, tt)
         assert loss[b, 7] == 0.0
-        check_grad(g[b], ref["g_alpha"], tol)
+        check_grad(g[b], ref["g_alpha"], tg)
     s.close()
 
 
@@ -250,6 +273,11 @@ def test_synthesize_matches_oracle_mom():
     got = pdf.synthesize(64, wl.side, wl.freq_hz, txn, rxn, eps, tol=1e-11, device=DEV)
     ref, _ = forward.mom_solve(eps, wl.side, ops.wavenumber(wl.freq_hz), txn, rxn)
     assert rel(got, ref) < 1e-9, rel(got, ref)
+    # a 96 x 96 grid (the fine grid of the 48 x 48 inversion grid)
+    eps96 = si.rasterize(shapes, 96, wl.side)
+    got = pdf.synthesize(96, wl.side, wl.freq_hz, tx, rx, eps96, tol=1e-11, device=DEV)
+    ref, _ = forward.mom_solve(eps96, wl.side, ops.wavenumber(wl.freq_hz), tx, rx)
+    assert rel(got, ref) < 1e-9, rel(got, ref)
     # empty support: zero field
     z = pdf.synthesize(16, wl.side, wl.freq_hz, tx, rx, np.ones((16, 16)), device=DEV)
     assert np.all(z == 0)
@@ -283,7 +311,7 @@ def test_synthesize_batch_matches_single_and_oracle_currents():
 
 
 def test_tile_choices_do_not_change_results_and_autotune_picks_one():
-    for (M, K, Ni, Ns, B) in [(32, 9, 16, 32, 3), (8, 5, 33, 17, 2), (64, 15, 32, 32, 1)]:
+    for (M, K, Ni, Ns, B) in [(32, 9, 16, 32, 3), (8, 5, 33, 17, 2), (64, 15, 32, 32, 1), (48, 13, 24, 24, 2)]:
         case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
         s = solver_for(case, "fp32")
         alpha = torch.tensor(rand_alpha(s.alpha_shape, seed=M), dtype=s.cdtype, device=DEV)
@@ -311,9 +339,11 @@ def test_reconstruct_multi_equals_separate_reconstructions():
     """Uneven batching: handles of different grids, antenna counts, truncations, batches and
     precisions advanced in one graph give exactly what each handle gives alone."""
     # same-class pairs (one grid, the same receiver / incidence tile counts) run as grouped launches:
-    # M = 16 with N_s <= 16, N_i <= 16, and M = 32 with 16 < N_s <= 32, N_i <= 16
+    # M = 16 with N_s <= 16, N_i <= 16, M = 32 with 16 < N_s <= 32, N_i <= 16, and M = 48 with
+    # N_s <= 16, N_i <= 16
     shapes = [(16, 7, 6, 8, 2, "fp32"), (32, 9, 16, 32, 3, "fp32"), (16, 5, 4, 6, 2, "fp64"), (8, 5, 3, 5, 1, "fp32"),
-              (16, 5, 5, 7, 3, "fp32"), (32, 11, 12, 20, 2, "fp32"), (16, 9, 9, 13, 1, "fp32")]
+              (16, 5, 5, 7, 3, "fp32"), (32, 11, 12, 20, 2, "fp32"), (16, 9, 9, 13, 1, "fp32"),
+              (48, 9, 16, 16, 2, "fp32"), (48, 13, 12, 14, 1, "fp32")]
     sol, eps, datas = [], [], []
     for (M, K, Ni, Ns, B, prec) in shapes:
         case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))

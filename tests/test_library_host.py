@@ -121,9 +121,12 @@ def test_argument_errors_without_device():
     assert lib.pdf_setup(ctypes.byref(g), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
                          ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EINVAL
     p.version = 1
-    g48 = B.Grid(48, 1.5, 0.0, 0.0)
-    assert lib.pdf_setup(ctypes.byref(g48), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
-                         ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EUNSUPPORTED
+    for m_bad, prec in ((40, B.FP32), (96, B.FP32), (64, B.FP64)):  # not LDS-resident / no plan
+        p.precision = prec
+        gb = B.Grid(m_bad, 1.5, 0.0, 0.0)
+        assert lib.pdf_setup(ctypes.byref(gb), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
+                             ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EUNSUPPORTED, m_bad
+    p.precision = B.FP32
     bad = np.array([[np.nan, 0.0]] * 4)
     arr2 = B.Array(4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     assert lib.pdf_setup(ctypes.byref(g), 4e8, ctypes.byref(arr2), ctypes.byref(arr), 9, 1, ctypes.byref(p),
