@@ -24,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -40,26 +41,45 @@ def log(*a):
 
 
 # kernel names in the library's timing order, and how they appear in profiler output
-KERNEL_SYMBOLS = {
-    "fwd_conv": "k_fwd_conv<float, 64, true>",
+KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant)
+    "fwd_conv": "k_fwd_conv<float, 64, true,",
     "pixel_reduce": "k_pixel_reduce_mfma<",
     "image_reg": "k_image_reg<float>",
     "adj_gemm": "k_adj_gemm_mfma<",
-    "adj_conv": "k_adj_conv<float, 64>",
+    "adj_conv": "k_adj_conv<float, 64,",
 }
+
+
+def kernel_variant(name):
+    """The template instance of a kernel symbol without spaces, e.g. k_adj_conv<float,64,false>."""
+    m = re.search(r"(k_\w+<[^>]*>)", name)
+    return m.group(1).replace(" ", "") if m else name.replace(" ", "")
+
+
+def tuned_variants(wl, tuned):
+    """Template instance of each step kernel that the tile / plan choice `tuned` launches."""
+    ct, pb, fpp, app = tuned
+    tf = lambda b: "true" if b else "false"
+    nrt, nct, nrta = -(-wl.n_rx // 16), -(-wl.n_tx // 32), -(-wl.n_tx // 16)
+    return {"fwd_conv": f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
+            "pixel_reduce": f"k_pixel_reduce_mfma<{nrt},{nct},{pb}>",
+            "image_reg": "k_image_reg<float>",
+            "adj_gemm": f"k_adj_gemm_mfma<{nrta},{ct}>",
+            "adj_conv": f"k_adj_conv<float,{wl.M},{tf(app)}>"}
 CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")
 
 
 # the sources the step kernels and their launches are built from
-STEP_SOURCES = ("api.hip", "conv_kernels.h", "cplx.h", "fft_lds.h", "handle.h", "init_kernels.h",
-                "pixel_kernels.h")
+STEP_SOURCES = ("csrc/api.hip", "csrc/conv_kernels.h", "csrc/cplx.h", "csrc/fft_lds.h", "csrc/handle.h",
+                "csrc/init_kernels.h", "csrc/pixel_kernels.h", "build.py")   # build.py: the compiler flags
 
 
 def kernel_source_hash():
-    """SHA-256 over the step kernels' sources: traffic counts are valid only for the code they were taken on."""
+    """SHA-256 over the step kernels' sources and compiler flags: traffic counts are valid only for the
+    code they were taken on."""
     import hashlib
-    d = os.path.join(ROOT, "paper_2602_13805_amd", "csrc")
+    d = os.path.join(ROOT, "paper_2602_13805_amd")
     h = hashlib.sha256()
     for name in STEP_SOURCES:
         h.update(name.encode())
@@ -104,6 +124,8 @@ def summarize_rocprof(dirs, kind, copy_mib):
                     k = _short_kernel(r["Kernel_Name"])
                     if k is None:
                         continue
+                    if k != "calibration_copy":
+                        k = (k, kernel_variant(r["Kernel_Name"]))
                     acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
     cal = avg.get("calibration_copy", {})
@@ -118,18 +140,21 @@ def summarize_rocprof(dirs, kind, copy_mib):
     lines.append(f"calibration_write_kib: {cal['WRITE_SIZE']:.1f}")
     lines.append(f"fetch_scale: {f_scale:.4f}")
     lines.append(f"write_scale: {w_scale:.4f}")
-    for k in KERNEL_SYMBOLS:
-        if k not in avg or "FETCH_SIZE" not in avg[k] or "WRITE_SIZE" not in avg[k]:
+    order = list(KERNEL_SYMBOLS)
+    for k in sorted((k for k in avg if k != "calibration_copy"), key=lambda k: (order.index(k[0]), k[1])):
+        if "FETCH_SIZE" not in avg[k] or "WRITE_SIZE" not in avg[k]:
             continue
         fb = avg[k]["FETCH_SIZE"] * 1024.0 * f_scale
         wb = avg[k]["WRITE_SIZE"] * 1024.0 * w_scale
-        lines.append(f"kernel {k} fetch_kib={avg[k]['FETCH_SIZE']:.1f} write_kib={avg[k]['WRITE_SIZE']:.1f} "
-                     f"bytes={fb + wb:.0f}")
+        n = len(acc[k]["FETCH_SIZE"])
+        lines.append(f"kernel {k[0]} {k[1]} fetch_kib={avg[k]['FETCH_SIZE']:.1f} "
+                     f"write_kib={avg[k]['WRITE_SIZE']:.1f} bytes={fb + wb:.0f} dispatches={n}")
     return "\n".join(lines)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if taken on these sources."""
+def measured_traffic(kernel, variant):
+    """HBM bytes per launch of `kernel` (template instance `variant`) from the committed counter
+    summary, if taken on these sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     meta, per = {}, {}
@@ -138,15 +163,16 @@ def measured_traffic(kernel):
             line = line.strip()
             if line.startswith("kernel "):
                 parts = line.split()
-                per[parts[1]] = dict(kv.split("=") for kv in parts[2:])
+                per[(parts[1], parts[2])] = dict(kv.split("=") for kv in parts[3:])
             elif ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 meta[k.strip()] = v.strip()
     if meta.get("source_sha256") != kernel_source_hash():
         return None, "kernel sources changed since the counters were taken"
-    if kernel not in per:
-        return None, "kernel not in the counter summary"
-    return float(per[kernel]["bytes"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size"
+    if (kernel, variant) not in per:
+        return None, f"{variant} not in the counter summary"
+    return (float(per[(kernel, variant)]["bytes"]),
+            f"rocprofv3 FETCH_SIZE + WRITE_SIZE of {variant}, scaled by a copy kernel of known size")
 
 
 def workload_cost(wl, B, ntiles):
@@ -250,6 +276,17 @@ def main():
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
     ap.add_argument("--summary-kind", choices=["stats", "pmc"], default="stats")
+    ap.add_argument("--save-fields", metavar="NPZ",
+                    help="synthesise the batch's measured fields, write them to this file and exit")
+    ap.add_argument("--load-fields", metavar="NPZ",
+                    help="take the batch's measured fields from a file written by --save-fields instead of "
+                         "synthesising them (profiled runs: only the step's kernels run on the device)")
+    ap.add_argument("--tiles", metavar="CT,PB,FPP,APP",
+                    help="use this tile / FFT-plan choice instead of autotuning (counter runs: no tuning "
+                         "launches mixed into the step kernels' averages)")
+    ap.add_argument("--all-variants", action="store_true",
+                    help="after the timed steps, run one step under every tile / plan choice (counter runs: "
+                         "every variant of every step kernel measured inside a step)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         print(summarize_rocprof(args.summarize_rocprof, args.summary_kind, args.copy_calibration_mib or 256))
@@ -269,9 +306,19 @@ def main():
     wl = si.WORKLOADS["cfg2"]
     B = args.batch
     t0 = time.time()
-    esca, eps = synthesize_batch(pdf, si, wl, B, dev)
+    if args.load_fields:
+        with np.load(args.load_fields) as f:
+            esca, eps = f["esca"], f["eps"]
+            if esca.shape[0] != B or int(f["seed0"]) != 0:
+                raise SystemExit(f"{args.load_fields} holds another batch")
+        log(f"loaded the measured fields of {B} instances")
+    else:
+        esca, eps = synthesize_batch(pdf, si, wl, B, dev)
+        log(f"synthesised {B} instances in {time.time() - t0:.1f} s")
     synth_s = time.time() - t0
-    log(f"synthesised {B} instances in {synth_s:.1f} s")
+    if args.save_fields:
+        np.savez(args.save_fields, esca=esca, eps=eps, seed0=0)
+        return
 
     if args.copy_calibration_mib:
         # an elementwise kernel (not a DMA copy): reads and writes exactly this many MiB each
@@ -285,8 +332,12 @@ def main():
     s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=B, device=dev)
     s.set_data(torch.tensor(esca, dtype=s.cdtype, device=dev))
     alpha = s.init_alpha()
-    tuned, tune_ms = s.autotune(5)   # tile shapes and FFT plans; results do not depend on them
-    log(f"autotuned (column tiles, load batch, forward plan, adjoint plan) = {tuned}")
+    if args.tiles:
+        tuned = tuple(int(x) for x in args.tiles.split(","))
+        s.set_tiles(*tuned)
+    else:
+        tuned, _ = s.autotune(5)   # tile shapes and FFT plans; results do not depend on them
+    log(f"tiles (column tiles, load batch, forward plan, adjoint plan) = {tuned}")
     m, v, t = s.new_state()
     loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
@@ -305,6 +356,14 @@ def main():
     log(f"{args.steps} steps x {B} instances in {dt:.3f} s: {value:.1f} instance-iters/s; kernels {kern_ms}")
     if not np.all(np.isfinite(loss.cpu().numpy()[:, 5])):
         raise RuntimeError("non-finite loss in the timed steps")
+    if args.all_variants:
+        for ct in (1, 2, 4):
+            for pb in (4, 8):
+                for plan in range(4):
+                    s.set_tiles(ct, pb, plan >> 1, plan & 1)
+                    s.step(alpha, m, v, t, loss)
+        s.set_tiles(*tuned)
+        torch.cuda.synchronize()
 
     bytes_, flops = workload_cost(wl, B, s_ntiles(wl.M))
     dom = max(kern_ms, key=kern_ms.get)
@@ -315,7 +374,7 @@ def main():
     else:
         roof = dict(bound="hbm", achieved=bytes_[dom] / dur / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"], roof["traffic_source"] = measured_traffic(dom)
+    roof["traffic"], roof["traffic_source"] = measured_traffic(dom, tuned_variants(wl, tuned)[dom])
     roof["kernel"] = dom
     roof["algorithmic_bytes"] = bytes_[dom]
     roof["algorithmic_flops"] = flops[dom]
@@ -375,9 +434,9 @@ def main():
                                "K=15, FP32; fields from FP64 MoM on 128x128 with +-2 deg jitter and 10% AWGN",
                    "batch": B, "M": wl.M, "K": wl.K, "n_tx": wl.n_tx, "n_rx": wl.n_rx,
                    "freq_hz": wl.freq_hz, "parallelism": "none (one GPU, independent instances)"},
-        "roofline": roof, "kernels": per_kernel, "timed_kernel_steps": nrec, "synthesis_seconds": synth_s,
-        "autotuned": dict(gemm_column_tiles=tuned[0], reduce_load_batch=tuned[1], fwd_rows_pingpong=tuned[2],
-                          adj_rows_pingpong=tuned[3]),
+        "roofline": roof, "kernels": per_kernel, "timed_kernel_steps": nrec, "synthesis_seconds": None if args.load_fields else synth_s,
+        "tiles": dict(gemm_column_tiles=tuned[0], reduce_load_batch=tuned[1], fwd_rows_pingpong=tuned[2],
+                      adj_rows_pingpong=tuned[3], source="given" if args.tiles else "autotuned"),
         "paper_context": {"seconds_per_reconstruction": 0.88, "hardware": "1x RTX 4090",
                           "note": "Table 1; 64x64, 36/36 antennas at 20 wavelengths, iteration count not stated"},
     }

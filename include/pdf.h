@@ -178,13 +178,16 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
  * pixel reduction's load batch (4 incidences at four wavefronts per SIMD, or
  * 8 at two), and for each convolution kernel whether its row FFT passes
  * alternate between the two halves of the LDS tile (one barrier per pass) or
- * run in place (two).  Every candidate computes each result in the same
+ * run in place (two); the two plans are timed as pairs inside whole
+ * loss-gradient passes.  Every candidate computes each result in the same
  * order, so the choice changes timing only, never a value.  choice: host
  * int32 [4] out (column tiles, load batch, forward plan, adjoint plan), may
- * be NULL; ms: host double [9] out (three GEMM, two reduction, two forward
- * and two adjoint timings), may be NULL.  FP64 handles and grids with M*M
- * not a multiple of 32 keep the defaults (2, 4, 1, 0).  Synchronous;
- * overwrites the handle's scratch arrays (not alpha, data or Adam state). */
+ * be NULL; ms: host double [9] out (three GEMM and two reduction timings,
+ * then the loss-gradient pass with plans (0,0), (0,1), (1,0), (1,1)), may be
+ * NULL.  FP64 handles and grids with M*M not a multiple of 32 keep the
+ * defaults (2, 4, 1, 0).  Synchronous; overwrites the handle's scratch arrays
+ * and its internal Adam moments (every pdf_reconstruct re-initialises them),
+ * not alpha or the data. */
 int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms);
 /* Sets the choices directly (ct in {1, 2, 4}, pb in {4, 8}, plans 0 or 1). */
 int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_pp, int32_t adj_pp);

@@ -983,27 +983,25 @@ extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double
                             &t[3 + i])))
       return rc;
   }
-  // FFT plans of the two convolution kernels (scratch in and out: g0 as coefficients, J and E written)
-  for (int i = 0; i < 2; ++i) {
-    h->tune_fpp = i;
-    if ((rc = time_launches(h, reps, [&]() { return launch_fwd<float>(h, fwd_args<float>(h, h->g0), true); },
-                            &t[5 + i])))
-      return rc;
-  }
-  for (int i = 0; i < 2; ++i) {
-    h->tune_app = i;
-    if ((rc = time_launches(
-             h, reps,
-             [&]() { return launch_adj<float>(h, adj_args<float>(h, h->g0, nullptr, nullptr, nullptr, nullptr, nullptr)); },
-             &t[7 + i])))
-      return rc;
-  }
   best_ct = cts[t[0] <= t[1] ? (t[0] <= t[2] ? 0 : 2) : (t[1] <= t[2] ? 1 : 2)];
   best_pb = pbs[t[3] <= t[4] ? 0 : 1];
   h->tune_ct = best_ct;
   h->tune_pb = best_pb;
-  h->tune_fpp = t[6] <= t[5] ? 1 : 0;
-  h->tune_app = t[8] <= t[7] ? 1 : 0;
+  // FFT plans of the two convolution kernels, timed inside the whole loss-gradient pass (their
+  // speed depends on the kernels around them); scratch in and out: g0 as coefficients, the Adam
+  // moment m (re-initialised by every reconstruction) as the gradient, loss_w as the loss record
+  int best_plan = 0;
+  for (int i = 0; i < 4; ++i) {
+    h->tune_fpp = i >> 1;
+    h->tune_app = i & 1;
+    if ((rc = time_launches(h, reps, [&]() {
+           return run_iteration<float>(h, h->g0, h->m, h->loss_w, nullptr, nullptr, nullptr, nullptr, nullptr);
+         }, &t[5 + i])))
+      return rc;
+    if (t[5 + i] < t[5 + best_plan]) best_plan = i;
+  }
+  h->tune_fpp = best_plan >> 1;
+  h->tune_app = best_plan & 1;
   h->tuned = true;
   if (choice) choice[0] = best_ct, choice[1] = best_pb, choice[2] = h->tune_fpp, choice[3] = h->tune_app;
   if (ms)
