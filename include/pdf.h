@@ -98,7 +98,7 @@ int pdf_default_params(pdf_params* p);
  *   grid, tx, rx, params: host structs (params may be NULL for defaults).
  *   freq_hz: frequency.  K: truncation per axis, 1 <= K <= M.
  *   stream: hipStream_t for every later call (must not be NULL).
- * Supported: M in {8, 16, 32, 48, 64} (FP32) or {8, 16, 32, 48} (FP64); Ni, Ns >= 1.
+ * Supported: M in {8, 16, 32, 48, 64} (FP32 and FP64); Ni, Ns >= 1.
  * Errors: PDF_EINVAL (bad sizes / null), PDF_EUNSUPPORTED (other M),
  * PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (||E_inc|| = 0). */
 int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
@@ -172,25 +172,19 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
                     int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
                     void* chi_cco_dev, pdf_report* rep);
 
-/* Tile shapes and FFT plans of this handle's FP32 kernels, chosen by timing
- * `reps` launches of each candidate on the handle's own buffers: the G_S^H
- * GEMM's column tiles per wavefront (1, 2 or 4 tiles of 32 pixels), the
- * pixel reduction's load batch (4 incidences at four wavefronts per SIMD, or
- * 8 at two), and for each convolution kernel whether its row FFT passes
- * alternate between the two halves of the LDS tile (one barrier per pass) or
- * run in place (two); the two plans are timed as pairs inside whole
- * loss-gradient passes.  Every candidate computes each result in the same
- * order, so the choice changes timing only, never a value.  choice: host
- * int32 [4] out (column tiles, load batch, forward plan, adjoint plan), may
- * be NULL; ms: host double [9] out (three GEMM and two reduction timings,
- * then the loss-gradient pass with plans (0,0), (0,1), (1,0), (1,1)), may be
- * NULL.  FP64 handles and grids with M*M not a multiple of 32 keep the
- * defaults (2, 4, 1, 0).  Synchronous; overwrites the handle's scratch arrays
- * and its internal Adam moments (every pdf_reconstruct re-initialises them),
- * not alpha or the data. */
+/* Tile shapes of this handle's FP32 MFMA kernels, chosen by timing `reps`
+ * launches of each candidate on the handle's own buffers: the G_S^H GEMM's
+ * column tiles per wavefront (1, 2 or 4 tiles of 32 pixels) and the pixel
+ * reduction's load batch (4 incidences at four wavefronts per SIMD, or 8 at
+ * two).  Every candidate computes each result in the same order, so the
+ * choice changes timing only, never a value.  choice: host int32 [2] out
+ * (column tiles, load batch), may be NULL; ms: host double [5] out (three
+ * GEMM and two reduction timings), may be NULL.  FP64 handles and grids with
+ * M*M not a multiple of 32 keep the defaults (2, 4).  Synchronous;
+ * overwrites the handle's scratch arrays, not alpha or the data. */
 int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms);
-/* Sets the choices directly (ct in {1, 2, 4}, pb in {4, 8}, plans 0 or 1). */
-int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_pp, int32_t adj_pp);
+/* Sets the choices directly (ct in {1, 2, 4}, pb in {4, 8}). */
+int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb);
 
 /* Uneven batching: the reconstructions of n handles (different grids, antenna
  * counts, truncations, batch sizes and precisions) advanced together.  Every

@@ -14,117 +14,154 @@ struct ConvCfg {
   static constexpr int M = M_;
   static constexpr int P = 2 * M;
   static constexpr int N = M * M;
-  using TileL = Tile<P>;             // P x P tile in LDS, row stride P + 1
+  // The tile holds the M stored rows of the padded P x P grid (row stride
+  // P + 1); rows M..P-1 are zero padding and are never stored: the column
+  // phase works on the M stored entries of each column (see col_conv).
+  using TileL = Tile<P>;
   // M = 48 (P = 96 = 3 * 32) takes radix-12 / radix-3 passes: every
   // per-thread element count carries the factor 3
   static constexpr bool TRI = M % 3 == 0;
-  static constexpr int NT = M >= 64 ? 1024 : (TRI ? 384 : (M >= 32 ? 256 : 64));
-  static constexpr int EPT_M = TRI ? 12 : 8;      // length-M transforms (basis), workgroup-wide
-  static constexpr int EPT_R = TRI ? 12 : 8;      // length-P transforms along rows, workgroup-wide
-  static constexpr int EPT_C = TRI ? 24 : 16;     // length-P transforms along columns, wave-local
+  static constexpr int NT = M >= 64 ? 512 : (TRI ? 384 : (M >= 32 ? 256 : 64));
+  static constexpr int EPT_M = TRI ? 12 : 8;                 // length-M transforms (basis), workgroup-wide
+  static constexpr int EPT_R = TRI ? 12 : (M >= 64 ? 16 : 8);  // length-P transforms along rows, workgroup-wide
+  static constexpr int EPT_C = TRI ? 12 : (M >= 64 ? 16 : 8);  // length-M column chains, wave-local
   static constexpr int PPT = N / NT;              // pixels owned per thread
   static_assert(N % NT == 0, "pixel ownership must be exact");
-  static_assert(P >= 16, "the column pass needs P >= 16");
-  static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(P) * TileL::LD + P);
-  static constexpr int BOT = M * TileL::LD;       // offset of rows M..2M-1: the second region
-  using Rows = Vecs<P, M, true>;                 // the M nonzero rows, elements along a row
-  using Cols = Vecs<P, P, false, false, true>;   // all P columns, wave-local
+  static_assert(P >= 16, "the column phase needs P >= 16");
+  static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(M) * TileL::LD + P);
+  // waves per SIMD the register allocation must allow: two 512-thread FP32
+  // workgroups per CU at M = 64 (67 KB of LDS each) need four
+  static constexpr int WPE = sizeof(T) == 4 ? 4 : 2;
+  using Rows = Vecs<P, M, true>;                 // the M stored rows, elements along a row
+  using Cols = Vecs<P, P, false, false, true>;   // all P columns (their M stored entries), wave-local
   using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
   using ColsM = Vecs<P, M, false>;
   using ModeRows = Vecs<P, M, true, true>;       // the K rows / columns of the kept modes
   using ModeCols = Vecs<P, M, false, true>;
 };
 
-// Column phase of the convolution, in place on all P columns: forward FFT
-// (rows >= M are zero), multiplication by the spectrum, inverse FFT, rows
-// < M kept.  Each wavefront owns whole columns, so the phase needs no
-// workgroup barrier until its end.  The forward transform's last pass and the
-// inverse transform's first pass share their registers (both radix R2 on the
-// elements j + R1 r of butterfly j), so the spectrum is multiplied in
-// registers and one LDS round trip is saved.
-// The input column (rows < M) is read from the region at element offset
-// src; the result is in rows < M of the tile (offset 0).
+// Column phase of the convolution, in place on all P columns of the M x P
+// tile.  For a column with stored entries x (the padded entries M..P-1 are
+// zero) the phase computes y = crop_M(IFFT_P(ghat[., c] FFT_P(pad(x)))).  The
+// even and odd frequencies of the padded transform are FFT_M(x) and
+// FFT_M(x w) with w[n] = exp(-2 pi i n / P), and the cropped inverse splits
+// the same way, so
+//   y[n] = IFFT_M(ghat[2k, c] FFT_M(x))[n] + conj(w[n]) IFFT_M(ghat[2k+1, c] FFT_M(x w))[n]:
+// two length-M chains per column instead of one length-P transform, and no
+// storage for the padded half.  Each wavefront owns whole columns; x and the
+// first chain's result stay in registers while each chain exchanges through
+// the column's own M entries.  A chain's forward last pass and inverse first
+// pass share their registers, so the spectrum is applied in registers.
+// The adjoint uses conj(ghat).
 template <typename T, int M>
-__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
+__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
   using C = ConvCfg<T, M>;
-  constexpr int P = C::P;
-  using F = Fft<T, P, C::EPT_C, C::NT, typename C::Cols, 1>;
-  constexpr int R1 = F::radix(1), R2 = P / R1;  // forward radices R1 then R2, inverse R2 then R1
-  static_assert(R2 <= 16 && R2 <= C::EPT_C, "column transform must take two passes");
+  constexpr int P = C::P, EPT = C::EPT_C;
+  using F = Fft<T, M, EPT, C::NT, typename C::Cols, 2>;   // tw[2k] = exp(-2 pi i k / M)
+  constexpr int R1 = F::radix(1), R2 = M / R1;            // forward radices R1 then R2, inverse R2 then R1
+  static_assert(R2 == 1 || (R2 <= 16 && EPT % R2 == 0), "a chain takes one or two passes");
   const F f{buf, tw, typename C::Cols{}};
-  // spectrum multiply on the registers of a pass whose butterfly j holds elements j + NSOUT r
-  auto mul_ghat = [&](typename F::Regs& g, auto rc, int NSOUT) {
+  typename F::Regs x;
+  f.assign(x);
+  f.template load<R1, 1, -1, R1>(x, NoLoad());  // butterfly j holds elements j + (M / R1) r
+  // output position of register (q, u, r) after the chain's last (inverse) pass
+  auto out_pos = [&](int q, int u, int r) {
+    const int j = x.t[q] + u * F::TPV;
+    if constexpr (R2 == 1)
+      return r;
+    else
+      return (j / R2) * R2 * R1 + (j % R2) + r * R2;
+  };
+  // spectrum of the chain's frequency k = j + NSOUT r (row 2k + c of ghat) on the registers of butterfly j
+  auto mul_ghat = [&](typename F::Regs& g, int c, auto rc, int NSOUT) {
     constexpr int R = decltype(rc)::value;
 #pragma unroll
     for (int q = 0; q < F::UPT; ++q) {
       if (!g.act[q]) continue;
 #pragma unroll
-      for (int u = 0; u < C::EPT_C / R; ++u) {
+      for (int u = 0; u < EPT / R; ++u) {
         const int j = g.t[q] + u * F::TPV;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          cx<T> w = ghat[(j + r * NSOUT) * P + g.vec[q]];
+          cx<T> w = ghat[(2 * (j + r * NSOUT) + c) * P + g.vec[q]];
           if (adjoint) w.y = -w.y;
           g.v[q][u * R + r] = g.v[q][u * R + r] * w;
         }
       }
     }
   };
-  if constexpr (R2 == 1) {
-    typename F::Regs g;
-    f.assign(g);
-    f.template load<R1, 1, -1, R1 / 2>(g, NoLoad(), src);
-    F::sync();
-    f.template compute<R1, -1, R1 / 2, R1>(g);
-    mul_ghat(g, std::integral_constant<int, R1>{}, 1);
-    f.template compute<R1, +1, R1, R1 / 2>(g);
-    f.template store<R1, 1, R1 / 2>(g);
-  } else {
-    {  // first pass: from the source region into the whole column (they overlap: wave sync between)
-      typename F::Regs g1;
-      f.assign(g1);
-      f.template load<R1, 1, -1, R1 / 2>(g1, NoLoad(), src);
-      F::sync();
-      f.template compute<R1, -1, R1 / 2, R1>(g1);
-      f.template store<R1, 1, R1>(g1);
-      F::sync();
+  cx<T> acc[F::UPT][EPT];
+  static_for<2>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;  // 0: even frequencies, 1: odd
+    F::sync();  // every lane's reads of the column are done before it is overwritten
+    typename F::Regs g = x;
+    if constexpr (c == 1) {  // the odd chain transforms x w
+#pragma unroll
+      for (int q = 0; q < F::UPT; ++q) {
+        if (!g.act[q]) continue;
+#pragma unroll
+        for (int u = 0; u < EPT / R1; ++u) {
+          const int j = g.t[q] + u * F::TPV;
+#pragma unroll
+          for (int r = 0; r < R1; ++r) g.v[q][u * R1 + r] = g.v[q][u * R1 + r] * tw[j + r * (M / R1)];
+        }
+      }
     }
-    typename F::Regs g;
-    f.assign(g);
-    f.template load<R2, R1, -1, R2>(g, NoLoad());
-    F::sync();
-    f.template compute<R2, -1, R2, R2>(g);
-    mul_ghat(g, std::integral_constant<int, R2>{}, R1);
-    f.template compute<R2, +1, R2, R2>(g);
-    f.template store<R2, 1, R2>(g);
-    F::sync();
-    f.template pass<R1, R2, +1, R1, M / R2>(NoLoad());
-  }
+    if constexpr (R2 == 1) {
+      f.template compute<R1, -1, R1, R1>(g);
+      mul_ghat(g, c, std::integral_constant<int, R1>{}, 1);
+      f.template compute<R1, +1, R1, R1>(g);
+    } else {
+      f.template compute<R1, -1, R1, R1>(g);
+      f.template store<R1, 1, R1>(g);
+      F::sync();
+      f.template load<R2, R1, -1, R2>(g, NoLoad());
+      f.template compute<R2, -1, R2, R2>(g);
+      mul_ghat(g, c, std::integral_constant<int, R2>{}, R1);
+      f.template compute<R2, +1, R2, R2>(g);
+      F::sync();
+      f.template store<R2, 1, R2>(g);
+      F::sync();
+      f.template load<R1, R2, +1, R1>(g, NoLoad());
+      f.template compute<R1, +1, R1, R1>(g);
+    }
+    if constexpr (c == 0) {
+#pragma unroll
+      for (int q = 0; q < F::UPT; ++q)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc[q][e] = g.v[q][e];
+    } else {
+      F::sync();
+#pragma unroll
+      for (int q = 0; q < F::UPT; ++q) {
+        if (!g.act[q]) continue;
+#pragma unroll
+        for (int u = 0; u < EPT / R1; ++u)
+#pragma unroll
+          for (int r = 0; r < R1; ++r) {
+            const int n = out_pos(q, u, r);
+            cx<T> w = tw[n];
+            w.y = -w.y;
+            buf[f.vs.addr(g.vec[q], n)] = acc[q][u * R1 + r] + g.v[q][u * R1 + r] * w;
+          }
+      }
+    }
+  });
   __syncthreads();  // the row pass that follows reads every column
 }
 
-// x -> G_D x (or G_D^H x) for x on the M x M block of region `src` (element
-// offset 0: rows 0..M-1 of the tile, or BOT: rows M..2M-1); returns the
-// offset of the region holding the result.  The spectrum ghat is pre-scaled
-// by 1/P^2.  With PP the row passes alternate between the two regions (one
-// barrier each), else they run in place (two barriers each); which is faster
-// depends on the kernel around it (the autotuner times both).  The column
-// phase is wave-local and ends with a workgroup barrier.
-template <typename T, int M, bool PP>
-__device__ __forceinline__ int conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
+// x -> G_D x (or G_D^H x) for x on the M x M block of the tile; the result
+// replaces it.  The spectrum ghat is pre-scaled by 1/P^2.  Row passes are
+// workgroup-wide and in place; the column phase is wave-local and ends with a
+// workgroup barrier.
+template <typename T, int M>
+__device__ __forceinline__ void conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
   using C = ConvCfg<T, M>;
-  constexpr int P = C::P, BOT = C::BOT;
+  constexpr int P = C::P;
   const Fft<T, P, C::EPT_R, C::NT, typename C::Rows, 1> rows{buf, tw, typename C::Rows{}};
-  if constexpr (PP) {
-    const int r = rows.template run_pp<-1, M, P>(src, src == 0 ? BOT : 0);
-    col_conv<T, M>(buf, tw, ghat, adjoint, r);
-    return rows.template run_pp<+1, P, M>(0, BOT);
-  } else {
-    rows.template run<-1, M, P>(NoLoad(), src);
-    col_conv<T, M>(buf, tw, ghat, adjoint, src);
-    rows.template run<+1, P, M>(NoLoad(), 0);
-    return 0;
-  }
+  rows.template run<-1, M, P>();   // the right half of each row is zero padding
+  col_conv<T, M>(buf, tw, ghat, adjoint);
+  rows.template run<+1, P, M>();   // only the left half is kept
 }
 
 __device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
@@ -143,18 +180,15 @@ struct FwdArgs {
 
 // alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
 // E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
-// PP: the convolution's row passes alternate between the tile's halves (one
-// barrier each) or run in place; a tuning choice with identical results.
-template <typename T, int M, bool FROM_ALPHA, bool PP>
+template <typename T, int M, bool FROM_ALPHA>
 __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::P * C::TileL::LD;
+  cx<T>* tw = buf + C::M * C::TileL::LD;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
   cx<T> jr[C::PPT];
-  int src = 0;  // region holding J
   if constexpr (FROM_ALPHA) {
     // the coefficients (K^2 <= N) are loaded with the twiddles in one round trip
     const int K = a.K, KK = K * K, kmin = -(K / 2);
@@ -163,11 +197,8 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) av[q] = al[min(tid + q * C::NT, KK - 1)];
     for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
-    // both regions start at zero: the mode passes write only the K kept rows
-    for (int e = tid; e < C::N; e += C::NT) {
-      buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
-      buf[C::BOT + C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
-    }
+    // the M x M block starts at zero: the mode passes transform only the K kept rows
+    for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
@@ -178,14 +209,12 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     typename C::ModeRows mr;
     mr.nv = K;
     mr.kmin = kmin;
-    int r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run_pp<+1>(0, C::BOT);
-    r = Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run_pp<+1>(
-        r, r == 0 ? C::BOT : 0);
-    src = r;
+    Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
+    Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = buf[r + C::TileL::at(n / M, n % M)];
+      jr[q] = buf[C::TileL::at(n / M, n % M)];
       if (a.J) a.J[off + n] = jr[q];
     }
   } else {
@@ -199,7 +228,7 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     }
     __syncthreads();
   }
-  const int res = conv_core<T, M, PP>(buf, tw, a.ghat, false, src);
+  conv_core<T, M>(buf, tw, a.ghat, false);
   // all loads of the epilogue are issued before their use (the workgroup
   // fills its CU, so nothing else hides their latency)
   cx<T> ei[C::PPT];
@@ -213,23 +242,23 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    a.E[off + n] = buf[res + C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
+    a.E[off + n] = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
   }
 }
 
-template <typename T, int M, bool FROM_ALPHA, bool PP>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv(FwdArgs<T> a) {
+template <typename T, int M, bool FROM_ALPHA>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_fwd_conv(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fwd_conv_body<T, M, FROM_ALPHA, PP>(a, blockIdx.x, smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA>(a, blockIdx.x, smem_raw);
 }
 
 // One launch over several argument sets (handles of one shape class).
-template <typename T, int M, bool FROM_ALPHA, bool PP>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
+template <typename T, int M, bool FROM_ALPHA>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
                                                                          const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = group_of(start, n, blockIdx.x);
-  fwd_conv_body<T, M, FROM_ALPHA, PP>(a[g], blockIdx.x - start[g], smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 template <typename T>
@@ -264,11 +293,11 @@ struct AdjArgs {
 //   g_alpha = B^H g_J  (unnormalised forward DFT on the kept modes)
 // The state loss's own derivative in R vanishes because R is its per-pixel
 // least-squares minimiser, so only the regulariser part g_R reaches R.
-template <typename T, int M, bool PP>
+template <typename T, int M>
 __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::P * C::TileL::LD;
+  cx<T>* tw = buf + C::M * C::TileL::LD;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
@@ -326,7 +355,8 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
     gj[q] = gJ;
   }
   __syncthreads();
-  int r = conv_core<T, M, PP>(buf, tw, a.ghat, true, 0);
+  conv_core<T, M>(buf, tw, a.ghat, true);
+  constexpr int r = 0;  // offset of the result in the tile
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
@@ -371,29 +401,31 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   }
 }
 
-template <typename T, int M, bool PP>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv(AdjArgs<T> a) {
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_adj_conv(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  adj_conv_body<T, M, PP>(a, blockIdx.x, smem_raw);
+  // the N_i workgroups of an instance read its per-pixel R, den and g_R: one XCD serves them
+  adj_conv_body<T, M>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
 }
 
-template <typename T, int M, bool PP>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_adj_conv_group(const AdjArgs<T>* __restrict__ a,
+template <typename T, int M>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_adj_conv_group(const AdjArgs<T>* __restrict__ a,
                                                                         const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int g = group_of(start, n, blockIdx.x);
-  adj_conv_body<T, M, PP>(a[g], blockIdx.x - start[g], smem_raw);
+  const int bx = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = group_of(start, n, bx);
+  adj_conv_body<T, M>(a[g], bx - start[g], smem_raw);
 }
 
 // alpha = F_T(J) on the kept modes (Sec. 2.3, Eq. 9): forward DFT of one
 // set of pixel currents divided by M^2 (grid: one workgroup per current).
 template <typename T, int M>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_analyze(const cx<T>* J, const cx<T>* twg, cx<T>* alpha,
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_analyze(const cx<T>* J, const cx<T>* twg, cx<T>* alpha,
                                                                   int K) {
   using C = ConvCfg<T, M>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::P * C::TileL::LD;
+  cx<T>* tw = buf + C::M * C::TileL::LD;
   const size_t v = blockIdx.x;
   const int tid = threadIdx.x;
   cx<T> jv[C::PPT];
@@ -407,15 +439,14 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT)) void k_analyze(const cx<T>* J,
   }
   __syncthreads();
   const int kmin = -(K / 2);
-  int r = Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run_pp<-1>(
-      0, C::BOT);
+  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>();
   typename C::ModeCols mc;
   mc.nv = K;
   mc.kmin = kmin;
-  r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run_pp<-1>(r, r == 0 ? C::BOT : 0);
+  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>();
   const T s = T(1) / T(C::N);
   for (int e = tid; e < K * K; e += C::NT) {
-    const cx<T> g = buf[r + C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))];
+    const cx<T> g = buf[C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))];
     alpha[v * K * K + e] = cx<T>{s * g.x, s * g.y};
   }
 }

@@ -40,6 +40,17 @@ __host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
   return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup x to XCD
+// x mod 8), and each XCD has its own L2.  This maps the hardware order x of an
+// n-workgroup grid to a logical order in which every XCD takes one contiguous
+// range of logical workgroups (a bijection of [0, n)), so that neighbouring
+// logical workgroups, which share inputs, share an L2.
+__device__ __forceinline__ int xcd_remap(int x, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n % X, c = x % X, slot = x / X;
+  return c * q + (c < r ? c : r) + slot;
+}
+
 // Grouped launches: one launch serves several argument sets, set g taking the
 // workgroups [start[g], start[g+1]).  Returns g for workgroup bx (the search
 // is uniform over the workgroup).

@@ -49,8 +49,6 @@ struct pdf_handle {
   // tile shapes of the FP32 MFMA kernels (chosen by pdf_autotune; results do not depend on them)
   int tune_ct = 2;           // column tiles per wave of the G_S^H GEMM: 1, 2 or 4
   int tune_pb = 4;           // load batch of the pixel reduction: 4 or 8
-  int tune_fpp = 1;          // forward convolution rows: 1 between the tile's halves, 0 in place
-  int tune_app = 0;          // adjoint convolution rows: likewise
   bool tuned = false;
   // optional per-kernel event timing
   bool timing = false;
