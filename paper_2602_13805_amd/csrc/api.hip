@@ -123,10 +123,10 @@ static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
 template <typename T, int M>
 static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
-  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+  if constexpr (C::ADJ_LDS_BYTES <= 160 * 1024) {
     auto k = k_adj_conv<T, M>;
-    set_lds(k, C::LDS_BYTES);
-    hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::LDS_BYTES, h->stream, a);
+    set_lds(k, C::ADJ_LDS_BYTES);
+    hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::ADJ_LDS_BYTES, h->stream, a);
     return check_launch(h, "k_adj_conv");
   } else {
     return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident convolution");
@@ -219,6 +219,10 @@ static RegArgs<T> reg_args(pdf_handle* h, double* loss, int* tstep, const int* f
   a.loss = loss;
   a.tstep = tstep;
   a.frozen = frozen;
+  a.adam_c = h->adam_c;
+  a.lr = h->prm.lr;
+  a.b1 = h->prm.adam_b1;
+  a.b2 = h->prm.adam_b2;
   a.M = h->M;
   a.Ni = h->Ni;
   a.Ns = h->Ns;
@@ -315,8 +319,7 @@ static FwdArgs<T> fwd_args(pdf_handle* h, const void* alpha) {
 }
 
 template <typename T>
-static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, void* v, int* tstep,
-                           const int* frozen) {
+static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, void* v, const int* frozen) {
   AdjArgs<T> a;
   a.J = (const cx<T>*)h->J;
   a.E = (const cx<T>*)h->E;
@@ -334,9 +337,8 @@ static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, 
   a.alpha = (cx<T>*)alpha_upd;
   a.m = (T*)m;
   a.v = (T*)v;
-  a.tstep = tstep;
   a.frozen = frozen;
-  a.lr = h->prm.lr;
+  a.adam_c = h->adam_c;
   a.b1 = h->prm.adam_b1;
   a.b2 = h->prm.adam_b2;
   a.eps = h->prm.adam_eps;
@@ -361,7 +363,7 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   if ((rc = mark(h))) return rc;
   if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
   if ((rc = mark(h))) return rc;
-  if ((rc = launch_adj<T>(h, adj_args<T>(h, grad, alpha_upd, m, v, tstep, frozen)))) return rc;
+  if ((rc = launch_adj<T>(h, adj_args<T>(h, grad, alpha_upd, m, v, frozen)))) return rc;
   return mark(h);
 }
 
@@ -419,7 +421,7 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
     red[i] = reduce_args<float>(h, (const cx<float>*)h->J, (const cx<float>*)h->E, nullptr);
     reg[i] = reg_args<float>(h, h->loss, h->tstep, h->frozen);
     ag[i] = AdjGemmArgs{(const cx<float>*)h->gs, (const cx<float>*)h->dres, (cx<float>*)h->h, h->Ni, h->Ns, h->N};
-    adj[i] = adj_args<float>(h, nullptr, alphas[i], h->m, h->v, h->tstep, h->frozen);
+    adj[i] = adj_args<float>(h, nullptr, alphas[i], h->m, h->v, h->frozen);
     const int cnt[5] = {h->B * h->Ni, h->ntiles * h->B, h->B, g->nbx * h->B, h->B * h->Ni};
     for (int k = 0; k < 5; ++k) st[k * size_t(n + 1) + i + 1] = st[k * size_t(n + 1) + i] + cnt[k];
   }
@@ -458,8 +460,8 @@ static void group_conv_m(const Group* g, hipStream_t st, bool adjoint) {
       hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::LDS_BYTES, st, g->fwd, g->st[0], g->n);
     } else {
       auto k = k_adj_conv_group<float, M>;
-      set_lds(k, C::LDS_BYTES);
-      hipLaunchKernelGGL(k, dim3(g->tot[4]), dim3(C::NT), C::LDS_BYTES, st, g->adj, g->st[4], g->n);
+      set_lds(k, C::ADJ_LDS_BYTES);
+      hipLaunchKernelGGL(k, dim3(g->tot[4]), dim3(C::NT), C::ADJ_LDS_BYTES, st, g->adj, g->st[4], g->n);
     }
   }
 }
@@ -723,6 +725,7 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   HIP_TRY(hipMalloc(&h->err, sizeof(double) * B));
   HIP_TRY(hipMalloc(&h->frozen, sizeof(int) * B));
   HIP_TRY(hipMalloc(&h->tstep, sizeof(int) * B));
+  HIP_TRY(hipMalloc(&h->adam_c, 2 * sizeof(double) * B));
   HIP_TRY(hipMalloc(&h->m, 2 * sizeof(T) * B * Ni * KK));
   HIP_TRY(hipMalloc(&h->v, 2 * sizeof(T) * B * Ni * KK));
   HIP_TRY(hipMalloc(&h->loss, sizeof(double) * 8 * B));
@@ -800,7 +803,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   void* ptrs[] = {h->gsT, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
-                  h->v,    h->loss, h->loss_w};
+                  h->v,    h->loss, h->loss_w, h->adam_c};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;

@@ -32,6 +32,12 @@ struct ConvCfg {
   // waves per SIMD the register allocation must allow: two 512-thread FP32
   // workgroups per CU at M = 64 (67 KB of LDS each) need four
   static constexpr int WPE = sizeof(T) == 4 ? 4 : 2;
+  // the adjoint keeps g_J (PPT values per thread) through the convolution; at
+  // M = 64 in FP32 the first GJ_LDS of them wait in LDS after the twiddles
+  // (12 KB, still two workgroups per CU), which keeps the kernel within its
+  // 128 registers
+  static constexpr int GJ_LDS = (M == 64 && sizeof(T) == 4) ? 3 : 0;
+  static constexpr size_t ADJ_LDS_BYTES = LDS_BYTES + sizeof(cx<T>) * size_t(GJ_LDS) * NT;
   using Rows = Vecs<P, M, true>;                 // the M stored rows, elements along a row
   using Cols = Vecs<P, P, false, false, true>;   // all P columns (their M stored entries), wave-local
   using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
@@ -279,9 +285,9 @@ struct AdjArgs {
   cx<T>* alpha;        // Adam: parameters updated in place (null: no update)
   T* m;
   T* v;
-  const int* tstep;    // [B] steps taken including this one
   const int* frozen;   // [B] nonzero: skip the update, or null
-  double lr, b1, b2, eps;
+  const double* adam_c;  // [B][2] lr / (1 - b1^t), 1 / (1 - b2^t) of this step (with alpha)
+  double b1, b2, eps;
   int Ni, K;
   T beta;
 };
@@ -303,56 +309,66 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   const size_t off = size_t(bp) * C::N;
   const size_t eoff = size_t(a.e_shared ? p : bp) * C::N;
   const size_t boff = size_t(b) * C::N;
-  const T ws = T(2.0 / a.Ss[0]);
-  const T wd = T(a.hsign * 2.0 / a.Sd[b]);
+  const T ws = T(2) / T(a.Ss[0]);
+  const T wd = T(2 * a.hsign) / T(a.Sd[b]);
   const T beta = a.beta;
-  // all loads of the prologue are issued before their use (the workgroup
-  // fills its CU, so nothing else hides their latency); optional inputs are
-  // uniform branches around whole groups of loads
-  cx<T> Jv[C::PPT], Ev[C::PPT], Rv[C::PPT], Hv[C::PPT], Gv[C::PPT];
-  T Dv[C::PPT];
-#pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int n = tid + q * C::NT;
-    Ev[q] = a.E[eoff + n];
-    Rv[q] = a.R[boff + n];
-    Hv[q] = a.h[off + n];
-  }
-  if (a.J) {
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) Jv[q] = a.J[off + tid + q * C::NT];
-  } else {
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) Jv[q] = cx<T>{T(0), T(0)};
-  }
-  const bool has_gr = a.gR != nullptr;
-  if (has_gr) {
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) {
-      Gv[q] = a.gR[boff + tid + q * C::NT];
-      Dv[q] = a.den[boff + tid + q * C::NT];
-    }
-  }
+  // the prologue's loads are issued in batches of QB pixels per thread, all
+  // loads of a batch before their use; optional inputs are uniform branches
+  // around whole groups of loads.  Batches bound the registers live next to
+  // g_J, which stays in registers through the convolution.
+  constexpr int QB = C::PPT <= 4 ? C::PPT : (C::PPT % 4 == 0 ? 4 : (C::PPT % 3 == 0 ? 3 : (C::PPT % 2 == 0 ? 2 : 1)));
+  static_assert(C::PPT % QB == 0, "whole batches");
+  const bool has_j = a.J != nullptr, has_gr = a.gR != nullptr;
   for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
   cx<T> gj[C::PPT];
+  cx<T>* gjs = tw + C::P;  // [GJ_LDS][NT], each thread's own entries
 #pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int n = tid + q * C::NT;
-    const cx<T> J = Jv[q], E = Ev[q], R = Rv[q];
-    const cx<T> s = R * E - beta * J;
-    const cx<T> gs = ws * s;
-    cx<T> gE = cmul_conj_a(R, gs);
-    cx<T> gJ = (-beta) * gs + wd * Hv[q];
-    if (has_gr) {
-      const cx<T> g = Gv[q];
-      const T inv = T(1) / Dv[q];
-      const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
-      gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
-      gJ = gJ + (beta * inv) * (g * E);
+  for (int q0 = 0; q0 < C::PPT; q0 += QB) {
+    cx<T> Jv[QB], Ev[QB], Rv[QB], Hv[QB], Gv[QB];
+    T Dv[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int n = tid + (q0 + q) * C::NT;
+      Ev[q] = a.E[eoff + n];
+      Rv[q] = a.R[boff + n];
+      Hv[q] = a.h[off + n];
     }
-    gJ = gJ + beta * gE;
-    buf[C::TileL::at(n / M, n % M)] = gE;
-    gj[q] = gJ;
+    if (has_j) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) Jv[q] = a.J[off + tid + (q0 + q) * C::NT];
+    } else {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) Jv[q] = cx<T>{T(0), T(0)};
+    }
+    if (has_gr) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        Gv[q] = a.gR[boff + tid + (q0 + q) * C::NT];
+        Dv[q] = a.den[boff + tid + (q0 + q) * C::NT];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int n = tid + (q0 + q) * C::NT;
+      const cx<T> J = Jv[q], E = Ev[q], R = Rv[q];
+      const cx<T> s = R * E - beta * J;
+      const cx<T> gs = ws * s;
+      cx<T> gE = cmul_conj_a(R, gs);
+      cx<T> gJ = (-beta) * gs + wd * Hv[q];
+      if (has_gr) {
+        const cx<T> g = Gv[q];
+        const T inv = T(1) / Dv[q];
+        const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
+        gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
+        gJ = gJ + (beta * inv) * (g * E);
+      }
+      gJ = gJ + beta * gE;
+      buf[C::TileL::at(n / M, n % M)] = gE;
+      if (q0 + q < C::GJ_LDS)
+        gjs[(q0 + q) * C::NT + tid] = gJ;
+      else
+        gj[q0 + q] = gJ;
+    }
   }
   __syncthreads();
   conv_core<T, M>(buf, tw, a.ghat, true);
@@ -361,7 +377,7 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
     cx<T>& x = buf[r + C::TileL::at(n / M, n % M)];
-    x = x + gj[q];
+    x = x + (q < C::GJ_LDS ? gjs[q * C::NT + tid] : gj[q]);
   }
   __syncthreads();
   const int K = a.K, kmin = -(K / 2);
@@ -371,11 +387,10 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   mc.kmin = kmin;
   Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(NoLoad(), r);
   const bool upd = a.alpha && !(a.frozen && a.frozen[b]);
-  double bc1 = 1.0, bc2 = 1.0;
+  T lr1 = T(0), ic2 = T(0);
   if (upd) {
-    const int t = a.tstep[b];
-    bc1 = 1.0 - pow(a.b1, double(t));
-    bc2 = 1.0 - pow(a.b2, double(t));
+    lr1 = T(a.adam_c[2 * b]);
+    ic2 = T(a.adam_c[2 * b + 1]);
   }
   for (int e = tid; e < K * K; e += C::NT) {
     const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
@@ -392,7 +407,7 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
       a.m[2 * idx + 1] = m1;
       a.v[2 * idx] = v0;
       a.v[2 * idx + 1] = v1;
-      const T lr1 = T(a.lr / bc1), ic2 = T(1.0 / bc2), eps = T(a.eps);
+      const T eps = T(a.eps);
       cx<T> al = a.alpha[idx];
       al.x -= lr1 * m0 / (sqrt(v0 * ic2) + eps);
       al.y -= lr1 * m1 / (sqrt(v1 * ic2) + eps);

@@ -42,6 +42,7 @@ struct pdf_handle {
   double* err = nullptr;     // [B]
   int* frozen = nullptr;     // [B]
   int* tstep = nullptr;      // [B]
+  double* adam_c = nullptr;  // [B][2] Adam bias corrections of the current step
   void* m = nullptr;         // [B][Ni][K][K][2] real
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]

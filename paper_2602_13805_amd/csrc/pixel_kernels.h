@@ -329,6 +329,8 @@ struct RegArgs {
   double* loss;         // [B][8] out, or null
   int* tstep;           // [B] incremented when non-null
   const int* frozen;    // [B] or null
+  double* adam_c;       // [B][2] out with tstep: lr / (1 - b1^t), 1 / (1 - b2^t) at the new step t
+  double lr, b1, b2;
   int M, Ni, Ns, ntiles;
   double beta, lam_bound, lam_tv, lam_bridge, tau_b, eps_tv, eps_abs;
   int r_stopgrad;
@@ -390,7 +392,14 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
   cx<T>* c = reinterpret_cast<cx<T>*>(smem_raw);   // chi [M][M]
   double* red = reinterpret_cast<double*>(c + N);
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) a.tstep[b] += 1;
+  if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) {
+    // the step is counted here, so the adjoint's Adam epilogue reads its bias
+    // corrections instead of evaluating them in every thread
+    const int t = a.tstep[b] + 1;
+    a.tstep[b] = t;
+    a.adam_c[2 * b] = a.lr / (1.0 - pow(a.b1, double(t)));
+    a.adam_c[2 * b + 1] = 1.0 / (1.0 - pow(a.b2, double(t)));
+  }
   double dsum = 0.0;
   const int NO = a.Ni * a.Ns;
   for (int o = tid; o < NO; o += nt) {
