@@ -42,11 +42,11 @@ def log(*a):
 
 # kernel names in the library's timing order, and how they appear in profiler output
 KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant)
-    "fwd_conv": "k_fwd_conv<float, 64, true>",
+    "fwd_conv": "k_fwd_conv<float, 64, true,",
     "pixel_reduce": "k_pixel_reduce_mfma<",
     "image_reg": "k_image_reg<float>",
     "adj_gemm": "k_adj_gemm_mfma<",
-    "adj_conv": "k_adj_conv<float, 64>",
+    "adj_conv": "k_adj_conv<float, 64,",
 }
 
 
@@ -57,14 +57,15 @@ def kernel_variant(name):
 
 
 def tuned_variants(wl, tuned):
-    """Template instance of each step kernel that the tile choice `tuned` launches."""
-    ct, pb = tuned
+    """Template instance of each step kernel that the tile / plan choice `tuned` launches."""
+    ct, pb, fpp, app = tuned
+    tf = lambda b: "true" if b else "false"
     nrt, nct, nrta = -(-wl.n_rx // 16), -(-wl.n_tx // 32), -(-wl.n_tx // 16)
-    return {"fwd_conv": f"k_fwd_conv<float,{wl.M},true>",
+    return {"fwd_conv": f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
             "pixel_reduce": f"k_pixel_reduce_mfma<{nrt},{nct},{pb}>",
             "image_reg": "k_image_reg<float>",
             "adj_gemm": f"k_adj_gemm_mfma<{nrta},{ct}>",
-            "adj_conv": f"k_adj_conv<float,{wl.M}>"}
+            "adj_conv": f"k_adj_conv<float,{wl.M},{tf(app)}>"}
 CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")
 
@@ -280,12 +281,12 @@ def main():
     ap.add_argument("--load-fields", metavar="NPZ",
                     help="take the batch's measured fields from a file written by --save-fields instead of "
                          "synthesising them (profiled runs: only the step's kernels run on the device)")
-    ap.add_argument("--tiles", metavar="CT,PB",
-                    help="use this tile choice instead of autotuning (counter runs: no tuning launches mixed "
-                         "into the step kernels' averages)")
+    ap.add_argument("--tiles", metavar="CT,PB,FPP,APP",
+                    help="use this tile / FFT-plan choice instead of autotuning (counter runs: no tuning "
+                         "launches mixed into the step kernels' averages)")
     ap.add_argument("--all-variants", action="store_true",
-                    help="after the timed steps, run one step under every tile choice (counter runs: every "
-                         "variant of every step kernel measured inside a step)")
+                    help="after the timed steps, run one step under every tile / plan choice (counter runs: "
+                         "every variant of every step kernel measured inside a step)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         print(summarize_rocprof(args.summarize_rocprof, args.summary_kind, args.copy_calibration_mib or 256))
@@ -335,8 +336,8 @@ def main():
         tuned = tuple(int(x) for x in args.tiles.split(","))
         s.set_tiles(*tuned)
     else:
-        tuned, _ = s.autotune(5)   # tile shapes; results do not depend on them
-    log(f"tiles (column tiles, load batch) = {tuned}")
+        tuned, _ = s.autotune(5)   # tile shapes and FFT plans; results do not depend on them
+    log(f"tiles (column tiles, load batch, forward plan, adjoint plan) = {tuned}")
     m, v, t = s.new_state()
     loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
@@ -358,8 +359,9 @@ def main():
     if args.all_variants:
         for ct in (1, 2, 4):
             for pb in (4, 8):
-                s.set_tiles(ct, pb)
-                s.step(alpha, m, v, t, loss)
+                for plan in range(4):
+                    s.set_tiles(ct, pb, plan >> 1, plan & 1)
+                    s.step(alpha, m, v, t, loss)
         s.set_tiles(*tuned)
         torch.cuda.synchronize()
 
@@ -433,8 +435,8 @@ def main():
                    "batch": B, "M": wl.M, "K": wl.K, "n_tx": wl.n_tx, "n_rx": wl.n_rx,
                    "freq_hz": wl.freq_hz, "parallelism": "none (one GPU, independent instances)"},
         "roofline": roof, "kernels": per_kernel, "timed_kernel_steps": nrec, "synthesis_seconds": None if args.load_fields else synth_s,
-        "tiles": dict(gemm_column_tiles=tuned[0], reduce_load_batch=tuned[1],
-                      source="given" if args.tiles else "autotuned"),
+        "tiles": dict(gemm_column_tiles=tuned[0], reduce_load_batch=tuned[1], fwd_plan=tuned[2],
+                      adj_plan=tuned[3], source="given" if args.tiles else "autotuned"),
         "paper_context": {"seconds_per_reconstruction": 0.88, "hardware": "1x RTX 4090",
                           "note": "Table 1; 64x64, 36/36 antennas at 20 wavelengths, iteration count not stated"},
     }

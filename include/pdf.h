@@ -172,19 +172,27 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
                     int32_t* reached_iter_dev, double* best_err_dev, int32_t* best_iter_dev,
                     void* chi_cco_dev, pdf_report* rep);
 
-/* Tile shapes of this handle's FP32 MFMA kernels, chosen by timing `reps`
- * launches of each candidate on the handle's own buffers: the G_S^H GEMM's
- * column tiles per wavefront (1, 2 or 4 tiles of 32 pixels) and the pixel
- * reduction's load batch (4 incidences at four wavefronts per SIMD, or 8 at
- * two).  Every candidate computes each result in the same order, so the
- * choice changes timing only, never a value.  choice: host int32 [2] out
- * (column tiles, load batch), may be NULL; ms: host double [5] out (three
- * GEMM and two reduction timings), may be NULL.  FP64 handles and grids with
- * M*M not a multiple of 32 keep the defaults (2, 4).  Synchronous;
- * overwrites the handle's scratch arrays, not alpha or the data. */
+/* Tile shapes and FFT plans of this handle's FP32 kernels, chosen by timing
+ * `reps` launches of each candidate on the handle's own buffers: the G_S^H
+ * GEMM's column tiles per wavefront (1, 2 or 4 tiles of 32 pixels), the
+ * pixel reduction's load batch (4 incidences at four wavefronts per SIMD, or
+ * 8 at two), and for each convolution kernel its plan: 0 keeps only the M
+ * stored rows of the padded tile in LDS with in-place row passes (two
+ * barriers each; at M = 64 two workgroups per CU), 1 keeps all 2M rows and
+ * alternates the row passes between the halves (one barrier each, twice the
+ * LDS).  The plans are timed as pairs inside whole loss-gradient passes.
+ * Every candidate computes each result in the same order, so the choice
+ * changes timing only, never a value.  choice: host int32 [4] out (column
+ * tiles, load batch, forward plan, adjoint plan), may be NULL; ms: host
+ * double [9] out (three GEMM and two reduction timings, then the
+ * loss-gradient pass with plans (0,0), (0,1), (1,0), (1,1)), may be NULL.
+ * FP64 handles and grids with M*M not a multiple of 32 keep the defaults
+ * (2, 4, 0, 0).  Synchronous; overwrites the handle's scratch arrays and its
+ * internal Adam moments (every pdf_reconstruct re-initialises them), not
+ * alpha or the data. */
 int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms);
-/* Sets the choices directly (ct in {1, 2, 4}, pb in {4, 8}). */
-int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb);
+/* Sets the choices directly (ct in {1, 2, 4}, pb in {4, 8}, plans 0 or 1). */
+int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_pp, int32_t adj_pp);
 
 /* Uneven batching: the reconstructions of n handles (different grids, antenna
  * counts, truncations, batch sizes and precisions) advanced together.  Every

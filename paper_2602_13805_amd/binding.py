@@ -78,7 +78,7 @@ SIGNATURES = {
     "pdf_warm_start": (c_i32, [c_vp, c_vp, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp]),
     "pdf_analyze": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "pdf_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
-    "pdf_set_tiles": (c_i32, [c_vp, c_i32, c_i32]),
+    "pdf_set_tiles": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32]),
     "pdf_reconstruct_multi": (c_i32, [c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                       c_vp]),
     "pdf_timing": (c_i32, [c_vp, c_i32, c_i32]),
@@ -341,15 +341,15 @@ class Solver:
                     iters_run=rep.iters_run, n_reached=rep.n_reached, seconds=rep.seconds)
 
     def autotune(self, reps: int = 5):
-        """Times the tile candidates on this handle and keeps the fastest.
-        Returns ((column tiles, load batch), the five timings in ms)."""
-        choice = (c_i32 * 2)()
-        ms = np.zeros(5, np.float64)
+        """Times the tile and FFT-plan candidates on this handle and keeps the fastest.
+        Returns ((column tiles, load batch, forward plan, adjoint plan), the nine timings in ms)."""
+        choice = (c_i32 * 4)()
+        ms = np.zeros(9, np.float64)
         self._call(load().pdf_autotune, reps, ctypes.cast(choice, c_vp), ms.ctypes.data)
         return tuple(choice), ms
 
-    def set_tiles(self, ct: int, pb: int):
-        _check(load().pdf_set_tiles(self.h, ct, pb), self.h)
+    def set_tiles(self, ct: int, pb: int, fwd_pp: int = 0, adj_pp: int = 0):
+        _check(load().pdf_set_tiles(self.h, ct, pb, fwd_pp, adj_pp), self.h)
 
     def timing(self, enable: bool, max_steps: int = 1000):
         """Start (or stop) recording per-kernel HIP events on the library stream."""

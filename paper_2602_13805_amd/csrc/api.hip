@@ -85,22 +85,33 @@ static void set_lds(K kernel, size_t bytes) {
                               int(bytes));
 }
 
-template <typename T, int M, bool FA>
+template <typename T, int M, bool FA, bool PP>
 static void launch_fwd_t(pdf_handle* h, const FwdArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
-  auto k = k_fwd_conv<T, M, FA>;
-  set_lds(k, C::LDS_BYTES);
-  hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::LDS_BYTES, h->stream, a);
+  auto k = k_fwd_conv<T, M, FA, PP>;
+  set_lds(k, C::lds(PP));
+  hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::lds(PP), h->stream, a);
 }
 
 template <typename T, int M>
 static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int nblk) {
   using C = ConvCfg<T, M>;
-  if constexpr (C::LDS_BYTES <= 160 * 1024) {
+  if constexpr (C::lds(false) <= 160 * 1024) {
+    // FP64 handles keep the default plan (no tuning there)
+    const bool pp = sizeof(T) == 4 && h->tune_fpp != 0;
+    if constexpr (sizeof(T) == 4 && C::lds(true) <= 160 * 1024) {
+      if (pp) {
+        if (from_alpha)
+          launch_fwd_t<T, M, true, true>(h, a, nblk);
+        else
+          launch_fwd_t<T, M, false, true>(h, a, nblk);
+        return check_launch(h, "k_fwd_conv");
+      }
+    }
     if (from_alpha)
-      launch_fwd_t<T, M, true>(h, a, nblk);
+      launch_fwd_t<T, M, true, false>(h, a, nblk);
     else
-      launch_fwd_t<T, M, false>(h, a, nblk);
+      launch_fwd_t<T, M, false, false>(h, a, nblk);
     return check_launch(h, "k_fwd_conv");
   } else {
     return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident convolution");
@@ -120,13 +131,25 @@ static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
 }
 
+template <typename T, int M, bool PP>
+static void launch_adj_t(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
+  using C = ConvCfg<T, M>;
+  auto k = k_adj_conv<T, M, PP>;
+  set_lds(k, C::adj_lds(PP));
+  hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::adj_lds(PP), h->stream, a);
+}
+
 template <typename T, int M>
 static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
-  if constexpr (C::ADJ_LDS_BYTES <= 160 * 1024) {
-    auto k = k_adj_conv<T, M>;
-    set_lds(k, C::ADJ_LDS_BYTES);
-    hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::ADJ_LDS_BYTES, h->stream, a);
+  if constexpr (C::adj_lds(false) <= 160 * 1024) {
+    if constexpr (sizeof(T) == 4 && C::adj_lds(true) <= 160 * 1024) {
+      if (h->tune_app != 0) {
+        launch_adj_t<T, M, true>(h, a, nblk);
+        return check_launch(h, "k_adj_conv");
+      }
+    }
+    launch_adj_t<T, M, false>(h, a, nblk);
     return check_launch(h, "k_adj_conv");
   } else {
     return fail(h, PDF_EUNSUPPORTED, "grid too large for the LDS-resident convolution");
@@ -384,7 +407,7 @@ struct Group {
   const AdjArgs<float>* adj = nullptr;
   const int* st[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // [n + 1] workgroup starts per kernel
   int tot[5] = {0, 0, 0, 0, 0};
-  int n = 0, M = 0, ntiles = 0, nbx = 0, nt_reg = 0, nrt = 0, nct = 0, nrta = 0, ct = 2, pb = 4;
+  int n = 0, M = 0, ntiles = 0, nbx = 0, nt_reg = 0, nrt = 0, nct = 0, nrta = 0, ct = 2, pb = 4, fpp = 0, app = 0;
   size_t lds_reg = 0, lds_ag = 0;
   ~Group() {
     if (dmem) (void)hipFree(dmem);
@@ -402,6 +425,8 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
   g->nrta = (h0->Ni + 15) / 16;
   g->ct = h0->tune_ct;
   g->pb = h0->tune_pb;
+  g->fpp = h0->tune_fpp;
+  g->app = h0->tune_app;
   g->nbx = (h0->N + 128 * g->ct - 1) / (128 * g->ct);
   g->nt_reg = h0->N < 1024 ? h0->N : 1024;
   g->lds_reg = sizeof(cx<float>) * size_t(h0->N) + 16 * sizeof(double);
@@ -450,19 +475,31 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
   return PDF_OK;
 }
 
+template <int M, bool PP>
+static void group_conv_t(const Group* g, hipStream_t st, bool adjoint) {
+  using C = ConvCfg<float, M>;
+  if (!adjoint) {
+    auto k = k_fwd_conv_group<float, M, true, PP>;
+    set_lds(k, C::lds(PP));
+    hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::lds(PP), st, g->fwd, g->st[0], g->n);
+  } else {
+    auto k = k_adj_conv_group<float, M, PP>;
+    set_lds(k, C::adj_lds(PP));
+    hipLaunchKernelGGL(k, dim3(g->tot[4]), dim3(C::NT), C::adj_lds(PP), st, g->adj, g->st[4], g->n);
+  }
+}
+
 template <int M>
 static void group_conv_m(const Group* g, hipStream_t st, bool adjoint) {
   using C = ConvCfg<float, M>;
-  if constexpr (C::LDS_BYTES <= 160 * 1024) {
-    if (!adjoint) {
-      auto k = k_fwd_conv_group<float, M, true>;
-      set_lds(k, C::LDS_BYTES);
-      hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::LDS_BYTES, st, g->fwd, g->st[0], g->n);
-    } else {
-      auto k = k_adj_conv_group<float, M>;
-      set_lds(k, C::ADJ_LDS_BYTES);
-      hipLaunchKernelGGL(k, dim3(g->tot[4]), dim3(C::NT), C::ADJ_LDS_BYTES, st, g->adj, g->st[4], g->n);
+  if constexpr (C::adj_lds(false) <= 160 * 1024) {
+    if constexpr (C::adj_lds(true) <= 160 * 1024) {
+      if ((adjoint ? g->app : g->fpp) != 0) {
+        group_conv_t<M, true>(g, st, adjoint);
+        return;
+      }
     }
+    group_conv_t<M, false>(g, st, adjoint);
   }
 }
 
@@ -944,11 +981,11 @@ extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double
   if (!h || reps < 1) return fail(h, PDF_EINVAL, "bad argument");
   if (h->prec != PDF_FP32 || h->N % 32 != 0) {  // only FP32 handles have choices
     h->tuned = true;
-    if (choice) choice[0] = h->tune_ct, choice[1] = h->tune_pb;
+    if (choice) choice[0] = h->tune_ct, choice[1] = h->tune_pb, choice[2] = h->tune_fpp, choice[3] = h->tune_app;
     return PDF_OK;
   }
   int rc;
-  double t[5];
+  double t[9];
   const int cts[3] = {1, 2, 4}, pbs[2] = {4, 8};
   int best_ct = h->tune_ct, best_pb = h->tune_pb;
   for (int i = 0; i < 3; ++i) {
@@ -968,17 +1005,36 @@ extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double
   best_pb = pbs[t[3] <= t[4] ? 0 : 1];
   h->tune_ct = best_ct;
   h->tune_pb = best_pb;
+  // FFT plans of the two convolution kernels, timed inside the whole loss-gradient pass (their
+  // speed depends on the kernels around them); scratch in and out: g0 as coefficients, the Adam
+  // moment m (re-initialised by every reconstruction) as the gradient, loss_w as the loss record
+  int best_plan = 0;
+  for (int i = 0; i < 4; ++i) {
+    h->tune_fpp = i >> 1;
+    h->tune_app = i & 1;
+    if ((rc = time_launches(h, reps, [&]() {
+           return run_iteration<float>(h, h->g0, h->m, h->loss_w, nullptr, nullptr, nullptr, nullptr, nullptr);
+         }, &t[5 + i])))
+      return rc;
+    if (t[5 + i] < t[5 + best_plan]) best_plan = i;
+  }
+  h->tune_fpp = best_plan >> 1;
+  h->tune_app = best_plan & 1;
   h->tuned = true;
-  if (choice) choice[0] = best_ct, choice[1] = best_pb;
+  if (choice) choice[0] = best_ct, choice[1] = best_pb, choice[2] = h->tune_fpp, choice[3] = h->tune_app;
   if (ms)
-    for (int i = 0; i < 5; ++i) ms[i] = t[i];
+    for (int i = 0; i < 9; ++i) ms[i] = t[i];
   return PDF_OK;
 }
 
-extern "C" int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb) {
-  if (!h || (ct != 1 && ct != 2 && ct != 4) || (pb != 4 && pb != 8)) return fail(h, PDF_EINVAL, "bad tile choice");
+extern "C" int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_pp, int32_t adj_pp) {
+  if (!h || (ct != 1 && ct != 2 && ct != 4) || (pb != 4 && pb != 8) || (fwd_pp != 0 && fwd_pp != 1) ||
+      (adj_pp != 0 && adj_pp != 1))
+    return fail(h, PDF_EINVAL, "bad tile choice");
   h->tune_ct = ct;
   h->tune_pb = pb;
+  h->tune_fpp = fwd_pp;
+  h->tune_app = adj_pp;
   h->tuned = true;
   return PDF_OK;
 }
@@ -1324,7 +1380,7 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
     if (!hs[best]->tuned)
       if (int rc = pdf_autotune(hs[best], 5, nullptr, nullptr)) return rc;
     for (int i : idx)
-      pdf_set_tiles(hs[i], hs[best]->tune_ct, hs[best]->tune_pb);
+      pdf_set_tiles(hs[i], hs[best]->tune_ct, hs[best]->tune_pb, hs[best]->tune_fpp, hs[best]->tune_app);
     units.emplace_back(new Unit());
     Unit& u = *units.back();
     for (int i : idx) u.rs.push_back(rs[i]);

@@ -38,6 +38,16 @@ struct ConvCfg {
   // 128 registers
   static constexpr int GJ_LDS = (M == 64 && sizeof(T) == 4) ? 3 : 0;
   static constexpr size_t ADJ_LDS_BYTES = LDS_BYTES + sizeof(cx<T>) * size_t(GJ_LDS) * NT;
+  // The second plan (PP) stores all 2M rows: the row passes then alternate
+  // between rows 0..M-1 and M..2M-1 (BOT), one barrier per pass instead of
+  // two, at twice the LDS (at M = 64 in FP32: one workgroup per CU, so four
+  // waves per SIMD are not needed and the adjoint keeps all of g_J in
+  // registers).  Both plans compute every value in the same order.
+  static constexpr int BOT = M * TileL::LD;
+  static constexpr size_t lds(bool pp) { return pp ? sizeof(cx<T>) * (size_t(2 * M) * TileL::LD + P) : LDS_BYTES; }
+  static constexpr size_t adj_lds(bool pp) { return pp ? lds(true) : ADJ_LDS_BYTES; }
+  static constexpr int wpe(bool pp) { return pp && 2 * lds(true) > 160 * 1024 ? 2 : WPE; }
+  static constexpr int gj_lds(bool pp) { return pp ? 0 : GJ_LDS; }
   using Rows = Vecs<P, M, true>;                 // the M stored rows, elements along a row
   using Cols = Vecs<P, P, false, false, true>;   // all P columns (their M stored entries), wave-local
   using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
@@ -156,18 +166,27 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
   __syncthreads();  // the row pass that follows reads every column
 }
 
-// x -> G_D x (or G_D^H x) for x on the M x M block of the tile; the result
-// replaces it.  The spectrum ghat is pre-scaled by 1/P^2.  Row passes are
-// workgroup-wide and in place; the column phase is wave-local and ends with a
-// workgroup barrier.
-template <typename T, int M>
-__device__ __forceinline__ void conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+// x -> G_D x (or G_D^H x) for x on the M x M block of the region at element
+// offset src of the tile (0, or BOT with PP); returns the offset of the
+// region holding the result.  Row passes are workgroup-wide (in place, or
+// with PP alternating between the two regions); the column phase is
+// wave-local, works in the region the rows end in, and ends with a workgroup
+// barrier.
+template <typename T, int M, bool PP>
+__device__ __forceinline__ int conv_core(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, int src) {
   using C = ConvCfg<T, M>;
-  constexpr int P = C::P;
+  constexpr int P = C::P, BOT = C::BOT;
   const Fft<T, P, C::EPT_R, C::NT, typename C::Rows, 1> rows{buf, tw, typename C::Rows{}};
-  rows.template run<-1, M, P>();   // the right half of each row is zero padding
-  col_conv<T, M>(buf, tw, ghat, adjoint);
-  rows.template run<+1, P, M>();   // only the left half is kept
+  if constexpr (PP) {
+    const int r = rows.template run_pp<-1, M, P>(src, src == 0 ? BOT : 0);  // right halves are zero padding
+    col_conv<T, M>(buf + r, tw, ghat, adjoint);
+    return rows.template run_pp<+1, P, M>(r, r == 0 ? BOT : 0);            // only the left halves are kept
+  } else {
+    rows.template run<-1, M, P>(NoLoad(), src);
+    col_conv<T, M>(buf + src, tw, ghat, adjoint);
+    rows.template run<+1, P, M>(NoLoad(), src);
+    return src;
+  }
 }
 
 __device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
@@ -186,15 +205,18 @@ struct FwdArgs {
 
 // alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
 // E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
-template <typename T, int M, bool FROM_ALPHA>
+// PP: the plan of the row passes (see ConvCfg), a tuning choice with
+// identical results.
+template <typename T, int M, bool FROM_ALPHA, bool PP>
 __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::M * C::TileL::LD;
+  cx<T>* tw = buf + (PP ? 2 : 1) * C::M * C::TileL::LD;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
   cx<T> jr[C::PPT];
+  int src = 0;  // region holding J
   if constexpr (FROM_ALPHA) {
     // the coefficients (K^2 <= N) are loaded with the twiddles in one round trip
     const int K = a.K, KK = K * K, kmin = -(K / 2);
@@ -203,8 +225,12 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) av[q] = al[min(tid + q * C::NT, KK - 1)];
     for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
-    // the M x M block starts at zero: the mode passes transform only the K kept rows
-    for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+    // the M x M block (both regions with PP) starts at zero: the mode passes
+    // transform only the K kept rows
+    for (int e = tid; e < C::N; e += C::NT) {
+      buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+      if constexpr (PP) buf[C::BOT + C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
@@ -215,12 +241,18 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     typename C::ModeRows mr;
     mr.nv = K;
     mr.kmin = kmin;
-    Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
-    Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
+    if constexpr (PP) {
+      const int r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run_pp<+1>(0, C::BOT);
+      src = Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run_pp<+1>(
+          r, r == 0 ? C::BOT : 0);
+    } else {
+      Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
+      Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
+    }
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = buf[C::TileL::at(n / M, n % M)];
+      jr[q] = buf[src + C::TileL::at(n / M, n % M)];
       if (a.J) a.J[off + n] = jr[q];
     }
   } else {
@@ -234,7 +266,7 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     }
     __syncthreads();
   }
-  conv_core<T, M>(buf, tw, a.ghat, false);
+  const int res = conv_core<T, M, PP>(buf, tw, a.ghat, false, src);
   // all loads of the epilogue are issued before their use (the workgroup
   // fills its CU, so nothing else hides their latency)
   cx<T> ei[C::PPT];
@@ -248,23 +280,23 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
-    a.E[off + n] = buf[C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
+    a.E[off + n] = buf[res + C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
   }
 }
 
-template <typename T, int M, bool FROM_ALPHA>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_fwd_conv(FwdArgs<T> a) {
+template <typename T, int M, bool FROM_ALPHA, bool PP>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::wpe(PP))) void k_fwd_conv(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fwd_conv_body<T, M, FROM_ALPHA>(a, blockIdx.x, smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA, PP>(a, blockIdx.x, smem_raw);
 }
 
 // One launch over several argument sets (handles of one shape class).
-template <typename T, int M, bool FROM_ALPHA>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
+template <typename T, int M, bool FROM_ALPHA, bool PP>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::wpe(PP))) void k_fwd_conv_group(const FwdArgs<T>* __restrict__ a,
                                                                          const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = group_of(start, n, blockIdx.x);
-  fwd_conv_body<T, M, FROM_ALPHA>(a[g], blockIdx.x - start[g], smem_raw);
+  fwd_conv_body<T, M, FROM_ALPHA, PP>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 template <typename T>
@@ -299,11 +331,12 @@ struct AdjArgs {
 //   g_alpha = B^H g_J  (unnormalised forward DFT on the kept modes)
 // The state loss's own derivative in R vanishes because R is its per-pixel
 // least-squares minimiser, so only the regulariser part g_R reaches R.
-template <typename T, int M>
+template <typename T, int M, bool PP>
 __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
+  constexpr int GJL = C::gj_lds(PP);
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + C::M * C::TileL::LD;
+  cx<T>* tw = buf + (PP ? 2 : 1) * C::M * C::TileL::LD;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
@@ -364,20 +397,19 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
       }
       gJ = gJ + beta * gE;
       buf[C::TileL::at(n / M, n % M)] = gE;
-      if (q0 + q < C::GJ_LDS)
+      if (q0 + q < GJL)
         gjs[(q0 + q) * C::NT + tid] = gJ;
       else
         gj[q0 + q] = gJ;
     }
   }
   __syncthreads();
-  conv_core<T, M>(buf, tw, a.ghat, true);
-  constexpr int r = 0;  // offset of the result in the tile
+  const int r = conv_core<T, M, PP>(buf, tw, a.ghat, true, 0);  // offset of the result in the tile
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int n = tid + q * C::NT;
     cx<T>& x = buf[r + C::TileL::at(n / M, n % M)];
-    x = x + (q < C::GJ_LDS ? gjs[q * C::NT + tid] : gj[q]);
+    x = x + (q < GJL ? gjs[q * C::NT + tid] : gj[q]);
   }
   __syncthreads();
   const int K = a.K, kmin = -(K / 2);
@@ -416,20 +448,20 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   }
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_adj_conv(AdjArgs<T> a) {
+template <typename T, int M, bool PP>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::wpe(PP))) void k_adj_conv(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the N_i workgroups of an instance read its per-pixel R, den and g_R: one XCD serves them
-  adj_conv_body<T, M>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
+  adj_conv_body<T, M, PP>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::WPE)) void k_adj_conv_group(const AdjArgs<T>* __restrict__ a,
-                                                                        const int* __restrict__ start, int n) {
+template <typename T, int M, bool PP>
+__global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::wpe(PP))) void k_adj_conv_group(
+    const AdjArgs<T>* __restrict__ a, const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int bx = xcd_remap(blockIdx.x, gridDim.x);
   const int g = group_of(start, n, bx);
-  adj_conv_body<T, M>(a[g], bx - start[g], smem_raw);
+  adj_conv_body<T, M, PP>(a[g], bx - start[g], smem_raw);
 }
 
 // alpha = F_T(J) on the kept modes (Sec. 2.3, Eq. 9): forward DFT of one

@@ -50,6 +50,8 @@ struct pdf_handle {
   // tile shapes of the FP32 MFMA kernels (chosen by pdf_autotune; results do not depend on them)
   int tune_ct = 2;           // column tiles per wave of the G_S^H GEMM: 1, 2 or 4
   int tune_pb = 4;           // load batch of the pixel reduction: 4 or 8
+  int tune_fpp = 0;          // forward convolution: 0 half tile in place, 1 full tile with alternating row passes
+  int tune_app = 0;          // adjoint convolution: likewise
   bool tuned = false;
   // optional per-kernel event timing
   bool timing = false;

@@ -319,14 +319,16 @@ def test_tile_choices_do_not_change_results_and_autotune_picks_one():
         outs = []
         for ct in (1, 2, 4):
             for pb in (4, 8):
-                s.set_tiles(ct, pb)
-                loss, g = s.loss_grad(alpha)
-                outs.append((loss.clone(), g.clone()))
+                for fpp, app in ((0, 0), (1, 1), (0, 1)):
+                    s.set_tiles(ct, pb, fpp, app)
+                    loss, g = s.loss_grad(alpha)
+                    outs.append((loss.clone(), g.clone()))
         for loss, g in outs[1:]:
             assert torch.equal(loss, outs[0][0]) and torch.equal(g, outs[0][1]), (M, Ni, Ns)
-        (ct, pb), ms = s.autotune(3)
-        print(f"autotune M={M} Ni={Ni} Ns={Ns} B={B}: ct={ct} pb={pb} ms={np.round(ms, 4).tolist()}", flush=True)
-        assert ct in (1, 2, 4) and pb in (4, 8) and np.all(ms > 0)
+        (ct, pb, fpp, app), ms = s.autotune(3)
+        print(f"autotune M={M} Ni={Ni} Ns={Ns} B={B}: ct={ct} pb={pb} fwd_plan={fpp} adj_plan={app} "
+              f"ms={np.round(ms, 4).tolist()}", flush=True)
+        assert ct in (1, 2, 4) and pb in (4, 8) and fpp in (0, 1) and app in (0, 1) and np.all(ms > 0)
         loss, g = s.loss_grad(alpha)
         assert torch.equal(loss, outs[0][0]) and torch.equal(g, outs[0][1])
         with pytest.raises(pdf.PdfError):
