@@ -564,7 +564,7 @@ def uneven_leg(pdf, si, wl, n_inst, iters, dev):
         s.close()
     work = n_inst * iters
     return dict(instances=n_inst, handles=len(sols), iterations=iters,
-                shapes="M from {32, 48, 64}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), cfg2 profiles",
+                shapes="M from {32, 48, 64, 96}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), cfg2 profiles",
                 instance_iters_per_s=work / multi_s, seconds=multi_s,
                 sequential_instance_iters_per_s=work / seq_s, sequential_seconds=seq_s,
                 speedup_over_sequential=seq_s / multi_s, setup_seconds=setup_s,

@@ -98,7 +98,7 @@ int pdf_default_params(pdf_params* p);
  *   grid, tx, rx, params: host structs (params may be NULL for defaults).
  *   freq_hz: frequency.  K: truncation per axis, 1 <= K <= M.
  *   stream: hipStream_t for every later call (must not be NULL).
- * Supported: M in {8, 16, 32, 48, 64} (FP32 and FP64); Ni, Ns >= 1.
+ * Supported: M in {8, 16, 32, 48, 64} (FP32 and FP64) or 96 (FP32); Ni, Ns >= 1.
  * Errors: PDF_EINVAL (bad sizes / null), PDF_EUNSUPPORTED (other M),
  * PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (||E_inc|| = 0). */
 int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
@@ -180,7 +180,9 @@ int pdf_reconstruct(pdf_handle* h, int32_t n_iter, int32_t n_check, int32_t star
  * stored rows of the padded tile in LDS with in-place row passes (two
  * barriers each; at M = 64 two workgroups per CU), 1 keeps all 2M rows and
  * alternates the row passes between the halves (one barrier each, twice the
- * LDS).  The plans are timed as pairs inside whole loss-gradient passes.
+ * LDS; grids where that exceeds one CU's LDS, M = 96, have plan 0 only and
+ * run it whatever is set).  The plans are timed as pairs inside whole
+ * loss-gradient passes.
  * Every candidate computes each result in the same order, so the choice
  * changes timing only, never a value.  choice: host int32 [4] out (column
  * tiles, load batch, forward plan, adjoint plan), may be NULL; ms: host

@@ -72,7 +72,7 @@ extern "C" int pdf_default_params(pdf_params* p) {
 }
 
 static bool supported_m(int prec, int M) {
-  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 48 || M == 64;
+  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 48 || M == 64 || M == 96;
   return M == 8 || M == 16 || M == 32 || M == 48 || M == 64;
 }
 
@@ -127,6 +127,7 @@ static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
     case 32: return launch_fwd_m<T, 32>(h, a, from_alpha, nblk);
     case 48: return launch_fwd_m<T, 48>(h, a, from_alpha, nblk);
     case 64: return launch_fwd_m<T, 64>(h, a, from_alpha, nblk);
+    case 96: return launch_fwd_m<T, 96>(h, a, from_alpha, nblk);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
 }
@@ -165,6 +166,7 @@ static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
     case 32: return launch_adj_m<T, 32>(h, a, nblk);
     case 48: return launch_adj_m<T, 48>(h, a, nblk);
     case 64: return launch_adj_m<T, 64>(h, a, nblk);
+    case 96: return launch_adj_m<T, 96>(h, a, nblk);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
 }
@@ -510,6 +512,7 @@ static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
     case 32: group_conv_m<32>(g, st, adjoint); break;
     case 48: group_conv_m<48>(g, st, adjoint); break;
     case 64: group_conv_m<64>(g, st, adjoint); break;
+    case 96: group_conv_m<96>(g, st, adjoint); break;
   }
 }
 
@@ -631,7 +634,8 @@ static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_
     c.eta_max = h->prm.cco_eta_max;
     c.delta = h->prm.cco_delta;
     const int nt = h->N < 1024 ? h->N : 1024;
-    const size_t lds = 6 * sizeof(T) * size_t(h->N) + 16 * sizeof(double);
+    if (h->N > kCcoPix * 1024) return fail(h, PDF_EUNSUPPORTED, "grid too large for the CCO kernel");
+    const size_t lds = 4 * sizeof(T) * size_t(h->N) + 16 * sizeof(double);
     set_lds(k_cco<T>, lds);
     hipLaunchKernelGGL(k_cco<T>, dim3(h->B), dim3(nt), lds, h->stream, c);
     if ((rc = check_launch(h, "k_cco"))) return rc;
@@ -864,7 +868,7 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   if (batch < 1) return fail(nullptr, PDF_EINVAL, "batch must be >= 1");
   if (!stream) return fail(nullptr, PDF_EINVAL, "a non-default stream is required");
   if (!supported_m(prm.precision, grid->M))
-    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48 or 64");
+    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48 or 64 (FP32 also 96)");
   if (rx->n > 64) return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 receivers");
   if (!(prm.beta > 0) || prm.gf_radius < 0) return fail(nullptr, PDF_EINVAL, "beta must be > 0");
   pdf_handle* h = new pdf_handle();
@@ -977,6 +981,23 @@ static int time_launches(pdf_handle* h, int reps, F fn, double* ms) {
   return rc;
 }
 
+// Whether an FP32 handle's grid has the second convolution plan (all 2M rows
+// of the padded tile in one CU's LDS).
+template <int M>
+static bool full_tile_fits() {
+  return ConvCfg<float, M>::lds(true) <= 160 * 1024;
+}
+static bool full_tile_fits(int M) {
+  switch (M) {
+    case 8: return full_tile_fits<8>();
+    case 16: return full_tile_fits<16>();
+    case 32: return full_tile_fits<32>();
+    case 48: return full_tile_fits<48>();
+    case 64: return full_tile_fits<64>();
+  }
+  return false;
+}
+
 extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms) {
   if (!h || reps < 1) return fail(h, PDF_EINVAL, "bad argument");
   if (h->prec != PDF_FP32 || h->N % 32 != 0) {  // only FP32 handles have choices
@@ -1008,8 +1029,10 @@ extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double
   // FFT plans of the two convolution kernels, timed inside the whole loss-gradient pass (their
   // speed depends on the kernels around them); scratch in and out: g0 as coefficients, the Adam
   // moment m (re-initialised by every reconstruction) as the gradient, loss_w as the loss record
+  // (where the full tile does not fit, only plan 0 exists: its time stands for all four)
+  const int nplans = full_tile_fits(h->M) ? 4 : 1;
   int best_plan = 0;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < nplans; ++i) {
     h->tune_fpp = i >> 1;
     h->tune_app = i & 1;
     if ((rc = time_launches(h, reps, [&]() {
@@ -1018,6 +1041,7 @@ extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double
       return rc;
     if (t[5 + i] < t[5 + best_plan]) best_plan = i;
   }
+  for (int i = nplans; i < 4; ++i) t[5 + i] = t[5];
   h->tune_fpp = best_plan >> 1;
   h->tune_app = best_plan & 1;
   h->tuned = true;
@@ -1098,6 +1122,7 @@ static int launch_analyze(pdf_handle* h, int n, const void* J, void* alpha) {
     case 32: return launch_analyze_m<T, 32>(h, n, J, alpha);
     case 48: return launch_analyze_m<T, 48>(h, n, J, alpha);
     case 64: return launch_analyze_m<T, 64>(h, n, J, alpha);
+    case 96: return launch_analyze_m<T, 96>(h, n, J, alpha);
   }
   return fail(h, PDF_EUNSUPPORTED, "unsupported M");
 }

@@ -21,17 +21,24 @@ struct ConvCfg {
   // M = 48 (P = 96 = 3 * 32) takes radix-12 / radix-3 passes: every
   // per-thread element count carries the factor 3
   static constexpr bool TRI = M % 3 == 0;
-  static constexpr int NT = M >= 64 ? 512 : (TRI ? 384 : (M >= 32 ? 256 : 64));
-  static constexpr int EPT_M = TRI ? 12 : 8;                 // length-M transforms (basis), workgroup-wide
-  static constexpr int EPT_R = TRI ? 12 : (M >= 64 ? 16 : 8);  // length-P transforms along rows, workgroup-wide
-  static constexpr int EPT_C = TRI ? 12 : (M >= 64 ? 16 : 8);  // length-M column chains, wave-local
+  static constexpr int NT = M >= 96 ? 768 : (M >= 64 ? 512 : (TRI ? 384 : (M >= 32 ? 256 : 64)));
+  static constexpr int EPT_M = TRI ? 12 : 8;                                     // length-M transforms (basis), workgroup-wide
+  static constexpr int EPT_R = M >= 96 ? 24 : (TRI ? 12 : (M >= 64 ? 16 : 8));  // length-P transforms along rows, workgroup-wide
+  static constexpr int EPT_C = M >= 96 ? 24 : (TRI ? 12 : (M >= 64 ? 16 : 8));  // length-M column chains, wave-local
   static constexpr int PPT = N / NT;              // pixels owned per thread
   static_assert(N % NT == 0, "pixel ownership must be exact");
   static_assert(P >= 16, "the column phase needs P >= 16");
   static constexpr size_t LDS_BYTES = sizeof(cx<T>) * (size_t(M) * TileL::LD + P);
-  // waves per SIMD the register allocation must allow: two 512-thread FP32
-  // workgroups per CU at M = 64 (67 KB of LDS each) need four
-  static constexpr int WPE = sizeof(T) == 4 ? 4 : 2;
+  // waves per SIMD the register allocation must allow: as many as the
+  // workgroups that fit one CU's 160 KB of LDS bring (two 512-thread FP32
+  // workgroups at M = 64 need four; one 768-thread workgroup at M = 96,
+  // three), at most four in FP32 and two in FP64
+  static constexpr int lds_waves(size_t bytes) {
+    const int w = int((160 * 1024) / bytes) * (NT / 64) / 4;
+    const int cap = sizeof(T) == 4 ? 4 : 2;
+    return w < 1 ? 1 : (w > cap ? cap : w);
+  }
+  static constexpr int WPE = lds_waves(LDS_BYTES);
   // the adjoint keeps g_J (PPT values per thread) through the convolution; at
   // M = 64 in FP32 the first GJ_LDS of them wait in LDS after the twiddles
   // (12 KB, still two workgroups per CU), which keeps the kernel within its
@@ -46,7 +53,7 @@ struct ConvCfg {
   static constexpr int BOT = M * TileL::LD;
   static constexpr size_t lds(bool pp) { return pp ? sizeof(cx<T>) * (size_t(2 * M) * TileL::LD + P) : LDS_BYTES; }
   static constexpr size_t adj_lds(bool pp) { return pp ? lds(true) : ADJ_LDS_BYTES; }
-  static constexpr int wpe(bool pp) { return pp && 2 * lds(true) > 160 * 1024 ? 2 : WPE; }
+  static constexpr int wpe(bool pp) { return pp ? lds_waves(lds(true)) : WPE; }
   static constexpr int gj_lds(bool pp) { return pp ? 0 : GJ_LDS; }
   using Rows = Vecs<P, M, true>;                 // the M stored rows, elements along a row
   using Cols = Vecs<P, P, false, false, true>;   // all P columns (their M stored entries), wave-local

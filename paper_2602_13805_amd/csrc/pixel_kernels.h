@@ -655,18 +655,48 @@ struct CcoArgs {
 // CCO (Sec. 2.4, Eqs. 10-11): chi_cco = (1 + eta) G(chi|chi) + eta chi with the
 // self-guided filter G on Re and Im separately and
 // eta = eta_max sigmoid((|chi| - tau) / delta); optional relative error of
-// 1 + chi_cco against the true permittivity.  One instance per block.
+// 1 + chi_cco against the true permittivity.  One instance per block of
+// min(N, 1024) threads, each with at most kCcoPix pixels (N <= 9216).  LDS
+// holds Re chi, Im chi and the filter coefficients A, b of one part at a
+// time: the real part is filtered first and kept in registers.
+constexpr int kCcoPix = 9;
+
+template <typename T>
+__device__ __forceinline__ void gf_coeffs(const T* p, T* A, T* bb, int M, int r, T ge, int tid, int nt) {
+  const int N = M * M;
+  for (int n = tid; n < N; n += nt) {
+    const int i = n / M, j = n % M;
+    T s = 0, s2 = 0;
+    int cnt = 0;
+    for (int di = -r; di <= r; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= M) continue;
+      for (int dj = -r; dj <= r; ++dj) {
+        const int jj = j + dj;
+        if (jj < 0 || jj >= M) continue;
+        const T v = p[ii * M + jj];
+        s += v;
+        s2 += v * v;
+        ++cnt;
+      }
+    }
+    const T mu = s / T(cnt);
+    const T var = s2 / T(cnt) - mu * mu;
+    const T a = var / (var + ge);
+    A[n] = a;
+    bb[n] = (T(1) - a) * mu;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_cco(CcoArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int M = a.M, N = M * M;
-  T* pr = reinterpret_cast<T*>(smem_raw);  // Re chi, Im chi, A_re, b_re, A_im, b_im
+  T* pr = reinterpret_cast<T*>(smem_raw);  // Re chi, Im chi, A and b of the part being filtered
   T* pi = pr + N;
-  T* Ar = pi + N;
-  T* br = Ar + N;
-  T* Ai = br + N;
-  T* bi = Ai + N;
-  double* red = reinterpret_cast<double*>(bi + N);
+  T* A = pi + N;
+  T* bb = A + N;
+  double* red = reinterpret_cast<double*>(bb + N);
   const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   for (int n = tid; n < N; n += nt) {
     const cx<T> z = a.chi[size_t(b) * N + n];
@@ -675,40 +705,28 @@ __global__ __launch_bounds__(1024) void k_cco(CcoArgs<T> a) {
   }
   __syncthreads();
   const T ge = T(a.gf_eps);
-  for (int n = tid; n < N; n += nt) {
-    const int i = n / M, j = n % M;
-    for (int part = 0; part < 2; ++part) {
-      const T* p = part ? pi : pr;
-      T s = 0, s2 = 0;
-      int cnt = 0;
-      for (int di = -a.r; di <= a.r; ++di) {
-        const int ii = i + di;
-        if (ii < 0 || ii >= M) continue;
-        for (int dj = -a.r; dj <= a.r; ++dj) {
-          const int jj = j + dj;
-          if (jj < 0 || jj >= M) continue;
-          const T v = p[ii * M + jj];
-          s += v;
-          s2 += v * v;
-          ++cnt;
-        }
-      }
-      const T mu = s / T(cnt);
-      const T var = s2 / T(cnt) - mu * mu;
-      const T A = var / (var + ge);
-      (part ? Ai : Ar)[n] = A;
-      (part ? bi : br)[n] = (T(1) - A) * mu;
-    }
+  gf_coeffs(pr, A, bb, M, a.r, ge, tid, nt);
+  __syncthreads();
+  T gr[kCcoPix];
+#pragma unroll
+  for (int k = 0; k < kCcoPix; ++k) {
+    const int n = tid + k * nt;
+    gr[k] = T(0);
+    if (n < N) gr[k] = box_mean(A, n / M, n % M, M, a.r) * pr[n] + box_mean(bb, n / M, n % M, M, a.r);
   }
+  __syncthreads();  // A and b are rewritten for the imaginary part
+  gf_coeffs(pi, A, bb, M, a.r, ge, tid, nt);
   __syncthreads();
   double enum_ = 0, eden = 0;
-  for (int n = tid; n < N; n += nt) {
+#pragma unroll
+  for (int k = 0; k < kCcoPix; ++k) {
+    const int n = tid + k * nt;
+    if (n >= N) continue;
     const int i = n / M, j = n % M;
-    const T gr = box_mean(Ar, i, j, M, a.r) * pr[n] + box_mean(br, i, j, M, a.r);
-    const T gi = box_mean(Ai, i, j, M, a.r) * pi[n] + box_mean(bi, i, j, M, a.r);
+    const T gi = box_mean(A, i, j, M, a.r) * pi[n] + box_mean(bb, i, j, M, a.r);
     const T mag = sqrt(pr[n] * pr[n] + pi[n] * pi[n]);
     const T eta = T(a.eta_max) / (T(1) + exp(-(mag - T(a.tau)) / T(a.delta)));
-    const cx<T> o{(T(1) + eta) * gr + eta * pr[n], (T(1) + eta) * gi + eta * pi[n]};
+    const cx<T> o{(T(1) + eta) * gr[k] + eta * pr[n], (T(1) + eta) * gi + eta * pi[n]};
     if (a.out) a.out[size_t(b) * N + n] = o;
     if (a.eps_true) {
       const cx<T> e = a.eps_true[size_t(b) * N + n];

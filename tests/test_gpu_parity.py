@@ -77,6 +77,7 @@ CASES = [
     (48, 48, 3, 5, 1, "fp32", 1e-4),    # full basis on the radix-3 grid, even K (mapped wrap past 0)
     (48, 21, 36, 36, 1, "fp32", 1e-4),  # largest truncation of the uneven draws, the paper's antenna count
     (64, 15, 8, 12, 1, "fp64", 1e-9),   # the benchmark grid in FP64
+    (96, 15, 12, 16, 1, "fp32", 1e-4),  # P = 192: 12-, 8- and 2-point row passes, 96-point column chains
 ]
 
 
@@ -141,9 +142,11 @@ def test_init_alpha_parity(prec, tol):
     s.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-10)])
-def test_image_and_cco_parity(prec, tol):
-    case = make_case(32, 9, 8, 12, seeds=(0, 1))
+@pytest.mark.parametrize("M,K,prec,tol", [(32, 9, "fp32", 1e-4), (32, 9, "fp64", 1e-10), (64, 15, "fp64", 1e-10),
+                                           (96, 15, "fp32", 1e-4)])
+def test_image_and_cco_parity(M, K, prec, tol):
+    print(f"image / CCO M={M} K={K} {prec}", flush=True)
+    case = make_case(M, K, 8, 12, seeds=(0, 1))
     s = solver_for(case, prec)
     alpha = np.stack([oinit.alpha0(c["prob"])[0][0] for c in case["cases"]])
     eps = np.stack([c["eps"] for c in case["cases"]])
@@ -312,7 +315,8 @@ def test_synthesize_batch_matches_single_and_oracle_currents():
 
 
 def test_tile_choices_do_not_change_results_and_autotune_picks_one():
-    for (M, K, Ni, Ns, B) in [(32, 9, 16, 32, 3), (8, 5, 33, 17, 2), (64, 15, 32, 32, 1), (48, 13, 24, 24, 2)]:
+    for (M, K, Ni, Ns, B) in [(32, 9, 16, 32, 3), (8, 5, 33, 17, 2), (64, 15, 32, 32, 1), (48, 13, 24, 24, 2),
+                              (96, 11, 8, 12, 1)]:
         case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
         s = solver_for(case, "fp32")
         alpha = torch.tensor(rand_alpha(s.alpha_shape, seed=M), dtype=s.cdtype, device=DEV)
@@ -329,6 +333,8 @@ def test_tile_choices_do_not_change_results_and_autotune_picks_one():
         print(f"autotune M={M} Ni={Ni} Ns={Ns} B={B}: ct={ct} pb={pb} fwd_plan={fpp} adj_plan={app} "
               f"ms={np.round(ms, 4).tolist()}", flush=True)
         assert ct in (1, 2, 4) and pb in (4, 8) and fpp in (0, 1) and app in (0, 1) and np.all(ms > 0)
+        if M == 96:  # the full tile does not fit: plan 0 only
+            assert (fpp, app) == (0, 0) and np.all(ms[5:] == ms[5])
         loss, g = s.loss_grad(alpha)
         assert torch.equal(loss, outs[0][0]) and torch.equal(g, outs[0][1])
         with pytest.raises(pdf.PdfError):
