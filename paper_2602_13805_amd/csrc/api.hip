@@ -190,6 +190,7 @@ static ReduceArgs<T> reduce_args(pdf_handle* h, const cx<T>* J, const cx<T>* E, 
   a.E = E;
   a.gs = (const cx<T>*)h->gs;
   a.gsT = (const cx<T>*)h->gsT;
+  a.gsA = h->gsA;
   a.Rfix = Rfix;
   a.R = (cx<T>*)h->R;
   a.den = (T*)h->den;
@@ -736,6 +737,28 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
       for (int n = 0; n < h->N; ++n) gst[size_t(n) * h->Ns + q] = t.gs[size_t(q) * h->N + n];
     if ((rc = upload<T>(h, &h->gsT, gst, 1.0))) return rc;
   }
+  if (sizeof(T) == 4 && h->N % 32 == 0) {
+    // A operands of the FP32 receiver GEMM (real-expanded 32x32x2 MFMA) in lane
+    // order: for pixel n and row tile r, lane m + 32 cp holds sgn * part of
+    // G_S[q][n], q = 16 r + m / 2, part = (m % 2) ^ cp (0 Re, 1 Im), sgn = -1
+    // for (m % 2, cp) = (0, 1); zero for q >= Ns
+    const int nrt = (h->Ns + 15) / 16;
+    std::vector<float> ga(size_t(h->N) * nrt * 64);
+    for (int n = 0; n < h->N; ++n)
+      for (int r = 0; r < nrt; ++r)
+        for (int l = 0; l < 64; ++l) {
+          const int m = l & 31, cp = l >> 5, c = m & 1, part = c ^ cp, q = 16 * r + (m >> 1);
+          float v = 0.f;
+          if (q < h->Ns) {
+            const std::complex<double>& g = t.gs[size_t(q) * h->N + n];
+            v = float(part ? g.imag() : g.real());
+            if (c == 0 && cp == 1) v = -v;
+          }
+          ga[(size_t(n) * nrt + r) * 64 + l] = v;
+        }
+    HIP_TRY(hipMalloc(&h->gsA, sizeof(float) * ga.size()));
+    HIP_TRY(hipMemcpy(h->gsA, ga.data(), sizeof(float) * ga.size(), hipMemcpyHostToDevice));
+  }
   if ((rc = upload<T>(h, &h->einc, t.einc, 1.0))) return rc;
   // ||E_inc||^2 of the values actually used (after rounding to T)
   double ss = 0.0;
@@ -841,7 +864,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
-  void* ptrs[] = {h->gsT, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
+  void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
                   h->v,    h->loss, h->loss_w, h->adam_c};

@@ -19,6 +19,7 @@ struct pdf_handle {
   void* tw = nullptr;     // [P] exp(-2 pi i k / P)
   void* gs = nullptr;     // [Ns][N]
   void* gsT = nullptr;    // [N][Ns] (transposed copy for the MFMA receiver GEMM)
+  float* gsA = nullptr;   // FP32: [N][ceil(Ns/16)][64] A operands of that GEMM in lane order
   void* einc = nullptr;   // [Ni][N]
   double* Ss = nullptr;   // device scalar ||E_inc||^2
   double* Sd = nullptr;   // device [B] ||E_sca||^2

@@ -44,6 +44,7 @@ struct ReduceArgs {
   const cx<T>* E;       // [B][Ni][N]
   const cx<T>* gs;      // [Ns][N]
   const cx<T>* gsT;     // [N][Ns] (the same operator, receiver-contiguous)
+  const float* gsA;     // FP32 MFMA path: [N][ceil(Ns/16)][64] A operands in lane order (see below)
   const cx<T>* Rfix;    // [B][N] fixed contrast, or null (least squares)
   cx<T>* R;             // [B][N] out (least squares only)
   T* den;               // [B][N] out
@@ -161,9 +162,6 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
   const int px = tid & (SUB - 1), half = tid / SUB;
   const int lane = tid & 63, w = tid >> 6;
   const int m = lane & 31, cp = lane >> 5;    // A row within the tile / k component (0 Re J, 1 Im J)
-  const int c = m & 1, comp = c ^ cp;         // D part (0 Re, 1 Im) / which part of G
-  const float sgn = (c == 0 && cp == 1) ? -1.f : 1.f;
-  const float* G = reinterpret_cast<const float*>(a.gsT);
   const float* Jsrc = cp ? Ji : Jr;
   const double beta = a.beta;
   floatx16 acc[NRT][NCT];
@@ -243,34 +241,50 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
       const double q = beta * (xr * xr + xi * xi);
       a.chi[size_t(b) * N + n] = cx<float>{float((rr * xr + ri * xi) / q), float((ri * xr - rr * xi) / q)};
     }
-    // 2. receiver GEMM over this sub-tile; operands of KC pixels are loaded
-    // before their MFMAs so that the L2 latency of the G_S rows overlaps
+    // 2. receiver GEMM over this sub-tile.  The A operands come precomputed
+    // per (pixel, row tile) in lane order: lane l = m + 32 cp holds
+    // sgn * (Re or Im) G_S[q][n] for q = 16 h + m / 2, or 0 for a padding
+    // receiver, so each is one coalesced load at a constant stride; the next
+    // chunk's loads are issued before this chunk's MFMAs
     const int kmax = min(SUB, N - sub0);
     const int k0 = w * (SUB / 4), k1 = min(k0 + SUB / 4, kmax);
     constexpr int KC = 4;
-    for (int kb = k0; kb < k1; kb += KC) {
-      float av[KC][NRT], bv[KC][NCT];
+    if (k0 < k1) {  // wave-uniform
+      const float* Ab = a.gsA + size_t(sub0) * NRT * 64 + lane;
+      // pixels past the range (clamped loads) are masked by a zero operand
+      auto load_a = [&](float (&av)[KC][NRT], int kb) {
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const int k = kb + kk;
-        const bool in = k < k1;
-        const float* grow = G + size_t(sub0 + (in ? k : k0)) * 2 * Ns;
+        for (int kk = 0; kk < KC; ++kk) {
+          const int k = kb + kk;
+          const float in = k < k1 ? 1.f : 0.f;
+          const int kc = k < k1 ? k : k0;
 #pragma unroll
-        for (int h = 0; h < NRT; ++h) {
-          // a zero A operand masks pixels past the range and padding receivers
-          const int q = 16 * h + (m >> 1);
-          av[kk][h] = ((in && q < Ns) ? sgn : 0.f) * grow[2 * min(q, Ns - 1) + comp];
+          for (int h = 0; h < NRT; ++h) av[kk][h] = in * Ab[(size_t(kc) * NRT + h) * 64];
+        }
+      };
+      float av[KC][NRT];
+      load_a(av, k0);
+      for (int kb = k0; kb < k1; kb += KC) {
+        float an[KC][NRT], bv[KC][NCT];
+        load_a(an, kb + KC);  // past the end: clamped, masked, unused
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+          const int k = kb + kk;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) bv[kk][t] = Jsrc[(k < k1 ? k : k0) * LDJ + 32 * t + m];
         }
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) bv[kk][t] = Jsrc[(in ? k : k0) * LDJ + 32 * t + m];
+        for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+          for (int h = 0; h < NRT; ++h)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+              acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][h], bv[kk][t], acc[h][t], 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+          for (int h = 0; h < NRT; ++h) av[kk][h] = an[kk][h];
       }
-#pragma unroll
-      for (int kk = 0; kk < KC; ++kk)
-#pragma unroll
-        for (int h = 0; h < NRT; ++h)
-#pragma unroll
-          for (int t = 0; t < NCT; ++t)
-            acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][h], bv[kk][t], acc[h][t], 0, 0, 0);
     }
     __syncthreads();  // the staging buffers are rewritten by the next sub-tile
   }
@@ -540,56 +554,51 @@ __device__ __forceinline__ void adj_gemm_mfma_body(const AdjGemmArgs& args, int 
   const int m = lane & 31, cp = lane >> 5;
   const int c = m & 1;
   const int n0 = (bx * 4 + w) * 32 * CT;
-  if (n0 >= N) return;  // wave-uniform; no barrier follows
-  int nct = (N - n0) / 32;
-  nct = nct < CT ? nct : CT;
   const float* Gf = reinterpret_cast<const float*>(gs);
-  floatx16 acc[NRT][CT];
+  // the wave's CT column tiles one after another: a tile's stores drain while
+  // the next tile's loads and MFMAs run, and only one tile's accumulators
+  // are live (each output sums over the receivers in the same order)
+  for (int t = 0; t < CT; ++t) {
+    const int nt0 = n0 + 32 * t;
+    if (nt0 >= N) break;  // wave-uniform; no barrier follows
+    floatx16 acc[NRT];
 #pragma unroll
-  for (int r = 0; r < NRT; ++r)
+    for (int r = 0; r < NRT; ++r)
 #pragma unroll
-    for (int t = 0; t < CT; ++t)
+      for (int e = 0; e < 16; ++e) acc[r][e] = 0.f;
+    for (int qb = 0; qb < Ns; qb += KC) {
+      float av[KC][NRT], bv[KC];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[r][t][e] = 0.f;
-  for (int qb = 0; qb < Ns; qb += KC) {
-    float av[KC][NRT], bv[KC][CT];
+      for (int kk = 0; kk < KC; ++kk) {
+        const int q = qb + kk;
+        const bool in = q < Ns;
+        // unconditional loads from clamped (in-bounds) addresses, then a select
+        // (a zero A operand masks receivers past Ns)
+        const int qc = min(q, Ns - 1);
+        bv[kk] = Gf[(size_t(qc) * N + nt0 + m) * 2 + cp];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int q = qb + kk;
-      const bool in = q < Ns;
-      // unconditional loads from clamped (in-bounds) addresses, then a select
-      // (a zero A operand masks receivers past Ns; tiles past nct are not stored)
-      const int qc = min(q, Ns - 1);
-#pragma unroll
-      for (int t = 0; t < CT; ++t) bv[kk][t] = Gf[(size_t(qc) * N + n0 + 32 * (t < nct ? t : 0) + m) * 2 + cp];
-#pragma unroll
-      for (int r = 0; r < NRT; ++r) {
-        const cx<float> d = xs[qc * LDX + 16 * r + (m >> 1)];
-        av[kk][r] = (in ? 1.f : 0.f) * (c == 0 ? (cp == 0 ? d.x : d.y) : (cp == 0 ? d.y : -d.x));
+        for (int r = 0; r < NRT; ++r) {
+          const cx<float> d = xs[qc * LDX + 16 * r + (m >> 1)];
+          av[kk][r] = (in ? 1.f : 0.f) * (c == 0 ? (cp == 0 ? d.x : d.y) : (cp == 0 ? d.y : -d.x));
+        }
       }
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+          acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][r], bv[kk], acc[r], 0, 0, 0);
     }
+    // lane (l % 32 = pixel, l / 32) holds rows i = (e % 4) + 8 (e / 4) + 4 (l / 32): pairs (e, e + 1)
+    // with e even are (Re, Im) of incidence p = 16 r + i / 2
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk)
-#pragma unroll
-      for (int r = 0; r < NRT; ++r)
-#pragma unroll
-        for (int t = 0; t < CT; ++t)
-          acc[r][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][r], bv[kk][t], acc[r][t], 0, 0, 0);
-  }
-  // lane (l % 32 = pixel, l / 32) holds rows i = (e % 4) + 8 (e / 4) + 4 (l / 32): pairs (e, e + 1)
-  // with e even are (Re, Im) of incidence p = 16 r + i / 2
-#pragma unroll
-  for (int r = 0; r < NRT; ++r)
-#pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      if (t >= nct) continue;
+    for (int r = 0; r < NRT; ++r)
 #pragma unroll
       for (int e = 0; e < 16; e += 2) {
         const int i = (e & 3) + 8 * (e >> 2) + 4 * cp;
         const int p = 16 * r + (i >> 1);
-        if (p < Ni) h[(size_t(b) * Ni + p) * N + n0 + 32 * t + m] = cx<float>{acc[r][t][e], acc[r][t][e + 1]};
+        if (p < Ni) h[(size_t(b) * Ni + p) * N + nt0 + m] = cx<float>{acc[r][e], acc[r][e + 1]};
       }
-    }
+  }
 }
 
 template <int NRT, int CT>
