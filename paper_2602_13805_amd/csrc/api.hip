@@ -89,17 +89,17 @@ template <typename T, int M, bool FA, bool PP>
 static void launch_fwd_t(pdf_handle* h, const FwdArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
   auto k = k_fwd_conv<T, M, FA, PP>;
-  set_lds(k, C::lds(PP));
-  hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::lds(PP), h->stream, a);
+  set_lds(k, C::fwd_lds(PP, FA));
+  hipLaunchKernelGGL(k, dim3(nblk), dim3(C::NT), C::fwd_lds(PP, FA), h->stream, a);
 }
 
 template <typename T, int M>
 static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int nblk) {
   using C = ConvCfg<T, M>;
-  if constexpr (C::lds(false) <= 160 * 1024) {
+  if constexpr (C::fwd_lds(false, true) <= 160 * 1024) {
     // FP64 handles keep the default plan (no tuning there)
     const bool pp = sizeof(T) == 4 && h->tune_fpp != 0;
-    if constexpr (sizeof(T) == 4 && C::lds(true) <= 160 * 1024) {
+    if constexpr (sizeof(T) == 4 && C::fwd_lds(true, true) <= 160 * 1024) {
       if (pp) {
         if (from_alpha)
           launch_fwd_t<T, M, true, true>(h, a, nblk);
@@ -120,6 +120,8 @@ static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int
 
 template <typename T>
 static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
+  if (from_alpha && !a.J)  // the coefficient path keeps J in its output between phases
+    return fail(h, PDF_EINVAL, "internal: coefficient synthesis without a J buffer");
   const int nblk = h->B * h->Ni;
   switch (h->M) {
     case 8: return launch_fwd_m<T, 8>(h, a, from_alpha, nblk);
@@ -483,8 +485,8 @@ static void group_conv_t(const Group* g, hipStream_t st, bool adjoint) {
   using C = ConvCfg<float, M>;
   if (!adjoint) {
     auto k = k_fwd_conv_group<float, M, true, PP>;
-    set_lds(k, C::lds(PP));
-    hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::lds(PP), st, g->fwd, g->st[0], g->n);
+    set_lds(k, C::fwd_lds(PP, true));
+    hipLaunchKernelGGL(k, dim3(g->tot[0]), dim3(C::NT), C::fwd_lds(PP, true), st, g->fwd, g->st[0], g->n);
   } else {
     auto k = k_adj_conv_group<float, M, PP>;
     set_lds(k, C::adj_lds(PP));

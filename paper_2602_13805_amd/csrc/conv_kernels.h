@@ -55,6 +55,7 @@ struct ConvCfg {
   static constexpr size_t adj_lds(bool pp) { return pp ? lds(true) : ADJ_LDS_BYTES; }
   static constexpr int wpe(bool pp) { return pp ? lds_waves(lds(true)) : WPE; }
   static constexpr int gj_lds(bool pp) { return pp ? 0 : GJ_LDS; }
+  static constexpr size_t fwd_lds(bool pp, bool) { return lds(pp); }
   using Rows = Vecs<P, M, true>;                 // the M stored rows, elements along a row
   using Cols = Vecs<P, P, false, false, true>;   // all P columns (their M stored entries), wave-local
   using RowsM = Vecs<P, M, true>;                // length-M rows of the top-left M x M block
@@ -76,14 +77,30 @@ struct ConvCfg {
 // the column's own M entries.  A chain's forward last pass and inverse first
 // pass share their registers, so the spectrum is applied in registers.
 // The adjoint uses conj(ghat).
-template <typename T, int M>
-__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint) {
+// BANDED: the tile's columns hold a permuted spectrum (the band-limited
+// forward path below): column c < M is spectrum column 2c + 1, column M + j
+// (j < ncols - M) is spectrum column 2 wrap(kmin + j); columns from ncols on
+// are skipped.  Otherwise column c is spectrum column c and all P are done.
+template <typename T, int M, bool BANDED = false>
+__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint,
+                                         int ncols = 2 * M, int kmin = 0) {
   using C = ConvCfg<T, M>;
   constexpr int P = C::P, EPT = C::EPT_C;
   using F = Fft<T, M, EPT, C::NT, typename C::Cols, 2>;   // tw[2k] = exp(-2 pi i k / M)
   constexpr int R1 = F::radix(1), R2 = M / R1;            // forward radices R1 then R2, inverse R2 then R1
   static_assert(R2 == 1 || (R2 <= 16 && EPT % R2 == 0), "a chain takes one or two passes");
-  const F f{buf, tw, typename C::Cols{}};
+  typename C::Cols cols;
+  cols.nv = ncols;
+  const F f{buf, tw, cols};
+  auto spec_col = [&](int c) {
+    if constexpr (BANDED) {
+      if (c < M) return 2 * c + 1;
+      const int k = kmin + c - M;  // in (-M, M)
+      return 2 * (k < 0 ? k + M : k);
+    } else {
+      return c;
+    }
+  };
   typename F::Regs x;
   f.assign(x);
   f.template load<R1, 1, -1, R1>(x, NoLoad());  // butterfly j holds elements j + (M / R1) r
@@ -106,7 +123,7 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
         const int j = g.t[q] + u * F::TPV;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          cx<T> w = ghat[(2 * (j + r * NSOUT) + c) * P + g.vec[q]];
+          cx<T> w = ghat[(2 * (j + r * NSOUT) + c) * P + spec_col(g.vec[q])];
           if (adjoint) w.y = -w.y;
           g.v[q][u * R + r] = g.v[q][u * R + r] * w;
         }
@@ -198,6 +215,24 @@ __device__ __forceinline__ int conv_core(cx<T>* buf, const cx<T>* tw, const cx<T
 
 __device__ __forceinline__ int wrap_mode(int k, int M) { return ((k % M) + M) % M; }
 
+// The 2M half-rows of the M x P tile as vectors of length M: vector v is the
+// left (v even) or right (v odd) half of row v / 2.
+template <int P>
+struct HalfRows {
+  static constexpr int NV = P;
+  static constexpr bool WL = false;
+  int nv = P;
+  __device__ __forceinline__ int addr(int v, int k) const { return (v >> 1) * Tile<P>::LD + (v & 1) * (P / 2) + k; }
+};
+
+// First-pass load of x[k] w[k], w[k] = exp(-2 pi i k / P) (tw holds the P-point twiddles).
+template <typename T>
+struct TwistLoad {
+  const cx<T>* tw;
+  template <typename C>
+  __device__ __forceinline__ C operator()(int, int k, C v) const { return v * tw[k]; }
+};
+
 template <typename T>
 struct FwdArgs {
   const cx<T>* in;     // alpha [BP][K][K] (from_alpha) or pixel currents [BP][N]
@@ -212,18 +247,37 @@ struct FwdArgs {
 
 // alpha -> J = F_T^*(alpha) (zero-filled inverse FFT), then
 // E = E_inc + G_D J + beta J (Sec. 2.2, Eq. 6; Sec. 2.3, Eq. 9).
-// PP: the plan of the row passes (see ConvCfg), a tuning choice with
-// identical results.
+//
+// From the coefficients the convolution uses that J is band-limited: with
+// U[y][kx] the inverse column transforms of the K kept mode columns, the even
+// frequencies of each zero-padded row's length-P transform are M U[y][k]
+// (nonzero for the K kept k only) and the odd ones are FFT_M(J[y][.] w),
+// w[x] = exp(-2 pi i x / P).  The tile holds the odd frequencies in columns
+// 0..M-1 and the K even ones in columns M..M+K-1, so the column phase
+// convolves M + K columns instead of 2M; the cropped inverse row transform is
+// then IFFT_M(even) + conj(w) IFFT_M(odd) on the two halves of each row.
+// From given currents (the start value) the general convolution runs.
+// PP: the plan of the row passes of the general convolution (see ConvCfg), a
+// tuning choice with identical results; the band-limited path has one plan.
 template <typename T, int M, bool FROM_ALPHA, bool PP>
 __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
+  constexpr int P = C::P;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + (PP ? 2 : 1) * C::M * C::TileL::LD;
   const int p = bp % a.Ni;
   const int tid = threadIdx.x;
   const size_t off = size_t(bp) * C::N;
-  cx<T> jr[C::PPT];
-  int src = 0;  // region holding J
+  // epilogue loads (issued early: nothing else on the CU hides their latency)
+  auto load_einc = [&](cx<T>(&ei)[C::PPT]) {
+    if (a.einc) {
+#pragma unroll
+      for (int q = 0; q < C::PPT; ++q) ei[q] = a.einc[size_t(p) * C::N + tid + q * C::NT];
+    } else {
+#pragma unroll
+      for (int q = 0; q < C::PPT; ++q) ei[q] = cx<T>{T(0), T(0)};
+    }
+  };
   if constexpr (FROM_ALPHA) {
     // the coefficients (K^2 <= N) are loaded with the twiddles in one round trip
     const int K = a.K, KK = K * K, kmin = -(K / 2);
@@ -231,13 +285,9 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     cx<T> av[C::PPT];
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) av[q] = al[min(tid + q * C::NT, KK - 1)];
-    for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
-    // the M x M block (both regions with PP) starts at zero: the mode passes
-    // transform only the K kept rows
-    for (int e = tid; e < C::N; e += C::NT) {
-      buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
-      if constexpr (PP) buf[C::BOT + C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
-    }
+    for (int k = tid; k < P; k += C::NT) tw[k] = a.tw[k];
+    // the M x M block starts at zero: the mode passes transform only the K kept columns
+    for (int e = tid; e < C::N; e += C::NT) buf[C::TileL::at(e / M, e % M)] = cx<T>{T(0), T(0)};
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
@@ -245,49 +295,78 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
       if (e < KK) buf[C::TileL::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))] = av[q];
     }
     __syncthreads();
-    typename C::ModeRows mr;
-    mr.nv = K;
-    mr.kmin = kmin;
-    if constexpr (PP) {
-      const int r = Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run_pp<+1>(0, C::BOT);
-      src = Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run_pp<+1>(
-          r, r == 0 ? C::BOT : 0);
-    } else {
-      Fft<T, M, C::EPT_M, C::NT, typename C::ModeRows, 2>{buf, tw, mr}.template run<+1>();
-      Fft<T, M, C::EPT_M, C::NT, typename C::ColsM, 2>{buf, tw, typename C::ColsM{}}.template run<+1>();
+    // U: inverse transforms along y of the K kept mode columns
+    typename C::ModeCols mc;
+    mc.nv = K;
+    mc.kmin = kmin;
+    Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<+1>();
+    // even frequencies M U[y][k] of the kept k, compact in columns M..M+K-1
+    for (int e = tid; e < M * K; e += C::NT) {
+      const int y = e / K, j = e % K;
+      buf[C::TileL::at(y, M + j)] = T(M) * buf[C::TileL::at(y, wrap_mode(kmin + j, M))];
     }
+    // (the next pass stores to columns 0..M-1 only after its first barrier)
+    // J: inverse transforms along x of all M rows
+    Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
+    rowsm.template run<+1>();
+    // J goes to its output now and is read back by the same threads in the
+    // epilogue (still in L2), which keeps it out of the registers the column
+    // phase needs; J is required here
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
-      jr[q] = buf[src + C::TileL::at(n / M, n % M)];
-      if (a.J) a.J[off + n] = jr[q];
+      a.J[off + n] = buf[C::TileL::at(n / M, n % M)];
+    }
+    // odd frequencies FFT_M(J w) of each row, in place in columns 0..M-1
+    rowsm.template run<-1>(TwistLoad<T>{tw});
+    col_conv<T, M, true>(buf, tw, a.ghat, false, M + K, kmin);
+    // even part back to natural order (zero where no mode is kept) in columns M..P-1
+    cx<T> ev[C::PPT];
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int e = tid + q * C::NT;
+      const int y = e / M, k = e % M, j = wrap_mode(k - kmin, M);
+      ev[q] = j < K ? buf[C::TileL::at(y, M + j)] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int e = tid + q * C::NT;
+      buf[C::TileL::at(e / M, M + e % M)] = ev[q];
+    }
+    __syncthreads();
+    // inverse transforms of both halves of every row
+    Fft<T, M, C::EPT_M, C::NT, HalfRows<P>, 2>{buf, tw, HalfRows<P>{}}.template run<+1>();
+    cx<T> ei[C::PPT], jr[C::PPT];
+    load_einc(ei);
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) jr[q] = a.J[off + tid + q * C::NT];
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int n = tid + q * C::NT, y = n / M, x = n % M;
+      cx<T> w = tw[x];
+      w.y = -w.y;
+      a.E[off + n] = buf[C::TileL::at(y, M + x)] + buf[C::TileL::at(y, x)] * w + a.beta * jr[q] + ei[q];
     }
   } else {
+    cx<T> jr[C::PPT];
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) jr[q] = a.in[off + tid + q * C::NT];
-    for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
+    for (int k = tid; k < P; k += C::NT) tw[k] = a.tw[k];
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int n = tid + q * C::NT;
       buf[C::TileL::at(n / M, n % M)] = jr[q];
     }
     __syncthreads();
-  }
-  const int res = conv_core<T, M, PP>(buf, tw, a.ghat, false, src);
-  // all loads of the epilogue are issued before their use (the workgroup
-  // fills its CU, so nothing else hides their latency)
-  cx<T> ei[C::PPT];
-  if (a.einc) {
+    const int res = conv_core<T, M, PP>(buf, tw, a.ghat, false, 0);
+    cx<T> ei[C::PPT];
+    load_einc(ei);
 #pragma unroll
-    for (int q = 0; q < C::PPT; ++q) ei[q] = a.einc[size_t(p) * C::N + tid + q * C::NT];
-  } else {
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) ei[q] = cx<T>{T(0), T(0)};
-  }
-#pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int n = tid + q * C::NT;
-    a.E[off + n] = buf[res + C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
+    for (int q = 0; q < C::PPT; ++q) {
+      const int n = tid + q * C::NT;
+      a.E[off + n] = buf[res + C::TileL::at(n / M, n % M)] + a.beta * jr[q] + ei[q];
+    }
   }
 }
 
