@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "PDF loss+grad iters/s and reconstructions/s at 64² to fixed rel. image error"
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12       # flop/s, MI355X FP32 vector (= FP32 matrix)
+CLOCK_HZ = 2.4e9           # MI355X peak engine clock
+N_CU = 256                 # compute units (4 SIMDs each)
 
 
 def log(*a):
@@ -116,6 +118,8 @@ def summarize_rocprof(dirs, kind, copy_mib):
                          f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                          f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
         return "\n".join(lines)
+    if kind == "mfma":
+        return _summarize_mfma(dirs)
     acc = {}
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
@@ -149,6 +153,45 @@ def summarize_rocprof(dirs, kind, copy_mib):
         n = len(acc[k]["FETCH_SIZE"])
         lines.append(f"kernel {k[0]} {k[1]} fetch_kib={avg[k]['FETCH_SIZE']:.1f} "
                      f"write_kib={avg[k]['WRITE_SIZE']:.1f} bytes={fb + wb:.0f} dispatches={n}")
+    return "\n".join(lines)
+
+
+def _summarize_mfma(dirs):
+    """Matrix-core use per step kernel from one counter pass (SQ_INSTS_MFMA, SQ_VALU_MFMA_BUSY_CYCLES)
+    taken together with a kernel trace: busy cycles over the kernel's duration times the clock and the
+    1024 SIMDs of the chip."""
+    import csv
+    import glob
+    cnt, dur = {}, {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    k = _short_kernel(r["Kernel_Name"])
+                    if k is not None and k != "calibration_copy":
+                        key = (k, kernel_variant(r["Kernel_Name"]))
+                        cnt.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    k = _short_kernel(r["Kernel_Name"])
+                    if k is not None and k != "calibration_copy":
+                        key = (k, kernel_variant(r["Kernel_Name"]))
+                        dur.setdefault(key, []).append(
+                            (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    lines = [f"source_sha256: {kernel_source_hash()}",
+             f"clock_hz: {CLOCK_HZ:.3g}", f"simds: {4 * N_CU}"]
+    order = list(KERNEL_SYMBOLS)
+    for key in sorted(cnt, key=lambda k: (order.index(k[0]), k[1])):
+        c = {n: sum(v) / len(v) for n, v in cnt[key].items()}
+        ts = sorted(dur.get(key, []))
+        if not ts or "SQ_VALU_MFMA_BUSY_CYCLES" not in c:
+            continue
+        t = ts[len(ts) // 2]
+        busy = c["SQ_VALU_MFMA_BUSY_CYCLES"]
+        lines.append(f"kernel {key[0]} {key[1]} dispatches={len(ts)} mfma_insts={c.get('SQ_INSTS_MFMA', 0.0):.0f} "
+                     f"mfma_busy_cycles={busy:.0f} median_us={t * 1e6:.1f} "
+                     f"mfma_busy_frac={busy / (t * CLOCK_HZ * 4 * N_CU):.3f}")
     return "\n".join(lines)
 
 
@@ -275,7 +318,7 @@ def main():
                     help="instances of the uneven-shape batch leg (0: skip it)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
-    ap.add_argument("--summary-kind", choices=["stats", "pmc"], default="stats")
+    ap.add_argument("--summary-kind", choices=["stats", "pmc", "mfma"], default="stats")
     ap.add_argument("--save-fields", metavar="NPZ",
                     help="synthesise the batch's measured fields, write them to this file and exit")
     ap.add_argument("--load-fields", metavar="NPZ",
