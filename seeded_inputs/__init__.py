@@ -266,3 +266,21 @@ def add_noise(esca: np.ndarray, nu: float, n1: np.ndarray, n2: np.ndarray) -> np
     An SNR in dB maps to nu = 10^(-SNR/20)."""
     scale = nu * np.linalg.norm(esca) / np.sqrt(esca.size)
     return esca + scale * (n1 + 1j * n2) / np.sqrt(2.0)
+
+
+def fcnn_theta(seed: int, B: int, K: int, H: int, out_scale: float = 0.0) -> np.ndarray:
+    """Start weights of the coefficient network (three dense layers 2K^2 -> H -> H -> 2K^2,
+    each a block of (in + 1) x out numbers, the last row the bias) for B reconstructions:
+    U[-1/sqrt(in), 1/sqrt(in)] for every weight and bias, the output block multiplied by
+    out_scale (0: the network starts at alpha_hat = alpha_0).  [B][n_params] float64."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x4643])))
+    D = 2 * K * K
+    shapes = [(D, H), (H, H), (H, D)]
+    out = np.empty((B, sum((i + 1) * o for i, o in shapes)))
+    for b in range(B):
+        parts = []
+        for li, (i, o) in enumerate(shapes):
+            s = (out_scale if li == 2 else 1.0) / math.sqrt(i)
+            parts.append(rng.uniform(-s, s, size=(i + 1) * o))
+        out[b] = np.concatenate(parts)
+    return out
