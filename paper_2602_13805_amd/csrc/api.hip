@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "conv_kernels.h"
+#include "fcnn_kernels.h"
 #include "handle.h"
 #include "init_kernels.h"
 #include "pixel_kernels.h"
@@ -869,7 +870,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
-                  h->v,    h->loss, h->loss_w, h->adam_c};
+                  h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -1123,6 +1124,227 @@ extern "C" int pdf_warm_start(pdf_handle* h, pdf_mlp* net, float s_in, float s_o
   hipLaunchKernelGGL(k_pick_start<float>, dim3((len + 255) / 256, h->B), dim3(256), 0, h->stream,
                      (cx<float>*)alpha_dev, (const cx<float>*)h->g0, h->loss, h->loss_w, len, chosen_dev, loss_dev);
   return check_launch(h, "k_pick_start");
+}
+
+// ------------------------------------------------------------------ coefficient network
+
+// Sizes of the network of a handle with hidden width H, its workspace
+// (activations A1, A2, pre-activation gradients G1, G2, the gradient g at
+// alpha_hat) and the launches of one forward pass or one step.
+template <typename T>
+struct FcNet {
+  int R = 0, Q = 0, D = 0, H = 0, B = 0;
+  size_t P = 0, off[3] = {0, 0, 0};
+  T *A1 = nullptr, *A2 = nullptr, *G1 = nullptr, *G2 = nullptr;
+  cx<T>* g = nullptr;
+};
+
+static size_t fc_params(int K, int H) {
+  const size_t D = size_t(2) * K * K;
+  return (D + 1) * H + size_t(H + 1) * H + size_t(H + 1) * D;
+}
+
+template <typename T>
+static int fc_prepare(pdf_handle* h, int H, FcNet<T>* n) {
+  if (H < 1 || H > 4096) return fail(h, PDF_EINVAL, "hidden width outside 1..4096");
+  if (h->Ni > kFcMaxRows) return fail(h, PDF_EUNSUPPORTED, "the coefficient network takes at most 64 incidences");
+  n->R = h->Ni;
+  n->Q = h->K * h->K;
+  n->D = 2 * n->Q;
+  n->H = H;
+  n->B = h->B;
+  n->off[0] = 0;
+  n->off[1] = size_t(n->D + 1) * H;
+  n->off[2] = n->off[1] + size_t(H + 1) * H;
+  n->P = fc_params(h->K, H);
+  const size_t rows = size_t(h->B) * n->R;
+  const size_t hid = rows * H * sizeof(T), gb = rows * n->Q * sizeof(cx<T>);
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t need = 4 * al(hid) + al(gb);
+  if (h->fc_bytes < need) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->fc_ws) HIP_TRY(hipFree(h->fc_ws));
+    h->fc_ws = nullptr;
+    h->fc_bytes = 0;
+    HIP_TRY(hipMalloc(&h->fc_ws, need));
+    h->fc_bytes = need;
+  }
+  unsigned char* w = static_cast<unsigned char*>(h->fc_ws);
+  n->A1 = reinterpret_cast<T*>(w);
+  n->A2 = reinterpret_cast<T*>(w + al(hid));
+  n->G1 = reinterpret_cast<T*>(w + 2 * al(hid));
+  n->G2 = reinterpret_cast<T*>(w + 3 * al(hid));
+  n->g = reinterpret_cast<cx<T>*>(w + 4 * al(hid));
+  return PDF_OK;
+}
+
+template <typename T>
+static FcRows<T> fc_real(const T* p, int width) {
+  FcRows<T> r;
+  r.re = p;
+  r.width = width;
+  return r;
+}
+
+template <typename T>
+static FcRows<T> fc_split(const cx<T>* p, int width) {
+  FcRows<T> r;
+  r.cxv = p;
+  r.width = width;
+  return r;
+}
+
+template <typename T, int RPW>
+static void fc_launch(pdf_handle* h, const FcLayerArgs<T>& a, int kind) {
+  const size_t lds = sizeof(T) * (size_t(kFcMaxRows) * kFcRed + size_t(kFcRed) * (kFcCols + 1));
+  if (kind == 0) {
+    set_lds(k_fc_fwd<T, RPW, false>, lds);
+    hipLaunchKernelGGL((k_fc_fwd<T, RPW, false>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+                       h->stream, a);
+  } else if (kind == 1) {
+    set_lds(k_fc_fwd<T, RPW, true>, lds);
+    hipLaunchKernelGGL((k_fc_fwd<T, RPW, true>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+                       h->stream, a);
+  } else {
+    set_lds(k_fc_bwd<T, RPW>, lds);
+    hipLaunchKernelGGL((k_fc_bwd<T, RPW>), dim3((a.n_in + kFcCols - 1) / kFcCols, h->B), dim3(256), lds, h->stream,
+                       a);
+  }
+}
+
+// kind 0: hidden forward layer, 1: output layer, 2: hidden pre-activation gradient
+template <typename T>
+static int fc_layer(pdf_handle* h, const FcLayerArgs<T>& a, int kind) {
+  const int rpw = (a.R + 3) / 4;
+  if (rpw <= 1) fc_launch<T, 1>(h, a, kind);
+  else if (rpw <= 2) fc_launch<T, 2>(h, a, kind);
+  else if (rpw <= 4) fc_launch<T, 4>(h, a, kind);
+  else if (rpw <= 8) fc_launch<T, 8>(h, a, kind);
+  else fc_launch<T, 16>(h, a, kind);
+  return check_launch(h, kind == 2 ? "k_fc_bwd" : "k_fc_fwd");
+}
+
+template <typename T>
+static FcLayerArgs<T> fc_layer_args(const FcNet<T>& n, int l, const T* theta) {
+  FcLayerArgs<T> a{};
+  a.theta = theta + n.off[l];
+  a.theta_stride = n.P;
+  a.R = n.R;
+  a.n_in = l == 0 ? n.D : n.H;
+  a.n_out = l == 2 ? n.D : n.H;
+  return a;
+}
+
+// alpha_hat = alpha_0 + f_theta(alpha_0); activations kept in the workspace.
+template <typename T>
+static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, const T* theta, cx<T>* alpha_hat) {
+  int rc;
+  FcLayerArgs<T> a = fc_layer_args(n, 0, theta);
+  a.in = fc_split(alpha0, n.D);
+  a.in_stride = size_t(n.R) * n.Q;
+  a.act = n.A1;
+  if ((rc = fc_layer(h, a, 0))) return rc;
+  a = fc_layer_args(n, 1, theta);
+  a.in = fc_real<T>(n.A1, n.H);
+  a.in_stride = size_t(n.R) * n.H;
+  a.act = n.A2;
+  if ((rc = fc_layer(h, a, 0))) return rc;
+  a = fc_layer_args(n, 2, theta);
+  a.in = fc_real<T>(n.A2, n.H);
+  a.in_stride = size_t(n.R) * n.H;
+  a.alpha0 = alpha0;
+  a.alpha_hat = alpha_hat;
+  return fc_layer(h, a, 1);
+}
+
+template <typename T>
+static int fc_step(pdf_handle* h, int H, const cx<T>* alpha0, T* theta, T* m, T* v, int t, cx<T>* alpha_hat,
+                   double* loss) {
+  FcNet<T> n;
+  int rc;
+  if ((rc = fc_prepare<T>(h, H, &n))) return rc;
+  if ((rc = fc_forward<T>(h, n, alpha0, theta, alpha_hat))) return rc;
+  if ((rc = run_iteration<T>(h, alpha_hat, n.g, loss, nullptr, nullptr, nullptr, nullptr, nullptr))) return rc;
+  // pre-activation gradients with the weights before the update
+  FcLayerArgs<T> a = fc_layer_args(n, 2, theta);
+  a.in = fc_split<T>(n.g, n.D);
+  a.in_stride = size_t(n.R) * n.Q;
+  a.a_prev = n.A2;
+  a.gprev = n.G2;
+  if ((rc = fc_layer(h, a, 2))) return rc;
+  a = fc_layer_args(n, 1, theta);
+  a.in = fc_real<T>(n.G2, n.H);
+  a.in_stride = size_t(n.R) * n.H;
+  a.a_prev = n.A1;
+  a.gprev = n.G1;
+  if ((rc = fc_layer(h, a, 2))) return rc;
+  FcAdamArgs<T> d{};
+  d.in[0] = fc_split(alpha0, n.D);
+  d.in_stride[0] = size_t(n.R) * n.Q;
+  d.in[1] = fc_real<T>(n.A1, n.H);
+  d.in[2] = fc_real<T>(n.A2, n.H);
+  d.in_stride[1] = d.in_stride[2] = size_t(n.R) * n.H;
+  d.g[0] = fc_real<T>(n.G1, n.H);
+  d.g[1] = fc_real<T>(n.G2, n.H);
+  d.g_stride[0] = d.g_stride[1] = size_t(n.R) * n.H;
+  d.g[2] = fc_split<T>(n.g, n.D);
+  d.g_stride[2] = size_t(n.R) * n.Q;
+  d.tile_start[0] = 0;
+  for (int l = 0; l < 3; ++l) {
+    d.n_in[l] = l == 0 ? n.D : n.H;
+    d.n_out[l] = l == 2 ? n.D : n.H;
+    d.off[l] = n.off[l];
+    const int tiles = ((d.n_in[l] + 1 + kFcAdamRows - 1) / kFcAdamRows) * ((d.n_out[l] + kFcCols - 1) / kFcCols);
+    d.tile_start[l + 1] = d.tile_start[l] + tiles;
+  }
+  d.R = n.R;
+  d.theta = theta;
+  d.m = m;
+  d.v = v;
+  d.theta_stride = n.P;
+  d.b1 = h->prm.adam_b1;
+  d.b2 = h->prm.adam_b2;
+  d.eps = h->prm.adam_eps;
+  d.lr1 = h->prm.lr / (1.0 - std::pow(h->prm.adam_b1, double(t)));
+  d.ic2 = 1.0 / (1.0 - std::pow(h->prm.adam_b2, double(t)));
+  hipLaunchKernelGGL(k_fc_adam<T>, dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
+  return check_launch(h, "k_fc_adam");
+}
+
+extern "C" int pdf_fcnn_size(const pdf_handle* h, int32_t hidden, int64_t* n_params) {
+  if (!h || !n_params || hidden < 1 || hidden > 4096) return PDF_EINVAL;
+  *n_params = int64_t(fc_params(h->K, hidden));
+  return PDF_OK;
+}
+
+extern "C" int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, const void* alpha0_dev, const void* theta_dev,
+                                void* alpha_hat_dev) {
+  if (!h || !alpha0_dev || !theta_dev || !alpha_hat_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
+  int rc;
+  if (h->prec == PDF_FP32) {
+    FcNet<float> n;
+    if ((rc = fc_prepare<float>(h, hidden, &n))) return rc;
+    return fc_forward<float>(h, n, (const cx<float>*)alpha0_dev, (const float*)theta_dev, (cx<float>*)alpha_hat_dev);
+  }
+  FcNet<double> n;
+  if ((rc = fc_prepare<double>(h, hidden, &n))) return rc;
+  return fc_forward<double>(h, n, (const cx<double>*)alpha0_dev, (const double*)theta_dev,
+                            (cx<double>*)alpha_hat_dev);
+}
+
+extern "C" int pdf_fcnn_step(pdf_handle* h, int32_t hidden, const void* alpha0_dev, void* theta_dev, void* m_dev,
+                             void* v_dev, int32_t t, void* alpha_hat_dev, double* loss_dev) {
+  if (!h || !alpha0_dev || !theta_dev || !m_dev || !v_dev || !alpha_hat_dev)
+    return fail(h, PDF_EINVAL, "null argument");
+  if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
+  if (t < 1) return fail(h, PDF_EINVAL, "the step number t counts from 1");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32
+             ? fc_step<float>(h, hidden, (const cx<float>*)alpha0_dev, (float*)theta_dev, (float*)m_dev,
+                              (float*)v_dev, t, (cx<float>*)alpha_hat_dev, loss_dev)
+             : fc_step<double>(h, hidden, (const cx<double>*)alpha0_dev, (double*)theta_dev, (double*)m_dev,
+                               (double*)v_dev, t, (cx<double>*)alpha_hat_dev, loss_dev);
 }
 
 template <typename T, int M>

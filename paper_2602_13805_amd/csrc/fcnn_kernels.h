@@ -1,0 +1,236 @@
+// Coefficient network of the solver (Sec. 3.1, Fig. 4): alpha_hat = alpha_0 +
+// f_theta(Re/Im alpha_0), Adam on theta (Sec. 3.3).  One network per
+// reconstruction, shared by its N_i incidences: each incidence is a row of
+// width D = 2 K^2 ([Re alpha_0[i, :], Im alpha_0[i, :]]), layers D -> H -> H
+// -> D with tanh after the first two.  Parameters of one reconstruction are
+// flat: per layer a block of (in + 1) x out values, row-major [k][n], the last
+// row the bias.
+//
+// The three products of a layer are skinny GEMMs with per-reconstruction
+// weights (N_i <= 64 rows): each weight is used by N_i rows only, so the
+// weight stream from HBM and the Adam state dominate; one workgroup computes
+// all rows of 64 output columns, staging 64 reduction indices of the rows and
+// the matching weight tile through LDS, each wave owning a quarter of the rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cplx.h"
+
+namespace pdfk {
+
+constexpr int kFcCols = 64;    // output columns per workgroup (one per lane)
+constexpr int kFcRed = 64;     // reduction indices staged per pass
+constexpr int kFcMaxRows = 64; // incidences per reconstruction
+constexpr int kFcAdamRows = 16;  // weight rows per Adam tile (4 per wave)
+
+template <typename T>
+__device__ __forceinline__ T fc_tanh(T z);
+template <>
+__device__ __forceinline__ float fc_tanh<float>(float z) { return tanhf(z); }
+template <>
+__device__ __forceinline__ double fc_tanh<double>(double z) { return tanh(z); }
+
+// Row r, column c of a real row matrix given either as T [rows][width] or as
+// the [Re | Im] split of complex [rows][Q] values (width 2Q).
+template <typename T>
+struct FcRows {
+  const T* re = nullptr;        // real rows, or null
+  const cx<T>* cxv = nullptr;   // complex rows (split), or null
+  int width = 0;                // real width (2Q for complex rows)
+  __device__ __forceinline__ T at(int r, int c) const {
+    if (cxv) {
+      const int q = width >> 1;
+      const cx<T> z = cxv[size_t(r) * q + (c < q ? c : c - q)];
+      return c < q ? z.x : z.y;
+    }
+    return re[size_t(r) * width + c];
+  }
+};
+
+template <typename T>
+struct FcLayerArgs {
+  FcRows<T> in;          // per reconstruction: rows [R][in]; .re/.cxv point at reconstruction 0
+  size_t in_stride;      // elements (T or cx<T>) between reconstructions
+  const T* theta;        // parameters of reconstruction 0, this layer's block
+  size_t theta_stride;   // parameters per reconstruction
+  int R, n_in, n_out;    // rows, layer input and output widths
+  // forward epilogue: hidden (tanh) into act, or output rows added to alpha_0 into alpha_hat
+  T* act;                // [B][R][n_out] or null
+  const cx<T>* alpha0;   // [B][R][Q] (output layer)
+  cx<T>* alpha_hat;      // [B][R][Q] (output layer)
+  // input-gradient epilogue: gprev = (sum_c g[r][c] W[n][c]) (1 - a[r][n]^2)
+  const T* a_prev;       // [B][R][n_in]
+  T* gprev;              // [B][R][n_in]
+};
+
+// Stage rows [R][c0, c0 + kFcRed) of `in` (zeros past the width) into As.
+template <typename T>
+__device__ __forceinline__ void fc_stage_rows(T* As, const FcRows<T>& in, int R, int c0, int width) {
+  for (int e = threadIdx.x; e < R * kFcRed; e += blockDim.x) {
+    const int r = e / kFcRed, cc = e % kFcRed, c = c0 + cc;
+    As[e] = c < width ? in.at(r, c) : T(0);
+  }
+}
+
+// out[r][n] = sum_c A[r][c] W'(c, n) for the 64 columns n0.. of this workgroup,
+// with W'(c, n) = W[c][n] (forward, TRANS = false) or W[n][c] (input gradient).
+template <typename T, int RPW, bool TRANS>
+__device__ __forceinline__ void fc_gemm_tile(T* As, T* Ws, const FcRows<T>& in, const T* W, int R, int n_red,
+                                             int ld_w, int n_cols, int n0, T (&acc)[RPW]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) acc[i] = T(0);
+  for (int c0 = 0; c0 < n_red; c0 += kFcRed) {
+    fc_stage_rows(As, in, R, c0, n_red);
+    for (int e = threadIdx.x; e < kFcRed * kFcCols; e += blockDim.x) {
+      if (!TRANS) {   // W[c][n]: consecutive threads along n
+        const int cc = e / kFcCols, j = e % kFcCols, c = c0 + cc, n = n0 + j;
+        Ws[cc * (kFcCols + 1) + j] = (c < n_red && n < n_cols) ? W[size_t(c) * ld_w + n] : T(0);
+      } else {        // W[n][c]: consecutive threads along c, transposed into Ws[c][n]
+        const int j = e / kFcRed, cc = e % kFcRed, c = c0 + cc, n = n0 + j;
+        Ws[cc * (kFcCols + 1) + j] = (c < n_red && n < n_cols) ? W[size_t(n) * ld_w + c] : T(0);
+      }
+    }
+    __syncthreads();
+    const T* arow = As + wv * RPW * kFcRed;
+#pragma unroll 4
+    for (int cc = 0; cc < kFcRed; ++cc) {
+      const T w = Ws[cc * (kFcCols + 1) + lane];
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) acc[i] += arow[i * kFcRed + cc] * w;
+    }
+    __syncthreads();
+  }
+}
+
+// Forward of one layer.  Grid (ceil(n_out / 64), B), 256 threads; R <= 4 RPW.
+template <typename T, int RPW, bool OUT>
+__global__ void __launch_bounds__(256) k_fc_fwd(FcLayerArgs<T> a) {
+  extern __shared__ unsigned char fc_smem[];
+  T* As = reinterpret_cast<T*>(fc_smem);
+  T* Ws = As + kFcMaxRows * kFcRed;
+  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  FcRows<T> in = a.in;
+  if (in.cxv) in.cxv += size_t(b) * a.in_stride; else in.re += size_t(b) * a.in_stride;
+  const T* W = a.theta + size_t(b) * a.theta_stride;
+  T acc[RPW];
+  fc_gemm_tile<T, RPW, false>(As, Ws, in, W, a.R, a.n_in, a.n_out, a.n_out, n0, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
+  if (n >= a.n_out) return;
+  const T bias = W[size_t(a.n_in) * a.n_out + n];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wv * RPW + i;
+    if (r >= a.R) break;
+    const T z = acc[i] + bias;
+    const size_t row = size_t(b) * a.R + r;
+    if (!OUT) {
+      a.act[row * a.n_out + n] = fc_tanh(z);
+    } else {   // Delta alpha row [Re | Im] added to alpha_0
+      const int q = a.n_out >> 1, mode = n < q ? n : n - q;
+      const T* a0 = reinterpret_cast<const T*>(a.alpha0 + row * q + mode);
+      T* ah = reinterpret_cast<T*>(a.alpha_hat + row * q + mode);
+      const int part = n < q ? 0 : 1;
+      ah[part] = a0[part] + z;
+    }
+  }
+}
+
+// Gradient with respect to a hidden layer's pre-activation:
+// gprev[r][n] = (sum_c g[r][c] W[n][c]) (1 - a_prev[r][n]^2), n < n_in.
+// Grid (ceil(n_in / 64), B), 256 threads.
+template <typename T, int RPW>
+__global__ void __launch_bounds__(256) k_fc_bwd(FcLayerArgs<T> a) {
+  extern __shared__ unsigned char fc_smem[];
+  T* As = reinterpret_cast<T*>(fc_smem);
+  T* Ws = As + kFcMaxRows * kFcRed;
+  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  FcRows<T> g = a.in;
+  if (g.cxv) g.cxv += size_t(b) * a.in_stride; else g.re += size_t(b) * a.in_stride;
+  const T* W = a.theta + size_t(b) * a.theta_stride;
+  T acc[RPW];
+  fc_gemm_tile<T, RPW, true>(As, Ws, g, W, a.R, a.n_out, a.n_out, a.n_in, n0, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
+  if (n >= a.n_in) return;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wv * RPW + i;
+    if (r >= a.R) break;
+    const size_t idx = (size_t(b) * a.R + r) * a.n_in + n;
+    const T av = a.a_prev[idx];
+    a.gprev[idx] = acc[i] * (T(1) - av * av);
+  }
+}
+
+template <typename T>
+struct FcAdamArgs {
+  FcRows<T> in[3];        // layer inputs of reconstruction 0: X (split alpha_0), A1, A2
+  size_t in_stride[3];
+  FcRows<T> g[3];         // gradients at the layer outputs: G1, G2, [Re g | Im g]
+  size_t g_stride[3];
+  int n_in[3], n_out[3];
+  size_t off[3];          // parameter block offsets
+  int tile_start[4];      // first tile of each layer (tile_start[3] = tiles per reconstruction)
+  int R;
+  T* theta;
+  T* m;
+  T* v;
+  size_t theta_stride;
+  double lr1, ic2;        // lr / (1 - b1^t), 1 / (1 - b2^t)
+  double b1, b2, eps;
+};
+
+// Weight gradients dW[k][n] = sum_r in[r][k] g[r][n] (in[r][n_in] = 1: bias row)
+// of every layer, each followed at once by its bias-corrected Adam update.
+// Grid (tiles per reconstruction, B), 256 threads; a tile is 16 rows x 64
+// columns of one layer's block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
+  __shared__ T Is[kFcMaxRows * kFcAdamRows];
+  __shared__ T Gs[kFcMaxRows * kFcCols];
+  const int b = blockIdx.y;
+  int l = 0;
+  while (l < 2 && int(blockIdx.x) >= a.tile_start[l + 1]) ++l;
+  const int n_in = a.n_in[l], n_out = a.n_out[l];
+  const int ntn = (n_out + kFcCols - 1) / kFcCols;
+  const int t = blockIdx.x - a.tile_start[l];
+  const int k0 = (t / ntn) * kFcAdamRows, n0 = (t % ntn) * kFcCols;
+  FcRows<T> in = a.in[l], g = a.g[l];
+  if (in.cxv) in.cxv += size_t(b) * a.in_stride[l]; else in.re += size_t(b) * a.in_stride[l];
+  if (g.cxv) g.cxv += size_t(b) * a.g_stride[l]; else g.re += size_t(b) * a.g_stride[l];
+  const int R = a.R;
+  for (int e = threadIdx.x; e < R * kFcAdamRows; e += blockDim.x) {
+    const int r = e / kFcAdamRows, kk = e % kFcAdamRows, k = k0 + kk;
+    Is[e] = k < n_in ? in.at(r, k) : (k == n_in ? T(1) : T(0));
+  }
+  for (int e = threadIdx.x; e < R * kFcCols; e += blockDim.x) {
+    const int r = e / kFcCols, j = e % kFcCols, n = n0 + j;
+    Gs[e] = n < n_out ? g.at(r, n) : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
+  if (n >= n_out) return;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int r = 0; r < R; ++r) {
+    const T gv = Gs[r * kFcCols + lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += Is[r * kFcAdamRows + wv * 4 + i] * gv;
+  }
+  const size_t base = size_t(b) * a.theta_stride + a.off[l];
+  const T b1 = T(a.b1), b2 = T(a.b2), lr1 = T(a.lr1), ic2 = T(a.ic2), eps = T(a.eps);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = k0 + wv * 4 + i;
+    if (k > n_in) break;
+    const size_t idx = base + size_t(k) * n_out + n;
+    const T gw = acc[i];
+    const T mm = b1 * a.m[idx] + (T(1) - b1) * gw;
+    const T vv = b2 * a.v[idx] + (T(1) - b2) * (gw * gw);
+    a.m[idx] = mm;
+    a.v[idx] = vv;
+    a.theta[idx] -= lr1 * mm / (sqrt(vv * ic2) + eps);
+  }
+}
+
+}  // namespace pdfk

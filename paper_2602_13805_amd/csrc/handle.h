@@ -48,6 +48,9 @@ struct pdf_handle {
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]
   double* loss_w = nullptr;  // [B][8] second loss record (start selection)
+  // coefficient-network workspace (activations and gradients of one step), grown on demand
+  void* fc_ws = nullptr;
+  size_t fc_bytes = 0;
   // tile shapes of the FP32 MFMA kernels (chosen by pdf_autotune; results do not depend on them)
   int tune_ct = 2;           // column tiles per wave of the G_S^H GEMM: 1, 2 or 4
   int tune_pb = 4;           // load batch of the pixel reduction: 4 or 8
