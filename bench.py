@@ -314,6 +314,9 @@ def main():
     ap.add_argument("--warm-pairs", type=int, default=20000,
                     help="training pairs of the warm-start network (0: skip the warm-start leg)")
     ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--fcnn-iters", type=int, default=300,
+                    help="Adam steps of the coefficient-network leg (0: skip it)")
+    ap.add_argument("--fcnn-hidden", type=int, default=256, help="hidden width of the coefficient network")
     ap.add_argument("--uneven", type=int, default=512,
                     help="instances of the uneven-shape batch leg (0: skip it)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
@@ -469,6 +472,10 @@ def main():
         if args.warm_pairs > 0:
             extra["warm_start"] = warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev)
             log(f"warm start: {extra['warm_start']}")
+    if args.fcnn_iters > 0:
+        extra["coefficient_network"] = fcnn_leg(pdf, si, wl, s, eps, args.fcnn_hidden, args.fcnn_iters,
+                                                args.steps, dev)
+        log(f"coefficient network: {extra['coefficient_network']}")
     if args.uneven > 0:
         extra["uneven_batch"] = uneven_leg(pdf, si, wl, args.uneven, 200, dev)
         log(f"uneven batch: {extra['uneven_batch']}")
@@ -494,6 +501,87 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(si, wl, esca[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def fcnn_cost(B, R, K, H):
+    """Algorithmic HBM bytes and flops of the coefficient network's kernels in one step (FP32):
+    forward (3 layers), pre-activation gradients (2 layers), weight gradients with Adam."""
+    D = 2 * K * K
+    layers = [(D, H), (H, H), (H, D)]
+    P = sum((i + 1) * o for i, o in layers)
+    fwd_b = 4 * B * sum((i + 1) * o + R * (i + o) for i, o in layers)
+    fwd_f = 2 * B * R * sum(i * o for i, o in layers)
+    bwd_b = 4 * B * sum(i * o + R * (o + 2 * i) for i, o in layers[1:])
+    bwd_f = 2 * B * R * sum(i * o for i, o in layers[1:])
+    adam_b = 4 * B * (6 * P + sum(R * (i + o) for i, o in layers))
+    adam_f = B * (2 * R * P + 10 * P)
+    return dict(fwd=(fwd_b, fwd_f), bwd=(bwd_b, bwd_f), adam=(adam_b, adam_f)), P
+
+
+def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
+    """The coefficient network (Sec. 3.1): Adam on per-instance network weights theta, the loss taken
+    at alpha_hat = alpha_0 + f_theta(alpha_0), from the same back-propagation start as the direct
+    optimisation.  Image error reached in `iters` steps (checked every 10) next to the direct
+    optimisation's, then `steps` timed steps split into network and physics kernels."""
+    import numpy as np
+    import torch
+    B, K = s.B, s.K
+    eps_t = torch.tensor(eps, dtype=s.cdtype, device=dev)
+    a0 = s.init_alpha()
+    sc = dict(s_in=1.0 / float(a0.abs().pow(2).mean().sqrt()), s_out=1.0 / H)
+    theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=torch.float32, device=dev)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    ah = torch.empty_like(a0)
+    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
+    _, _, err0 = s.image(a0, eps_t)
+    best = err0.clone()
+    t = 0
+    for _ in range(iters):
+        t += 1
+        s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
+        if t % 10 == 0:
+            _, _, err = s.image(s.fcnn_forward(H, a0, theta, **sc), eps_t)
+            best = torch.minimum(best, err)
+    if not np.all(np.isfinite(loss.cpu().numpy()[:, 5])):
+        raise RuntimeError("non-finite loss in the coefficient-network steps")
+    direct = s.reconstruct(iters, n_check=10, eps_true=eps_t)
+    best_d = direct["best_err"].cpu().numpy()
+    best_n = best.cpu().numpy()
+    # timed steps, continuing from the trained weights
+    torch.cuda.synchronize()
+    s.timing(True, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t += 1
+        s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phys_ms, _ = s.timing_read()
+    s.timing(False)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.fcnn_forward(H, a0, theta, **sc)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) / steps * 1e3
+    step_ms = dt / steps * 1e3
+    net_ms = step_ms - sum(phys_ms.values())
+    cost, P = fcnn_cost(B, s.Ni, K, H)
+    net_bytes = sum(c[0] for c in cost.values())
+    net_flops = sum(c[1] for c in cost.values())
+    return dict(
+        hidden=H, params_per_instance=P, iterations=iters, s_in=sc["s_in"], s_out=sc["s_out"],
+        mean_best_image_error=float(best_n.mean()), mean_best_image_error_direct=float(best_d.mean()),
+        mean_start_image_error=float(err0.cpu().numpy().mean()),
+        frac_better_than_direct=float(np.mean(best_n < best_d - 1e-6)),
+        instance_iters_per_s=B * steps / dt, ms_per_step=step_ms, physics_kernels_ms=sum(phys_ms.values()),
+        network_ms=net_ms, network_forward_ms=fwd_ms,
+        network_roofline=dict(bound="hbm", algorithmic_bytes=net_bytes, algorithmic_flops=net_flops,
+                              achieved=net_bytes / (net_ms * 1e-3) / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                              frac=net_bytes / (net_ms * 1e-3) / HBM_PEAK,
+                              basis="network kernels' algorithmic bytes / (step time - physics kernels' "
+                                    "event-timed durations)"),
+        start="back-propagation alpha_0; output layer zero, so alpha_hat = alpha_0 at step 1",
+        weights="U[-1/sqrt(in), 1/sqrt(in)] hidden layers, seed 1")
 
 
 def warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev):

@@ -303,13 +303,17 @@ int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev);
 
 /* Coefficient network (Sec. 3.1, Fig. 4): instead of optimising alpha, a
  * fully connected network whose input is Re and Im of the start coefficients
- * alpha_0 predicts a correction, alpha_hat = alpha_0 + f_theta(alpha_0), and
+ * alpha_0 predicts a correction,
+ * alpha_hat = alpha_0 + s_out f_theta(s_in alpha_0), and
  * Adam (Sec. 3.3, the handle's lr, b1, b2, eps) trains its weights theta on
  * the loss at alpha_hat.  The paper's layer sizes are not available; here
  * every instance has its own network, shared by its Ni incidences: each
  * incidence is one row [Re alpha_0[i][:], Im alpha_0[i][:]] of width
  * D = 2 K^2 (modes in the [K][K] order), three dense layers D -> H -> H -> D,
- * tanh after the first two, output row [Re, Im] of Delta alpha[i][:].
+ * tanh after the first two, output row [Re, Im] of Delta alpha[i][:] / s_out.
+ * s_in = 1 / rms(alpha_0) and s_out = 1 / H give unit-scale inputs and a
+ * first Adam step that moves alpha_hat about as far as a direct Adam step
+ * moves alpha; s_in = s_out = 1 is the plain network (any finite values).
  * theta layout (handle precision, per instance, n_params values): per layer
  * a block of (in + 1) x out values, row-major [k][n], rows 0..in-1 the
  * weights (z[n] = sum_k x[k] W[k][n] + W[in][n]), row `in` the bias; the
@@ -319,10 +323,10 @@ int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev);
  * values in the handle (allocated on the first call, grown when needed). */
 int pdf_fcnn_size(const pdf_handle* h, int32_t hidden, int64_t* n_params);
 
-/* alpha_hat_dev [B][Ni][K][K] out = alpha_0 + f_theta(alpha_0); alpha0_dev
+/* alpha_hat_dev [B][Ni][K][K] out = alpha_0 + s_out f_theta(s_in alpha_0); alpha0_dev
  * the same shape, theta_dev [B][n_params].  alpha_hat must not alias alpha_0. */
-int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, const void* alpha0_dev, const void* theta_dev,
-                     void* alpha_hat_dev);
+int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
+                     const void* theta_dev, void* alpha_hat_dev);
 
 /* One Adam step on theta in place: alpha_hat at the current weights (written
  * to alpha_hat_dev), loss and gradient there as in pdf_loss_grad (loss_dev as
@@ -331,8 +335,8 @@ int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, const void* alpha0_dev, cons
  * buffers of theta's shape, zero before step 1; t: this step's number,
  * counting from 1 (the bias corrections are fixed at launch, so a captured
  * graph of this call replays step t).  Requires pdf_set_data. */
-int pdf_fcnn_step(pdf_handle* h, int32_t hidden, const void* alpha0_dev, void* theta_dev, void* m_dev,
-                  void* v_dev, int32_t t, void* alpha_hat_dev, double* loss_dev);
+int pdf_fcnn_step(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
+                  void* theta_dev, void* m_dev, void* v_dev, int32_t t, void* alpha_hat_dev, double* loss_dev);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * each kernel of pdf_loss_grad / pdf_step (for benchmarks).  enable != 0

@@ -78,8 +78,8 @@ SIGNATURES = {
     "pdf_warm_start": (c_i32, [c_vp, c_vp, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp]),
     "pdf_analyze": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "pdf_fcnn_size": (c_i32, [c_vp, c_i32, ctypes.POINTER(ctypes.c_int64)]),
-    "pdf_fcnn_forward": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
-    "pdf_fcnn_step": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "pdf_fcnn_forward": (c_i32, [c_vp, c_i32, c_f64, c_f64, c_vp, c_vp, c_vp]),
+    "pdf_fcnn_step": (c_i32, [c_vp, c_i32, c_f64, c_f64, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
     "pdf_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "pdf_set_tiles": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32]),
     "pdf_reconstruct_multi": (c_i32, [c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
@@ -295,16 +295,18 @@ class Solver:
         _check(load().pdf_fcnn_size(self.h, hidden, ctypes.byref(n)), self.h)
         return n.value
 
-    def fcnn_forward(self, hidden: int, alpha0: torch.Tensor, theta: torch.Tensor):
-        """alpha_hat = alpha_0 + f_theta(alpha_0) [B, Ni, K, K]."""
+    def fcnn_forward(self, hidden: int, alpha0: torch.Tensor, theta: torch.Tensor, s_in: float = 1.0,
+                     s_out: float = 1.0):
+        """alpha_hat = alpha_0 + s_out f_theta(s_in alpha_0) [B, Ni, K, K]."""
         alpha0 = self._want(alpha0, self.alpha_shape, self.cdtype, "alpha0")
         theta = self._want(theta, (self.B, self.fcnn_size(hidden)), self.rdtype, "theta")
         ah = torch.empty_like(alpha0)
-        self._call(load().pdf_fcnn_forward, hidden, _ptr(alpha0), _ptr(theta), _ptr(ah))
+        self._call(load().pdf_fcnn_forward, hidden, float(s_in), float(s_out), _ptr(alpha0), _ptr(theta), _ptr(ah))
         return ah
 
     def fcnn_step(self, hidden: int, alpha0: torch.Tensor, theta, m, v, t: int,
-                  alpha_hat: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None):
+                  alpha_hat: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None,
+                  s_in: float = 1.0, s_out: float = 1.0):
         """One Adam step on the network weights theta [B, n_params] in place (m, v alike, zero
         before step 1; t counts from 1).  Returns alpha_hat at the weights before the update."""
         alpha0 = self._want(alpha0, self.alpha_shape, self.cdtype, "alpha0")
@@ -316,8 +318,8 @@ class Solver:
         self._want(alpha_hat, self.alpha_shape, self.cdtype, "alpha_hat", inplace=True)
         if loss is not None:
             self._want(loss, (self.B, LOSS_STRIDE), torch.float64, "loss", inplace=True)
-        self._call(load().pdf_fcnn_step, hidden, _ptr(alpha0), _ptr(theta), _ptr(m), _ptr(v), int(t),
-                   _ptr(alpha_hat), _ptr(loss))
+        self._call(load().pdf_fcnn_step, hidden, float(s_in), float(s_out), _ptr(alpha0), _ptr(theta), _ptr(m),
+                   _ptr(v), int(t), _ptr(alpha_hat), _ptr(loss))
         return alpha_hat
 
     def warm_start(self, net: "Mlp", s_in: float, s_out: float):

@@ -1187,10 +1187,11 @@ static FcRows<T> fc_real(const T* p, int width) {
 }
 
 template <typename T>
-static FcRows<T> fc_split(const cx<T>* p, int width) {
+static FcRows<T> fc_split(const cx<T>* p, int width, double scale) {
   FcRows<T> r;
   r.cxv = p;
   r.width = width;
+  r.scale = T(scale);
   return r;
 }
 
@@ -1235,12 +1236,13 @@ static FcLayerArgs<T> fc_layer_args(const FcNet<T>& n, int l, const T* theta) {
   return a;
 }
 
-// alpha_hat = alpha_0 + f_theta(alpha_0); activations kept in the workspace.
+// alpha_hat = alpha_0 + s_out f_theta(s_in alpha_0); activations kept in the workspace.
 template <typename T>
-static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, const T* theta, cx<T>* alpha_hat) {
+static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, const T* theta, cx<T>* alpha_hat,
+                      double s_in, double s_out) {
   int rc;
   FcLayerArgs<T> a = fc_layer_args(n, 0, theta);
-  a.in = fc_split(alpha0, n.D);
+  a.in = fc_split(alpha0, n.D, s_in);
   a.in_stride = size_t(n.R) * n.Q;
   a.act = n.A1;
   if ((rc = fc_layer(h, a, 0))) return rc;
@@ -1254,20 +1256,21 @@ static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, con
   a.in_stride = size_t(n.R) * n.H;
   a.alpha0 = alpha0;
   a.alpha_hat = alpha_hat;
+  a.out_scale = T(s_out);
   return fc_layer(h, a, 1);
 }
 
 template <typename T>
-static int fc_step(pdf_handle* h, int H, const cx<T>* alpha0, T* theta, T* m, T* v, int t, cx<T>* alpha_hat,
-                   double* loss) {
+static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>* alpha0, T* theta, T* m, T* v,
+                   int t, cx<T>* alpha_hat, double* loss) {
   FcNet<T> n;
   int rc;
   if ((rc = fc_prepare<T>(h, H, &n))) return rc;
-  if ((rc = fc_forward<T>(h, n, alpha0, theta, alpha_hat))) return rc;
+  if ((rc = fc_forward<T>(h, n, alpha0, theta, alpha_hat, s_in, s_out))) return rc;
   if ((rc = run_iteration<T>(h, alpha_hat, n.g, loss, nullptr, nullptr, nullptr, nullptr, nullptr))) return rc;
   // pre-activation gradients with the weights before the update
   FcLayerArgs<T> a = fc_layer_args(n, 2, theta);
-  a.in = fc_split<T>(n.g, n.D);
+  a.in = fc_split<T>(n.g, n.D, s_out);   // dL/dY = s_out [Re g | Im g]
   a.in_stride = size_t(n.R) * n.Q;
   a.a_prev = n.A2;
   a.gprev = n.G2;
@@ -1279,7 +1282,7 @@ static int fc_step(pdf_handle* h, int H, const cx<T>* alpha0, T* theta, T* m, T*
   a.gprev = n.G1;
   if ((rc = fc_layer(h, a, 2))) return rc;
   FcAdamArgs<T> d{};
-  d.in[0] = fc_split(alpha0, n.D);
+  d.in[0] = fc_split(alpha0, n.D, s_in);
   d.in_stride[0] = size_t(n.R) * n.Q;
   d.in[1] = fc_real<T>(n.A1, n.H);
   d.in[2] = fc_real<T>(n.A2, n.H);
@@ -1287,7 +1290,7 @@ static int fc_step(pdf_handle* h, int H, const cx<T>* alpha0, T* theta, T* m, T*
   d.g[0] = fc_real<T>(n.G1, n.H);
   d.g[1] = fc_real<T>(n.G2, n.H);
   d.g_stride[0] = d.g_stride[1] = size_t(n.R) * n.H;
-  d.g[2] = fc_split<T>(n.g, n.D);
+  d.g[2] = fc_split<T>(n.g, n.D, s_out);
   d.g_stride[2] = size_t(n.R) * n.Q;
   d.tile_start[0] = 0;
   for (int l = 0; l < 3; ++l) {
@@ -1317,34 +1320,43 @@ extern "C" int pdf_fcnn_size(const pdf_handle* h, int32_t hidden, int64_t* n_par
   return PDF_OK;
 }
 
-extern "C" int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, const void* alpha0_dev, const void* theta_dev,
-                                void* alpha_hat_dev) {
+static int fc_check_scales(pdf_handle* h, double s_in, double s_out) {
+  if (!std::isfinite(s_in) || !std::isfinite(s_out)) return fail(h, PDF_EINVAL, "s_in and s_out must be finite");
+  return PDF_OK;
+}
+
+extern "C" int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
+                                const void* theta_dev, void* alpha_hat_dev) {
   if (!h || !alpha0_dev || !theta_dev || !alpha_hat_dev) return fail(h, PDF_EINVAL, "null argument");
   if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
   int rc;
+  if ((rc = fc_check_scales(h, s_in, s_out))) return rc;
   if (h->prec == PDF_FP32) {
     FcNet<float> n;
     if ((rc = fc_prepare<float>(h, hidden, &n))) return rc;
-    return fc_forward<float>(h, n, (const cx<float>*)alpha0_dev, (const float*)theta_dev, (cx<float>*)alpha_hat_dev);
+    return fc_forward<float>(h, n, (const cx<float>*)alpha0_dev, (const float*)theta_dev, (cx<float>*)alpha_hat_dev,
+                             s_in, s_out);
   }
   FcNet<double> n;
   if ((rc = fc_prepare<double>(h, hidden, &n))) return rc;
   return fc_forward<double>(h, n, (const cx<double>*)alpha0_dev, (const double*)theta_dev,
-                            (cx<double>*)alpha_hat_dev);
+                            (cx<double>*)alpha_hat_dev, s_in, s_out);
 }
 
-extern "C" int pdf_fcnn_step(pdf_handle* h, int32_t hidden, const void* alpha0_dev, void* theta_dev, void* m_dev,
-                             void* v_dev, int32_t t, void* alpha_hat_dev, double* loss_dev) {
+extern "C" int pdf_fcnn_step(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
+                             void* theta_dev, void* m_dev, void* v_dev, int32_t t, void* alpha_hat_dev,
+                             double* loss_dev) {
   if (!h || !alpha0_dev || !theta_dev || !m_dev || !v_dev || !alpha_hat_dev)
     return fail(h, PDF_EINVAL, "null argument");
   if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
   if (t < 1) return fail(h, PDF_EINVAL, "the step number t counts from 1");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  if (int rc = fc_check_scales(h, s_in, s_out)) return rc;
   return h->prec == PDF_FP32
-             ? fc_step<float>(h, hidden, (const cx<float>*)alpha0_dev, (float*)theta_dev, (float*)m_dev,
-                              (float*)v_dev, t, (cx<float>*)alpha_hat_dev, loss_dev)
-             : fc_step<double>(h, hidden, (const cx<double>*)alpha0_dev, (double*)theta_dev, (double*)m_dev,
-                               (double*)v_dev, t, (cx<double>*)alpha_hat_dev, loss_dev);
+             ? fc_step<float>(h, hidden, s_in, s_out, (const cx<float>*)alpha0_dev, (float*)theta_dev,
+                              (float*)m_dev, (float*)v_dev, t, (cx<float>*)alpha_hat_dev, loss_dev)
+             : fc_step<double>(h, hidden, s_in, s_out, (const cx<double>*)alpha0_dev, (double*)theta_dev,
+                               (double*)m_dev, (double*)v_dev, t, (cx<double>*)alpha_hat_dev, loss_dev);
 }
 
 template <typename T, int M>

@@ -1,5 +1,5 @@
 // Coefficient network of the solver (Sec. 3.1, Fig. 4): alpha_hat = alpha_0 +
-// f_theta(Re/Im alpha_0), Adam on theta (Sec. 3.3).  One network per
+// s_out f_theta(s_in Re/Im alpha_0), Adam on theta (Sec. 3.3).  One network per
 // reconstruction, shared by its N_i incidences: each incidence is a row of
 // width D = 2 K^2 ([Re alpha_0[i, :], Im alpha_0[i, :]]), layers D -> H -> H
 // -> D with tanh after the first two.  Parameters of one reconstruction are
@@ -22,7 +22,7 @@ namespace pdfk {
 constexpr int kFcCols = 64;    // output columns per workgroup (one per lane)
 constexpr int kFcRed = 64;     // reduction indices staged per pass
 constexpr int kFcMaxRows = 64; // incidences per reconstruction
-constexpr int kFcAdamRows = 16;  // weight rows per Adam tile (4 per wave)
+constexpr int kFcAdamRows = 64;  // weight rows per Adam tile (16 per wave)
 
 template <typename T>
 __device__ __forceinline__ T fc_tanh(T z);
@@ -32,17 +32,18 @@ template <>
 __device__ __forceinline__ double fc_tanh<double>(double z) { return tanh(z); }
 
 // Row r, column c of a real row matrix given either as T [rows][width] or as
-// the [Re | Im] split of complex [rows][Q] values (width 2Q).
+// the [Re | Im] split of complex [rows][Q] values (width 2Q) times `scale`.
 template <typename T>
 struct FcRows {
   const T* re = nullptr;        // real rows, or null
   const cx<T>* cxv = nullptr;   // complex rows (split), or null
   int width = 0;                // real width (2Q for complex rows)
+  T scale = T(1);               // factor on complex rows
   __device__ __forceinline__ T at(int r, int c) const {
     if (cxv) {
       const int q = width >> 1;
       const cx<T> z = cxv[size_t(r) * q + (c < q ? c : c - q)];
-      return c < q ? z.x : z.y;
+      return scale * (c < q ? z.x : z.y);
     }
     return re[size_t(r) * width + c];
   }
@@ -55,8 +56,10 @@ struct FcLayerArgs {
   const T* theta;        // parameters of reconstruction 0, this layer's block
   size_t theta_stride;   // parameters per reconstruction
   int R, n_in, n_out;    // rows, layer input and output widths
-  // forward epilogue: hidden (tanh) into act, or output rows added to alpha_0 into alpha_hat
+  // forward epilogue: hidden (tanh) into act, or out_scale times the output rows added to
+  // alpha_0 into alpha_hat
   T* act;                // [B][R][n_out] or null
+  T out_scale;
   const cx<T>* alpha0;   // [B][R][Q] (output layer)
   cx<T>* alpha_hat;      // [B][R][Q] (output layer)
   // input-gradient epilogue: gprev = (sum_c g[r][c] W[n][c]) (1 - a[r][n]^2)
@@ -64,12 +67,24 @@ struct FcLayerArgs {
   T* gprev;              // [B][R][n_in]
 };
 
-// Stage rows [R][c0, c0 + kFcRed) of `in` (zeros past the width) into As.
+constexpr int kFcThreads = 256;
+constexpr int kFcStage = kFcMaxRows * kFcRed / kFcThreads;   // staged values per thread (each tile)
+
+// Stage rows [R][c0, c0 + kFcRed) of `in` (zeros past the width) into As:
+// every load is issued before the first LDS store, so a thread has all of
+// them in flight at once.
 template <typename T>
 __device__ __forceinline__ void fc_stage_rows(T* As, const FcRows<T>& in, int R, int c0, int width) {
-  for (int e = threadIdx.x; e < R * kFcRed; e += blockDim.x) {
-    const int r = e / kFcRed, cc = e % kFcRed, c = c0 + cc;
-    As[e] = c < width ? in.at(r, c) : T(0);
+  T v[kFcStage];
+#pragma unroll
+  for (int i = 0; i < kFcStage; ++i) {
+    const int e = threadIdx.x + i * kFcThreads, r = e / kFcRed, c = c0 + e % kFcRed;
+    v[i] = (r < R && c < width) ? in.at(r, c) : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < kFcStage; ++i) {
+    const int e = threadIdx.x + i * kFcThreads;
+    if (e < R * kFcRed) As[e] = v[i];
   }
 }
 
@@ -82,15 +97,24 @@ __device__ __forceinline__ void fc_gemm_tile(T* As, T* Ws, const FcRows<T>& in, 
 #pragma unroll
   for (int i = 0; i < RPW; ++i) acc[i] = T(0);
   for (int c0 = 0; c0 < n_red; c0 += kFcRed) {
-    fc_stage_rows(As, in, R, c0, n_red);
-    for (int e = threadIdx.x; e < kFcRed * kFcCols; e += blockDim.x) {
+    T wv_[kFcRed * kFcCols / kFcThreads];
+#pragma unroll
+    for (int i = 0; i < kFcRed * kFcCols / kFcThreads; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
       if (!TRANS) {   // W[c][n]: consecutive threads along n
-        const int cc = e / kFcCols, j = e % kFcCols, c = c0 + cc, n = n0 + j;
-        Ws[cc * (kFcCols + 1) + j] = (c < n_red && n < n_cols) ? W[size_t(c) * ld_w + n] : T(0);
-      } else {        // W[n][c]: consecutive threads along c, transposed into Ws[c][n]
-        const int j = e / kFcRed, cc = e % kFcRed, c = c0 + cc, n = n0 + j;
-        Ws[cc * (kFcCols + 1) + j] = (c < n_red && n < n_cols) ? W[size_t(n) * ld_w + c] : T(0);
+        const int c = c0 + e / kFcCols, n = n0 + e % kFcCols;
+        wv_[i] = (c < n_red && n < n_cols) ? W[size_t(c) * ld_w + n] : T(0);
+      } else {        // W[n][c]: consecutive threads along c
+        const int n = n0 + e / kFcRed, c = c0 + e % kFcRed;
+        wv_[i] = (c < n_red && n < n_cols) ? W[size_t(n) * ld_w + c] : T(0);
       }
+    }
+    fc_stage_rows(As, in, R, c0, n_red);
+#pragma unroll
+    for (int i = 0; i < kFcRed * kFcCols / kFcThreads; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
+      if (!TRANS) Ws[(e / kFcCols) * (kFcCols + 1) + e % kFcCols] = wv_[i];
+      else Ws[(e % kFcRed) * (kFcCols + 1) + e / kFcRed] = wv_[i];   // transposed into Ws[c][n]
     }
     __syncthreads();
     const T* arow = As + wv * RPW * kFcRed;
@@ -132,7 +156,7 @@ __global__ void __launch_bounds__(256) k_fc_fwd(FcLayerArgs<T> a) {
       const T* a0 = reinterpret_cast<const T*>(a.alpha0 + row * q + mode);
       T* ah = reinterpret_cast<T*>(a.alpha_hat + row * q + mode);
       const int part = n < q ? 0 : 1;
-      ah[part] = a0[part] + z;
+      ah[part] = a0[part] + a.out_scale * z;
     }
   }
 }
@@ -183,10 +207,12 @@ struct FcAdamArgs {
 
 // Weight gradients dW[k][n] = sum_r in[r][k] g[r][n] (in[r][n_in] = 1: bias row)
 // of every layer, each followed at once by its bias-corrected Adam update.
-// Grid (tiles per reconstruction, B), 256 threads; a tile is 16 rows x 64
-// columns of one layer's block.
+// Grid (tiles per reconstruction, B), 256 threads; a tile is 64 rows x 64
+// columns of one layer's block, 16 rows per wave, so each staged gradient
+// tile serves 64 weight rows.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
+  constexpr int RW = kFcAdamRows / 4;   // weight rows per wave
   __shared__ T Is[kFcMaxRows * kFcAdamRows];
   __shared__ T Gs[kFcMaxRows * kFcCols];
   const int b = blockIdx.y;
@@ -200,36 +226,64 @@ __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
   if (in.cxv) in.cxv += size_t(b) * a.in_stride[l]; else in.re += size_t(b) * a.in_stride[l];
   if (g.cxv) g.cxv += size_t(b) * a.g_stride[l]; else g.re += size_t(b) * a.g_stride[l];
   const int R = a.R;
-  for (int e = threadIdx.x; e < R * kFcAdamRows; e += blockDim.x) {
-    const int r = e / kFcAdamRows, kk = e % kFcAdamRows, k = k0 + kk;
-    Is[e] = k < n_in ? in.at(r, k) : (k == n_in ? T(1) : T(0));
+  constexpr int NI = kFcMaxRows * kFcAdamRows / kFcThreads, NG = kFcMaxRows * kFcCols / kFcThreads;
+  T iv[NI], gv_[NG];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int e = threadIdx.x + i * kFcThreads, r = e / kFcAdamRows, k = k0 + e % kFcAdamRows;
+    iv[i] = (r < R && k < n_in) ? in.at(r, k) : (k == n_in ? T(1) : T(0));
   }
-  for (int e = threadIdx.x; e < R * kFcCols; e += blockDim.x) {
-    const int r = e / kFcCols, j = e % kFcCols, n = n0 + j;
-    Gs[e] = n < n_out ? g.at(r, n) : T(0);
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int e = threadIdx.x + i * kFcThreads, r = e / kFcCols, n = n0 + e % kFcCols;
+    gv_[i] = (r < R && n < n_out) ? g.at(r, n) : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int e = threadIdx.x + i * kFcThreads;
+    if (e < R * kFcAdamRows) Is[e] = iv[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int e = threadIdx.x + i * kFcThreads;
+    if (e < R * kFcCols) Gs[e] = gv_[i];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
   if (n >= n_out) return;
-  T acc[4] = {T(0), T(0), T(0), T(0)};
+  T acc[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) acc[i] = T(0);
   for (int r = 0; r < R; ++r) {
     const T gv = Gs[r * kFcCols + lane];
+    const T* irow = Is + r * kFcAdamRows + wv * RW;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += Is[r * kFcAdamRows + wv * 4 + i] * gv;
+    for (int i = 0; i < RW; ++i) acc[i] += irow[i] * gv;
   }
   const size_t base = size_t(b) * a.theta_stride + a.off[l];
   const T b1 = T(a.b1), b2 = T(a.b2), lr1 = T(a.lr1), ic2 = T(a.ic2), eps = T(a.eps);
+  // every row's theta, m, v loaded before the first store (the three arrays
+  // may not be proven disjoint, so loads after a store would wait for it)
+  T th[RW], mo[RW], ve[RW];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int k = k0 + wv * 4 + i;
+  for (int i = 0; i < RW; ++i) {
+    const int k = k0 + wv * RW + i;
+    const size_t idx = base + size_t(k) * n_out + n;
+    th[i] = k <= n_in ? a.theta[idx] : T(0);
+    mo[i] = k <= n_in ? a.m[idx] : T(0);
+    ve[i] = k <= n_in ? a.v[idx] : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const int k = k0 + wv * RW + i;
     if (k > n_in) break;
     const size_t idx = base + size_t(k) * n_out + n;
     const T gw = acc[i];
-    const T mm = b1 * a.m[idx] + (T(1) - b1) * gw;
-    const T vv = b2 * a.v[idx] + (T(1) - b2) * (gw * gw);
+    const T mm = b1 * mo[i] + (T(1) - b1) * gw;
+    const T vv = b2 * ve[i] + (T(1) - b2) * (gw * gw);
     a.m[idx] = mm;
     a.v[idx] = vv;
-    a.theta[idx] -= lr1 * mm / (sqrt(vv * ic2) + eps);
+    a.theta[idx] = th[i] - lr1 * mm / (sqrt(vv * ic2) + eps);
   }
 }
 

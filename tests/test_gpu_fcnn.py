@@ -15,13 +15,13 @@ pytestmark = pytest.mark.gpu
 pdf = pytest.importorskip("paper_2602_13805_amd")
 
 CASES = [
-    # (M, K, Ni, Ns, batch, hidden, precision)
-    (16, 5, 6, 8, 2, 16, "fp64"),      # widths below one column tile
-    (32, 7, 12, 16, 2, 80, "fp64"),    # D = 98, H = 80: ragged column and reduction tiles
-    (16, 3, 1, 4, 3, 8, "fp64"),       # one incidence per instance
-    (32, 9, 33, 16, 1, 64, "fp32"),    # 33 rows: the 16-rows-per-wave variant with a ragged last wave
-    (16, 5, 64, 64, 1, 32, "fp32"),    # largest incidence count
-    (64, 15, 32, 32, 2, 256, "fp32"),  # the benchmark shape (D = 450)
+    # (M, K, Ni, Ns, batch, hidden, precision, scaled): scaled = s_in 1 / rms(alpha_0), s_out 1 / H
+    (16, 5, 6, 8, 2, 16, "fp64", False),      # widths below one column tile
+    (32, 7, 12, 16, 2, 80, "fp64", True),     # D = 98, H = 80: ragged column and reduction tiles
+    (16, 3, 1, 4, 3, 8, "fp64", True),        # one incidence per instance
+    (32, 9, 33, 16, 1, 64, "fp32", False),    # 33 rows: the 16-rows-per-wave variant with a ragged last wave
+    (16, 5, 64, 64, 1, 32, "fp32", True),     # largest incidence count
+    (64, 15, 32, 32, 2, 256, "fp32", True),   # the benchmark shape (D = 450)
 ]
 
 
@@ -35,14 +35,15 @@ def _inputs(case, B, K, H, Ni, seed):
     return a0, theta
 
 
-@pytest.mark.parametrize("M,K,Ni,Ns,B,H,prec", CASES)
-def test_fcnn_steps_match_the_oracle(M, K, Ni, Ns, B, H, prec):
-    print(f"case fcnn M={M} K={K} Ni={Ni} Ns={Ns} B={B} H={H} {prec}", flush=True)
+@pytest.mark.parametrize("M,K,Ni,Ns,B,H,prec,scaled", CASES)
+def test_fcnn_steps_match_the_oracle(M, K, Ni, Ns, B, H, prec, scaled):
+    print(f"case fcnn M={M} K={K} Ni={Ni} Ns={Ns} B={B} H={H} {prec} scaled={scaled}", flush=True)
     case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
     s = solver_for(case, prec)
     P = s.fcnn_size(H)
     assert P == ofcnn.n_params(K, H)
     a0, theta = _inputs(case, B, K, H, Ni, seed=M + K + H)
+    s_in, s_out = (1.0 / float(np.sqrt(np.mean(np.abs(a0) ** 2))), 1.0 / H) if scaled else (1.0, 1.0)
     a0d = torch.tensor(a0, dtype=s.cdtype, device=DEV)
     th = torch.tensor(theta, dtype=s.rdtype, device=DEV)
     m = torch.zeros_like(th)
@@ -51,11 +52,12 @@ def test_fcnn_steps_match_the_oracle(M, K, Ni, Ns, B, H, prec):
     ref = [dict(theta=theta[b].copy(), m=np.zeros(P), v=np.zeros(P), th_err=0.0) for b in range(B)]
     n_steps = 3 if prec == "fp64" else 1
     for t in range(1, n_steps + 1):
-        ah = s.fcnn_step(H, a0d, th, m, v, t, loss=loss).cpu().numpy()
+        ah = s.fcnn_step(H, a0d, th, m, v, t, loss=loss, s_in=s_in, s_out=s_out).cpu().numpy()
         got_loss = loss.cpu().numpy()
         for b, c in enumerate(case["cases"]):
             r = ref[b]
-            th_n, m_n, v_n, ah_ref, out = ofcnn.step(r["theta"], r["m"], r["v"], t, a0[b], c["prob"], K, H)
+            th_n, m_n, v_n, ah_ref, out = ofcnn.step(r["theta"], r["m"], r["v"], t, a0[b], c["prob"], K, H,
+                                                     s_in=s_in, s_out=s_out)
             if prec == "fp64":
                 e_ah = _rel_max(ah[b], ah_ref)
                 assert e_ah < 1e-9, (t, b, e_ah)
@@ -99,15 +101,16 @@ def test_fcnn_step_with_adam_state_fp32():
     c = case["cases"][0]
     a0, theta = _inputs(case, B, K, H, Ni, seed=7)
     P = ofcnn.n_params(K, H)
+    sc = dict(s_in=1.0 / float(np.sqrt(np.mean(np.abs(a0) ** 2))), s_out=1.0 / H)
     th, m, v = theta[0].copy(), np.zeros(P), np.zeros(P)
     for t in (1, 2):
-        th, m, v, _, _ = ofcnn.step(th, m, v, t, a0[0], c["prob"], K, H)
-    th3, m3, v3, ah3, out3 = ofcnn.step(th, m, v, 3, a0[0], c["prob"], K, H)
+        th, m, v, _, _ = ofcnn.step(th, m, v, t, a0[0], c["prob"], K, H, **sc)
+    th3, m3, v3, ah3, out3 = ofcnn.step(th, m, v, 3, a0[0], c["prob"], K, H, **sc)
     s = solver_for(case, "fp32")
     td = torch.tensor(th[None], dtype=torch.float32, device=DEV)
     mdv = torch.tensor(m[None], dtype=torch.float32, device=DEV)
     vdv = torch.tensor(v[None], dtype=torch.float32, device=DEV)
-    ah = s.fcnn_step(H, torch.tensor(a0, dtype=s.cdtype, device=DEV), td, mdv, vdv, 3).cpu().numpy()[0]
+    ah = s.fcnn_step(H, torch.tensor(a0, dtype=s.cdtype, device=DEV), td, mdv, vdv, 3, **sc).cpu().numpy()[0]
     _, tg = term_tolerances(out3, "fp32", 1e-4)
     assert _rel_max(ah, ah3) < 1e-5
     assert _rel_max(mdv.cpu().numpy()[0], m3) < tg
@@ -129,10 +132,11 @@ def test_fcnn_forward_zero_output_layer_is_alpha0_and_full_size_forward():
     th0 = torch.tensor(si.fcnn_theta(3, 2, 15, H, out_scale=0.0), dtype=torch.float32, device=DEV)
     assert torch.equal(s.fcnn_forward(H, a0d, th0), a0d)
     theta = si.fcnn_theta(4, 2, 15, H, out_scale=1.0)
-    ah = s.fcnn_forward(H, a0d, torch.tensor(theta, dtype=torch.float32, device=DEV)).cpu().numpy()
-    for b in range(2):
-        ref = ofcnn.forward(theta[b], a0[b], 15, H)[0]
-        assert _rel_max(ah[b], ref) < 1e-5
+    for s_in, s_out in ((1.0, 1.0), (30.0, 1.0 / H)):
+        ah = s.fcnn_forward(H, a0d, torch.tensor(theta, dtype=torch.float32, device=DEV), s_in, s_out).cpu().numpy()
+        for b in range(2):
+            ref = ofcnn.forward(theta[b], a0[b], 15, H, s_in, s_out)[0]
+            assert _rel_max(ah[b] - a0[b], ref - a0[b]) < 1e-5
     s.close()
 
 
@@ -146,8 +150,10 @@ def test_fcnn_argument_checks():
     assert e.value.code == pdf.binding.PDF_EINVAL
     lib = pdf.binding.load()
     p = pdf.binding._ptr
-    assert lib.pdf_fcnn_forward(s.h, 8, p(a0), p(th), p(a0)) == pdf.binding.PDF_EINVAL   # alias
-    assert lib.pdf_fcnn_step(s.h, 8, p(a0), p(th), p(th), p(th), 0, p(torch.empty_like(a0)), None) \
-        == pdf.binding.PDF_EINVAL                                                         # t = 0
-    assert lib.pdf_fcnn_forward(s.h, 5000, p(a0), p(th), p(torch.empty_like(a0))) == pdf.binding.PDF_EINVAL
+    out = torch.empty_like(a0)
+    assert lib.pdf_fcnn_forward(s.h, 8, 1.0, 1.0, p(a0), p(th), p(a0)) == pdf.binding.PDF_EINVAL   # alias
+    assert lib.pdf_fcnn_step(s.h, 8, 1.0, 1.0, p(a0), p(th), p(th), p(th), 0, p(out), None) \
+        == pdf.binding.PDF_EINVAL                                                                  # t = 0
+    assert lib.pdf_fcnn_forward(s.h, 5000, 1.0, 1.0, p(a0), p(th), p(out)) == pdf.binding.PDF_EINVAL
+    assert lib.pdf_fcnn_forward(s.h, 8, float("nan"), 1.0, p(a0), p(th), p(out)) == pdf.binding.PDF_EINVAL
     s.close()

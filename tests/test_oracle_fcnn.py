@@ -16,11 +16,12 @@ def _alpha(Ni, K, scale, seed):
     return scale * (rng.standard_normal((Ni, K, K)) + 1j * rng.standard_normal((Ni, K, K)))
 
 
-def _torch_forward(theta_t, alpha0_t, K, H):
+def _torch_forward(theta_t, alpha0_t, K, H, s_in=1.0, s_out=1.0):
     """alpha_hat by torch ops, written from the layer description alone."""
     D = 2 * K * K
     off = 0
-    z = torch.cat([alpha0_t.reshape(alpha0_t.shape[0], -1).real, alpha0_t.reshape(alpha0_t.shape[0], -1).imag], 1)
+    x = alpha0_t.reshape(alpha0_t.shape[0], -1) * s_in
+    z = torch.cat([x.real, x.imag], 1)
     for li, (i, o) in enumerate([(D, H), (H, H), (H, D)]):
         blk = theta_t[off:off + (i + 1) * o].reshape(i + 1, o)
         off += (i + 1) * o
@@ -28,7 +29,7 @@ def _torch_forward(theta_t, alpha0_t, K, H):
         if li < 2:
             z = torch.tanh(z)
     q = K * K
-    return alpha0_t + torch.complex(z[:, :q], z[:, q:]).reshape(alpha0_t.shape)
+    return alpha0_t + s_out * torch.complex(z[:, :q], z[:, q:]).reshape(alpha0_t.shape)
 
 
 def test_backward_matches_central_differences_of_a_linear_functional():
@@ -38,10 +39,12 @@ def test_backward_matches_central_differences_of_a_linear_functional():
     rng = np.random.default_rng(5)
     c = rng.standard_normal((Ni, K, K)) + 1j * rng.standard_normal((Ni, K, K))
 
+    s_in, s_out = 3.0, 0.25
+
     def L(th):   # sum Re(conj(c) alpha_hat): its gradient dL/dRe + i dL/dIm is c
-        return float(np.sum(np.real(np.conj(c) * fcnn.forward(th, a0, K, H)[0])))
-    _, cache = fcnn.forward(theta, a0, K, H)
-    g = fcnn.backward(theta, cache, c, K, H)
+        return float(np.sum(np.real(np.conj(c) * fcnn.forward(th, a0, K, H, s_in, s_out)[0])))
+    _, cache = fcnn.forward(theta, a0, K, H, s_in, s_out)
+    g = fcnn.backward(theta, cache, c, K, H, s_out)
     assert g.shape == (fcnn.n_params(K, H),) == theta.shape
     h = 1e-6
     fd = np.empty_like(theta)
@@ -59,13 +62,14 @@ def test_forward_and_backward_match_torch_autograd():
     a0 = _alpha(Ni, K, 0.5, 3)
     rng = np.random.default_rng(6)
     c = rng.standard_normal((Ni, K, K)) + 1j * rng.standard_normal((Ni, K, K))
-    ah, cache = fcnn.forward(theta, a0, K, H)
-    tt = torch.tensor(theta, requires_grad=True)
-    aht = _torch_forward(tt, torch.tensor(a0), K, H)
-    assert np.max(np.abs(aht.detach().numpy() - ah)) < 1e-14
-    (aht.conj() * torch.tensor(c)).real.sum().backward()
-    g = fcnn.backward(theta, cache, c, K, H)
-    assert np.max(np.abs(tt.grad.numpy() - g)) < 1e-12 * np.max(np.abs(g))
+    for s_in, s_out in ((1.0, 1.0), (7.0, 1.0 / H)):
+        ah, cache = fcnn.forward(theta, a0, K, H, s_in, s_out)
+        tt = torch.tensor(theta, requires_grad=True)
+        aht = _torch_forward(tt, torch.tensor(a0), K, H, s_in, s_out)
+        assert np.max(np.abs(aht.detach().numpy() - ah)) < 1e-14
+        (aht.conj() * torch.tensor(c)).real.sum().backward()
+        g = fcnn.backward(theta, cache, c, K, H, s_out)
+        assert np.max(np.abs(tt.grad.numpy() - g)) < 1e-12 * np.max(np.abs(g))
 
 
 def test_composition_with_the_physics_loss_central_differences():
@@ -100,9 +104,9 @@ def test_three_adam_steps_match_torch_end_to_end():
     a0t = torch.tensor(a0)
     th = theta
     for t in range(1, 4):
-        th, m, v, ah, out = fcnn.step(th, m, v, t, a0, prob, K, H)
+        th, m, v, ah, out = fcnn.step(th, m, v, t, a0, prob, K, H, s_in=20.0, s_out=1.0 / H)
         opt.zero_grad()
-        L = _torch_loss(_torch_forward(tt, a0t, K, H), prob)
+        L = _torch_loss(_torch_forward(tt, a0t, K, H, 20.0, 1.0 / H), prob)
         assert abs(L.item() - out["L"]) < 1e-11 * out["L"]
         L.backward()
         opt.step()
