@@ -42,10 +42,10 @@ struct FcRows {
   __device__ __forceinline__ T at(int r, int c) const {
     if (cxv) {
       const int q = width >> 1;
-      const cx<T> z = cxv[size_t(r) * q + (c < q ? c : c - q)];
+      const cx<T> z = cxv[r * q + (c < q ? c : c - q)];
       return scale * (c < q ? z.x : z.y);
     }
-    return re[size_t(r) * width + c];
+    return re[r * width + c];
   }
 };
 
@@ -68,55 +68,49 @@ struct FcLayerArgs {
 };
 
 constexpr int kFcThreads = 256;
-constexpr int kFcStage = kFcMaxRows * kFcRed / kFcThreads;   // staged values per thread (each tile)
-
-// Stage rows [R][c0, c0 + kFcRed) of `in` (zeros past the width) into As:
-// every load is issued before the first LDS store, so a thread has all of
-// them in flight at once.
-template <typename T>
-__device__ __forceinline__ void fc_stage_rows(T* As, const FcRows<T>& in, int R, int c0, int width) {
-  T v[kFcStage];
-#pragma unroll
-  for (int i = 0; i < kFcStage; ++i) {
-    const int e = threadIdx.x + i * kFcThreads, r = e / kFcRed, c = c0 + e % kFcRed;
-    v[i] = (r < R && c < width) ? in.at(r, c) : T(0);
-  }
-#pragma unroll
-  for (int i = 0; i < kFcStage; ++i) {
-    const int e = threadIdx.x + i * kFcThreads;
-    if (e < R * kFcRed) As[e] = v[i];
-  }
-}
+constexpr int kFcWTile = kFcRed * kFcCols / kFcThreads;   // weight-tile values per thread
 
 // out[r][n] = sum_c A[r][c] W'(c, n) for the 64 columns n0.. of this workgroup,
 // with W'(c, n) = W[c][n] (forward, TRANS = false) or W[n][c] (input gradient).
+// The rows (at most 4 RPW) and the weight tile of reduction block c + 1 are
+// loaded into registers while block c is multiplied out of LDS.
 template <typename T, int RPW, bool TRANS>
 __device__ __forceinline__ void fc_gemm_tile(T* As, T* Ws, const FcRows<T>& in, const T* W, int R, int n_red,
                                              int ld_w, int n_cols, int n0, T (&acc)[RPW]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T wr[kFcWTile], ar[RPW];
+  auto load = [&](int c0) {
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) acc[i] = T(0);
-  for (int c0 = 0; c0 < n_red; c0 += kFcRed) {
-    T wv_[kFcRed * kFcCols / kFcThreads];
-#pragma unroll
-    for (int i = 0; i < kFcRed * kFcCols / kFcThreads; ++i) {
+    for (int i = 0; i < kFcWTile; ++i) {
       const int e = threadIdx.x + i * kFcThreads;
       if (!TRANS) {   // W[c][n]: consecutive threads along n
         const int c = c0 + e / kFcCols, n = n0 + e % kFcCols;
-        wv_[i] = (c < n_red && n < n_cols) ? W[size_t(c) * ld_w + n] : T(0);
+        wr[i] = (c < n_red && n < n_cols) ? W[c * ld_w + n] : T(0);
       } else {        // W[n][c]: consecutive threads along c
         const int n = n0 + e / kFcRed, c = c0 + e % kFcRed;
-        wv_[i] = (c < n_red && n < n_cols) ? W[size_t(n) * ld_w + c] : T(0);
+        wr[i] = (c < n_red && n < n_cols) ? W[n * ld_w + c] : T(0);
       }
     }
-    fc_stage_rows(As, in, R, c0, n_red);
 #pragma unroll
-    for (int i = 0; i < kFcRed * kFcCols / kFcThreads; ++i) {
-      const int e = threadIdx.x + i * kFcThreads;
-      if (!TRANS) Ws[(e / kFcCols) * (kFcCols + 1) + e % kFcCols] = wv_[i];
-      else Ws[(e % kFcRed) * (kFcCols + 1) + e / kFcRed] = wv_[i];   // transposed into Ws[c][n]
+    for (int i = 0; i < RPW; ++i) {
+      const int e = threadIdx.x + i * kFcThreads, r = e / kFcRed, c = c0 + e % kFcRed;
+      ar[i] = (r < R && c < n_red) ? in.at(r, c) : T(0);
     }
+  };
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) acc[i] = T(0);
+  load(0);
+  for (int c0 = 0; c0 < n_red; c0 += kFcRed) {
+#pragma unroll
+    for (int i = 0; i < kFcWTile; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
+      if (!TRANS) Ws[(e / kFcCols) * (kFcCols + 1) + e % kFcCols] = wr[i];
+      else Ws[(e % kFcRed) * (kFcCols + 1) + e / kFcRed] = wr[i];   // transposed into Ws[c][n]
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) As[threadIdx.x + i * kFcThreads] = ar[i];
     __syncthreads();
+    if (c0 + kFcRed < n_red) load(c0 + kFcRed);
     const T* arow = As + wv * RPW * kFcRed;
 #pragma unroll 4
     for (int cc = 0; cc < kFcRed; ++cc) {
