@@ -535,6 +535,8 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
     loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
     _, _, err0 = s.image(a0, eps_t)
     best = err0.clone()
+    targets = (0.40, 0.30)
+    first = {tg: torch.where(err0 <= tg, 0, -1) for tg in targets}   # first checked step at or below tg
     t = 0
     for _ in range(iters):
         t += 1
@@ -542,11 +544,23 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
         if t % 10 == 0:
             _, _, err = s.image(s.fcnn_forward(H, a0, theta, **sc), eps_t)
             best = torch.minimum(best, err)
+            for tg in targets:
+                first[tg] = torch.where((first[tg] < 0) & (err <= tg), t, first[tg])
     if not np.all(np.isfinite(loss.cpu().numpy()[:, 5])):
         raise RuntimeError("non-finite loss in the coefficient-network steps")
     direct = s.reconstruct(iters, n_check=10, eps_true=eps_t)
     best_d = direct["best_err"].cpu().numpy()
     best_n = best.cpu().numpy()
+    fixed = {}
+    for tg in targets:
+        fn = first[tg].cpu().numpy()
+        dr = s.reconstruct(iters, n_check=10, eps_true=eps_t,
+                           target=torch.full((B,), tg, dtype=torch.float64, device=dev))["reached"].cpu().numpy()
+        fixed[f"{tg:.2f}"] = dict(
+            network=dict(frac_reached=float(np.mean(fn >= 0)),
+                         mean_iters=float(fn[fn >= 0].mean()) if np.any(fn >= 0) else None),
+            direct=dict(frac_reached=float(np.mean(dr >= 0)),
+                        mean_iters=float(dr[dr >= 0].mean()) if np.any(dr >= 0) else None))
     # timed steps, continuing from the trained weights
     torch.cuda.synchronize()
     s.timing(True, steps)
@@ -573,6 +587,7 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
         mean_best_image_error=float(best_n.mean()), mean_best_image_error_direct=float(best_d.mean()),
         mean_start_image_error=float(err0.cpu().numpy().mean()),
         frac_better_than_direct=float(np.mean(best_n < best_d - 1e-6)),
+        fixed_error_targets=fixed, check_every=10,
         instance_iters_per_s=B * steps / dt, ms_per_step=step_ms, physics_kernels_ms=sum(phys_ms.values()),
         network_ms=net_ms, network_forward_ms=fwd_ms,
         network_roofline=dict(bound="hbm", algorithmic_bytes=net_bytes, algorithmic_flops=net_flops,
