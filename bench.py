@@ -247,8 +247,9 @@ def workload_cost(wl, B, ntiles):
     return bytes_, flops
 
 
-def synthesize_batch(pdf, si, wl, B, dev):
-    """Measured fields of B random instances: FP64 MoM on the fine grid with jittered antennas, plus noise."""
+def synthesize_batch(pdf, si, wl, B, dev, noise=None):
+    """Measured fields of B random instances: FP64 MoM on the fine grid with jittered antennas, plus
+    noise of relative level `noise` (default: the workload's)."""
     import numpy as np
     Ni, Ns, M = wl.n_tx, wl.n_rx, wl.M
     from concurrent.futures import ThreadPoolExecutor
@@ -270,7 +271,7 @@ def synthesize_batch(pdf, si, wl, B, dev):
     esca = np.zeros((B, Ni, Ns), np.complex128)
     for b in range(B):
         n1, n2 = si.draw_noise(b, e[b].shape)
-        esca[b] = si.add_noise(e[b], wl.noise, n1, n2)
+        esca[b] = si.add_noise(e[b], wl.noise if noise is None else noise, n1, n2)
     return esca, eps
 
 
@@ -317,6 +318,10 @@ def main():
     ap.add_argument("--fcnn-iters", type=int, default=300,
                     help="Adam steps of the coefficient-network leg (0: skip it)")
     ap.add_argument("--fcnn-hidden", type=int, default=256, help="hidden width of the coefficient network")
+    ap.add_argument("--positions", type=int, default=100,
+                    help="realisations per sigma of the antenna-position leg (0: skip it)")
+    ap.add_argument("--sweep-batch", type=int, default=32,
+                    help="instances per (beta, M_F, SNR) combination of the parameter-sweep leg (0: skip it)")
     ap.add_argument("--uneven", type=int, default=512,
                     help="instances of the uneven-shape batch leg (0: skip it)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
@@ -476,6 +481,12 @@ def main():
         extra["coefficient_network"] = fcnn_leg(pdf, si, wl, s, eps, args.fcnn_hidden, args.fcnn_iters,
                                                 args.steps, dev)
         log(f"coefficient network: {extra['coefficient_network']}")
+    if args.positions > 0:
+        extra["position_uncertainty"] = positions_leg(pdf, si, wl, args.positions, dev)
+        log(f"position uncertainty: {extra['position_uncertainty']}")
+    if args.sweep_batch > 0:
+        extra["parameter_sweep"] = sweep_leg(pdf, si, wl, args.sweep_batch, dev)
+        log(f"parameter sweep: {extra['parameter_sweep']}")
     if args.uneven > 0:
         extra["uneven_batch"] = uneven_leg(pdf, si, wl, args.uneven, 200, dev)
         log(f"uneven batch: {extra['uneven_batch']}")
@@ -518,6 +529,37 @@ def fcnn_cost(B, R, K, H):
     return dict(fwd=(fwd_b, fwd_f), bwd=(bwd_b, bwd_f), adam=(adam_b, adam_f)), P
 
 
+def network_errors(pdf, si, s, eps_t, H, iters, record_at=(), dev="cuda:0"):
+    """Coefficient-network reconstructions of every instance of s from its back-propagation start
+    (reading Z20 scales, output layer zero at the start): image error at the start, its minimum
+    over checks every 10 steps, the error after each step count in record_at, and the first
+    checked step at or below 0.40 and 0.30 (-1: never)."""
+    import torch
+    B, K = s.B, s.K
+    a0 = s.init_alpha()
+    sc = dict(s_in=1.0 / float(a0.abs().pow(2).mean().sqrt()), s_out=1.0 / H)
+    theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=s.rdtype, device=dev)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    ah = torch.empty_like(a0)
+    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
+    _, _, err0 = s.image(a0, eps_t)
+    best, at = err0.clone(), {}
+    targets = (0.40, 0.30)
+    first = {tg: torch.where(err0 <= tg, 0, -1) for tg in targets}
+    for t in range(1, iters + 1):
+        s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
+        if t % 10 == 0 or t in record_at:
+            _, _, err = s.image(s.fcnn_forward(H, a0, theta, **sc), eps_t)
+            if t in record_at:
+                at[t] = err
+            if t % 10 == 0:
+                best = torch.minimum(best, err)
+                for tg in targets:
+                    first[tg] = torch.where((first[tg] < 0) & (err <= tg), t, first[tg])
+    return dict(a0=a0, theta=theta, m=m, v=v, ah=ah, loss=loss, sc=sc, t=iters, err0=err0, best=best,
+                at=at, first=first)
+
+
 def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
     """The coefficient network (Sec. 3.1): Adam on per-instance network weights theta, the loss taken
     at alpha_hat = alpha_0 + f_theta(alpha_0), from the same back-propagation start as the direct
@@ -527,25 +569,9 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
     import torch
     B, K = s.B, s.K
     eps_t = torch.tensor(eps, dtype=s.cdtype, device=dev)
-    a0 = s.init_alpha()
-    sc = dict(s_in=1.0 / float(a0.abs().pow(2).mean().sqrt()), s_out=1.0 / H)
-    theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=torch.float32, device=dev)
-    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
-    ah = torch.empty_like(a0)
-    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
-    _, _, err0 = s.image(a0, eps_t)
-    best = err0.clone()
-    targets = (0.40, 0.30)
-    first = {tg: torch.where(err0 <= tg, 0, -1) for tg in targets}   # first checked step at or below tg
-    t = 0
-    for _ in range(iters):
-        t += 1
-        s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
-        if t % 10 == 0:
-            _, _, err = s.image(s.fcnn_forward(H, a0, theta, **sc), eps_t)
-            best = torch.minimum(best, err)
-            for tg in targets:
-                first[tg] = torch.where((first[tg] < 0) & (err <= tg), t, first[tg])
+    r = network_errors(pdf, si, s, eps_t, H, iters, dev=dev)
+    a0, theta, m, v, ah, loss, sc, t = (r[k] for k in ("a0", "theta", "m", "v", "ah", "loss", "sc", "t"))
+    err0, best, first, targets = r["err0"], r["best"], r["first"], (0.40, 0.30)
     if not np.all(np.isfinite(loss.cpu().numpy()[:, 5])):
         raise RuntimeError("non-finite loss in the coefficient-network steps")
     direct = s.reconstruct(iters, n_check=10, eps_true=eps_t)
@@ -597,6 +623,119 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
                                     "event-timed durations)"),
         start="back-propagation alpha_0; output layer zero, so alpha_hat = alpha_0 at step 1",
         weights="U[-1/sqrt(in), 1/sqrt(in)] hidden layers, seed 1")
+
+
+H_NET = 256   # hidden width of the coefficient network in the benchmark's legs
+
+
+def positions_leg(pdf, si, wl, n_real, dev):
+    """Antenna-position uncertainty (Sec. 4): one cfg2 profile measured with every Tx and Rx displaced
+    by N(0, sigma^2) in x and y, sigma in {1, 2, 3} mm, n_real realisations each, plus the exact
+    positions; all reconstructed with the nominal positions as one batch (direct Adam, 100
+    iterations, and the coefficient network, 100 steps).  Noise-free, so the spread of the image
+    error is the position errors' alone."""
+    import numpy as np
+    import torch
+    sigmas = (0.0, 1e-3, 2e-3, 3e-3)
+    shapes = si.draw_profile(wl, 0)
+    tx0 = si.antenna_positions(wl.n_tx, wl.radius)
+    rx0 = si.antenna_positions(wl.n_rx, wl.radius)
+    txs, rxs = [], []
+    for si_idx, sg in enumerate(sigmas):
+        for r in range(n_real if sg > 0 else 1):
+            dt, dr = si.draw_position_errors(1000 * si_idx + r, wl.n_tx, wl.n_rx, sg)
+            txs.append(tx0 + dt)
+            rxs.append(rx0 + dr)
+    B = len(txs)
+    epsf = si.rasterize(shapes, wl.M_fine, wl.side)
+    eps = si.rasterize(shapes, wl.M, wl.side)
+    t0 = time.time()
+    es = pdf.synthesize_batch(wl.M_fine, wl.side, wl.freq_hz, txs, rxs, np.repeat(epsf[None], B, 0), tol=1e-10,
+                              device=dev)
+    synth_s = time.time() - t0
+    s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx0, rx0, wl.K, batch=B, device=dev)
+    s.set_data(torch.tensor(es, dtype=s.cdtype, device=dev))
+    eps_t = torch.tensor(np.repeat(eps[None], B, 0), dtype=s.cdtype, device=dev)
+    res = s.reconstruct(100, n_check=100)
+    _, _, e_dir = s.image(res["alpha"], eps_t)
+    e_net = network_errors(pdf, si, s, eps_t, H_NET, 100, record_at=(100,), dev=dev)["at"][100]
+    e_dir, e_net = e_dir.cpu().numpy(), e_net.cpu().numpy()
+    out, i = {}, 0
+    for sg in sigmas:
+        n = n_real if sg > 0 else 1
+        out[f"sigma={sg * 1e3:g}mm"] = dict(
+            realisations=n,
+            direct=dict(mean=float(e_dir[i:i + n].mean()), std=float(e_dir[i:i + n].std())),
+            network=dict(mean=float(e_net[i:i + n].mean()), std=float(e_net[i:i + n].std())))
+        i += n
+    s.close()
+    return dict(instances=B, per_sigma=out, synthesis_seconds=synth_s,
+                recipe="cfg2 profile seed 0, FP64 MoM on 128x128 at displaced antennas, no noise; "
+                       "inversion with the nominal positions; image error after 100 iterations")
+
+
+def sweep_leg(pdf, si, wl, Bs, dev):
+    """The sensitivity study of Sec. 4.1-4.2.1 on synthetic cfg2 profiles: beta in {3, 6, 9} x M_F in
+    {6, 7, 9} (K = 2 M_F, the corner blocks) x SNR in {20, 10, 5} dB, each combination a handle of Bs
+    instances (the same profiles and noise draws throughout), all 27 in one shape class and so
+    advanced by one grouped launch per kernel.  Mean image error after k = 10, 30 and 100 Adam
+    iterations from each handle's back-propagation start, and the grouped rate against the same
+    handles run one after another; then the same combinations through the coefficient network."""
+    import numpy as np
+    import torch
+    betas, mfs, snrs, ks = (3.0, 6.0, 9.0), (6, 7, 9), (20.0, 10.0, 5.0), (10, 30, 100)
+    clean, eps = synthesize_batch(pdf, si, wl, Bs, dev, noise=0.0)
+    tx = si.antenna_positions(wl.n_tx, wl.radius)
+    rx = si.antenna_positions(wl.n_rx, wl.radius)
+    eps_t = None
+    sol, keys = [], []
+    for snr in snrs:
+        nu = 10.0 ** (-snr / 20.0)
+        es = np.stack([si.add_noise(clean[b], nu, *si.draw_noise(b, clean[b].shape)) for b in range(Bs)])
+        for beta in betas:
+            for mf in mfs:
+                p = pdf.default_params("fp32", beta=beta)
+                sv = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, 2 * mf, batch=Bs, params=p, device=dev)
+                sv.set_data(torch.tensor(es, dtype=sv.cdtype, device=dev))
+                if eps_t is None:
+                    eps_t = torch.tensor(eps, dtype=sv.cdtype, device=dev)
+                sol.append(sv)
+                keys.append((beta, mf, snr))
+    errs, timing = {}, {}
+    for k in ks:
+        got, info = pdf.reconstruct_multi(sol, k, n_check=k)
+        for (beta, mf, snr), sv, g in zip(keys, sol, got):
+            _, _, err = sv.image(g["alpha"], eps_t)
+            errs.setdefault(f"beta={beta:g} M_F={mf} SNR={snr:g}dB", {})[f"k={k}"] = float(err.mean())
+        timing[k] = info["seconds"]
+    t0 = time.perf_counter()
+    for sv in sol:
+        sv.reconstruct(ks[-1], n_check=ks[-1])
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    n_inst = len(sol) * Bs
+    best = min(errs, key=lambda c: errs[c][f"k={ks[-1]}"])
+    # the paper's solver is the coefficient network: the same combinations through it (handle by
+    # handle; the network has no grouped launch)
+    errs_net = {}
+    t0 = time.perf_counter()
+    for (beta, mf, snr), sv in zip(keys, sol):
+        r = network_errors(pdf, si, sv, eps_t, H_NET, ks[-1], record_at=ks, dev=dev)
+        errs_net[f"beta={beta:g} M_F={mf} SNR={snr:g}dB"] = {f"k={k}": float(r["at"][k].mean()) for k in ks}
+    torch.cuda.synchronize()
+    net_s = time.perf_counter() - t0
+    best_net = min(errs_net, key=lambda c: errs_net[c][f"k={ks[-1]}"])
+    for sv in sol:
+        sv.close()
+    return dict(handles=len(sol), instances=n_inst, batch_per_handle=Bs,
+                mean_image_error=errs, lowest_at_k100=best,
+                network_mean_image_error=errs_net, network_lowest_at_k100=best_net,
+                network_hidden=H_NET, network_seconds=net_s,
+                grouped_instance_iters_per_s=n_inst * ks[-1] / timing[ks[-1]],
+                sequential_instance_iters_per_s=n_inst * ks[-1] / seq,
+                speedup_over_sequential=seq / timing[ks[-1]],
+                recipe="cfg2 profiles seeds 0.., clean FP64 MoM with +-2 deg jitter, AWGN at the SNR "
+                       "(relative level 10^(-SNR/20)), same draws for every combination")
 
 
 def warm_start_leg(pdf, si, wl, s, eps_t, target, R, args, dev):

@@ -284,3 +284,10 @@ def fcnn_theta(seed: int, B: int, K: int, H: int, out_scale: float = 0.0) -> np.
             parts.append(rng.uniform(-s, s, size=(i + 1) * o))
         out[b] = np.concatenate(parts)
     return out
+
+
+def draw_position_errors(seed: int, n_tx: int, n_rx: int, sigma_m: float):
+    """Antenna position errors: independent N(0, sigma_m^2) offsets of x and y for every Tx
+    and Rx (metres), as [n][2] arrays."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x504F53])))
+    return rng.normal(0.0, sigma_m, size=(n_tx, 2)), rng.normal(0.0, sigma_m, size=(n_rx, 2))
