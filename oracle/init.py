@@ -10,6 +10,9 @@
    with the exact line-search step of that quadratic (the paper gives no step
    size):  g = grad L^CSI(0),  t* = (||g||^2/2) / (||A_d g||^2/S_d + ||A_s g||^2/S_s),
    alpha_0 = -t* g, where A_d = G_S F_T^* and A_s = [R_0 G_D - beta(I - R_0)] F_T^*.
+4. The full CSI start the paper sets aside for its cost: L^CSI is quadratic in
+   alpha for fixed R_0, so it is minimised by conjugate gradients (Fletcher-
+   Reeves directions, the exact step along each); one CG step is step 3.
 """
 from __future__ import annotations
 
@@ -93,3 +96,41 @@ def alpha0(prob: Problem):
     g = csi_gradient_at_zero(prob, R0)
     t = 0.5 * float(np.sum(np.abs(g) ** 2)) / csi_curvature(prob, R0, g)
     return -t * g, dict(chi0=chi0, R0=R0, g=g, t=t)
+
+
+def csi_gradient(prob: Problem, R0, alpha):
+    """grad L^CSI (dL/dRe + i dL/dIm) at alpha [F, Ni, K, K] with R fixed at R0: 2 A^H (A alpha - b)
+    written out through the adjoints of G_S, G_D and the synthesis."""
+    M, F, Ni, K = prob.M, prob.F, prob.Ni, prob.K
+    beta = prob.params.beta
+    g = []
+    for f in range(F):
+        J = fourier.synthesize(alpha[f], M)
+        E = prob.einc[f].reshape(Ni, M, M) + ops.gd_apply(J, prob.ghat[f]) + beta * J
+        g_s = 2.0 * (R0[None] * E - beta * J) / prob.S_s[f]
+        g_E = np.conj(R0)[None] * g_s
+        d = J.reshape(Ni, M * M) @ prob.gs[f].T - prob.esca[f]
+        hS = (d @ np.conj(prob.gs[f])).reshape(Ni, M, M)
+        g_J = -beta * g_s + beta * g_E + ops.gd_adjoint_apply(g_E, prob.ghat[f]) + 2.0 * hS / prob.S_d[f]
+        g.append(fourier.synth_adjoint(g_J, K))
+    return np.array(g)
+
+
+def csi_cg(prob: Problem, n_iter: int):
+    """alpha after n_iter conjugate-gradient steps on L^CSI from zero (R fixed at the
+    back-propagation R_0): direction p_1 = -g_1, p_k = -g_k + (||g_k||^2 / ||g_{k-1}||^2) p_{k-1},
+    step t_k = -Re<g_k, p_k> / (2 (||A_d p_k||^2 / S_d + ||A_s p_k||^2 / S_s)).  n_iter = 1 is
+    alpha0().  Returns alpha and the loss after every step."""
+    _, R0, _ = bp_contrast(prob)
+    alpha = np.zeros((prob.F, prob.Ni, prob.K, prob.K), np.complex128)
+    p, gn_old, losses = None, None, []
+    for k in range(n_iter):
+        g = csi_gradient(prob, R0, alpha)
+        gn = float(np.sum(np.abs(g) ** 2))
+        p = -g if k == 0 else -g + (gn / gn_old) * p
+        gn_old = gn
+        q = csi_curvature(prob, R0, p)
+        t = -float(np.sum(np.real(np.conj(g) * p))) / (2.0 * q) if q > 0 else 0.0
+        alpha = alpha + t * p
+        losses.append(csi_loss(prob, R0, alpha))
+    return alpha, dict(R0=R0, losses=losses)

@@ -133,3 +133,58 @@ def test_reconstruction_improves_on_the_start():
     start = cco.image_error(cco.cco(loss.evaluate(a0, prob, grad=False)["chi"]), et)
     assert res["loss"][-1] < res["loss"][0]
     assert res["err"] < start
+
+
+def test_csi_gradient_at_any_alpha_fd():
+    prob, _ = problem()
+    _, info = init.alpha0(prob)
+    R0 = info["R0"]
+    rng = np.random.default_rng(3)
+    a = 0.05 * (rng.standard_normal(info["g"].shape) + 1j * rng.standard_normal(info["g"].shape))
+    g = init.csi_gradient(prob, R0, a)
+    assert np.max(np.abs(init.csi_gradient(prob, R0, np.zeros_like(a)) - info["g"])) < 1e-13 * np.max(np.abs(g))
+    for _ in range(8):
+        idx = tuple(rng.integers(0, s) for s in a.shape)
+        for d in (1.0, 1j):
+            h = 1e-6
+            ap, am = a.copy(), a.copy()
+            ap[idx] += h * d
+            am[idx] -= h * d
+            fd = (init.csi_loss(prob, R0, ap) - init.csi_loss(prob, R0, am)) / (2 * h)
+            an = g[idx].real if d == 1.0 else g[idx].imag
+            assert abs(fd - an) < 1e-6 * np.max(np.abs(g))
+
+
+def test_csi_cg_reaches_the_least_squares_minimiser():
+    """On a tiny case (36 real unknowns) CG ends at the minimiser of the quadratic, found here
+    independently by numpy's least squares on the explicit real matrix of the affine map
+    alpha -> weighted residuals; one CG step is the one-step start; the loss never increases."""
+    tx = si.antenna_positions(2, WL.radius)
+    rx = si.antenna_positions(3, WL.radius)
+    es, _ = forward.mom_solve(si.rasterize(si.draw_profile(WL, 1), 16, WL.side), WL.side, K0, tx, rx)
+    prob = loss.build_problem(8, 3, WL.side, [WL.freq_hz], tx, rx, es)
+    _, R0, _ = init.bp_contrast(prob)
+    shape = (1, prob.Ni, 3, 3)
+    n = 2 * int(np.prod(shape))
+
+    def resid(alpha):   # weighted residual vector whose squared norm is L^CSI
+        M, beta = prob.M, prob.params.beta
+        J = fourier.synthesize(alpha[0], M)
+        D = J.reshape(prob.Ni, M * M) @ prob.gs[0].T - prob.esca[0]
+        s = R0[None] * (prob.einc[0].reshape(prob.Ni, M, M) + ops.gd_apply(J, prob.ghat[0]) + beta * J) - beta * J
+        r = np.concatenate([D.ravel() / np.sqrt(prob.S_d[0]), s.ravel() / np.sqrt(prob.S_s[0])])
+        return np.concatenate([r.real, r.imag])
+
+    def unflat(x):
+        return (x[:n // 2] + 1j * x[n // 2:]).reshape(shape)
+    b = resid(np.zeros(shape, np.complex128))
+    A = np.stack([resid(unflat(np.eye(n)[i])) - b for i in range(n)], axis=1)
+    x, *_ = np.linalg.lstsq(A, -b, rcond=None)
+    a_ls = unflat(x)
+    L_ls = init.csi_loss(prob, R0, a_ls)
+    a_cg, info = init.csi_cg(prob, 60)
+    assert abs(info["losses"][-1] - L_ls) < 1e-10 * L_ls
+    assert np.max(np.abs(a_cg - a_ls)) < 1e-6 * np.max(np.abs(a_ls))
+    assert all(l1 <= l0 * (1 + 1e-12) for l0, l1 in zip(info["losses"], info["losses"][1:]))
+    a1, _ = init.csi_cg(prob, 1)
+    assert np.max(np.abs(a1 - init.alpha0(prob)[0])) < 1e-14 * np.max(np.abs(a1))
