@@ -138,6 +138,16 @@ int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev,
  * step size.  alpha_dev: output [B][Ni][K][K]. */
 int pdf_init_alpha(pdf_handle* h, void* alpha_dev);
 
+/* The full CSI start (Sec. 3.1), which the paper sets aside for its cost:
+ * L^CSI (Eq. 12) with R fixed at the back-propagation R_0 is quadratic in
+ * alpha, and n_iter >= 1 conjugate-gradient steps from zero minimise it
+ * (directions p_1 = -g_1, p_k = -g_k + (|g_k|^2 / |g_{k-1}|^2) p_{k-1}, each
+ * with its exact step).  n_iter = 1 gives pdf_init_alpha's start.  Each
+ * further step costs about two loss evaluations.  alpha_dev: output
+ * [B][Ni][K][K].  The library keeps a workspace of B Ni K^2 complex values in
+ * the handle (allocated on the first call with n_iter > 1). */
+int pdf_init_alpha_csi(pdf_handle* h, int32_t n_iter, void* alpha_dev);
+
 /* Images at alpha: chi = R/(beta(1-R)) and the CCO image (Eqs. 10-11).
  *   chi_dev, chi_cco_dev: [B][M][M] complex outputs, either may be NULL.
  *   eps_true_dev: [B][M][M] complex relative permittivity, may be NULL.

@@ -61,6 +61,7 @@ SIGNATURES = {
     "pdf_loss_grad": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "pdf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_init_alpha": (c_i32, [c_vp, c_vp]),
+    "pdf_init_alpha_csi": (c_i32, [c_vp, c_i32, c_vp]),
     "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                 ctypes.POINTER(Report)]),
@@ -321,6 +322,12 @@ class Solver:
         self._call(load().pdf_fcnn_step, hidden, float(s_in), float(s_out), _ptr(alpha0), _ptr(theta), _ptr(m),
                    _ptr(v), int(t), _ptr(alpha_hat), _ptr(loss))
         return alpha_hat
+
+    def init_alpha_csi(self, n_iter: int):
+        """The full CSI start: n_iter conjugate-gradient steps on L^CSI (1 = init_alpha)."""
+        a = self.zeros_alpha()
+        self._call(load().pdf_init_alpha_csi, int(n_iter), _ptr(a))
+        return a
 
     def warm_start(self, net: "Mlp", s_in: float, s_out: float):
         """Start values: the network's prediction where its loss beats the back-propagation start.

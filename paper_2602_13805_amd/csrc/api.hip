@@ -714,6 +714,67 @@ static int run_init(pdf_handle* h, void* alpha_out) {
   return check_launch(h, "k_line_search");
 }
 
+// The full CSI start: n_iter conjugate-gradient steps on L^CSI from zero (the
+// first is run_init's exact steepest-descent step).  Per further step: the
+// gradient at alpha (forward with E_inc, the reduction with R_0 fixed, the
+// data residual, G_S^H, the adjoint without an R-gradient), the conjugate
+// direction, its curvature (forward without E_inc, reduction with R_0) and
+// the exact step.
+template <typename T>
+static int run_csi(pdf_handle* h, int n_iter, void* alpha_out) {
+  int rc;
+  if ((rc = run_init<T>(h, alpha_out))) return rc;
+  if (n_iter <= 1) return PDF_OK;
+  const size_t len = size_t(h->Ni) * h->K * h->K;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t need = al(sizeof(cx<T>) * h->B * len) + 2 * al(sizeof(double) * h->B);
+  if (h->csi_bytes < need) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->csi_ws) HIP_TRY(hipFree(h->csi_ws));
+    h->csi_ws = nullptr;
+    h->csi_bytes = 0;
+    HIP_TRY(hipMalloc(&h->csi_ws, need));
+    h->csi_bytes = need;
+  }
+  unsigned char* w = static_cast<unsigned char*>(h->csi_ws);
+  cx<T>* p = reinterpret_cast<cx<T>*>(w);
+  double* gprev = reinterpret_cast<double*>(w + al(sizeof(cx<T>) * h->B * len));
+  double* dot = gprev + al(sizeof(double) * h->B) / sizeof(double);
+  cx<T>* alpha = (cx<T>*)alpha_out;
+  const cx<T>* R0 = (const cx<T>*)h->R0;
+  const int NO = h->Ni * h->Ns;
+  hipLaunchKernelGGL(k_csi_dir<T>, dim3(h->B), dim3(256), 0, h->stream, (const cx<T>*)h->g0, p, h->gnorm, gprev, dot,
+                     len, 1);
+  if ((rc = check_launch(h, "k_csi_dir"))) return rc;
+  for (int k = 1; k < n_iter; ++k) {
+    FwdArgs<T> f = fwd_args<T>(h, alpha);
+    if ((rc = launch_fwd<T>(h, f, true))) return rc;
+    if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, R0))) return rc;
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, h->B), dim3(256), 0, h->stream,
+                       (const cx<T>*)h->Dpart, h->ntiles, (const cx<T>*)h->esca, (cx<T>*)h->dres, NO);
+    if ((rc = check_launch(h, "k_csi_residual"))) return rc;
+    if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
+    AdjArgs<T> a = adj_args<T>(h, h->g0, nullptr, nullptr, nullptr, nullptr);
+    a.R = R0;
+    a.den = nullptr;
+    a.gR = nullptr;
+    if ((rc = launch_adj<T>(h, a))) return rc;
+    hipLaunchKernelGGL(k_sumsq<T>, dim3(h->B), dim3(256), 0, h->stream, (const cx<T>*)h->g0, len, h->gnorm);
+    if ((rc = check_launch(h, "k_sumsq"))) return rc;
+    hipLaunchKernelGGL(k_csi_dir<T>, dim3(h->B), dim3(256), 0, h->stream, (const cx<T>*)h->g0, p, h->gnorm, gprev,
+                       dot, len, 0);
+    if ((rc = check_launch(h, "k_csi_dir"))) return rc;
+    f.in = p;
+    f.einc = nullptr;
+    if ((rc = launch_fwd<T>(h, f, true))) return rc;
+    if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, R0))) return rc;
+    hipLaunchKernelGGL(k_csi_step<T>, dim3(h->B), dim3(256), 0, h->stream, h->lsp, (const cx<T>*)h->Dpart,
+                       h->ntiles, h->Ni, h->Ns, dot, h->Ss, h->Sd, (const cx<T>*)p, alpha, h->K * h->K);
+    if ((rc = check_launch(h, "k_csi_step"))) return rc;
+  }
+  return PDF_OK;
+}
+
 // ------------------------------------------------------------------ setup
 
 template <typename T>
@@ -870,7 +931,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
-                  h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws};
+                  h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws, h->csi_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -977,6 +1038,13 @@ extern "C" int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev
   return h->prec == PDF_FP32
              ? run_iteration<float>(h, alpha_dev, nullptr, loss_dev, alpha_dev, m_dev, v_dev, t_dev, nullptr)
              : run_iteration<double>(h, alpha_dev, nullptr, loss_dev, alpha_dev, m_dev, v_dev, t_dev, nullptr);
+}
+
+extern "C" int pdf_init_alpha_csi(pdf_handle* h, int32_t n_iter, void* alpha_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (n_iter < 1) return fail(h, PDF_EINVAL, "n_iter must be at least 1");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  return h->prec == PDF_FP32 ? run_csi<float>(h, n_iter, alpha_dev) : run_csi<double>(h, n_iter, alpha_dev);
 }
 
 extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {

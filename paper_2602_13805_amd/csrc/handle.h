@@ -51,6 +51,9 @@ struct pdf_handle {
   // coefficient-network workspace (activations and gradients of one step), grown on demand
   void* fc_ws = nullptr;
   size_t fc_bytes = 0;
+  // full-CSI-start workspace (conjugate direction, two scalars per instance), grown on demand
+  void* csi_ws = nullptr;
+  size_t csi_bytes = 0;
   // tile shapes of the FP32 MFMA kernels (chosen by pdf_autotune; results do not depend on them)
   int tune_ct = 2;           // column tiles per wave of the G_S^H GEMM: 1, 2 or 4
   int tune_pb = 4;           // load batch of the pixel reduction: 4 or 8

@@ -152,4 +152,89 @@ __global__ void k_fill_zero(T* x, size_t n) {
   if (i < n) x[i] = T(0);
 }
 
+// ---- the full CSI start (Sec. 3.1): conjugate gradients on the quadratic L^CSI, R fixed at R_0
+
+// Data residual of L^CSI: dres = (sum of the split-K parts of G_S J) - E_sca.
+// Grid (ceil(Ni Ns / 256), B).
+template <typename T>
+__global__ __launch_bounds__(256) void k_csi_residual(const cx<T>* Dpart, int ntiles, const cx<T>* esca, cx<T>* dres,
+                                                      int NO) {
+  const int b = blockIdx.y, o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= NO) return;
+  double xr = 0.0, xi = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const cx<T> v = Dpart[(size_t(b) * ntiles + t) * NO + o];
+    xr += v.x;
+    xi += v.y;
+  }
+  const cx<T> e = esca[size_t(b) * NO + o];
+  dres[size_t(b) * NO + o] = cx<T>{T(xr - double(e.x)), T(xi - double(e.y))};
+}
+
+// Conjugate direction p = -g + (||g||^2 / ||g_prev||^2) p (p = -g when first), the
+// numerator -Re<g, p> of the exact step, and ||g||^2 kept for the next direction.
+// One block per instance.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csi_dir(const cx<T>* g, cx<T>* p, const double* gn, double* gn_prev,
+                                                 double* dot, size_t len, int first) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  const double fr = (first || !(gn_prev[b] > 0.0)) ? 0.0 : gn[b] / gn_prev[b];
+  const T f = T(fr);
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const size_t k = size_t(b) * len + i;
+    const cx<T> gv = g[k];
+    cx<T> pv = cx<T>{-gv.x, -gv.y};
+    if (!first) {
+      const cx<T> po = p[k];
+      pv = cx<T>{f * po.x - gv.x, f * po.y - gv.y};
+    }
+    p[k] = pv;
+    acc -= double(gv.x) * pv.x + double(gv.y) * pv.y;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    dot[b] = s;
+    gn_prev[b] = gn[b];
+  }
+}
+
+// Exact step along p: t = dot / (2 (||G_S J_p||^2 / S_d + ||R_0 E_p - beta J_p||^2 / S_s)),
+// alpha += t p.  One block per instance.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csi_step(const double* lsp, const cx<T>* Dpart, int ntiles, int Ni, int Ns,
+                                                  const double* dot, const double* Ss, const double* Sd,
+                                                  const cx<T>* p, cx<T>* alpha, int KK) {
+  __shared__ double red[16];
+  __shared__ double tstar;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int NO = Ni * Ns;
+  double dsum = 0.0;
+  for (int o = tid; o < NO; o += blockDim.x) {
+    double xr = 0, xi = 0;
+    for (int t = 0; t < ntiles; ++t) {
+      const cx<T> v = Dpart[(size_t(b) * ntiles + t) * NO + o];
+      xr += v.x;
+      xi += v.y;
+    }
+    dsum += xr * xr + xi * xi;
+  }
+  const double sd = block_sum(dsum, red);
+  if (tid == 0) {
+    double ss = 0.0;
+    for (int t = 0; t < ntiles; ++t) ss += lsp[size_t(b) * ntiles + t];
+    const double q = sd / Sd[b] + ss / Ss[0];
+    tstar = q > 0 ? 0.5 * dot[b] / q : 0.0;
+  }
+  __syncthreads();
+  const T t = T(tstar);
+  const size_t len = size_t(Ni) * KK;
+  for (size_t e = tid; e < len; e += blockDim.x) {
+    const size_t k = size_t(b) * len + e;
+    const cx<T> a = alpha[k], d = p[k];
+    alpha[k] = cx<T>{a.x + t * d.x, a.y + t * d.y};
+  }
+}
+
 }  // namespace pdfk

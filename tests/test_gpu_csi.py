@@ -1,0 +1,50 @@
+"""GPU parity of the full CSI start (Sec. 3.1): conjugate gradients on L^CSI with R fixed at the
+back-propagation R_0, against the FP64 oracle; one step is the one-step start bit for bit, and
+L^CSI falls with every step at the benchmark size."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import init as oinit
+from tests.common import make_case
+from tests.test_gpu_parity import DEV, solver_for
+
+pytestmark = pytest.mark.gpu
+
+pdf = pytest.importorskip("paper_2602_13805_amd")
+
+
+def _rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("M,K,Ni,Ns,B,prec,steps,tol", [
+    (16, 7, 6, 8, 2, "fp64", (1, 2, 5, 12), 1e-8),
+    (32, 14, 12, 20, 2, "fp64", (3,), 1e-8),      # corner blocks, ragged tiles
+    (32, 9, 16, 32, 2, "fp32", (1, 3), 2e-3),
+])
+def test_csi_start_matches_the_oracle(M, K, Ni, Ns, B, prec, steps, tol):
+    print(f"case csi M={M} K={K} Ni={Ni} Ns={Ns} B={B} {prec} steps={steps}", flush=True)
+    case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+    s = solver_for(case, prec)
+    for n in steps:
+        got = s.init_alpha_csi(n).cpu().numpy()
+        for b, c in enumerate(case["cases"]):
+            ref, _ = oinit.csi_cg(c["prob"], n)
+            e = _rel_max(got[b], ref[0])
+            assert e < tol, (n, b, e)
+    assert torch.equal(s.init_alpha_csi(1), s.init_alpha())
+    s.close()
+
+
+def test_csi_loss_falls_with_every_step_cfg2_size():
+    case = make_case(64, 15, 32, 32, seeds=(0,))
+    s = solver_for(case, "fp32")
+    prob = case["cases"][0]["prob"]
+    _, R0, _ = oinit.bp_contrast(prob)
+    losses = [oinit.csi_loss(prob, R0, s.init_alpha_csi(n).cpu().numpy().astype(np.complex128)) for n in (1, 2, 4, 8)]
+    print("csi losses", losses, flush=True)
+    assert all(l1 < l0 for l0, l1 in zip(losses, losses[1:]))
+    with pytest.raises(pdf.PdfError):
+        s.init_alpha_csi(0)
+    s.close()
