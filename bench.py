@@ -318,6 +318,7 @@ def main():
     ap.add_argument("--fcnn-iters", type=int, default=300,
                     help="Adam steps of the coefficient-network leg (0: skip it)")
     ap.add_argument("--fcnn-hidden", type=int, default=256, help="hidden width of the coefficient network")
+    ap.add_argument("--no-csi", dest="csi", action="store_false", help="skip the full-CSI-start leg")
     ap.add_argument("--positions", type=int, default=100,
                     help="realisations per sigma of the antenna-position leg (0: skip it)")
     ap.add_argument("--sweep-batch", type=int, default=32,
@@ -481,6 +482,9 @@ def main():
         extra["coefficient_network"] = fcnn_leg(pdf, si, wl, s, eps, args.fcnn_hidden, args.fcnn_iters,
                                                 args.steps, dev)
         log(f"coefficient network: {extra['coefficient_network']}")
+    if args.csi:
+        extra["csi_start"] = csi_leg(pdf, si, wl, s, eps, dev)
+        log(f"CSI start: {extra['csi_start']}")
     if args.positions > 0:
         extra["position_uncertainty"] = positions_leg(pdf, si, wl, args.positions, dev)
         log(f"position uncertainty: {extra['position_uncertainty']}")
@@ -529,14 +533,14 @@ def fcnn_cost(B, R, K, H):
     return dict(fwd=(fwd_b, fwd_f), bwd=(bwd_b, bwd_f), adam=(adam_b, adam_f)), P
 
 
-def network_errors(pdf, si, s, eps_t, H, iters, record_at=(), dev="cuda:0"):
+def network_errors(pdf, si, s, eps_t, H, iters, record_at=(), dev="cuda:0", a0=None):
     """Coefficient-network reconstructions of every instance of s from its back-propagation start
     (reading Z20 scales, output layer zero at the start): image error at the start, its minimum
     over checks every 10 steps, the error after each step count in record_at, and the first
     checked step at or below 0.40 and 0.30 (-1: never)."""
     import torch
     B, K = s.B, s.K
-    a0 = s.init_alpha()
+    a0 = s.init_alpha() if a0 is None else a0
     sc = dict(s_in=1.0 / float(a0.abs().pow(2).mean().sqrt()), s_out=1.0 / H)
     theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=s.rdtype, device=dev)
     m, v = torch.zeros_like(theta), torch.zeros_like(theta)
@@ -626,6 +630,32 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev):
 
 
 H_NET = 256   # hidden width of the coefficient network in the benchmark's legs
+
+
+def csi_leg(pdf, si, wl, s, eps, dev):
+    """The full CSI start (Sec. 3.1) against the one-step start on the benchmark batch: its time for
+    n conjugate-gradient steps, L^CSI-driven start image error, and the best image error of 100
+    direct Adam iterations and of 100 network steps from it."""
+    import numpy as np
+    import torch
+    eps_t = torch.tensor(eps, dtype=s.cdtype, device=dev)
+    out = {}
+    for n in (1, 5, 20):
+        s.init_alpha_csi(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = s.init_alpha_csi(n)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        _, _, e0 = s.image(a, eps_t)
+        d = s.reconstruct(100, n_check=10, alpha=a.clone(), eps_true=eps_t)
+        r = network_errors(pdf, si, s, eps_t, H_NET, 100, dev=dev, a0=a)
+        out[f"cg_steps={n}"] = dict(ms=ms, start_image_error=float(e0.mean()),
+                                    direct_best_100=float(d["best_err"].mean()),
+                                    network_best_100=float(r["best"].mean()))
+    return dict(batch=s.B, per_steps=out,
+                note="start = n CG steps on L^CSI with R fixed at the back-propagation R_0; n = 1 is the "
+                     "benchmark's start; best image error over checks every 10 iterations, start included")
 
 
 def positions_leg(pdf, si, wl, n_real, dev):
