@@ -1281,9 +1281,33 @@ static void fc_launch(pdf_handle* h, const FcLayerArgs<T>& a, int kind) {
   }
 }
 
-// kind 0: hidden forward layer, 1: output layer, 2: hidden pre-activation gradient
+template <int RT>
+static void fc_launch_mfma(pdf_handle* h, const FcLayerArgs<float>& a, int kind) {
+  const size_t lds = kFcMfmaLds;
+  if (kind == 0) {
+    set_lds(k_fc_fwd_mfma<RT, false>, lds);
+    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, false>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+                       h->stream, a);
+  } else if (kind == 1) {
+    set_lds(k_fc_fwd_mfma<RT, true>, lds);
+    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, true>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+                       h->stream, a);
+  } else {
+    set_lds(k_fc_bwd_mfma<RT>, lds);
+    hipLaunchKernelGGL((k_fc_bwd_mfma<RT>), dim3((a.n_in + kFcCols - 1) / kFcCols, h->B), dim3(256), lds, h->stream,
+                       a);
+  }
+}
+
+// kind 0: hidden forward layer, 1: output layer, 2: hidden pre-activation gradient.
+// FP32 runs on the matrix cores, FP64 on the vector units.
 template <typename T>
 static int fc_layer(pdf_handle* h, const FcLayerArgs<T>& a, int kind) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.R <= 32) fc_launch_mfma<1>(h, a, kind);
+    else fc_launch_mfma<2>(h, a, kind);
+    return check_launch(h, kind == 2 ? "k_fc_bwd_mfma" : "k_fc_fwd_mfma");
+  }
   const int rpw = (a.R + 3) / 4;
   if (rpw <= 1) fc_launch<T, 1>(h, a, kind);
   else if (rpw <= 2) fc_launch<T, 2>(h, a, kind);

@@ -181,6 +181,156 @@ __global__ void __launch_bounds__(256) k_fc_bwd(FcLayerArgs<T> a) {
   }
 }
 
+// ---- FP32 layer products on the matrix cores (v_mfma_f32_32x32x2f32)
+//
+// Same tiles and staging as above: rows (RT tiles of 32) x 64 output columns per
+// workgroup, reduction blocks of 64 staged through LDS (rows at a padded stride
+// of 65 floats, so the 32 lanes reading one reduction index hit 32 banks).  Wave
+// w multiplies column tile (w & 1) over half (w >> 1) of each block; the two
+// halves are summed through LDS at the end.  Operand layout of the 32x32x2
+// product: lane l supplies A[l mod 32][l / 32] and B[l / 32][l mod 32]; register
+// j of lane l holds D[(j & 3) + 8 (j >> 2) + 4 (l / 32)][l mod 32].
+typedef float fc_floatx16 __attribute__((ext_vector_type(16)));
+constexpr int kFcLdA = kFcRed + 1;
+constexpr size_t kFcMfmaLds = sizeof(float) * (size_t(kFcMaxRows) * kFcLdA + size_t(kFcRed) * (kFcCols + 1));
+
+template <int RT, bool TRANS>
+__device__ __forceinline__ void fc_gemm_tile_mfma(float* As, float* Ws, const FcRows<float>& in, const float* W, int R,
+                                                  int n_red, int ld_w, int n_cols, int n0, fc_floatx16 (&acc)[RT]) {
+  constexpr int NA = RT * 32 * kFcRed / kFcThreads;   // staged row values per thread
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ct = wv & 1, kh = wv >> 1, l32 = lane & 31, lhi = lane >> 5;
+  float wr[kFcWTile], ar[NA];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < kFcWTile; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
+      if (!TRANS) {
+        const int c = c0 + e / kFcCols, n = n0 + e % kFcCols;
+        wr[i] = (c < n_red && n < n_cols) ? W[c * ld_w + n] : 0.f;
+      } else {
+        const int n = n0 + e / kFcRed, c = c0 + e % kFcRed;
+        wr[i] = (c < n_red && n < n_cols) ? W[n * ld_w + c] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = threadIdx.x + i * kFcThreads, r = e / kFcRed, c = c0 + e % kFcRed;
+      ar[i] = (r < R && c < n_red) ? in.at(r, c) : 0.f;
+    }
+  };
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[t][j] = 0.f;
+  load(0);
+  for (int c0 = 0; c0 < n_red; c0 += kFcRed) {
+#pragma unroll
+    for (int i = 0; i < kFcWTile; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
+      if (!TRANS) Ws[(e / kFcCols) * (kFcCols + 1) + e % kFcCols] = wr[i];
+      else Ws[(e % kFcRed) * (kFcCols + 1) + e / kFcRed] = wr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = threadIdx.x + i * kFcThreads;
+      As[(e / kFcRed) * kFcLdA + e % kFcRed] = ar[i];
+    }
+    __syncthreads();
+    if (c0 + kFcRed < n_red) load(c0 + kFcRed);
+#pragma unroll
+    for (int kk = 0; kk < kFcRed / 4; ++kk) {
+      const int c = kh * (kFcRed / 2) + 2 * kk + lhi;
+      const float bv = Ws[c * (kFcCols + 1) + ct * 32 + l32];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(As[(t * 32 + l32) * kFcLdA + c], bv, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // the second half's partial tiles into the first half's waves (As reused: 2 x RT x 1024 floats)
+  float* red = As;
+  if (kh == 1)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) red[((ct * RT + t) * 16 + j) * 64 + lane] = acc[t][j];
+  __syncthreads();
+  if (kh == 0)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] += red[((ct * RT + t) * 16 + j) * 64 + lane];
+}
+
+// Row and column of register j of this lane in the workgroup's output block.
+__device__ __forceinline__ int fc_mfma_row(int t, int j) {
+  return t * 32 + (j & 3) + 8 * (j >> 2) + 4 * ((threadIdx.x & 63) >> 5);
+}
+__device__ __forceinline__ int fc_mfma_col(int n0) { return n0 + ((threadIdx.x >> 6) & 1) * 32 + (threadIdx.x & 31); }
+
+// Forward of one layer, FP32 on MFMA.  Grid (ceil(n_out / 64), B), 256 threads; R <= 32 RT.
+template <int RT, bool OUT>
+__global__ void __launch_bounds__(256) k_fc_fwd_mfma(FcLayerArgs<float> a) {
+  extern __shared__ unsigned char fc_smem[];
+  float* As = reinterpret_cast<float*>(fc_smem);
+  float* Ws = As + kFcMaxRows * kFcLdA;
+  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  FcRows<float> in = a.in;
+  if (in.cxv) in.cxv += size_t(b) * a.in_stride; else in.re += size_t(b) * a.in_stride;
+  const float* W = a.theta + size_t(b) * a.theta_stride;
+  fc_floatx16 acc[RT];
+  fc_gemm_tile_mfma<RT, false>(As, Ws, in, W, a.R, a.n_in, a.n_out, a.n_out, n0, acc);
+  if ((threadIdx.x >> 6) >= 2) return;
+  const int n = fc_mfma_col(n0);
+  if (n >= a.n_out) return;
+  const float bias = W[size_t(a.n_in) * a.n_out + n];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int r = fc_mfma_row(t, j);
+      if (r >= a.R) continue;
+      const float z = acc[t][j] + bias;
+      const size_t row = size_t(b) * a.R + r;
+      if (!OUT) {
+        a.act[row * a.n_out + n] = fc_tanh(z);
+      } else {
+        const int q = a.n_out >> 1, mode = n < q ? n : n - q, part = n < q ? 0 : 1;
+        const float* a0 = reinterpret_cast<const float*>(a.alpha0 + row * q + mode);
+        float* ah = reinterpret_cast<float*>(a.alpha_hat + row * q + mode);
+        ah[part] = a0[part] + a.out_scale * z;
+      }
+    }
+}
+
+// Pre-activation gradient of a hidden layer, FP32 on MFMA.  Grid (ceil(n_in / 64), B), 256 threads.
+template <int RT>
+__global__ void __launch_bounds__(256) k_fc_bwd_mfma(FcLayerArgs<float> a) {
+  extern __shared__ unsigned char fc_smem[];
+  float* As = reinterpret_cast<float*>(fc_smem);
+  float* Ws = As + kFcMaxRows * kFcLdA;
+  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  FcRows<float> g = a.in;
+  if (g.cxv) g.cxv += size_t(b) * a.in_stride; else g.re += size_t(b) * a.in_stride;
+  const float* W = a.theta + size_t(b) * a.theta_stride;
+  fc_floatx16 acc[RT];
+  fc_gemm_tile_mfma<RT, true>(As, Ws, g, W, a.R, a.n_out, a.n_out, a.n_in, n0, acc);
+  if ((threadIdx.x >> 6) >= 2) return;
+  const int n = fc_mfma_col(n0);
+  if (n >= a.n_in) return;
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int r = fc_mfma_row(t, j);
+      if (r >= a.R) continue;
+      const size_t idx = (size_t(b) * a.R + r) * a.n_in + n;
+      const float av = a.a_prev[idx];
+      a.gprev[idx] = acc[t][j] * (1.f - av * av);
+    }
+}
+
 template <typename T>
 struct FcAdamArgs {
   FcRows<T> in[3];        // layer inputs of reconstruction 0: X (split alpha_0), A1, A2
