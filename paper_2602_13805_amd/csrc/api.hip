@@ -1205,6 +1205,7 @@ struct FcNet {
   size_t P = 0, off[3] = {0, 0, 0};
   T *A1 = nullptr, *A2 = nullptr, *G1 = nullptr, *G2 = nullptr;
   cx<T>* g = nullptr;
+  T *X = nullptr, *G3 = nullptr, *Y = nullptr;   // real [Re | Im] rows (FP32 path): s_in alpha_0, s_out g, output
 };
 
 static size_t fc_params(int K, int H) {
@@ -1228,7 +1229,7 @@ static int fc_prepare(pdf_handle* h, int H, FcNet<T>* n) {
   const size_t rows = size_t(h->B) * n->R;
   const size_t hid = rows * H * sizeof(T), gb = rows * n->Q * sizeof(cx<T>);
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t need = 4 * al(hid) + al(gb);
+  const size_t need = 4 * al(hid) + 4 * al(gb);
   if (h->fc_bytes < need) {
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (h->fc_ws) HIP_TRY(hipFree(h->fc_ws));
@@ -1243,6 +1244,9 @@ static int fc_prepare(pdf_handle* h, int H, FcNet<T>* n) {
   n->G1 = reinterpret_cast<T*>(w + 2 * al(hid));
   n->G2 = reinterpret_cast<T*>(w + 3 * al(hid));
   n->g = reinterpret_cast<cx<T>*>(w + 4 * al(hid));
+  n->X = reinterpret_cast<T*>(w + 4 * al(hid) + al(gb));
+  n->G3 = reinterpret_cast<T*>(w + 4 * al(hid) + 2 * al(gb));
+  n->Y = reinterpret_cast<T*>(w + 4 * al(hid) + 3 * al(gb));
   return PDF_OK;
 }
 
@@ -1328,14 +1332,31 @@ static FcLayerArgs<T> fc_layer_args(const FcNet<T>& n, int l, const T* theta) {
   return a;
 }
 
-// alpha_hat = alpha_0 + s_out f_theta(s_in alpha_0); activations kept in the workspace.
+// [Re | Im] real rows of complex rows (FP32 path).
+template <typename T>
+static int fc_split_rows(pdf_handle* h, const FcNet<T>& n, const cx<T>* z, double scale, T* out) {
+  const size_t cnt = size_t(n.B) * n.R * n.Q;
+  hipLaunchKernelGGL(k_fc_split<T>, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, h->stream, z, T(scale), out,
+                     n.Q, cnt);
+  return check_launch(h, "k_fc_split");
+}
+
+// alpha_hat = alpha_0 + s_out f_theta(s_in alpha_0); activations kept in the workspace.  The
+// FP32 path takes the network's real rows from n.X and joins the output rows n.Y into alpha_hat.
 template <typename T>
 static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, const T* theta, cx<T>* alpha_hat,
                       double s_in, double s_out) {
   int rc;
+  constexpr bool F32 = sizeof(T) == 4;
   FcLayerArgs<T> a = fc_layer_args(n, 0, theta);
-  a.in = fc_split(alpha0, n.D, s_in);
-  a.in_stride = size_t(n.R) * n.Q;
+  if (F32) {
+    if ((rc = fc_split_rows<T>(h, n, alpha0, s_in, n.X))) return rc;
+    a.in = fc_real<T>(n.X, n.D);
+    a.in_stride = size_t(n.R) * n.D;
+  } else {
+    a.in = fc_split(alpha0, n.D, s_in);
+    a.in_stride = size_t(n.R) * n.Q;
+  }
   a.act = n.A1;
   if ((rc = fc_layer(h, a, 0))) return rc;
   a = fc_layer_args(n, 1, theta);
@@ -1349,7 +1370,13 @@ static int fc_forward(pdf_handle* h, const FcNet<T>& n, const cx<T>* alpha0, con
   a.alpha0 = alpha0;
   a.alpha_hat = alpha_hat;
   a.out_scale = T(s_out);
-  return fc_layer(h, a, 1);
+  a.act = n.Y;
+  if ((rc = fc_layer(h, a, 1))) return rc;
+  if (!F32) return PDF_OK;
+  const size_t cnt = size_t(n.B) * n.R * n.Q;
+  hipLaunchKernelGGL(k_fc_join<T>, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, h->stream, alpha0,
+                     (const T*)n.Y, T(s_out), alpha_hat, n.Q, cnt);
+  return check_launch(h, "k_fc_join");
 }
 
 template <typename T>
@@ -1360,10 +1387,17 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
   if ((rc = fc_prepare<T>(h, H, &n))) return rc;
   if ((rc = fc_forward<T>(h, n, alpha0, theta, alpha_hat, s_in, s_out))) return rc;
   if ((rc = run_iteration<T>(h, alpha_hat, n.g, loss, nullptr, nullptr, nullptr, nullptr, nullptr))) return rc;
-  // pre-activation gradients with the weights before the update
+  // pre-activation gradients with the weights before the update; dL/dY = s_out [Re g | Im g]
+  constexpr bool F32 = sizeof(T) == 4;
   FcLayerArgs<T> a = fc_layer_args(n, 2, theta);
-  a.in = fc_split<T>(n.g, n.D, s_out);   // dL/dY = s_out [Re g | Im g]
-  a.in_stride = size_t(n.R) * n.Q;
+  if (F32) {
+    if ((rc = fc_split_rows<T>(h, n, n.g, s_out, n.G3))) return rc;
+    a.in = fc_real<T>(n.G3, n.D);
+    a.in_stride = size_t(n.R) * n.D;
+  } else {
+    a.in = fc_split<T>(n.g, n.D, s_out);
+    a.in_stride = size_t(n.R) * n.Q;
+  }
   a.a_prev = n.A2;
   a.gprev = n.G2;
   if ((rc = fc_layer(h, a, 2))) return rc;
@@ -1374,16 +1408,16 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
   a.gprev = n.G1;
   if ((rc = fc_layer(h, a, 2))) return rc;
   FcAdamArgs<T> d{};
-  d.in[0] = fc_split(alpha0, n.D, s_in);
-  d.in_stride[0] = size_t(n.R) * n.Q;
+  d.in[0] = F32 ? fc_real<T>(n.X, n.D) : fc_split(alpha0, n.D, s_in);
+  d.in_stride[0] = size_t(n.R) * (F32 ? n.D : n.Q);
   d.in[1] = fc_real<T>(n.A1, n.H);
   d.in[2] = fc_real<T>(n.A2, n.H);
   d.in_stride[1] = d.in_stride[2] = size_t(n.R) * n.H;
   d.g[0] = fc_real<T>(n.G1, n.H);
   d.g[1] = fc_real<T>(n.G2, n.H);
   d.g_stride[0] = d.g_stride[1] = size_t(n.R) * n.H;
-  d.g[2] = fc_split<T>(n.g, n.D, s_out);
-  d.g_stride[2] = size_t(n.R) * n.Q;
+  d.g[2] = F32 ? fc_real<T>(n.G3, n.D) : fc_split<T>(n.g, n.D, s_out);
+  d.g_stride[2] = size_t(n.R) * (F32 ? n.D : n.Q);
   d.tile_start[0] = 0;
   for (int l = 0; l < 3; ++l) {
     d.n_in[l] = l == 0 ? n.D : n.H;

@@ -269,7 +269,8 @@ __device__ __forceinline__ int fc_mfma_row(int t, int j) {
 }
 __device__ __forceinline__ int fc_mfma_col(int n0) { return n0 + ((threadIdx.x >> 6) & 1) * 32 + (threadIdx.x & 31); }
 
-// Forward of one layer, FP32 on MFMA.  Grid (ceil(n_out / 64), B), 256 threads; R <= 32 RT.
+// Forward of one layer, FP32 on MFMA: tanh rows of a hidden layer, or the output layer's plain
+// rows (OUT).  Grid (ceil(n_out / 64), B), 256 threads; R <= 32 RT.
 template <int RT, bool OUT>
 __global__ void __launch_bounds__(256) k_fc_fwd_mfma(FcLayerArgs<float> a) {
   extern __shared__ unsigned char fc_smem[];
@@ -293,14 +294,7 @@ __global__ void __launch_bounds__(256) k_fc_fwd_mfma(FcLayerArgs<float> a) {
       if (r >= a.R) continue;
       const float z = acc[t][j] + bias;
       const size_t row = size_t(b) * a.R + r;
-      if (!OUT) {
-        a.act[row * a.n_out + n] = fc_tanh(z);
-      } else {
-        const int q = a.n_out >> 1, mode = n < q ? n : n - q, part = n < q ? 0 : 1;
-        const float* a0 = reinterpret_cast<const float*>(a.alpha0 + row * q + mode);
-        float* ah = reinterpret_cast<float*>(a.alpha_hat + row * q + mode);
-        ah[part] = a0[part] + a.out_scale * z;
-      }
+      a.act[row * a.n_out + n] = OUT ? z : fc_tanh(z);   // output rows: joined to alpha_hat by k_fc_join
     }
 }
 
@@ -329,6 +323,32 @@ __global__ void __launch_bounds__(256) k_fc_bwd_mfma(FcLayerArgs<float> a) {
       const float av = a.a_prev[idx];
       a.gprev[idx] = acc[t][j] * (1.f - av * av);
     }
+}
+
+// out[row] = scale [Re z[row][:], Im z[row][:]] for the rows of Q complex values (n = rows Q
+// in all): the network's real rows of alpha_0 and of g, written once so that the layer
+// kernels stage contiguous floats.  Grid ceil(n / 256).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fc_split(const cx<T>* z, T scale, T* out, int Q, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t row = i / Q, c = i % Q;
+  const cx<T> v = z[i];
+  out[row * 2 * Q + c] = scale * v.x;
+  out[row * 2 * Q + Q + c] = scale * v.y;
+}
+
+// alpha_hat[row] = alpha_0[row] + scale (y[row][:Q] + i y[row][Q:]) (n = rows Q values).
+// Grid ceil(n / 256).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fc_join(const cx<T>* alpha0, const T* y, T scale, cx<T>* alpha_hat, int Q,
+                                                 size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t row = i / Q, c = i % Q;
+  const cx<T> a = alpha0[i];
+  const T re = y[row * 2 * Q + c], im = y[row * 2 * Q + Q + c];
+  alpha_hat[i] = cx<T>{a.x + scale * re, a.y + scale * im};
 }
 
 template <typename T>
@@ -395,19 +415,10 @@ __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
   if (n >= n_out) return;
-  T acc[RW];
-#pragma unroll
-  for (int i = 0; i < RW; ++i) acc[i] = T(0);
-  for (int r = 0; r < R; ++r) {
-    const T gv = Gs[r * kFcCols + lane];
-    const T* irow = Is + r * kFcAdamRows + wv * RW;
-#pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] += irow[i] * gv;
-  }
   const size_t base = size_t(b) * a.theta_stride + a.off[l];
-  const T b1 = T(a.b1), b2 = T(a.b2), lr1 = T(a.lr1), ic2 = T(a.ic2), eps = T(a.eps);
-  // every row's theta, m, v loaded before the first store (the three arrays
-  // may not be proven disjoint, so loads after a store would wait for it)
+  // every row's theta, m, v requested before the gradient is formed (their HBM
+  // latency overlaps the LDS products) and before the first store (the three
+  // arrays may not be proven disjoint, so loads after a store would wait for it)
   T th[RW], mo[RW], ve[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
@@ -417,6 +428,16 @@ __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
     mo[i] = k <= n_in ? a.m[idx] : T(0);
     ve[i] = k <= n_in ? a.v[idx] : T(0);
   }
+  T acc[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) acc[i] = T(0);
+  for (int r = 0; r < R; ++r) {
+    const T gv = Gs[r * kFcCols + lane];
+    const T* irow = Is + r * kFcAdamRows + wv * RW;
+#pragma unroll
+    for (int i = 0; i < RW; ++i) acc[i] += irow[i] * gv;
+  }
+  const T b1 = T(a.b1), b2 = T(a.b2), lr1 = T(a.lr1), ic2 = T(a.ic2), eps = T(a.eps);
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
     const int k = k0 + wv * RW + i;
