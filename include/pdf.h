@@ -331,6 +331,8 @@ int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev);
  * Requires Ni <= 64 (PDF_EUNSUPPORTED otherwise) and 1 <= hidden <= 4096.
  * The library keeps a workspace of 4 B Ni H reals and B Ni K^2 complex
  * values in the handle (allocated on the first call, grown when needed). */
+/* n_params out: values per instance.  Errors (PDF_EINVAL) leave their message
+ * in pdf_last_error(NULL). */
 int pdf_fcnn_size(const pdf_handle* h, int32_t hidden, int64_t* n_params);
 
 /* alpha_hat_dev [B][Ni][K][K] out = alpha_0 + s_out f_theta(s_in alpha_0); alpha0_dev

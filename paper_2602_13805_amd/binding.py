@@ -293,7 +293,7 @@ class Solver:
     def fcnn_size(self, hidden: int) -> int:
         """Parameters per instance of the coefficient network with hidden width `hidden`."""
         n = ctypes.c_int64()
-        _check(load().pdf_fcnn_size(self.h, hidden, ctypes.byref(n)), self.h)
+        _check(load().pdf_fcnn_size(self.h, hidden, ctypes.byref(n)))   # message in pdf_last_error(NULL)
         return n.value
 
     def fcnn_forward(self, hidden: int, alpha0: torch.Tensor, theta: torch.Tensor, s_in: float = 1.0,

@@ -1441,7 +1441,8 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
 }
 
 extern "C" int pdf_fcnn_size(const pdf_handle* h, int32_t hidden, int64_t* n_params) {
-  if (!h || !n_params || hidden < 1 || hidden > 4096) return PDF_EINVAL;
+  if (!h || !n_params) return fail(nullptr, PDF_EINVAL, "pdf_fcnn_size: null argument");
+  if (hidden < 1 || hidden > 4096) return fail(nullptr, PDF_EINVAL, "pdf_fcnn_size: hidden width outside 1..4096");
   *n_params = int64_t(fc_params(h->K, hidden));
   return PDF_OK;
 }

@@ -22,6 +22,8 @@ CASES = [
     (32, 9, 33, 16, 1, 64, "fp32", False),    # 33 rows: the 16-rows-per-wave variant with a ragged last wave
     (16, 5, 64, 64, 1, 32, "fp32", True),     # largest incidence count
     (64, 15, 32, 32, 2, 256, "fp32", True),   # the benchmark shape (D = 450)
+    (32, 7, 12, 16, 2, 80, "fp32", True),     # ragged hidden width on the matrix-core path
+    (16, 5, 40, 24, 2, 48, "fp32", False),    # two 32-row MFMA tiles, the second ragged
 ]
 
 
