@@ -8,9 +8,12 @@
 //
 // The three products of a layer are skinny GEMMs with per-reconstruction
 // weights (N_i <= 64 rows): each weight is used by N_i rows only, so the
-// weight stream from HBM and the Adam state dominate; one workgroup computes
+// weight stream from HBM and the Adam state dominate.  One workgroup computes
 // all rows of 64 output columns, staging 64 reduction indices of the rows and
-// the matching weight tile through LDS, each wave owning a quarter of the rows.
+// the matching weight tile through LDS: in FP32 on the matrix cores (below,
+// k_fc_*_mfma), in FP64 on the vector units with each wave owning a quarter
+// of the rows (k_fc_fwd, k_fc_bwd).  The weight gradients and Adam are one
+// kernel over all layers (k_fc_adam).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,8 +59,9 @@ struct FcLayerArgs {
   const T* theta;        // parameters of reconstruction 0, this layer's block
   size_t theta_stride;   // parameters per reconstruction
   int R, n_in, n_out;    // rows, layer input and output widths
-  // forward epilogue: hidden (tanh) into act, or out_scale times the output rows added to
-  // alpha_0 into alpha_hat
+  // forward epilogue: hidden (tanh) rows into act; the output layer writes its plain rows
+  // into act (FP32, joined to alpha_hat by k_fc_join) or alpha_0 + out_scale times them
+  // into alpha_hat (FP64)
   T* act;                // [B][R][n_out] or null
   T out_scale;
   const cx<T>* alpha0;   // [B][R][Q] (output layer)
