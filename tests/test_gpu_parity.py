@@ -395,3 +395,43 @@ def test_error_paths_on_device():
         s.set_data(torch.zeros((1, 4, 6), dtype=s.cdtype, device=DEV))  # ||E_sca|| = 0
     assert e.value.code == -4
     s.close()
+
+
+def test_cfg2_batch_of_256_in_the_benchmark_configuration():
+    """The benchmark's launch configuration (cfg2, 256 instances, autotuned tiles and FFT plans):
+    loss terms, gradient and one Adam step of sampled instances against the oracle, one by one.
+    Measured fields and coefficients are seeded random draws (any field is a valid input of the
+    loss), so no input comes from the device."""
+    wl = si.WORKLOADS["cfg2"]
+    B, sample = 256, (0, 97, 181, 255)
+    print("case cfg2 B=256 autotuned, sampled instances", sample, flush=True)
+    tx, rx = geometry(wl.n_tx, wl.n_rx)
+    rng = np.random.default_rng(256)
+    es = 0.1 * (rng.standard_normal((B, wl.n_tx, wl.n_rx)) + 1j * rng.standard_normal((B, wl.n_tx, wl.n_rx)))
+    alpha = np.stack([rand_alpha((wl.n_tx, wl.K, wl.K), 0.02, 1000 + b) for b in range(B)])
+    s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx, rx, wl.K, batch=B, device=DEV)
+    s.set_data(torch.tensor(es, dtype=s.cdtype, device=DEV))
+    tiles, _ = s.autotune(3)
+    print("tiles", tiles, flush=True)
+    ad = torch.tensor(alpha, dtype=s.cdtype, device=DEV)
+    loss, g = s.loss_grad(ad)
+    loss, g = loss.cpu().numpy(), g.cpu().numpy()
+    m, v, t = s.new_state()
+    s.step(ad, m, v, t)
+    stepped = ad.cpu().numpy()
+    for b in sample:
+        prob = oloss.build_problem(wl.M, wl.K, wl.side, [wl.freq_hz], tx, rx, es[b])
+        ref = oloss.evaluate(alpha[b], prob)
+        want = oracle_terms(ref)
+        tt, tg = term_tolerances(ref, "fp32", 1e-4)
+        assert np.all(np.abs(loss[b, :6] - want) <= tt * np.abs(want) + 1e-7 * abs(want[5])), (b, loss[b], want)
+        check_grad(g[b], ref["g_alpha"], tg)
+        a1, _, _ = oadam.adam_step(alpha[b], ref["g_alpha"], np.zeros(alpha[b].shape + (2,)),
+                                   np.zeros(alpha[b].shape + (2,)), 1)
+        # first Adam step: lr sign(g) wherever |g| >> eps; near-zero gradients may take either sign
+        gmax = np.max(np.abs(ref["g_alpha"]))
+        for part in (np.real, np.imag):
+            strong = np.abs(part(ref["g_alpha"])) > 1e-2 * gmax
+            assert np.max(np.abs(part(stepped[b] - a1)[strong])) < 1e-6
+        assert np.max(np.abs(stepped[b] - a1)) <= 2 * np.sqrt(2) * 1e-2
+    s.close()
