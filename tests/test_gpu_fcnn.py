@@ -159,3 +159,35 @@ def test_fcnn_argument_checks():
     assert lib.pdf_fcnn_forward(s.h, 5000, 1.0, 1.0, p(a0), p(th), p(out)) == pdf.binding.PDF_EINVAL
     assert lib.pdf_fcnn_forward(s.h, 8, float("nan"), 1.0, p(a0), p(th), p(out)) == pdf.binding.PDF_EINVAL
     s.close()
+
+
+def test_fcnn_step_batch_of_256_sampled():
+    """The network leg's configuration (cfg2, 256 instances, H = 256, the benchmark's scales): one
+    step, alpha_hat, loss terms and weight gradient of sampled instances against the oracle."""
+    M, K, Ni, Ns, B, H = 64, 15, 32, 32, 256, 256
+    sample = (0, 128, 255)
+    print("case fcnn B=256 H=256 sampled", sample, flush=True)
+    case = make_case(M, K, Ni, Ns, seeds=(0,))
+    rng = np.random.default_rng(77)
+    es = 0.1 * (rng.standard_normal((B, Ni, Ns)) + 1j * rng.standard_normal((B, Ni, Ns)))
+    a0 = np.stack([rand_alpha((Ni, K, K), scale=0.02, seed=500 + b) for b in range(B)])
+    theta = si.fcnn_theta(9, B, K, H, out_scale=0.2)
+    s_in, s_out = 1.0 / float(np.sqrt(np.mean(np.abs(a0) ** 2))), 1.0 / H
+    s = pdf.Solver(M, case["wl"].side, case["wl"].freq_hz, case["tx"], case["rx"], K, batch=B, device=DEV)
+    s.set_data(torch.tensor(es, dtype=s.cdtype, device=DEV))
+    th = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    loss = torch.zeros((B, pdf.binding.LOSS_STRIDE), dtype=torch.float64, device=DEV)
+    ah = s.fcnn_step(H, torch.tensor(a0, dtype=s.cdtype, device=DEV), th, m, v, 1, loss=loss, s_in=s_in,
+                     s_out=s_out).cpu().numpy()
+    got_loss, md = loss.cpu().numpy(), m.cpu().numpy()
+    for b in sample:
+        prob = oloss.build_problem(M, K, case["wl"].side, [case["wl"].freq_hz], case["tx"], case["rx"], es[b])
+        _, m_n, _, ah_ref, out = ofcnn.step(theta[b], np.zeros(theta.shape[1]), np.zeros(theta.shape[1]), 1, a0[b],
+                                            prob, K, H, s_in=s_in, s_out=s_out)
+        tt, tg = term_tolerances(out, "fp32", 1e-4)
+        assert _rel_max(ah[b], ah_ref) < 1e-5, b
+        want = oracle_terms(out)
+        assert np.all(np.abs(got_loss[b, :6] - want) <= tt * np.abs(want) + 1e-7 * abs(want[5])), b
+        assert _rel_max(md[b], m_n) < tg, (b, _rel_max(md[b], m_n))
+    s.close()
