@@ -188,3 +188,12 @@ def test_csi_cg_reaches_the_least_squares_minimiser():
     assert all(l1 <= l0 * (1 + 1e-12) for l0, l1 in zip(info["losses"], info["losses"][1:]))
     a1, _ = init.csi_cg(prob, 1)
     assert np.max(np.abs(a1 - init.alpha0(prob)[0])) < 1e-14 * np.max(np.abs(a1))
+    # what defines CG: after k steps the loss is the minimum over the Krylov subspace
+    # span{g0, N g0, ..., N^(k-1) g0}, N = A^T A, g0 = A^T b (steepest descent misses it from k = 2)
+    N, g0 = A.T @ A, A.T @ b
+    for k in (2, 3, 5):
+        V = np.linalg.qr(np.stack([np.linalg.matrix_power(N, j) @ g0 for j in range(k)], axis=1))[0]
+        y, *_ = np.linalg.lstsq(A @ V, -b, rcond=None)
+        L_kry = float(np.sum((A @ (V @ y) + b) ** 2))
+        L_cg = init.csi_cg(prob, k)[1]["losses"][-1]
+        assert abs(L_cg - L_kry) < 1e-8 * L_kry, (k, L_cg, L_kry)
