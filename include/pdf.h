@@ -6,9 +6,11 @@
  * measurement geometry, the composite PDF loss (Sec. 3.2, Eqs. 13-19) of
  * truncated Fourier coefficients alpha of the induced currents (Sec. 2.3,
  * Eq. 9) and its gradient, applies Adam (Sec. 3.3), computes the
- * back-propagation start (Sec. 3.1), the CIE contrast and the
- * contrast-compensated image (Sec. 2.4, Eqs. 10-11), and synthesises
- * measured fields with an FP64 method-of-moments solve (Sec. 2.1, Eqs. 3-4).
+ * back-propagation start (Sec. 3.1) or the full CSI start, the CIE contrast
+ * and the contrast-compensated image (Sec. 2.4, Eqs. 10-11), runs the
+ * solver's coefficient network (Sec. 3.1, Fig. 4: Adam on network weights
+ * instead of on alpha), and synthesises measured fields with an FP64
+ * method-of-moments solve (Sec. 2.1, Eqs. 3-4).
  *
  * Conventions (all entry points)
  *   - Every function returns an int status: PDF_OK (0) or a negative code.
