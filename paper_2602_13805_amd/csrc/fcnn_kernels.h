@@ -244,6 +244,7 @@ __device__ __forceinline__ void fc_gemm_tile_mfma(float* As, float* Ws, const Fc
     if (c0 + kFcRed < n_red) load(c0 + kFcRed);
 #pragma unroll
     for (int kk = 0; kk < kFcRed / 4; ++kk) {
+      if (c0 + kh * (kFcRed / 2) + 2 * kk >= n_red) break;   // wave-uniform: only zero padding is left
       const int c = kh * (kFcRed / 2) + 2 * kk + lhi;
       const float bv = Ws[c * (kFcCols + 1) + ct * 32 + l32];
 #pragma unroll
