@@ -612,15 +612,19 @@ def fcnn_leg(pdf, si, wl, s, eps, H, iters, steps, dev, target=None):
                          mean_iters=float(fn[fn >= 0].mean()) if np.any(fn >= 0) else None),
             direct=dict(frac_reached=float(np.mean(dr >= 0)),
                         mean_iters=float(dr[dr >= 0].mean()) if np.any(dr >= 0) else None))
-    # timed steps, continuing from the trained weights
+    # timed steps, continuing from the trained weights, without instrumentation; then as many steps
+    # with HIP events between the physics kernels for their durations
     torch.cuda.synchronize()
-    s.timing(True, steps)
     t0 = time.perf_counter()
     for _ in range(steps):
         t += 1
         s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    s.timing(True, steps)
+    for _ in range(steps):
+        t += 1
+        s.fcnn_step(H, a0, theta, m, v, t, ah, loss, **sc)
     phys_ms, _ = s.timing_read()
     s.timing(False)
     t0 = time.perf_counter()
