@@ -161,12 +161,18 @@ __global__ void k_antenna_field(const double* axy, const cx<double>* ascale, int
   out[idx] = ascale[a] * v;
 }
 
+// Stream-ordered device buffers of one solve.  The destructor first waits
+// for the stream, so every copy still queued (on an early error return too)
+// has finished with its host source or destination before the host vectors
+// declared ahead of this object are destroyed, then releases the buffers.
 struct Dev {
   hipStream_t st;
   std::vector<void*> ptrs;
   explicit Dev(hipStream_t s) : st(s) {}
   ~Dev() {
+    (void)hipStreamSynchronize(st);
     for (void* p : ptrs) (void)hipFreeAsync(p, st);
+    (void)hipStreamSynchronize(st);
   }
   template <typename T>
   hipError_t alloc(T** p, size_t bytes) {
@@ -239,7 +245,13 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   // incident fields and receiver operator on the support only: on the device
   // from the shared Hankel samples, else on the host
   const bool dev_fields = sh.dtab != nullptr;
-  std::vector<cd> tscale(ni);
+  // every host array handed to an asynchronous copy is declared here, ahead of
+  // the device buffers (dv), so it outlives the stream synchronisation in dv's
+  // destructor on every return path
+  std::vector<cd> tscale(ni), rscale(ns, sh.cell);
+  std::vector<cd> mone(ni, -1.0), bnorm(ni), rho(ni), rho_old(ni, 1.0), alpha(ni, 1.0), omega(ni, 1.0), tmp(ni),
+      tmp2(ni), beta(ni), nalpha(ni), nomega(ni);
+  std::vector<cd> xh(jc ? size_t(ni) * nS : 0);
   for (int p = 0; p < ni; ++p)
     tscale[p] = 1.0 / std::abs(pdfh::hankel1(0, k0 * std::hypot(tx->xy[2 * p] - sh.gx, tx->xy[2 * p + 1] - sh.gy)));
   if (!dev_fields)
@@ -274,7 +286,6 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   if (dev_fields) {
     double *dpx, *dpy, *daxy;
     cx<double>* dsc;
-    const std::vector<cd> rscale(ns, sh.cell);
     MOM_TRY(dv.alloc(&dpx, sizeof(double) * nS));
     MOM_TRY(dv.alloc(&dpy, sizeof(double) * nS));
     MOM_TRY(dv.alloc(&daxy, sizeof(double) * 2 * (ni + ns)));
@@ -331,8 +342,6 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
     hipLaunchKernelGGL(k_zaxpy2, vgrid, dim3(256), 0, st, z, a, b, sc1, w, sc2, nS, ni);
     return hipGetLastError();
   };
-  std::vector<cd> mone(ni, -1.0), bnorm(ni), rho(ni), rho_old(ni, 1.0), alpha(ni, 1.0),
-      omega(ni, 1.0), tmp(ni), tmp2(ni), beta(ni), nalpha(ni), nomega(ni);
   std::vector<bool> conv(ni, false);
   // x0 = E_inc, r0 = b - A x0, r_hat = r0
   MOM_TRY(hipMemcpyAsync(x, db, vb, hipMemcpyDeviceToDevice, st));
@@ -393,11 +402,7 @@ int solve_one(const Shared& sh, const pdf_array* tx, const pdf_array* rx, const 
   hipLaunchKernelGGL(k_scatter_out, dim3(ni * ns), dim3(256), 0, st, dgs, dchi, x, dout, nS, ns);
   MOM_TRY(hipGetLastError());
   MOM_TRY(hipMemcpyAsync(out, dout, sizeof(cd) * ni * ns, hipMemcpyDeviceToHost, st));
-  std::vector<cd> xh;
-  if (jc) {
-    xh.resize(size_t(ni) * nS);
-    MOM_TRY(hipMemcpyAsync(xh.data(), x, vb, hipMemcpyDeviceToHost, st));
-  }
+  if (jc) MOM_TRY(hipMemcpyAsync(xh.data(), x, vb, hipMemcpyDeviceToHost, st));
   MOM_TRY(hipStreamSynchronize(st));
   if (jc) {
     // induced current chi E per fine pixel, averaged over each d x d block
@@ -455,7 +460,9 @@ int make_shared(const pdf_grid* grid, double freq_hz, int n, const pdf_array* tx
       }
     });
     MOM_TRY(hipMalloc(reinterpret_cast<void**>(dtab), sizeof(cx<double>) * tab.size()));
+    // waited for here: tab is released at the end of this block
     MOM_TRY(hipMemcpyAsync(*dtab, tab.data(), sizeof(cd) * tab.size(), hipMemcpyHostToDevice, st));
+    MOM_TRY(hipStreamSynchronize(st));
     sh->dtab = *dtab;
   }
   MOM_TRY(hipStreamSynchronize(st));
