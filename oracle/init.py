@@ -22,27 +22,43 @@ from . import fourier, operators as ops
 from .loss import Problem
 
 
-def bp_contrast(prob: Problem):
-    """chi_0 and R_0 of the back-propagation start."""
+def bp_currents(prob: Problem):
+    """Back-propagation currents J_p = gamma_p G_S^H e_p, [F, Ni, M, M]."""
     M, F, Ni = prob.M, prob.F, prob.Ni
-    beta = prob.params.beta
-    w = 1.0 / prob.S_s
-    num = np.zeros((M, M), np.complex128)
-    den = np.zeros((M, M))
     Jbp = []
     for f in range(F):
         e = prob.esca[f]                                   # [Ni, Ns]
         u = e @ np.conj(prob.gs[f])                        # u_p = G_S^H e_p  [Ni, N]
         v = u @ prob.gs[f].T                               # v_p = G_S u_p    [Ni, Ns]
         gamma = np.sum(np.conj(v) * e, axis=1) / np.sum(np.abs(v) ** 2, axis=1)
-        J = (gamma[:, None] * u).reshape(Ni, M, M)
-        E = prob.einc[f].reshape(Ni, M, M) + ops.gd_apply(J, prob.ghat[f])
-        num += w[f] * np.sum(J * np.conj(E), axis=0)
+        Jbp.append((gamma[:, None] * u).reshape(Ni, M, M))
+    return np.array(Jbp)
+
+
+def ls_contrast(prob: Problem, J):
+    """Contrast of currents J [F, Ni, M, M]: the fields E_p = E_inc_p + G_D J_p of the state
+    equation (Eq. 3), the per-pixel least-squares contrast of J_p = chi E_p over all incidences
+    (frequencies weighted by 1 / ||E_inc,f||^2), chi_0 = sum J conj(E) / sum |E|^2, and
+    R_0 = beta chi_0 / (beta chi_0 + 1) (Eq. 7)."""
+    M, F, Ni = prob.M, prob.F, prob.Ni
+    beta = prob.params.beta
+    w = 1.0 / prob.S_s
+    num = np.zeros((M, M), np.complex128)
+    den = np.zeros((M, M))
+    for f in range(F):
+        E = prob.einc[f].reshape(Ni, M, M) + ops.gd_apply(J[f], prob.ghat[f])
+        num += w[f] * np.sum(J[f] * np.conj(E), axis=0)
         den += w[f] * np.sum(np.abs(E) ** 2, axis=0)
-        Jbp.append(J)
     chi0 = num / den
     R0 = beta * chi0 / (beta * chi0 + 1.0)
-    return chi0, R0, np.array(Jbp)
+    return chi0, R0
+
+
+def bp_contrast(prob: Problem):
+    """chi_0, R_0 and the currents of the back-propagation start."""
+    Jbp = bp_currents(prob)
+    chi0, R0 = ls_contrast(prob, Jbp)
+    return chi0, R0, Jbp
 
 
 def csi_gradient_at_zero(prob: Problem, R0):

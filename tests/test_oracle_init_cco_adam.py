@@ -36,6 +36,46 @@ def test_bp_scalar_is_least_squares():
             assert np.linalg.norm(g * v - e) >= f0 - 1e-15
 
 
+def test_ls_contrast_recovers_a_known_contrast():
+    # currents J = chi E_tot of a lossy profile solved on the inversion grid itself: E_inc + G_D J
+    # is then E_tot (the state equation, Eq. 3), and the per-pixel least squares over the
+    # incidences must return chi exactly (a complex chi, so a conjugate on the wrong factor fails)
+    M = 16
+    prob, shapes = problem(M=M, K=7, seed=3)
+    eps = 1.0 + (si.rasterize(shapes, M, WL.side) - 1.0) * (1.0 + 0.4j)
+    tx = si.antenna_positions(6, WL.radius)
+    rx = si.antenna_positions(8, WL.radius)
+    _, etot = forward.mom_solve(eps, WL.side, K0, tx, rx)
+    chi = (eps - 1.0).reshape(-1)
+    J = (chi[None, :] * etot).reshape(1, 6, M, M)
+    chi0, R0 = init.ls_contrast(prob, J)
+    support = np.abs(chi) > 0
+    assert support.sum() > 10
+    assert np.max(np.abs(chi0.reshape(-1) - chi)) < 1e-9 * np.max(np.abs(chi))
+    beta = prob.params.beta
+    assert np.max(np.abs(R0 - beta * chi0 / (beta * chi0 + 1.0))) < 1e-15
+    # Eq. 6-7: R_0 is the contraction of the CIE, beta J = R (E + beta J) pixel by pixel
+    Ecie = etot.reshape(1, 6, M, M) + beta * J
+    assert np.max(np.abs(beta * J - R0[None, None] * Ecie)) < 1e-9 * np.max(np.abs(beta * J))
+
+
+def test_bp_currents_are_the_best_scaled_back_projection():
+    prob, _ = problem(seed=1)
+    J = init.bp_currents(prob)[0]
+    for p in range(prob.Ni):
+        e = prob.esca[0][p]
+        u = (np.conj(prob.gs[0]).T @ e)
+        j = J[p].reshape(-1)
+        # parallel to G_S^H e_p
+        assert abs(abs(np.vdot(u, j)) - np.linalg.norm(u) * np.linalg.norm(j)) < 1e-12 * np.linalg.norm(u) * \
+            np.linalg.norm(j)
+        # and the scale that fits the data best (scan of complex factors)
+        f0 = np.linalg.norm(prob.gs[0] @ j - e)
+        for dr in np.linspace(-0.3, 0.3, 7):
+            for di in np.linspace(-0.3, 0.3, 7):
+                assert np.linalg.norm(prob.gs[0] @ (j * (1 + dr + 1j * di)) - e) >= f0 - 1e-14
+
+
 def test_alpha0_is_exact_line_search_of_csi():
     prob, _ = problem()
     a0, info = init.alpha0(prob)
