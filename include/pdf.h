@@ -135,6 +135,27 @@ int pdf_loss_grad(pdf_handle* h, const void* alpha_dev, void* grad_dev, double* 
 int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev,
              int32_t* t_dev, double* loss_dev);
 
+/* Size of the library's static device scratch (one copy per device, held from
+ * the first pdf_setup on that device until the process ends). */
+#define PDF_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* pdf_init_alpha_csi for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation with the same kernels and bitwise the same
+ * result, but its conjugate-gradient workspace (B Ni K^2 complex values plus
+ * two doubles per instance, each part rounded up to 256 bytes) lives in the
+ * library's static scratch instead of a buffer the handle allocates.  The call
+ * allocates and frees nothing.
+ *   Errors: PDF_EINVAL if n_iter > 1 and the workspace exceeds
+ *   PDF_STATIC_SCRATCH_BYTES (e.g. FP32, B = 256, Ni = 32, K = 15 needs
+ *   14.75 MB and fits); PDF_EHIP if the scratch's address could not be found
+ *   on the handle's device at pdf_setup.
+ * Every call on one device shares that device's scratch and leaves its
+ * contents behind (nothing in it needs to start at zero: each value is
+ * written before it is read within a call), so calls that overlap on one
+ * device race: run them on one stream, or order their streams. */
+int pdf_init_alpha_csi_noalloc(pdf_handle* h, int32_t n_iter, void* alpha_dev);
+
 /* Start value alpha_0 (Sec. 3.1): back-propagation image, R_0 by Eq. 7, and
  * one gradient step on L^CSI (Eq. 12) from zero with the exact line-search
  * step size.  alpha_dev: output [B][Ni][K][K]. */

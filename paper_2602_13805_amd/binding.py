@@ -62,6 +62,7 @@ SIGNATURES = {
     "pdf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_init_alpha": (c_i32, [c_vp, c_vp]),
     "pdf_init_alpha_csi": (c_i32, [c_vp, c_i32, c_vp]),
+    "pdf_init_alpha_csi_noalloc": (c_i32, [c_vp, c_i32, c_vp]),
     "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                 ctypes.POINTER(Report)]),
@@ -328,6 +329,13 @@ class Solver:
         a = self.zeros_alpha()
         self._call(load().pdf_init_alpha_csi, int(n_iter), _ptr(a))
         return a
+
+    def init_alpha_csi_noalloc(self, n_iter: int, out: torch.Tensor):
+        """init_alpha_csi into the caller's tensor `out`, with the library's static scratch as
+        its workspace (the call allocates no device memory)."""
+        self._want(out, self.alpha_shape, self.cdtype, "out", inplace=True)
+        self._call(load().pdf_init_alpha_csi_noalloc, int(n_iter), _ptr(out))
+        return out
 
     def warm_start(self, net: "Mlp", s_in: float, s_out: float):
         """Start values: the network's prediction where its loss beats the back-propagation start.

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -22,6 +23,34 @@
 using namespace pdfk;
 
 static thread_local std::string g_last_error = "no error";
+
+// Device memory for entry points that allocate nothing (pdf_init_alpha_csi_noalloc).
+// Each device holds its own copy of this array from the first use of the
+// library until the process ends.  In host code its name is not a device
+// address: kernels receive the address that hipGetSymbolAddress returns for
+// the current device (scratch_address), never the name itself.
+static __device__ __align__(256) unsigned char scratch[PDF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Address of `scratch` on the current device (looked up once per device).
+static hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 #define HIP_TRY(call)                                                              \
   do {                                                                             \
@@ -720,23 +749,25 @@ static int run_init(pdf_handle* h, void* alpha_out) {
 // data residual, G_S^H, the adjoint without an R-gradient), the conjugate
 // direction, its curvature (forward without E_inc, reduction with R_0) and
 // the exact step.
+static size_t csi_align(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of the conjugate-gradient workspace: the direction [B][Ni][K][K] and two
+// doubles per instance.  Every value in it is written before it is read within
+// one call, so it needs no clearing.
+static size_t csi_workspace_bytes(const pdf_handle* h) {
+  const size_t csz = h->prec == PDF_FP32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  return csi_align(csz * h->B * size_t(h->Ni) * h->K * h->K) + 2 * csi_align(sizeof(double) * h->B);
+}
+
+// ws: device workspace of csi_workspace_bytes(h) bytes (unused when n_iter == 1).
 template <typename T>
-static int run_csi(pdf_handle* h, int n_iter, void* alpha_out) {
+static int run_csi(pdf_handle* h, int n_iter, void* alpha_out, void* ws) {
   int rc;
   if ((rc = run_init<T>(h, alpha_out))) return rc;
   if (n_iter <= 1) return PDF_OK;
   const size_t len = size_t(h->Ni) * h->K * h->K;
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t need = al(sizeof(cx<T>) * h->B * len) + 2 * al(sizeof(double) * h->B);
-  if (h->csi_bytes < need) {
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    if (h->csi_ws) HIP_TRY(hipFree(h->csi_ws));
-    h->csi_ws = nullptr;
-    h->csi_bytes = 0;
-    HIP_TRY(hipMalloc(&h->csi_ws, need));
-    h->csi_bytes = need;
-  }
-  unsigned char* w = static_cast<unsigned char*>(h->csi_ws);
+  auto al = csi_align;
+  unsigned char* w = static_cast<unsigned char*>(ws);
   cx<T>* p = reinterpret_cast<cx<T>*>(w);
   double* gprev = reinterpret_cast<double*>(w + al(sizeof(cx<T>) * h->B * len));
   double* dot = gprev + al(sizeof(double) * h->B) / sizeof(double);
@@ -969,6 +1000,15 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   h->Ns = rx->n;
   h->B = batch;
   h->stream = (hipStream_t)stream;
+  // the handle's device and its copy of the static scratch (looked up here, at
+  // set-up, with that device current; a failure only disables the entry
+  // points that use it, which then report it)
+  if (hipGetDevice(&h->device) == hipSuccess) {
+    const hipError_t se = scratch_address(h->device, &h->scratch_dev);
+    if (se != hipSuccess) h->scratch_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(se);
+  } else {
+    h->scratch_err = "hipGetDevice failed";
+  }
   const size_t csz = prm.precision == PDF_FP32 ? 8 : 16;
   int tile = 256;
   if (prm.precision == PDF_FP32 && h->Ni > 64) {
@@ -1044,7 +1084,32 @@ extern "C" int pdf_init_alpha_csi(pdf_handle* h, int32_t n_iter, void* alpha_dev
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
   if (n_iter < 1) return fail(h, PDF_EINVAL, "n_iter must be at least 1");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
-  return h->prec == PDF_FP32 ? run_csi<float>(h, n_iter, alpha_dev) : run_csi<double>(h, n_iter, alpha_dev);
+  const size_t need = csi_workspace_bytes(h);
+  if (n_iter > 1 && h->csi_bytes < need) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->csi_ws) HIP_TRY(hipFree(h->csi_ws));
+    h->csi_ws = nullptr;
+    h->csi_bytes = 0;
+    HIP_TRY(hipMalloc(&h->csi_ws, need));
+    h->csi_bytes = need;
+  }
+  return h->prec == PDF_FP32 ? run_csi<float>(h, n_iter, alpha_dev, h->csi_ws)
+                             : run_csi<double>(h, n_iter, alpha_dev, h->csi_ws);
+}
+
+extern "C" int pdf_init_alpha_csi_noalloc(pdf_handle* h, int32_t n_iter, void* alpha_dev) {
+  if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (n_iter < 1) return fail(h, PDF_EINVAL, "n_iter must be at least 1");
+  if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  const size_t need = csi_workspace_bytes(h);
+  if (n_iter > 1 && need > PDF_STATIC_SCRATCH_BYTES)
+    return fail(h, PDF_EINVAL,
+                "the CSI workspace needs " + std::to_string(need) + " bytes; the static scratch holds " +
+                    std::to_string(size_t(PDF_STATIC_SCRATCH_BYTES)) + " (B Ni K^2 too large)");
+  if (!h->scratch_dev)
+    return fail(h, PDF_EHIP, "the static scratch of this device has no address: " + h->scratch_err);
+  return h->prec == PDF_FP32 ? run_csi<float>(h, n_iter, alpha_dev, h->scratch_dev)
+                             : run_csi<double>(h, n_iter, alpha_dev, h->scratch_dev);
 }
 
 extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {

@@ -14,6 +14,9 @@ struct pdf_handle {
   int tile = 256, ntiles = 0;
   pdf_params prm{};
   hipStream_t stream = nullptr;
+  int device = -1;                // device current at pdf_setup
+  void* scratch_dev = nullptr;    // that device's copy of the library's static scratch
+  std::string scratch_err;        // why scratch_dev is null, if it is
   // operator tables (handle precision)
   void* ghat = nullptr;   // [P][P] spectrum / P^2
   void* tw = nullptr;     // [P] exp(-2 pi i k / P)
