@@ -121,7 +121,8 @@ int pdf_set_data(pdf_handle* h, const void* esca_dev);
 /* Loss and gradient at alpha (Sec. 3.2, Eqs. 13-19; the adjoint is the chain
  * rule through every step, with the per-pixel least-squares contrast
  * R = beta sum J conj(E) / sum |E|^2 (Eqs. 6-7)).
- *   alpha_dev: [B][Ni][K][K] complex.  grad_dev: same shape, may be NULL.
+ *   alpha_dev: [B][Ni][K][K] complex.  grad_dev: same shape, may be NULL
+ *   (then only the forward kernels and the loss pass run, no adjoint).
  *   loss_dev: device double [B][PDF_LOSS_STRIDE], may be NULL.
  * Gradient convention: dL/dRe + i dL/dIm (that of PyTorch). */
 int pdf_loss_grad(pdf_handle* h, const void* alpha_dev, void* grad_dev, double* loss_dev);
@@ -372,6 +373,45 @@ int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, double s_in, double s_out, c
  * graph of this call replays step t).  Requires pdf_set_data. */
 int pdf_fcnn_step(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
                   void* theta_dev, void* m_dev, void* v_dev, int32_t t, void* alpha_hat_dev, double* loss_dev);
+
+/* Mean square (1/n) sum x_i^2 of n device reals (float for PDF_FP32, double
+ * for PDF_FP64), FP64 accumulation in a fixed order, written to the device
+ * double out_dev; asynchronous on `stream` (NULL: the default stream).  Used for the unit-RMS scales of
+ * network inputs and outputs (the coefficient network of Sec. 3.1: s_in =
+ * 1 / rms(alpha_0); the warm-start network's training data).  A complex array
+ * is passed as 2n reals.  Errors (PDF_EINVAL: null, n < 1, bad precision)
+ * leave their message in pdf_last_error(NULL). */
+int pdf_mean_square(int32_t precision, int64_t n, const void* x_dev, double* out_dev, void* stream);
+
+/* The linear pieces the loss is built from, applied alone to the handle's
+ * whole batch (B instances x Ni incidences), for adjoint (dot-product) tests
+ * of the device's own operators: the basis synthesis B = F_T^* (Sec. 2.3,
+ * Eq. 9), the domain operator G_D as the 2x-padded FFT convolution (Sec. 2.1,
+ * Eq. 3) and the receiver operator G_S (Sec. 2.1, Eq. 4), each through the
+ * kernels of the loss-gradient pass (the adjoint ones through the adjoint
+ * convolution with its analysis, and the G_S^H GEMM).
+ *   op                    x_dev                     y_dev
+ *   PDF_OP_SYNTH          alpha [B][Ni][K][K]       B alpha [B][Ni][M][M]
+ *   PDF_OP_SYNTH_ADJ      [B][Ni][M][M]             B^H x [B][Ni][K][K]
+ *   PDF_OP_GD             [B][Ni][M][M]             G_D x [B][Ni][M][M]
+ *   PDF_OP_GD_SYNTH       alpha [B][Ni][K][K]       G_D B alpha [B][Ni][M][M]
+ *   PDF_OP_GD_SYNTH_ADJ   [B][Ni][M][M]             B^H G_D^H x [B][Ni][K][K]
+ *   PDF_OP_GS             [B][Ni][M][M]             G_S x [B][Ni][Ns]
+ *   PDF_OP_GS_ADJ         [B][Ni][Ns]               G_S^H x [B][Ni][M][M]
+ * B^H is the unnormalised forward DFT on the kept modes (M^2 F_T).  x and y
+ * are device arrays in the handle's precision and must not alias.  Overwrites
+ * the handle's per-iteration scratch (not alpha, Adam state or the data).
+ * Errors: PDF_EINVAL (null, aliasing, unknown op). */
+enum {
+  PDF_OP_SYNTH = 0,
+  PDF_OP_SYNTH_ADJ = 1,
+  PDF_OP_GD = 2,
+  PDF_OP_GD_SYNTH = 3,
+  PDF_OP_GD_SYNTH_ADJ = 4,
+  PDF_OP_GS = 5,
+  PDF_OP_GS_ADJ = 6
+};
+int pdf_apply(pdf_handle* h, int32_t op, const void* x_dev, void* y_dev);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * each kernel of pdf_loss_grad / pdf_step (for benchmarks).  enable != 0

@@ -14,7 +14,9 @@ advances solvers of different shapes together; ``synthesize`` and
 ``synthesize_batch`` compute measured fields by FP64 MoM.
 """
 from .binding import (FP32, FP64, LOSS_NAMES, LOSS_STRIDE, Mlp, PdfError, PdfLoss, Solver, default_params,
+                      mean_abs2,
                       load, reconstruct_multi, synthesize, synthesize_batch, tables_host)
 
 __all__ = ["FP32", "FP64", "LOSS_NAMES", "LOSS_STRIDE", "Mlp", "PdfError", "PdfLoss", "Solver", "default_params",
+           "mean_abs2",
            "load", "reconstruct_multi", "synthesize", "synthesize_batch", "tables_host"]

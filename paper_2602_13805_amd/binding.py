@@ -63,6 +63,8 @@ SIGNATURES = {
     "pdf_init_alpha": (c_i32, [c_vp, c_vp]),
     "pdf_init_alpha_csi": (c_i32, [c_vp, c_i32, c_vp]),
     "pdf_init_alpha_csi_noalloc": (c_i32, [c_vp, c_i32, c_vp]),
+    "pdf_apply": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "pdf_mean_square": (c_i32, [c_i32, ctypes.c_int64, c_vp, c_vp, c_vp]),
     "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                 ctypes.POINTER(Report)]),
@@ -203,6 +205,22 @@ def synthesize_batch(M: int, side: float, freq_hz: float, tx_list, rx_list, eps:
     return (out, jc) if coarse > 0 else out
 
 
+def mean_abs2(x: torch.Tensor) -> float:
+    """Mean of |x|^2 over the elements of a real or complex device tensor, computed by the
+    library (pdf_mean_square); synchronous."""
+    if not (isinstance(x, torch.Tensor) and x.device.type == "cuda"):
+        raise ValueError("mean_abs2: expected a device tensor")
+    r = torch.view_as_real(x) if x.is_complex() else x
+    r = r.contiguous()
+    prec = {torch.float32: FP32, torch.float64: FP64}.get(r.dtype)
+    if prec is None or r.numel() < 1:
+        raise ValueError("mean_abs2: expected a non-empty float32/float64 (or complex) tensor")
+    out = torch.empty(1, dtype=torch.float64, device=x.device)
+    stream = torch.cuda.current_stream(x.device)
+    _check(load().pdf_mean_square(prec, r.numel(), _ptr(r), _ptr(out), c_vp(stream.cuda_stream)))
+    return float(out.item()) * (2.0 if x.is_complex() else 1.0)
+
+
 class Solver:
     """One measurement geometry with `batch` data sets on one GPU."""
 
@@ -336,6 +354,20 @@ class Solver:
         self._want(out, self.alpha_shape, self.cdtype, "out", inplace=True)
         self._call(load().pdf_init_alpha_csi_noalloc, int(n_iter), _ptr(out))
         return out
+
+    OPS = dict(synth=(0, "coef", "pix"), synth_adj=(1, "pix", "coef"), gd=(2, "pix", "pix"),
+               gd_synth=(3, "coef", "pix"), gd_synth_adj=(4, "pix", "coef"), gs=(5, "pix", "rx"),
+               gs_adj=(6, "rx", "pix"))
+
+    def apply(self, op: str, x: torch.Tensor) -> torch.Tensor:
+        """One linear piece of the loss on the whole batch: synth (B), synth_adj (B^H), gd (G_D),
+        gd_synth (G_D B), gd_synth_adj (B^H G_D^H), gs (G_S), gs_adj (G_S^H)."""
+        code, src, dst = self.OPS[op]
+        shape = dict(coef=self.alpha_shape, pix=(self.B, self.Ni, self.M, self.M), rx=(self.B, self.Ni, self.Ns))
+        x = self._want(x, shape[src], self.cdtype, "x")
+        y = torch.empty(shape[dst], dtype=self.cdtype, device=self.device)
+        self._call(load().pdf_apply, code, _ptr(x), _ptr(y))
+        return y
 
     def warm_start(self, net: "Mlp", s_in: float, s_out: float):
         """Start values: the network's prediction where its loss beats the back-propagation start.
@@ -576,9 +608,11 @@ class Mlp:
 class PdfLoss(torch.autograd.Function):
     """Total PDF loss per instance with the library's hand-written adjoint.
 
-    forward(alpha, solver, checkpoint) -> loss [B] (float64).  By default the
-    gradient from the same library call is kept for backward; with
-    checkpoint=True only alpha is kept and the gradient is recomputed.
+    forward(alpha, solver, checkpoint) -> loss [B] (float64).  By default one library
+    call computes loss and gradient and the gradient is kept for backward.  With
+    checkpoint=True the forward runs the loss kernels only (no adjoint), alpha is kept,
+    and backward runs the whole loss-gradient pass again: the adjoint's work is spent only
+    when a gradient is asked for.  The saved tensor has alpha's size either way.
     """
 
     @staticmethod

@@ -1066,6 +1066,9 @@ extern "C" int pdf_set_data(pdf_handle* h, const void* esca_dev) {
 extern "C" int pdf_loss_grad(pdf_handle* h, const void* alpha_dev, void* grad_dev, double* loss_dev) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
+  // without a gradient output only the forward kernels and the loss pass run
+  if (!grad_dev)
+    return h->prec == PDF_FP32 ? run_loss<float>(h, alpha_dev, loss_dev) : run_loss<double>(h, alpha_dev, loss_dev);
   return h->prec == PDF_FP32
              ? run_iteration<float>(h, alpha_dev, grad_dev, loss_dev, nullptr, nullptr, nullptr, nullptr, nullptr)
              : run_iteration<double>(h, alpha_dev, grad_dev, loss_dev, nullptr, nullptr, nullptr, nullptr, nullptr);
@@ -1116,6 +1119,99 @@ extern "C" int pdf_init_alpha(pdf_handle* h, void* alpha_dev) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
   return h->prec == PDF_FP32 ? run_init<float>(h, alpha_dev) : run_init<double>(h, alpha_dev);
+}
+
+// The linear pieces of the loss applied alone (see pdf_apply), with the
+// kernels of the loss-gradient pass: the forward convolution kernel without
+// incident field and with beta = 0, the adjoint convolution kernel with R and
+// the data term chosen so that its g_J is exactly the input (R = 0) or its g_E
+// is (R = 1, zero data term, unit weights), the split-K receiver GEMM with its
+// fixed-order sum, and the G_S^H GEMM.
+template <typename T>
+static int run_apply(pdf_handle* h, int op, const void* x, void* y) {
+  int rc;
+  const size_t nb = size_t(h->B), npix = nb * h->N;
+  auto fill = [&](void* buf, size_t n, double re) -> int {
+    hipLaunchKernelGGL(k_fill_cx<T>, dim3((n + 255) / 256), dim3(256), 0, h->stream, (cx<T>*)buf, T(re), T(0), n);
+    return check_launch(h, "k_fill_cx");
+  };
+  if (op == PDF_OP_SYNTH || op == PDF_OP_GD || op == PDF_OP_GD_SYNTH) {
+    FwdArgs<T> f = fwd_args<T>(h, x);
+    f.einc = nullptr;
+    f.beta = T(0);
+    if (op == PDF_OP_SYNTH) {
+      f.J = (cx<T>*)y;
+      f.E = (cx<T>*)h->E;
+    } else {
+      f.J = op == PDF_OP_GD ? nullptr : (cx<T>*)h->J;
+      f.E = (cx<T>*)y;
+    }
+    return launch_fwd<T>(h, f, op != PDF_OP_GD);
+  }
+  if (op == PDF_OP_SYNTH_ADJ || op == PDF_OP_GD_SYNTH_ADJ) {
+    // unit weights: 2 / Ss = 2 hsign / Sd = 1
+    hipLaunchKernelGGL(k_fill_double, dim3((h->B + 255) / 256), dim3(256), 0, h->stream, h->gnorm, 2.0, h->B);
+    if ((rc = check_launch(h, "k_fill_double"))) return rc;
+    AdjArgs<T> a = adj_args<T>(h, y, nullptr, nullptr, nullptr, nullptr);
+    a.J = nullptr;
+    a.gR = nullptr;
+    a.den = nullptr;
+    a.Ss = h->gnorm;
+    a.Sd = h->gnorm;
+    a.hsign = 1.0;
+    a.E = (const cx<T>*)x;
+    if (op == PDF_OP_SYNTH_ADJ) {
+      // R = 0: g_E = 0, g_J = h = x, result B^H x
+      if ((rc = fill(h->R, npix, 0.0))) return rc;
+      a.h = (const cx<T>*)x;
+    } else {
+      // R = 1, h = 0: g_E = x, g_J = -beta x + beta x = 0, result B^H G_D^H x
+      if ((rc = fill(h->R, npix, 1.0))) return rc;
+      if ((rc = fill(h->h, npix * h->Ni, 0.0))) return rc;
+      a.h = (const cx<T>*)h->h;
+    }
+    return launch_adj<T>(h, a);
+  }
+  if (op == PDF_OP_GS) {
+    if ((rc = fill(h->R, npix, 0.0))) return rc;
+    if ((rc = fill(h->dres, nb * h->Ni * h->Ns, 0.0))) return rc;
+    if ((rc = launch_reduce<T>(h, (const cx<T>*)x, (const cx<T>*)x, (const cx<T>*)h->R))) return rc;
+    const int NO = h->Ni * h->Ns;
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, h->B), dim3(256), 0, h->stream,
+                       (const cx<T>*)h->Dpart, h->ntiles, (const cx<T>*)h->dres, (cx<T>*)y, NO);
+    return check_launch(h, "k_csi_residual");
+  }
+  if (op == PDF_OP_GS_ADJ) return launch_adj_gemm<T>(h, (const cx<T>*)x, (cx<T>*)y);
+  return fail(h, PDF_EINVAL, "unknown operator");
+}
+
+extern "C" int pdf_apply(pdf_handle* h, int32_t op, const void* x_dev, void* y_dev) {
+  if (!h || !x_dev || !y_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (op < PDF_OP_SYNTH || op > PDF_OP_GS_ADJ) return fail(h, PDF_EINVAL, "unknown operator");
+  if (x_dev == y_dev) return fail(h, PDF_EINVAL, "x and y must not alias");
+  return h->prec == PDF_FP32 ? run_apply<float>(h, op, x_dev, y_dev) : run_apply<double>(h, op, x_dev, y_dev);
+}
+
+// (1/n) sum x^2 of n reals in one workgroup (fixed order, FP64 accumulation).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mean_square(const T* x, int64_t n, double* out) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += double(x[i]) * double(x[i]);
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[0] = s / double(n);
+}
+
+extern "C" int pdf_mean_square(int32_t precision, int64_t n, const void* x_dev, double* out_dev, void* stream) {
+  if (!x_dev || !out_dev) return fail(nullptr, PDF_EINVAL, "null argument");
+  if (n < 1 || (precision != PDF_FP32 && precision != PDF_FP64))
+    return fail(nullptr, PDF_EINVAL, "n must be >= 1 and precision PDF_FP32 or PDF_FP64");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == PDF_FP32)
+    hipLaunchKernelGGL(k_mean_square<float>, dim3(1), dim3(1024), 0, st, (const float*)x_dev, n, out_dev);
+  else
+    hipLaunchKernelGGL(k_mean_square<double>, dim3(1), dim3(1024), 0, st, (const double*)x_dev, n, out_dev);
+  return check_launch(nullptr, "k_mean_square");
 }
 
 // Average duration (ms) of `reps` launches of fn on the handle's stream.

@@ -147,6 +147,12 @@ __global__ void k_fill_int(int* x, int v, int n) {
 }
 
 template <typename T>
+__global__ void k_fill_cx(cx<T>* x, T re, T im, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cx<T>{re, im};
+}
+
+template <typename T>
 __global__ void k_fill_zero(T* x, size_t n) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) x[i] = T(0);

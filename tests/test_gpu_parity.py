@@ -256,11 +256,29 @@ def test_autograd_function_and_checkpoint():
     (pdf.PdfLoss.apply(alpha, s, False) * w).sum().backward()
     g1 = alpha.grad.clone()
     alpha.grad = None
-    (pdf.PdfLoss.apply(alpha, s, True) * w).sum().backward()
+    l_ck = pdf.PdfLoss.apply(alpha, s, True)
+    (l_ck * w).sum().backward()
     assert torch.equal(alpha.grad, g1)
-    _, g = s.loss_grad(alpha.detach().contiguous())
+    lo, g = s.loss_grad(alpha.detach().contiguous())
     assert torch.allclose(g1[1], 0.5 * g[1])
+    # the loss-only pass (no gradient output: no adjoint kernels) gives the same loss bit for bit
+    lo_only, none = s.loss_grad(alpha.detach().contiguous(), grad=False)
+    assert none is None and torch.equal(lo_only, lo) and torch.equal(l_ck.detach(), lo[:, 5])
     s.close()
+
+
+def test_mean_square_of_device_arrays():
+    rng = np.random.default_rng(5)
+    for dt in (torch.float32, torch.float64, torch.complex64, torch.complex128):
+        for n in (1, 1000, 300001):
+            x = torch.tensor(rng.standard_normal(n) * 3.0, device=DEV).to(dt if not dt.is_complex else
+                                                                              torch.float64)
+            if dt.is_complex:
+                x = torch.complex(x, 0.5 * x.flip(0)).to(dt)
+            ref = float(np.mean(np.abs(x.cpu().numpy().astype(np.complex128)) ** 2))
+            got = pdf.mean_abs2(x)
+            tol = 1e-6 if dt in (torch.float32, torch.complex64) else 1e-13
+            assert abs(got - ref) <= tol * ref, (dt, n, got, ref)
 
 
 def test_synthesize_matches_oracle_mom():
@@ -435,3 +453,27 @@ def test_cfg2_batch_of_256_in_the_benchmark_configuration():
             assert np.max(np.abs(part(stepped[b] - a1)[strong])) < 1e-6
         assert np.max(np.abs(stepped[b] - a1)) <= 2 * np.sqrt(2) * 1e-2
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_resume_100_plus_100_equals_200_steps(prec):
+    """Checkpoint and resume: the step state (alpha, Adam moments, step counters) is caller-visible
+    device memory, so 100 steps, a copy to the host, a new handle and 100 more steps equal 200 steps
+    on one handle bit for bit."""
+    case = make_case(16, 7, 6, 8, seeds=(0, 1))
+    s = solver_for(case, prec)
+    a = s.init_alpha()
+    m, v, t = s.new_state()
+    for _ in range(100):
+        s.step(a, m, v, t)
+    saved = [x.cpu().clone() for x in (a, m, v, t)]
+    for _ in range(100):
+        s.step(a, m, v, t)
+    s.close()
+    s2 = solver_for(case, prec)
+    a2, m2, v2, t2 = [x.to(DEV) for x in saved]
+    for _ in range(100):
+        s2.step(a2, m2, v2, t2)
+    assert torch.equal(a2, a) and torch.equal(m2, m) and torch.equal(v2, v) and torch.equal(t2, t)
+    assert int(t2[0]) == 200
+    s2.close()
