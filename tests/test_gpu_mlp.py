@@ -1,6 +1,9 @@
 """GPU parity of the warm-start network (an addition; the paper has none), of the Fourier
-analysis used for its targets, and of the start selection.  The network is compared with the
-FP64 oracle evaluated with the same bfloat16 rounding points (oracle.mlp, quant=True)."""
+analysis used for its targets, and of the start selection.  The network is held to the plain FP64
+oracle (oracle.mlp, quant=False) within a first-order bound derived from bfloat16's unit
+round-off and the layer products (test_bf16_network_within_the_rounding_bound_of_fp64); a second
+test checks where the device rounds, against the oracle evaluated with the same rounding points
+(quant=True)."""
 import numpy as np
 import pytest
 import torch
@@ -54,6 +57,93 @@ def test_mlp_forward_gradients_adam_match_oracle():
         b1, _, _ = omlp.adam_update(params[l][1], gb.astype(np.float64), 0.0, 0.0, 1, lr)
         assert np.max(np.abs(new[l][0] - W1)) < 1e-6, l
         assert np.max(np.abs(new[l][1] - b1)) < 1e-6, l
+    net.close()
+
+
+U_BF16 = 2.0 ** -8       # unit round-off of bfloat16 (8 significant bits, round to nearest even)
+# RMS relative error of rounding to 8 significant bits, for log-uniformly spread mantissas m in
+# [1, 2): the absolute error is uniform in +-u (variance u^2 / 3) and E[1/m^2] = 3 / (8 ln 2)
+R_BF16 = U_BF16 * np.sqrt(3.0 / (8.0 * np.log(2.0)) / 3.0)
+C_CONF = 3.0             # standard deviations allowed
+
+
+def _rounding_sd(A, B):
+    """RMS Frobenius norm of the error of A @ B when both operands are rounded to bfloat16,
+    errors independent across elements: (A B)_ij's error has variance
+    2 R^2 sum_k A_ik^2 B_kj^2 (FP32 accumulation adds 2^-24 per term: negligible)."""
+    return R_BF16 * np.sqrt(2.0 * np.sum((A * A) @ (B * B)))
+
+
+def _gain(W, axis):
+    """RMS gain of a layer product on an error of random direction: ||W||_F / sqrt(reduction width)."""
+    return np.linalg.norm(W) / np.sqrt(W.shape[axis])
+
+
+def _rms(v):
+    return float(np.sqrt(np.mean(np.asarray(v) ** 2)))
+
+
+def bf16_bounds(params, x, t, s_in):
+    """Error bounds of the device's output and weight gradients against the plain FP64 network:
+    C_CONF times the RMS error of a random-rounding model in which every layer product rounds
+    both operands to bfloat16 once, and errors made earlier pass through later layers with the
+    RMS gain of the layer product and of GELU's derivative at the FP64 pre-activations
+    (independent errors add in quadrature), forward and then backward."""
+    y, cache = omlp.forward(params, x, s_in=s_in)
+    L = len(params)
+    ez = [0.0] * L                     # RMS error of z_l
+    for l, (W, _) in enumerate(params):
+        a = cache[l][0]
+        ea = _rms(omlp.gelu_grad(cache[l - 1][1])) * ez[l - 1] if l > 0 else 0.0
+        ez[l] = np.hypot(_rounding_sd(a, W.T), _gain(W, 1) * ea)
+    _, dy = omlp.mse(y, t)
+    dz = dy
+    edz = 2.0 * ez[L - 1] / y.size     # error of dL/dy = 2 (y - t) / size
+    gW = [None] * L
+    for l in range(L - 1, -1, -1):
+        W, _ = params[l]
+        a = cache[l][0]
+        ea = _rms(omlp.gelu_grad(cache[l - 1][1])) * ez[l - 1] if l > 0 else 0.0
+        # dW = dz^T a: fresh rounding of both operands, then the errors carried by dz and by a
+        carried = np.hypot(edz * np.linalg.norm(a), np.linalg.norm(dz) * ea) / np.sqrt(a.shape[0])
+        gW[l] = C_CONF * np.hypot(_rounding_sd(dz.T, a), carried)
+        if l > 0:
+            gp = omlp.gelu_grad(cache[l - 1][1])
+            dh = dz @ W
+            edh = np.hypot(_rounding_sd(dz, W), _gain(W, 0) * edz)
+            # dz_{l-1} = dh * gelu'(z_{l-1}): error of dh, and of gelu' at the perturbed z
+            gpp = np.exp(-0.5 * cache[l - 1][1] ** 2) / np.sqrt(2.0 * np.pi) * (2.0 - cache[l - 1][1] ** 2)
+            edz = np.hypot(_rms(gp) * edh, _rms(dh * gpp) * ez[l - 1] / np.sqrt(dh.size))
+            dz = dh * gp
+    return y, C_CONF * ez[L - 1], gW
+
+
+def test_bf16_network_within_the_rounding_bound_of_fp64():
+    print(f"mlp bf16 vs fp64 sizes={SIZES}", flush=True)
+    B = 37
+    net = pdf.Mlp(SIZES, batch_max=64, device=DEV)
+    net.init_weights(21)
+    rng = np.random.default_rng(22)
+    x = rng.normal(size=(B, SIZES[0])).astype(np.float32)
+    t = rng.normal(size=(B, SIZES[-1])).astype(np.float32)
+    s_in = 0.8
+    params = host_params(net)
+    y_ref, ey, gW_bound = bf16_bounds(params, x.astype(np.float64), t.astype(np.float64), s_in)
+    y = net.forward(torch.tensor(x, device=DEV), s_in=s_in, s_out=1.0).cpu().numpy()
+    err_y = np.linalg.norm(y - y_ref)
+    print(f"output error {err_y / np.linalg.norm(y_ref):.2e} relative, bound {ey / np.linalg.norm(y_ref):.2e}",
+          flush=True)
+    assert err_y <= ey
+    net.train_step(torch.tensor(x, device=DEV), torch.tensor(t, device=DEV), None, s_in, 1e-3)
+    _, cache = omlp.forward(params, x.astype(np.float64), s_in=s_in)
+    _, dy = omlp.mse(y_ref, t.astype(np.float64))
+    go = omlp.backward(params, cache, dy)
+    for l in range(net.L):
+        gW, _ = net.get_layer(l, grad=True)
+        err = np.linalg.norm(gW - go[l][0])
+        print(f"layer {l}: weight-gradient error {err / np.linalg.norm(go[l][0]):.2e} relative, bound "
+              f"{gW_bound[l] / np.linalg.norm(go[l][0]):.2e}", flush=True)
+        assert err <= gW_bound[l], l
     net.close()
 
 
@@ -177,5 +267,17 @@ def test_trained_warm_start_gains_over_the_plain_start():
     assert int(chosen.sum()) > 0
     assert e_w.mean() < e_bp.mean()
     assert r_w.mean() < r_bp.mean()
+    # image-error bound of the bfloat16 network path: the start predicted by the device network and
+    # the start the plain FP64 network (same weights) predicts give image errors within 0.01 of
+    # each other on every held-out instance (both images from the same FP32 physics and CCO)
+    params = host_params(tr.net)
+    y64, _ = omlp.forward(params, ev.x.double().cpu().numpy(), s_in=tr.s_in)
+    a64 = torch.view_as_complex(torch.tensor(tr.s_out * y64, dtype=torch.float32).reshape(B, -1, 2)).reshape(
+        a_bp.shape).to(DEV).contiguous()
+    a16 = torch.view_as_complex(ws.predict(tr, ev.x).reshape(B, -1, 2)).reshape(a_bp.shape).contiguous()
+    d = np.abs(s.image(a16, eps_t)[2].cpu().numpy() - s.image(a64, eps_t)[2].cpu().numpy())
+    print(f"bfloat16 vs FP64 network start: image errors differ by at most {d.max():.2e} (mean {d.mean():.2e})",
+          flush=True)
+    assert d.max() <= 0.01
     tr.net.close()
     s.close()
