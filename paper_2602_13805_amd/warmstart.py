@@ -15,6 +15,7 @@ inputs, moves arrays and loops over batches.
 from __future__ import annotations
 
 import dataclasses
+import math
 import time
 from concurrent.futures import ThreadPoolExecutor
 from typing import Optional, Sequence
@@ -96,8 +97,8 @@ def train(data: Dataset, epochs: int = 40, batch: int = 256, lr: float = 1e-3, s
     """Trains a new network on `data` (inputs and targets scaled to unit RMS)."""
     n, n_in = data.x.shape
     n_out = data.t.shape[1]
-    s_in = float(1.0 / torch.sqrt(torch.mean(data.x.double() ** 2)))
-    s_out = float(torch.sqrt(torch.mean(data.t.double() ** 2)))
+    s_in = 1.0 / math.sqrt(_b.mean_abs2(data.x))
+    s_out = math.sqrt(_b.mean_abs2(data.t))
     tn = (data.t / s_out).contiguous()
     net = _b.Mlp([n_in, *hidden, n_out], batch_max=batch, device=device)
     net.init_weights(seed)

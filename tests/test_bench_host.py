@@ -122,3 +122,26 @@ def test_seeded_weight_and_position_draws():
     t2, _ = si.draw_position_errors(7, 32, 32, 2e-3)
     assert t1.shape == (32, 2) and np.allclose(t2, 2 * t1)       # one draw, scaled by sigma
     assert 0.5e-3 < np.std(np.concatenate([t1, r1])) < 1.5e-3
+
+
+def test_fixed_target_counts_count_only_instances_that_start_above_the_target():
+    import numpy as np
+    import bench
+    err0 = np.array([0.50, 0.35, 0.25, 0.60, 0.45])
+    # first checked step at or below 0.40 / 0.30 (0 = already at the start, -1 = never)
+    first = {0.40: np.array([30, 0, 0, -1, 10]), 0.30: np.array([50, 20, 0, -1, -1])}
+    clock = {0: 0.1, 10: 1.0, 20: 2.0, 30: 3.0, 40: 4.0, 50: 5.0}
+    out = bench.fixed_target_counts(first, lambda t: clock[t], err0)
+    a, b = out["0.40"], out["0.30"]
+    # 0.40: instances 0, 3, 4 start above it; 0 and 4 reach it, the last at step 30
+    assert (a["n_counted"], a["n_reached"], a["mean_iters"], a["seconds"]) == (3, 2, 20.0, 3.0)
+    assert a["per_s"] == 2 / 3.0
+    # 0.30: instances 0, 1, 3, 4; 0 at 50 and 1 at 20 (instance 2 starts below: never counted)
+    assert (b["n_counted"], b["n_reached"], b["mean_iters"], b["seconds"]) == (4, 2, 35.0, 5.0)
+    assert abs(b["frac_reached"] - 0.5) < 1e-15
+
+
+def test_floor_bytes_of_the_benchmark_instance():
+    import bench
+    # 8 B x [32*4096 + 2*32*4096 + 2*128^2 + 32*32 + 6*32*225]
+    assert bench.floor_bytes(64, 32, 32, 15) == 8 * (32 * 4096 + 64 * 4096 + 2 * 16384 + 1024 + 6 * 32 * 225)
