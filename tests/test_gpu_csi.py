@@ -21,7 +21,7 @@ def _rel_max(a, b):
 @pytest.mark.parametrize("M,K,Ni,Ns,B,prec,steps,tol", [
     (16, 7, 6, 8, 2, "fp64", (1, 2, 5, 12), 1e-8),
     (32, 14, 12, 20, 2, "fp64", (3,), 1e-8),      # corner blocks, ragged tiles
-    (32, 9, 16, 32, 2, "fp32", (1, 3), 2e-3),
+    (32, 9, 16, 32, 2, "fp32", (1, 3), 1e-5),    # CG scalars accumulated in FP64: ~1e-7 per step
 ])
 def test_csi_start_matches_the_oracle(M, K, Ni, Ns, B, prec, steps, tol):
     print(f"case csi M={M} K={K} Ni={Ni} Ns={Ns} B={B} {prec} steps={steps}", flush=True)
@@ -32,6 +32,7 @@ def test_csi_start_matches_the_oracle(M, K, Ni, Ns, B, prec, steps, tol):
         for b, c in enumerate(case["cases"]):
             ref, _ = oinit.csi_cg(c["prob"], n)
             e = _rel_max(got[b], ref[0])
+            print(f"csi {prec} n={n} b={b}: rel max {e:.2e}, norm-wise {np.linalg.norm(got[b] - ref[0]) / np.linalg.norm(ref[0]):.2e}", flush=True)
             assert e < tol, (n, b, e)
     assert torch.equal(s.init_alpha_csi(1), s.init_alpha())
     s.close()

@@ -131,13 +131,17 @@ def test_cfg2_full_size_parity():
     s.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 2e-4), ("fp64", 1e-9)])
+# FP32: the start is one exact line-search step, its inputs the back-propagation image and R_0;
+# FP32's unit round-off 6e-8 times a few dozen operations in sequence (two FFT convolutions, the
+# incidence sums, the receiver GEMMs; the step size from FP64-accumulated sums) leaves ~1e-6
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-9)])
 def test_init_alpha_parity(prec, tol):
     case = make_case(32, 9, 8, 12, seeds=(0, 1))
     s = solver_for(case, prec)
     a = s.init_alpha().cpu().numpy()
     for b, c in enumerate(case["cases"]):
         ref, info = oinit.alpha0(c["prob"])
+        print(f"init alpha {prec} b={b}: rel {rel(a[b], ref[0]):.2e}", flush=True)
         assert rel(a[b], ref[0]) < tol, rel(a[b], ref[0])
     s.close()
 

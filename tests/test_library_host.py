@@ -121,7 +121,7 @@ def test_argument_errors_without_device():
     assert lib.pdf_setup(ctypes.byref(g), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
                          ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EINVAL
     p.version = 1
-    for m_bad, prec in ((40, B.FP32), (96, B.FP64), (128, B.FP32)):  # no plan / not LDS-resident
+    for m_bad, prec in ((40, B.FP32), (100, B.FP64), (512, B.FP32)):  # grids without a plan
         p.precision = prec
         gb = B.Grid(m_bad, 1.5, 0.0, 0.0)
         assert lib.pdf_setup(ctypes.byref(gb), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
