@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "conv_big.h"
 #include "conv_kernels.h"
 #include "fcnn_kernels.h"
 #include "handle.h"
@@ -102,9 +103,12 @@ extern "C" int pdf_default_params(pdf_params* p) {
 }
 
 static bool supported_m(int prec, int M) {
-  if (prec == PDF_FP32) return M == 8 || M == 16 || M == 32 || M == 48 || M == 64 || M == 96;
-  return M == 8 || M == 16 || M == 32 || M == 48 || M == 64;
+  return M == 8 || M == 16 || M == 32 || M == 48 || M == 64 || M == 96 || M == 128 || M == 256;
 }
+
+// Grids whose convolution runs in passes through global memory (conv_big.h):
+// the padded half tile exceeds one CU's LDS.
+static bool big_grid(int prec, int M) { return prec == PDF_FP32 ? M >= 128 : M >= 96; }
 
 // ------------------------------------------------------------------ launchers
 
@@ -148,10 +152,99 @@ static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int
   }
 }
 
+// ---- grids beyond one CU's LDS: the convolution in three passes through S
+
+template <typename T, int M>
+static int launch_fwd_big_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
+  using C = BigCfg<T, M>;
+  const int bp = h->B * h->Ni;
+  cx<T>* S = (cx<T>*)h->S;
+  if (from_alpha) {
+    set_lds(k_big_rows_fwd<T, M, true>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_rows_fwd<T, M, true>), dim3(bp * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream, a, S);
+  } else {
+    set_lds(k_big_rows_fwd<T, M, false>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_rows_fwd<T, M, false>), dim3(bp * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream, a, S);
+  }
+  set_lds(k_big_cols<T, M>, C::COL_LDS);
+  hipLaunchKernelGGL((k_big_cols<T, M>), dim3(bp * C::CBLK), dim3(C::NTC), C::COL_LDS, h->stream, a.ghat, a.tw, S, 0);
+  if (from_alpha) {
+    set_lds(k_big_rows_inv<T, M, true>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_rows_inv<T, M, true>), dim3(bp * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream, a,
+                       (const cx<T>*)S);
+  } else {
+    set_lds(k_big_rows_inv<T, M, false>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_rows_inv<T, M, false>), dim3(bp * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream, a,
+                       (const cx<T>*)S);
+  }
+  return check_launch(h, "big-grid forward convolution");
+}
+
+template <typename T>
+static int launch_fwd_big(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
+  switch (h->M) {
+    case 128: return launch_fwd_big_m<T, 128>(h, a, from_alpha);
+    case 256: return launch_fwd_big_m<T, 256>(h, a, from_alpha);
+    case 96:
+      if constexpr (sizeof(T) == 8) return launch_fwd_big_m<T, 96>(h, a, from_alpha);
+      break;
+  }
+  return fail(h, PDF_EUNSUPPORTED, "unsupported M for the big-grid convolution");
+}
+
+// The analysis half of the adjoint for the K kept modes of the rows in S plus
+// g_J (src = null), or of the pixel arrays src: row transforms, then the
+// column DFT with the gradient output and Adam of a, results times scale.
+template <typename T, int M>
+static int launch_adj_tail_big_m(pdf_handle* h, const AdjArgs<T>& a, int npairs, const cx<T>* src, T scale) {
+  using C = BigCfg<T, M>;
+  cx<T>* S = (cx<T>*)h->S;
+  if (!src) {
+    set_lds(k_big_adj_rows_inv<T, M, true>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_adj_rows_inv<T, M, true>), dim3(npairs * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream,
+                       a.tw, S, (const cx<T>*)h->GJ, a.K);
+  } else {
+    set_lds(k_big_adj_rows_inv<T, M, false>, C::ROW_LDS);
+    hipLaunchKernelGGL((k_big_adj_rows_inv<T, M, false>), dim3(npairs * C::RBLK), dim3(C::NT), C::ROW_LDS,
+                       h->stream, a.tw, S, src, a.K);
+  }
+  hipLaunchKernelGGL((k_big_adj_final<T, M>), dim3(npairs), dim3(256), sizeof(cx<T>) * C::P, h->stream, a,
+                     (const cx<T>*)S, scale);
+  return check_launch(h, "big-grid analysis");
+}
+
+template <typename T, int M>
+static int launch_adj_big_m(pdf_handle* h, const AdjArgs<T>& a) {
+  using C = BigCfg<T, M>;
+  const int bp = h->B * h->Ni;
+  cx<T>* S = (cx<T>*)h->S;
+  set_lds(k_big_adj_rows<T, M>, C::ROW_LDS);
+  hipLaunchKernelGGL((k_big_adj_rows<T, M>), dim3(bp * C::RBLK), dim3(C::NT), C::ROW_LDS, h->stream, a, S,
+                     (cx<T>*)h->GJ);
+  set_lds(k_big_cols<T, M>, C::COL_LDS);
+  hipLaunchKernelGGL((k_big_cols<T, M>), dim3(bp * C::CBLK), dim3(C::NTC), C::COL_LDS, h->stream, a.ghat, a.tw, S, 1);
+  int rc = check_launch(h, "big-grid adjoint convolution");
+  if (rc) return rc;
+  return launch_adj_tail_big_m<T, M>(h, a, bp, nullptr, T(1));
+}
+
+template <typename T>
+static int launch_adj_big(pdf_handle* h, const AdjArgs<T>& a) {
+  switch (h->M) {
+    case 128: return launch_adj_big_m<T, 128>(h, a);
+    case 256: return launch_adj_big_m<T, 256>(h, a);
+    case 96:
+      if constexpr (sizeof(T) == 8) return launch_adj_big_m<T, 96>(h, a);
+      break;
+  }
+  return fail(h, PDF_EUNSUPPORTED, "unsupported M for the big-grid adjoint");
+}
+
 template <typename T>
 static int launch_fwd(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha) {
   if (from_alpha && !a.J)  // the coefficient path keeps J in its output between phases
     return fail(h, PDF_EINVAL, "internal: coefficient synthesis without a J buffer");
+  if (h->big) return launch_fwd_big<T>(h, a, from_alpha);
   const int nblk = h->B * h->Ni;
   switch (h->M) {
     case 8: return launch_fwd_m<T, 8>(h, a, from_alpha, nblk);
@@ -191,6 +284,7 @@ static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
 
 template <typename T>
 static int launch_adj(pdf_handle* h, const AdjArgs<T>& a) {
+  if (h->big) return launch_adj_big<T>(h, a);
   const int nblk = h->B * h->Ni;
   switch (h->M) {
     case 8: return launch_adj_m<T, 8>(h, a, nblk);
@@ -300,6 +394,10 @@ template <typename T>
 static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
   const RegArgs<T> a = reg_args<T>(h, loss, tstep, frozen);
   const int nt = h->N < 1024 ? h->N : 1024;
+  if (h->big) {  // chi read from global memory
+    hipLaunchKernelGGL((k_image_reg<T, true>), dim3(h->B), dim3(nt), 16 * sizeof(double), h->stream, a);
+    return check_launch(h, "k_image_reg");
+  }
   const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
   set_lds(k_image_reg<T>, lds);
   hipLaunchKernelGGL(k_image_reg<T>, dim3(h->B), dim3(nt), lds, h->stream, a);
@@ -666,6 +764,18 @@ static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_
     c.tau = h->prm.cco_tau;
     c.eta_max = h->prm.cco_eta_max;
     c.delta = h->prm.cco_delta;
+    if (h->big) {
+      // coefficients, then the image and per-workgroup error sums, then the errors
+      T* w = (T*)h->big_ws;
+      const int nblk = (h->N + 255) / 256;
+      double* part = reinterpret_cast<double*>(w + size_t(h->B) * 4 * h->N);
+      hipLaunchKernelGGL(k_cco_big_coef<T>, dim3(nblk, h->B), dim3(256), 0, h->stream, (const cx<T>*)h->chi, w, h->M,
+                         c.r, c.gf_eps);
+      hipLaunchKernelGGL(k_cco_big_apply<T>, dim3(nblk, h->B), dim3(256), 0, h->stream, (const cx<T>*)h->chi,
+                         (const T*)w, c, part);
+      if (c.err) hipLaunchKernelGGL(k_cco_big_err, dim3(h->B), dim3(1), 0, h->stream, (const double*)part, nblk, c.err);
+      return check_launch(h, "k_cco_big");
+    }
     const int nt = h->N < 1024 ? h->N : 1024;
     if (h->N > kCcoPix * 1024) return fail(h, PDF_EUNSUPPORTED, "grid too large for the CCO kernel");
     const size_t lds = 4 * sizeof(T) * size_t(h->N) + 16 * sizeof(double);
@@ -889,6 +999,12 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   HIP_TRY(hipMalloc(&h->v, 2 * sizeof(T) * B * Ni * KK));
   HIP_TRY(hipMalloc(&h->loss, sizeof(double) * 8 * B));
   HIP_TRY(hipMalloc(&h->loss_w, sizeof(double) * 8 * B));
+  if (h->big) {
+    HIP_TRY(hipMalloc(&h->S, C * B * Ni * N * 2));
+    HIP_TRY(hipMalloc(&h->GJ, C * B * Ni * N));
+    const size_t nblk = (N + 255) / 256;
+    HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * B * 4 * N + sizeof(double) * B * nblk * 2));
+  }
   return PDF_OK;
 }
 
@@ -962,7 +1078,8 @@ extern "C" void pdf_destroy(pdf_handle* h) {
   void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
-                  h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws, h->csi_ws};
+                  h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws, h->csi_ws, h->S,     h->GJ,
+                  h->big_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -986,7 +1103,7 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   if (batch < 1) return fail(nullptr, PDF_EINVAL, "batch must be >= 1");
   if (!stream) return fail(nullptr, PDF_EINVAL, "a non-default stream is required");
   if (!supported_m(prm.precision, grid->M))
-    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48 or 64 (FP32 also 96)");
+    return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48, 64, 96, 128 or 256");
   if (rx->n > 64) return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 receivers");
   if (!(prm.beta > 0) || prm.gf_radius < 0) return fail(nullptr, PDF_EINVAL, "beta must be > 0");
   pdf_handle* h = new pdf_handle();
@@ -999,6 +1116,7 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   h->Ni = tx->n;
   h->Ns = rx->n;
   h->B = batch;
+  h->big = big_grid(prm.precision, grid->M);
   h->stream = (hipStream_t)stream;
   // the handle's device and its copy of the static scratch (looked up here, at
   // set-up, with that device current; a failure only disables the entry
@@ -1661,8 +1779,36 @@ static int launch_analyze_m(pdf_handle* h, int n, const void* J, void* alpha) {
   }
 }
 
+// alpha = F_T(J) for big grids: chunks of at most B sets through S.
+template <typename T, int M>
+static int launch_analyze_big_m(pdf_handle* h, int n, const void* J, void* alpha) {
+  AdjArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.tw = (const cx<T>*)h->tw;
+  a.Ni = h->Ni;
+  a.K = h->K;
+  const size_t per = size_t(h->Ni) * h->N, kk = size_t(h->Ni) * h->K * h->K;
+  for (int c0 = 0; c0 < n; c0 += h->B) {
+    const int cn = std::min(h->B, n - c0);
+    a.galpha = (cx<T>*)alpha + size_t(c0) * kk;
+    int rc = launch_adj_tail_big_m<T, M>(h, a, cn * h->Ni, (const cx<T>*)J + size_t(c0) * per, T(1) / T(h->N));
+    if (rc) return rc;
+  }
+  return PDF_OK;
+}
+
 template <typename T>
 static int launch_analyze(pdf_handle* h, int n, const void* J, void* alpha) {
+  if (h->big) {
+    switch (h->M) {
+      case 128: return launch_analyze_big_m<T, 128>(h, n, J, alpha);
+      case 256: return launch_analyze_big_m<T, 256>(h, n, J, alpha);
+      case 96:
+        if constexpr (sizeof(T) == 8) return launch_analyze_big_m<T, 96>(h, n, J, alpha);
+        break;
+    }
+    return fail(h, PDF_EUNSUPPORTED, "unsupported M");
+  }
   switch (h->M) {
     case 8: return launch_analyze_m<T, 8>(h, n, J, alpha);
     case 16: return launch_analyze_m<T, 16>(h, n, J, alpha);
@@ -1937,7 +2083,7 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
   std::vector<std::unique_ptr<Unit>> units;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
-    if (h->prec == PDF_FP32 && h->N % 32 == 0)
+    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big)
       classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
     else {
       units.emplace_back(new Unit());

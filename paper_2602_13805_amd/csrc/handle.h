@@ -51,6 +51,13 @@ struct pdf_handle {
   void* v = nullptr;
   double* loss = nullptr;    // [B][8]
   double* loss_w = nullptr;  // [B][8] second loss record (start selection)
+  // grids whose padded half tile exceeds one CU's LDS run the convolution in
+  // passes through S; GJ holds g_J between the adjoint's passes; big_ws the
+  // CCO filter coefficients [B][4][N] and error parts [B][ceil(N/256)][2]
+  bool big = false;
+  void* S = nullptr;        // [B][Ni][M][2M]
+  void* GJ = nullptr;       // [B][Ni][N]
+  void* big_ws = nullptr;
   // coefficient-network workspace (activations and gradients of one step), grown on demand
   void* fc_ws = nullptr;
   size_t fc_bytes = 0;

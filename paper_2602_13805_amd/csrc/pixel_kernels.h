@@ -400,11 +400,13 @@ __device__ __forceinline__ RegTerm<T> reg_term(const cx<T>* c, int i, int j, int
 // One instance per block: data residual and L^Data from the split-K parts,
 // L^State from its partial sums, the three regularisers on chi with their
 // gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.
-template <typename T>
+// GCHI: chi is read from global memory (grids whose chi does not fit LDS)
+// instead of being staged in LDS.
+template <typename T, bool GCHI = false>
 __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsigned char* smem_raw) {
   const int M = a.M, N = M * M;
-  cx<T>* c = reinterpret_cast<cx<T>*>(smem_raw);   // chi [M][M]
-  double* red = reinterpret_cast<double*>(c + N);
+  const cx<T>* c = GCHI ? a.chi + size_t(b) * N : reinterpret_cast<const cx<T>*>(smem_raw);   // chi [M][M]
+  double* red = reinterpret_cast<double*>(smem_raw + (GCHI ? 0 : sizeof(cx<T>) * size_t(N)));
   const int tid = threadIdx.x, nt = blockDim.x;
   if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) {
     // the step is counted here, so the adjoint's Adam epilogue reads its bias
@@ -428,7 +430,10 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
     dsum += rr * rr + ri * ri;
     a.d[size_t(b) * NO + o] = cx<T>{T(rr), T(ri)};
   }
-  for (int n = tid; n < N; n += nt) c[n] = a.chi[size_t(b) * N + n];
+  if constexpr (!GCHI) {
+    cx<T>* cs = reinterpret_cast<cx<T>*>(smem_raw);
+    for (int n = tid; n < N; n += nt) cs[n] = a.chi[size_t(b) * N + n];
+  }
   __syncthreads();
   double vb = 0, vt = 0, vr = 0, rmax = 0;
   bool bad = false;
@@ -478,10 +483,10 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
   }
 }
 
-template <typename T>
+template <typename T, bool GCHI = false>
 __global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  image_reg_body<T>(a, blockIdx.x, smem_raw);
+  image_reg_body<T, GCHI>(a, blockIdx.x, smem_raw);
 }
 
 template <typename T>
