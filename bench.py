@@ -936,7 +936,8 @@ def uneven_leg(pdf, si, wl, n_inst, iters, dev):
                                    basis="per instance 8 B x [N_i N + 2 N_s N + 2 (2M)^2 + N_s N_i + 6 N_i K^2] "
                                          "(E_inc once, G_S and the G_D spectrum twice, data, alpha/m/v read "
                                          "and written), summed over the instances, per batched iteration"),
-                shapes="M from {32, 48, 64, 96}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), cfg2 profiles",
+                shapes="M from {32, 48, 64, 96, 128}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), "
+                       "cfg2 profiles",
                 instance_iters_per_s=work / multi_s, seconds=multi_s,
                 sequential_instance_iters_per_s=work / seq_s, sequential_seconds=seq_s,
                 speedup_over_sequential=seq_s / multi_s, setup_seconds=setup_s,

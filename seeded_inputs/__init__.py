@@ -216,7 +216,7 @@ def rasterize(shapes: Sequence[Shape], M: int, side: float, cx: float = 0.0,
     return eps
 
 
-def uneven_shapes(n: int, seed: int, grids=(32, 48, 64, 96), antennas=(16, 24, 32, 48, 64),
+def uneven_shapes(n: int, seed: int, grids=(32, 48, 64, 96, 128), antennas=(16, 24, 32, 48, 64),
                   truncations=(7, 9, 11, 13, 15, 17, 19, 21)):
     """Per-instance (M, N_i = N_s, K) of an uneven batch, drawn uniformly from the given sets
     (K <= M is kept by redrawing K)."""

@@ -48,9 +48,9 @@ def test_antennas_on_circle():
 def test_uneven_shapes_recipe():
     a = si.uneven_shapes(300, seed=5)
     assert a == si.uneven_shapes(300, seed=5)
-    assert all(M in (32, 48, 64, 96) and n in (16, 24, 32, 48, 64) and K % 2 == 1 and 7 <= K <= min(21, M)
+    assert all(M in (32, 48, 64, 96, 128) and n in (16, 24, 32, 48, 64) and K % 2 == 1 and 7 <= K <= min(21, M)
                for M, n, K in a)
     assert len(set(a)) > 40  # genuinely uneven
-    assert {M for M, _, _ in a} == {32, 48, 64, 96}
+    assert {M for M, _, _ in a} == {32, 48, 64, 96, 128}
     small = si.uneven_shapes(50, seed=1, grids=(8,), truncations=(5, 7, 9))
     assert all(K <= 8 for _, _, K in small)
