@@ -100,12 +100,43 @@ int pdf_default_params(pdf_params* p);
  *   grid, tx, rx, params: host structs (params may be NULL for defaults).
  *   freq_hz: frequency.  K: truncation per axis, 1 <= K <= M.
  *   stream: hipStream_t for every later call (must not be NULL).
- * Supported: M in {8, 16, 32, 48, 64} (FP32 and FP64) or 96 (FP32); Ni, Ns >= 1.
+ * Supported: M in {8, 16, 32, 48, 64, 96, 128, 256}; Ni, Ns >= 1 (FP32: at most
+ * 64 each).  Grids whose padded half tile does not fit one CU's LDS (FP32 from
+ * 128, FP64 from 96) run the convolution in passes through a device array of
+ * B Ni M 2M complex values that the handle allocates.
  * Errors: PDF_EINVAL (bad sizes / null), PDF_EUNSUPPORTED (other M),
  * PDF_ENOMEM, PDF_EHIP, PDF_ENONFINITE (||E_inc|| = 0). */
 int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* tx,
               const pdf_array* rx, int32_t K, int32_t batch,
               const pdf_params* params, void* stream, pdf_handle** out);
+
+/* Frequencies of a multi-frequency reconstruction. */
+typedef struct {
+  int32_t n_freq;    /* 1 .. 8                                                  */
+  const double* hz;  /* host [n_freq] frequencies, Hz                           */
+} pdf_freq;
+
+/* pdf_setup for data measured at several frequencies.  The medium is taken as
+ * non-dispersive: one contrast chi (and so one R of Eq. 7) for all
+ * frequencies, while the coefficients, currents, fields and operators are per
+ * frequency.  R is the per-pixel least-squares solution over all frequencies
+ * and incidences with each frequency weighted by 1 / ||E_inc,f||^2 (so that R
+ * minimises the summed state loss); L^State and L^Data (Eqs. 15-16) are
+ * summed over the frequencies, each normalised by its own ||E_inc,f||^2 and
+ * ||E_sca,f||^2; the regularisers act on the one chi.  With n_freq == 1 this
+ * is pdf_setup.  With n_freq > 1 the handle holds one reconstruction
+ * (batch must be 1, else PDF_EUNSUPPORTED) and every per-instance array
+ * carries the frequencies outermost: alpha, gradient [F][Ni][K][K]; Adam
+ * moments [F][Ni][K][K][2]; measured fields [F][Ni][Ns]; loss [1][8]; step
+ * counter [1]; images [1][M][M].  Such a handle serves pdf_set_data,
+ * pdf_loss_grad, pdf_step, pdf_init_alpha (the back-propagation start with the
+ * joint contrast and one exact line-search step on the summed L^CSI),
+ * pdf_image, pdf_reconstruct, pdf_autotune and pdf_set_tiles; the other
+ * entry points return PDF_EUNSUPPORTED for it.  Other arguments and errors as
+ * pdf_setup. */
+int pdf_setup_freq(const pdf_grid* grid, const pdf_freq* freq, const pdf_array* tx,
+                   const pdf_array* rx, int32_t K, int32_t batch,
+                   const pdf_params* params, void* stream, pdf_handle** out);
 
 /* Host-only FP64 operator tables (no device work), for checking pdf_setup:
  * ghat [2M][2M] (FFT of the embedded G_D kernel, unscaled), gs [Ns][N],
@@ -247,6 +278,17 @@ int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n_iter, int3
                           int32_t* const* reached_iter_dev, double* const* best_err_dev,
                           int32_t* const* best_iter_dev, void* const* chi_cco_dev,
                           pdf_report* rep);
+
+/* One Adam step (pdf_step) for each of n handles of any shapes, with the
+ * caller's arrays of each (the entries have pdf_step's meaning for hs[i];
+ * loss_dev may be NULL, or have NULL entries).  FP32 handles of one shape
+ * class (grid, receiver and incidence tile counts) are advanced by one
+ * grouped launch per kernel, the others one by one; the results equal n
+ * separate pdf_step calls bit for bit.  Each handle must appear once.
+ * Synchronous (the grouped launches' argument tables are built and released
+ * in the call).  The message of a failure is in pdf_last_error(NULL). */
+int pdf_step_multi(int32_t n, pdf_handle* const* hs, void* const* alpha_dev, void* const* m_dev,
+                   void* const* v_dev, int32_t* const* t_dev, double* const* loss_dev);
 
 /* FP64 method-of-moments synthesis of measured fields (Sec. 2.1, Eqs. 3-4):
  * solves (I - G_D X) E = E_inc on the support of chi = eps - 1 of a fine grid

@@ -46,6 +46,10 @@ class Params(ctypes.Structure):
                 ("r_stopgrad", c_i32)]
 
 
+class Freq(ctypes.Structure):
+    _fields_ = [("n_freq", c_i32), ("hz", ctypes.POINTER(c_f64))]
+
+
 class Report(ctypes.Structure):
     _fields_ = [("iters_run", c_i32), ("n_reached", c_i32), ("seconds", c_f64)]
 
@@ -55,6 +59,8 @@ SIGNATURES = {
     "pdf_default_params": (c_i32, [ctypes.POINTER(Params)]),
     "pdf_setup": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array), c_i32,
                           c_i32, ctypes.POINTER(Params), c_vp, ctypes.POINTER(c_vp)]),
+    "pdf_setup_freq": (c_i32, [ctypes.POINTER(Grid), ctypes.POINTER(Freq), ctypes.POINTER(Array),
+                               ctypes.POINTER(Array), c_i32, c_i32, ctypes.POINTER(Params), c_vp, ctypes.POINTER(c_vp)]),
     "pdf_tables_host": (c_i32, [ctypes.POINTER(Grid), c_f64, ctypes.POINTER(Array), ctypes.POINTER(Array),
                                 c_vp, c_vp, c_vp]),
     "pdf_set_data": (c_i32, [c_vp, c_vp]),
@@ -65,6 +71,7 @@ SIGNATURES = {
     "pdf_init_alpha_csi_noalloc": (c_i32, [c_vp, c_i32, c_vp]),
     "pdf_apply": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "pdf_mean_square": (c_i32, [c_i32, ctypes.c_int64, c_vp, c_vp, c_vp]),
+    "pdf_step_multi": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_image": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pdf_reconstruct": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                 ctypes.POINTER(Report)]),
@@ -222,9 +229,13 @@ def mean_abs2(x: torch.Tensor) -> float:
 
 
 class Solver:
-    """One measurement geometry with `batch` data sets on one GPU."""
+    """One measurement geometry with `batch` data sets on one GPU.
 
-    def __init__(self, M: int, side: float, freq_hz: float, tx, rx, K: int, batch: int = 1,
+    freq_hz may be a sequence of frequencies (one reconstruction, batch 1): then the
+    incidence axis of alpha, the gradient and the measured fields holds the frequencies
+    outermost (Ni = n_freq x antennas, [F][Ni][...] per instance)."""
+
+    def __init__(self, M: int, side: float, freq_hz, tx, rx, K: int, batch: int = 1,
                  params: Optional[Params] = None, precision: str = "fp32", device: str = "cuda:0",
                  cx: float = 0.0, cy: float = 0.0):
         lib = load()
@@ -234,16 +245,25 @@ class Solver:
         self.cdtype = torch.complex128 if self.precision == "fp64" else torch.complex64
         self.rdtype = torch.float64 if self.precision == "fp64" else torch.float32
         self.M, self.K, self.B = M, K, batch
-        self.Ni, self.Ns = len(tx), len(rx)
+        freqs = np.atleast_1d(np.asarray(freq_hz, dtype=np.float64))
+        self.F = int(freqs.size)
+        self.Ni, self.Ns = self.F * len(tx), len(rx)
         self.stream = torch.cuda.Stream(self.device)
         g = Grid(M, side, cx, cy)
         ta, self._tx = _array(tx)
         ra, self._rx = _array(rx)
         h = ctypes.c_void_p()
         torch.cuda.current_stream(self.device).synchronize()
-        _check(lib.pdf_setup(ctypes.byref(g), freq_hz, ctypes.byref(ta), ctypes.byref(ra), K, batch,
-                             ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
-                             ctypes.byref(h)))
+        if self.F == 1:
+            _check(lib.pdf_setup(ctypes.byref(g), float(freqs[0]), ctypes.byref(ta), ctypes.byref(ra), K, batch,
+                                 ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h)))
+        else:
+            self._freqs = np.ascontiguousarray(freqs)
+            fr = Freq(self.F, self._freqs.ctypes.data_as(ctypes.POINTER(c_f64)))
+            _check(lib.pdf_setup_freq(ctypes.byref(g), ctypes.byref(fr), ctypes.byref(ta), ctypes.byref(ra), K,
+                                      batch, ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)))
         self.h = h
 
     # stream ordering around each library call
@@ -499,6 +519,29 @@ def reconstruct_multi(solvers, n_iter: int, n_check: int = 10, alphas=None, eps_
     for r in res:
         r.update(iters_run=rep.iters_run, seconds=rep.seconds)
     return res, dict(iters_run=rep.iters_run, n_reached=rep.n_reached, seconds=rep.seconds)
+
+
+def step_multi(solvers, alphas, ms, vs, ts, losses=None):
+    """One Adam step for each solver (any shapes) with its own alpha, m, v, t (and loss) tensors;
+    solvers of one shape class advance in grouped launches.  Equal to separate Solver.step calls."""
+    n = len(solvers)
+    if n < 1 or not (len(alphas) == len(ms) == len(vs) == len(ts) == n):
+        raise ValueError("one alpha, m, v and t per solver")
+    for i, s in enumerate(solvers):
+        s._want(alphas[i], s.alpha_shape, s.cdtype, f"alphas[{i}]", inplace=True)
+        s._want(ms[i], s.alpha_shape + (2,), s.rdtype, f"ms[{i}]", inplace=True)
+        s._want(vs[i], s.alpha_shape + (2,), s.rdtype, f"vs[{i}]", inplace=True)
+        s._want(ts[i], (s.B,), torch.int32, f"ts[{i}]", inplace=True)
+        if losses is not None:
+            s._want(losses[i], (s.B, LOSS_STRIDE), torch.float64, f"losses[{i}]", inplace=True)
+        s._enter()
+    arr = lambda vals: (c_vp * n)(*[None if v is None else v.data_ptr() for v in vals])
+    hs = (c_vp * n)(*[s.h.value for s in solvers])
+    rc = load().pdf_step_multi(n, hs, arr(alphas), arr(ms), arr(vs), arr(ts),
+                               arr(losses) if losses is not None else None)
+    for s in solvers:
+        s._leave()
+    _check(rc)
 
 
 class Mlp:

@@ -18,6 +18,7 @@
 #include "fcnn_kernels.h"
 #include "handle.h"
 #include "init_kernels.h"
+#include "mf_kernels.h"
 #include "pixel_kernels.h"
 #include "tables.h"
 
@@ -323,6 +324,8 @@ static ReduceArgs<T> reduce_args(pdf_handle* h, const cx<T>* J, const cx<T>* E, 
   a.chi = (cx<T>*)h->chi;
   a.lsp = h->lsp;
   a.Dpart = (cx<T>*)h->Dpart;
+  a.wsum = h->mf_wsum;
+  a.wgt = h->mf_w;
   a.Ni = h->Ni;
   a.Ns = h->Ns;
   a.N = h->N;
@@ -359,6 +362,9 @@ static int launch_reduce(pdf_handle* h, const cx<T>* J, const cx<T>* E, const cx
 template <typename T>
 static RegArgs<T> reg_args(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
   RegArgs<T> a;
+  a.nfreq = h->F;
+  a.dn = h->dn;
+  a.sdf = h->sdf;
   a.chi = (const cx<T>*)h->chi;
   a.R = (const cx<T>*)h->R;
   a.Dpart = (const cx<T>*)h->Dpart;
@@ -494,6 +500,7 @@ static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, 
   a.m = (T*)m;
   a.v = (T*)v;
   a.frozen = frozen;
+  a.gr_w = T(1);
   a.adam_c = h->adam_c;
   a.b1 = h->prm.adam_b1;
   a.b2 = h->prm.adam_b2;
@@ -504,10 +511,22 @@ static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, 
   return a;
 }
 
+// Several frequencies (defined below, after the single-frequency runners they call).
+template <typename T>
+static int run_iteration_mf(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
+                            void* v, int* tstep, const int* frozen);
+template <typename T>
+static int mf_forward(pdf_handle* h, const void* alpha);
+template <typename T>
+static int run_init_mf(pdf_handle* h, void* alpha_out);
+template <typename T>
+static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen);
+
 // One evaluation of loss and gradient; with Adam buffers, also the update.
 template <typename T>
 static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
                          void* v, int* tstep, const int* frozen) {
+  if (h->F > 1) return run_iteration_mf<T>(h, alpha, grad, loss, alpha_upd, m, v, tstep, frozen);
   int rc;
   const FwdArgs<T> f = fwd_args<T>(h, alpha);
   if ((rc = mark(h))) return rc;
@@ -547,7 +566,16 @@ struct Group {
   }
 };
 
-static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::vector<void*>& alphas) {
+// Caller-owned step state of each member (pdf_step_multi); absent: the handles' own
+// reconstruction state (pdf_reconstruct_multi).
+struct StepBufs {
+  std::vector<void*> m, v;
+  std::vector<int*> t;
+  std::vector<double*> loss;
+};
+
+static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::vector<void*>& alphas,
+                       const StepBufs* bufs = nullptr) {
   pdf_handle* h0 = hs[0];
   g->hs = hs;
   g->n = int(hs.size());
@@ -577,9 +605,10 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
     pdf_handle* h = hs[i];
     fwd[i] = fwd_args<float>(h, alphas[i]);
     red[i] = reduce_args<float>(h, (const cx<float>*)h->J, (const cx<float>*)h->E, nullptr);
-    reg[i] = reg_args<float>(h, h->loss, h->tstep, h->frozen);
+    reg[i] = bufs ? reg_args<float>(h, bufs->loss[i], bufs->t[i], nullptr) : reg_args<float>(h, h->loss, h->tstep, h->frozen);
     ag[i] = AdjGemmArgs{(const cx<float>*)h->gs, (const cx<float>*)h->dres, (cx<float>*)h->h, h->Ni, h->Ns, h->N};
-    adj[i] = adj_args<float>(h, nullptr, alphas[i], h->m, h->v, h->frozen);
+    adj[i] = bufs ? adj_args<float>(h, nullptr, alphas[i], bufs->m[i], bufs->v[i], nullptr)
+                  : adj_args<float>(h, nullptr, alphas[i], h->m, h->v, h->frozen);
     const int cnt[5] = {h->B * h->Ni, h->ntiles * h->B, h->B, g->nbx * h->B, h->B * h->Ni};
     for (int k = 0; k < 5; ++k) st[k * size_t(n + 1) + i + 1] = st[k * size_t(n + 1) + i] + cnt[k];
   }
@@ -718,6 +747,10 @@ static int group_iterate(const Group* g, int k) {
 template <typename T>
 static int run_loss(pdf_handle* h, const void* alpha, double* loss) {
   int rc;
+  if (h->F > 1) {
+    if ((rc = mf_forward<T>(h, alpha))) return rc;
+    return launch_reg<T>(h, loss, nullptr, nullptr);
+  }
   FwdArgs<T> f;
   f.in = (const cx<T>*)alpha;
   f.einc = (const cx<T>*)h->einc;
@@ -737,18 +770,22 @@ template <typename T>
 static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_out, const void* eps_true,
                      double* err) {
   int rc;
-  FwdArgs<T> f;
-  f.in = (const cx<T>*)alpha;
-  f.einc = (const cx<T>*)h->einc;
-  f.ghat = (const cx<T>*)h->ghat;
-  f.tw = (const cx<T>*)h->tw;
-  f.J = (cx<T>*)h->J;
-  f.E = (cx<T>*)h->E;
-  f.Ni = h->Ni;
-  f.K = h->K;
-  f.beta = T(h->prm.beta);
-  if ((rc = launch_fwd<T>(h, f, true))) return rc;
-  if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  if (h->F > 1) {
+    if ((rc = mf_forward<T>(h, alpha))) return rc;
+  } else {
+    FwdArgs<T> f;
+    f.in = (const cx<T>*)alpha;
+    f.einc = (const cx<T>*)h->einc;
+    f.ghat = (const cx<T>*)h->ghat;
+    f.tw = (const cx<T>*)h->tw;
+    f.J = (cx<T>*)h->J;
+    f.E = (cx<T>*)h->E;
+    f.Ni = h->Ni;
+    f.K = h->K;
+    f.beta = T(h->prm.beta);
+    if ((rc = launch_fwd<T>(h, f, true))) return rc;
+    if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, nullptr))) return rc;
+  }
   if (chi_out)
     HIP_TRY(hipMemcpyAsync(chi_out, h->chi, sizeof(cx<T>) * size_t(h->B) * h->N, hipMemcpyDeviceToDevice,
                            h->stream));
@@ -789,6 +826,7 @@ static int run_image(pdf_handle* h, const void* alpha, void* chi_out, void* cco_
 // Start value (Sec. 3.1): BP image, R_0, single exact-line-search step on L^CSI.
 template <typename T>
 static int run_init(pdf_handle* h, void* alpha_out) {
+  if (h->F > 1) return run_init_mf<T>(h, alpha_out);
   int rc;
   cx<T>* u = (cx<T>*)h->h;
   // u_p = G_S^H e_p
@@ -831,6 +869,7 @@ static int run_init(pdf_handle* h, void* alpha_out) {
   a.tw = (const cx<T>*)h->tw;
   a.galpha = (cx<T>*)h->g0;
   a.alpha = nullptr;
+  a.gr_w = T(1);
   a.Ni = h->Ni;
   a.K = h->K;
   a.beta = T(h->prm.beta);
@@ -916,6 +955,140 @@ static int run_csi(pdf_handle* h, int n_iter, void* alpha_out, void* ws) {
   return PDF_OK;
 }
 
+// ------------------------------------------------------------------ several frequencies
+//
+// A container handle (F > 1, batch 1) holds one handle per frequency.  Per
+// frequency: coefficients alpha_f = alpha + f Ni K^2 (the [F][Ni][K][K]
+// layout), the forward convolution, the pixel reduction (which also writes its
+// per-pixel sums weighted by 1/||E_inc,f||^2 into the container's wsum), the
+// data residual, G_S,f^H d_f and the adjoint.  Joint: the contrast R, chi,
+// den and lsp (k_mf_combine), the loss and the regulariser gradient
+// (the container's regulariser pass, L^Data = sum_f ||d_f||^2 / ||E_sca,f||^2),
+// the Adam step count and bias corrections.
+
+// Forward passes of every frequency and the joint contrast; data residual norms per frequency.
+template <typename T>
+static int mf_forward(pdf_handle* h, const void* alpha) {
+  int rc;
+  const size_t len = size_t(h->sub[0]->Ni) * h->K * h->K;
+  for (int f = 0; f < h->F; ++f) {
+    pdf_handle* s = h->sub[f];
+    if ((rc = launch_fwd<T>(s, fwd_args<T>(s, (const cx<T>*)alpha + f * len), true))) return fail(h, rc, s->err_msg);
+    if ((rc = launch_reduce<T>(s, (const cx<T>*)s->J, (const cx<T>*)s->E, nullptr))) return fail(h, rc, s->err_msg);
+  }
+  hipLaunchKernelGGL(k_mf_combine<T>, dim3(h->ntiles), dim3(256), 0, h->stream, (const double*)h->wsum, h->F, h->N,
+                     h->prm.beta, (const cx<T>*)nullptr, (cx<T>*)h->R, (T*)h->den, (cx<T>*)h->chi, h->lsp);
+  if ((rc = check_launch(h, "k_mf_combine"))) return rc;
+  for (int f = 0; f < h->F; ++f) {
+    pdf_handle* s = h->sub[f];
+    const int NO = s->Ni * s->Ns;
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, 1), dim3(256), 0, h->stream, (const cx<T>*)s->Dpart,
+                       s->ntiles, (const cx<T>*)s->esca, (cx<T>*)s->dres, NO);
+    hipLaunchKernelGGL(k_sumsq<T>, dim3(1), dim3(256), 0, h->stream, (const cx<T>*)s->dres, size_t(NO), h->dn + f);
+  }
+  return check_launch(h, "data residuals");
+}
+
+template <typename T>
+static int run_iteration_mf(pdf_handle* h, const void* alpha, void* grad, double* loss, void* alpha_upd, void* m,
+                            void* v, int* tstep, const int* frozen) {
+  int rc;
+  if ((rc = mf_forward<T>(h, alpha))) return rc;
+  if ((rc = launch_reg<T>(h, loss, tstep, frozen))) return rc;
+  const size_t len = size_t(h->sub[0]->Ni) * h->K * h->K;
+  for (int f = 0; f < h->F; ++f) {
+    pdf_handle* s = h->sub[f];
+    if ((rc = launch_adj_gemm<T>(s, (const cx<T>*)s->dres, (cx<T>*)s->h))) return fail(h, rc, s->err_msg);
+    AdjArgs<T> a = adj_args<T>(s, grad ? (cx<T>*)grad + f * len : nullptr,
+                               alpha_upd ? (cx<T>*)alpha_upd + f * len : nullptr, m ? (T*)m + 2 * f * len : nullptr,
+                               v ? (T*)v + 2 * f * len : nullptr, frozen);
+    a.R = (const cx<T>*)h->R;
+    a.den = (const T*)h->den;
+    a.gR = (const cx<T>*)h->gR;
+    a.adam_c = h->adam_c;
+    a.gr_w = T(1.0 / s->ss_host);
+    if ((rc = launch_adj<T>(s, a))) return fail(h, rc, s->err_msg);
+  }
+  return PDF_OK;
+}
+
+// Start value over all frequencies (Sec. 3.1 with the frequencies joined): the
+// back-propagation currents per frequency, the joint least-squares contrast
+// R_0, the gradient of the summed L^CSI at zero per frequency, and one exact
+// line-search step along it.
+template <typename T>
+static int run_init_mf(pdf_handle* h, void* alpha_out) {
+  int rc;
+  MfPairs<T> pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.F = h->F;
+  pr.Ni = h->sub[0]->Ni;
+  pr.N = h->N;
+  for (int f = 0; f < h->F; ++f) {
+    pdf_handle* s = h->sub[f];
+    cx<T>* u = (cx<T>*)s->h;
+    if ((rc = launch_adj_gemm<T>(s, (const cx<T>*)s->esca, u))) return fail(h, rc, s->err_msg);
+    if ((rc = launch_reduce<T>(s, u, u, nullptr))) return fail(h, rc, s->err_msg);
+    hipLaunchKernelGGL(k_bp_gamma<T>, dim3(s->Ni), dim3(256), 0, h->stream, (const cx<T>*)s->Dpart, s->ntiles,
+                       (const cx<T>*)s->esca, u, s->Ni, s->Ns, s->N);
+    FwdArgs<T> fa = fwd_args<T>(s, u);
+    fa.J = nullptr;
+    fa.beta = T(0);
+    if ((rc = launch_fwd<T>(s, fa, false))) return fail(h, rc, s->err_msg);
+    pr.J[f] = u;
+    pr.E[f] = (const cx<T>*)s->E;
+    pr.w[f] = 1.0 / s->ss_host;
+  }
+  hipLaunchKernelGGL(k_mf_bp_contrast<T>, dim3((h->N + 255) / 256), dim3(256), 0, h->stream, pr, h->prm.beta,
+                     (cx<T>*)h->R0);
+  if ((rc = check_launch(h, "k_mf_bp_contrast"))) return rc;
+  MfLineSearch<T> ls;
+  std::memset(&ls, 0, sizeof(ls));
+  ls.F = h->F;
+  const size_t len = size_t(h->sub[0]->Ni) * h->K * h->K;
+  for (int f = 0; f < h->F; ++f) {
+    pdf_handle* s = h->sub[f];
+    cx<T>* u = (cx<T>*)s->h;
+    if ((rc = launch_adj_gemm<T>(s, (const cx<T>*)s->esca, u))) return fail(h, rc, s->err_msg);
+    AdjArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.E = (const cx<T>*)s->einc;
+    a.e_shared = 1;
+    a.h = u;
+    a.R = (const cx<T>*)h->R0;
+    a.Ss = s->Ss;
+    a.Sd = s->Sd;
+    a.hsign = -1.0;
+    a.ghat = (const cx<T>*)s->ghat;
+    a.tw = (const cx<T>*)s->tw;
+    a.galpha = (cx<T>*)s->g0;
+    a.gr_w = T(1);
+    a.Ni = s->Ni;
+    a.K = s->K;
+    a.beta = T(s->prm.beta);
+    if ((rc = launch_adj<T>(s, a))) return fail(h, rc, s->err_msg);
+    hipLaunchKernelGGL(k_sumsq<T>, dim3(1), dim3(256), 0, h->stream, (const cx<T>*)s->g0, len, h->gn + f);
+    // curvature along g_f with R_0: A_d g = G_S,f J_g, A_s g = R_0 (G_D J_g + beta J_g) - beta J_g
+    FwdArgs<T> fa = fwd_args<T>(s, s->g0);
+    fa.einc = nullptr;
+    if ((rc = launch_fwd<T>(s, fa, true))) return fail(h, rc, s->err_msg);
+    if ((rc = launch_reduce<T>(s, (const cx<T>*)s->J, (const cx<T>*)s->E, (const cx<T>*)h->R0)))
+      return fail(h, rc, s->err_msg);
+    ls.Dpart[f] = (const cx<T>*)s->Dpart;
+    ls.lsp[f] = s->lsp;
+    ls.Sd[f] = s->Sd;
+    ls.Ss[f] = s->Ss;
+    ls.g0[f] = (const cx<T>*)s->g0;
+  }
+  ls.gn = h->gn;
+  ls.alpha = (cx<T>*)alpha_out;
+  ls.ntiles = h->sub[0]->ntiles;
+  ls.NO = h->sub[0]->Ni * h->Ns;
+  ls.len = int(len);
+  hipLaunchKernelGGL(k_mf_line_search<T>, dim3(1), dim3(256), 0, h->stream, ls);
+  return check_launch(h, "k_mf_line_search");
+}
+
 // ------------------------------------------------------------------ setup
 
 template <typename T>
@@ -974,6 +1147,7 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   if (!(ss > 0.0)) return fail(h, PDF_ENONFINITE, "||E_inc|| = 0");
   HIP_TRY(hipMalloc(&h->Ss, sizeof(double)));
   HIP_TRY(hipMemcpy(h->Ss, &ss, sizeof(double), hipMemcpyHostToDevice));
+  h->ss_host = ss;
   const size_t C = sizeof(cx<T>);
   const size_t B = h->B, Ni = h->Ni, Ns = h->Ns, N = h->N, KK = size_t(h->K) * h->K;
   HIP_TRY(hipMalloc(&h->Sd, sizeof(double) * B));
@@ -1039,6 +1213,7 @@ extern "C" int pdf_tables_host(const pdf_grid* grid, double freq_hz, const pdf_a
 
 extern "C" int pdf_timing(pdf_handle* h, int32_t enable, int32_t max_steps) {
   if (!h) return fail(h, PDF_EINVAL, "null handle");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "per-kernel timing covers single-frequency handles");
   h->timing = false;
   h->ev_used = 0;
   if (!enable) return PDF_OK;
@@ -1074,6 +1249,12 @@ extern "C" int pdf_timing_read(pdf_handle* h, double* avg_ms, int32_t* n_steps) 
 extern "C" void pdf_destroy(pdf_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (pdf_handle*& s : h->sub) {
+    pdf_destroy(s);
+    s = nullptr;
+  }
+  for (void* p : {(void*)h->wsum, (void*)h->dn, (void*)h->gn, (void*)h->sdf})
+    if (p) (void)hipFree(p);
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
@@ -1159,8 +1340,98 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   return PDF_OK;
 }
 
+// Container buffers of a handle over several frequencies (see mf_forward).
+template <typename T>
+static int setup_mf_buffers(pdf_handle* h) {
+  const size_t C = sizeof(cx<T>), N = h->N, KK = size_t(h->K) * h->K, len = size_t(h->Ni) * KK;
+  HIP_TRY(hipMalloc(&h->R, C * N));
+  HIP_TRY(hipMalloc(&h->den, sizeof(T) * N));
+  HIP_TRY(hipMalloc(&h->chi, C * N));
+  HIP_TRY(hipMalloc(&h->gR, C * N));
+  HIP_TRY(hipMalloc(&h->R0, C * N));
+  HIP_TRY(hipMalloc(&h->lsp, sizeof(double) * h->ntiles));
+  HIP_TRY(hipMalloc(&h->Ss, sizeof(double)));
+  const double one = 1.0;  // the joint state loss comes weighted by 1 / ||E_inc,f||^2 already
+  HIP_TRY(hipMemcpy(h->Ss, &one, sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&h->loss, sizeof(double) * 8));
+  HIP_TRY(hipMalloc(&h->loss_w, sizeof(double) * 8));
+  HIP_TRY(hipMalloc(&h->tstep, sizeof(int)));
+  HIP_TRY(hipMalloc(&h->frozen, sizeof(int)));
+  HIP_TRY(hipMalloc(&h->adam_c, 2 * sizeof(double)));
+  HIP_TRY(hipMalloc(&h->err, sizeof(double)));
+  HIP_TRY(hipMalloc(&h->m, 2 * sizeof(T) * len));
+  HIP_TRY(hipMalloc(&h->v, 2 * sizeof(T) * len));
+  HIP_TRY(hipMalloc(&h->wsum, sizeof(double) * 4 * N * h->F));
+  HIP_TRY(hipMalloc(&h->dn, sizeof(double) * h->F));
+  HIP_TRY(hipMalloc(&h->gn, sizeof(double) * h->F));
+  HIP_TRY(hipMalloc(&h->sdf, sizeof(double) * h->F));
+  if (h->big) HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * 4 * N + sizeof(double) * ((N + 255) / 256) * 2));
+  return PDF_OK;
+}
+
+extern "C" int pdf_setup_freq(const pdf_grid* grid, const pdf_freq* freq, const pdf_array* tx, const pdf_array* rx,
+                              int32_t K, int32_t batch, const pdf_params* params, void* stream, pdf_handle** out) {
+  if (!out) return fail(nullptr, PDF_EINVAL, "out is null");
+  *out = nullptr;
+  if (!freq || !freq->hz || freq->n_freq < 1 || freq->n_freq > kMaxFreq)
+    return fail(nullptr, PDF_EINVAL, "pdf_freq needs 1 to 8 frequencies");
+  if (freq->n_freq == 1) return pdf_setup(grid, freq->hz[0], tx, rx, K, batch, params, stream, out);
+  if (batch != 1)
+    return fail(nullptr, PDF_EUNSUPPORTED, "several frequencies: one reconstruction per handle (batch 1)");
+  pdf_handle* h = new pdf_handle();
+  h->F = freq->n_freq;
+  for (int f = 0; f < h->F; ++f) {
+    const int rc = pdf_setup(grid, freq->hz[f], tx, rx, K, 1, params, stream, &h->sub[f]);
+    if (rc) {
+      const std::string msg = g_last_error;
+      pdf_destroy(h);
+      return fail(nullptr, rc, "frequency " + std::to_string(f) + ": " + msg);
+    }
+  }
+  const pdf_handle* s0 = h->sub[0];
+  h->prec = s0->prec;
+  h->prm = s0->prm;
+  h->M = s0->M;
+  h->N = s0->N;
+  h->P = s0->P;
+  h->K = s0->K;
+  h->Ns = s0->Ns;
+  h->Ni = h->F * s0->Ni;
+  h->B = 1;
+  h->big = s0->big;
+  h->stream = s0->stream;
+  h->device = s0->device;
+  h->scratch_dev = s0->scratch_dev;
+  h->scratch_err = s0->scratch_err;
+  h->tile = 256;
+  h->ntiles = (h->N + 255) / 256;
+  const int rc = h->prec == PDF_FP32 ? setup_mf_buffers<float>(h) : setup_mf_buffers<double>(h);
+  if (rc) {
+    g_last_error = h->err_msg;
+    pdf_destroy(h);
+    return rc;
+  }
+  for (int f = 0; f < h->F; ++f) {
+    h->sub[f]->mf_wsum = h->wsum + size_t(f) * 4 * h->N;
+    h->sub[f]->mf_w = 1.0 / h->sub[f]->ss_host;
+  }
+  *out = h;
+  return PDF_OK;
+}
+
 extern "C" int pdf_set_data(pdf_handle* h, const void* esca_dev) {
   if (!h || !esca_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) {
+    const size_t csz = h->prec == PDF_FP32 ? 8 : 16;
+    const size_t per = size_t(h->sub[0]->Ni) * h->Ns * csz;
+    for (int f = 0; f < h->F; ++f) {
+      if (int rc = pdf_set_data(h->sub[f], static_cast<const char*>(esca_dev) + f * per))
+        return fail(h, rc, "frequency " + std::to_string(f) + ": " + h->sub[f]->err_msg);
+      HIP_TRY(hipMemcpyAsync(h->sdf + f, h->sub[f]->Sd, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
+    h->data_set = true;
+    return PDF_OK;
+  }
   const size_t csz = h->prec == PDF_FP32 ? 8 : 16;
   HIP_TRY(hipMemcpyAsync(h->esca, esca_dev, csz * size_t(h->B) * h->Ni * h->Ns, hipMemcpyDeviceToDevice,
                          h->stream));
@@ -1203,6 +1474,7 @@ extern "C" int pdf_step(pdf_handle* h, void* alpha_dev, void* m_dev, void* v_dev
 
 extern "C" int pdf_init_alpha_csi(pdf_handle* h, int32_t n_iter, void* alpha_dev) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the full CSI start covers single-frequency handles");
   if (n_iter < 1) return fail(h, PDF_EINVAL, "n_iter must be at least 1");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
   const size_t need = csi_workspace_bytes(h);
@@ -1220,6 +1492,7 @@ extern "C" int pdf_init_alpha_csi(pdf_handle* h, int32_t n_iter, void* alpha_dev
 
 extern "C" int pdf_init_alpha_csi_noalloc(pdf_handle* h, int32_t n_iter, void* alpha_dev) {
   if (!h || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the full CSI start covers single-frequency handles");
   if (n_iter < 1) return fail(h, PDF_EINVAL, "n_iter must be at least 1");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
   const size_t need = csi_workspace_bytes(h);
@@ -1305,6 +1578,7 @@ static int run_apply(pdf_handle* h, int op, const void* x, void* y) {
 
 extern "C" int pdf_apply(pdf_handle* h, int32_t op, const void* x_dev, void* y_dev) {
   if (!h || !x_dev || !y_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the linear pieces are per frequency: apply them to one frequency");
   if (op < PDF_OP_SYNTH || op > PDF_OP_GS_ADJ) return fail(h, PDF_EINVAL, "unknown operator");
   if (x_dev == y_dev) return fail(h, PDF_EINVAL, "x and y must not alias");
   return h->prec == PDF_FP32 ? run_apply<float>(h, op, x_dev, y_dev) : run_apply<double>(h, op, x_dev, y_dev);
@@ -1373,6 +1647,13 @@ static bool full_tile_fits(int M) {
 
 extern "C" int pdf_autotune(pdf_handle* h, int32_t reps, int32_t* choice, double* ms) {
   if (!h || reps < 1) return fail(h, PDF_EINVAL, "bad argument");
+  if (h->F > 1) {  // the frequency handles share one shape: tune the first, use its choice for all
+    if (int rc = pdf_autotune(h->sub[0], reps, choice, ms)) return fail(h, rc, h->sub[0]->err_msg);
+    const pdf_handle* s0 = h->sub[0];
+    for (int f = 1; f < h->F; ++f) pdf_set_tiles(h->sub[f], s0->tune_ct, s0->tune_pb, s0->tune_fpp, s0->tune_app);
+    h->tuned = true;
+    return PDF_OK;
+  }
   if (h->prec != PDF_FP32 || h->N % 32 != 0) {  // only FP32 handles have choices
     h->tuned = true;
     if (choice) choice[0] = h->tune_ct, choice[1] = h->tune_pb, choice[2] = h->tune_fpp, choice[3] = h->tune_app;
@@ -1428,6 +1709,7 @@ extern "C" int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_
   if (!h || (ct != 1 && ct != 2 && ct != 4) || (pb != 4 && pb != 8) || (fwd_pp != 0 && fwd_pp != 1) ||
       (adj_pp != 0 && adj_pp != 1))
     return fail(h, PDF_EINVAL, "bad tile choice");
+  for (int f = 0; f < h->F && h->F > 1; ++f) pdf_set_tiles(h->sub[f], ct, pb, fwd_pp, adj_pp);
   h->tune_ct = ct;
   h->tune_pb = pb;
   h->tune_fpp = fwd_pp;
@@ -1439,6 +1721,7 @@ extern "C" int pdf_set_tiles(pdf_handle* h, int32_t ct, int32_t pb, int32_t fwd_
 extern "C" int pdf_warm_start(pdf_handle* h, pdf_mlp* net, float s_in, float s_out, void* alpha_dev,
                               int32_t* chosen_dev, double* loss_dev) {
   if (!h || !net || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the warm start covers single-frequency handles");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
   if (h->prec != PDF_FP32) return fail(h, PDF_EUNSUPPORTED, "the warm start serves FP32 handles");
   int32_t n_in = 0, n_out = 0, bmax = 0;
@@ -1697,12 +1980,16 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
   d.g_stride[0] = d.g_stride[1] = size_t(n.R) * n.H;
   d.g[2] = F32 ? fc_real<T>(n.G3, n.D) : fc_split<T>(n.g, n.D, s_out);
   d.g_stride[2] = size_t(n.R) * (F32 ? n.D : n.Q);
+  // two columns per lane where every width and block offset is even (H even; D = 2 K^2 always is)
+  const bool v2 = F32 && n.H % 2 == 0 && n.P % 2 == 0;
+  const int rows_t = v2 ? FcAdamTile<2>::ROWS : FcAdamTile<1>::ROWS;
+  const int cols_t = v2 ? FcAdamTile<2>::COLS : FcAdamTile<1>::COLS;
   d.tile_start[0] = 0;
   for (int l = 0; l < 3; ++l) {
     d.n_in[l] = l == 0 ? n.D : n.H;
     d.n_out[l] = l == 2 ? n.D : n.H;
     d.off[l] = n.off[l];
-    const int tiles = ((d.n_in[l] + 1 + kFcAdamRows - 1) / kFcAdamRows) * ((d.n_out[l] + kFcCols - 1) / kFcCols);
+    const int tiles = ((d.n_in[l] + 1 + rows_t - 1) / rows_t) * ((d.n_out[l] + cols_t - 1) / cols_t);
     d.tile_start[l + 1] = d.tile_start[l] + tiles;
   }
   d.R = n.R;
@@ -1715,7 +2002,13 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
   d.eps = h->prm.adam_eps;
   d.lr1 = h->prm.lr / (1.0 - std::pow(h->prm.adam_b1, double(t)));
   d.ic2 = 1.0 / (1.0 - std::pow(h->prm.adam_b2, double(t)));
-  hipLaunchKernelGGL(k_fc_adam<T>, dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
+  if constexpr (F32) {
+    if (v2) {
+      hipLaunchKernelGGL((k_fc_adam<T, 2>), dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
+      return check_launch(h, "k_fc_adam");
+    }
+  }
+  hipLaunchKernelGGL((k_fc_adam<T, 1>), dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
   return check_launch(h, "k_fc_adam");
 }
 
@@ -1734,6 +2027,7 @@ static int fc_check_scales(pdf_handle* h, double s_in, double s_out) {
 extern "C" int pdf_fcnn_forward(pdf_handle* h, int32_t hidden, double s_in, double s_out, const void* alpha0_dev,
                                 const void* theta_dev, void* alpha_hat_dev) {
   if (!h || !alpha0_dev || !theta_dev || !alpha_hat_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the coefficient network covers single-frequency handles");
   if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
   int rc;
   if ((rc = fc_check_scales(h, s_in, s_out))) return rc;
@@ -1754,6 +2048,7 @@ extern "C" int pdf_fcnn_step(pdf_handle* h, int32_t hidden, double s_in, double 
                              double* loss_dev) {
   if (!h || !alpha0_dev || !theta_dev || !m_dev || !v_dev || !alpha_hat_dev)
     return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the coefficient network covers single-frequency handles");
   if (alpha_hat_dev == alpha0_dev) return fail(h, PDF_EINVAL, "alpha_hat must not alias alpha_0");
   if (t < 1) return fail(h, PDF_EINVAL, "the step number t counts from 1");
   if (!h->data_set) return fail(h, PDF_EINVAL, "pdf_set_data has not been called");
@@ -1822,6 +2117,7 @@ static int launch_analyze(pdf_handle* h, int n, const void* J, void* alpha) {
 
 extern "C" int pdf_analyze(pdf_handle* h, int32_t n, const void* J_dev, void* alpha_dev) {
   if (!h || !J_dev || !alpha_dev) return fail(h, PDF_EINVAL, "null argument");
+  if (h->F > 1) return fail(h, PDF_EUNSUPPORTED, "the analysis is per frequency: apply it to one frequency");
   if (n < 1) return fail(h, PDF_EINVAL, "n must be >= 1");
   return h->prec == PDF_FP32 ? launch_analyze<float>(h, n, J_dev, alpha_dev)
                              : launch_analyze<double>(h, n, J_dev, alpha_dev);
@@ -2083,7 +2379,7 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
   std::vector<std::unique_ptr<Unit>> units;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
-    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big)
+    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1)
       classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
     else {
       units.emplace_back(new Unit());
@@ -2114,6 +2410,86 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
     }
   }
   return reconstruct_all(units, n_iter, n_check, start_given, rep);
+}
+
+static int step_multi_impl(int32_t n, pdf_handle* const* hs, void* const* alpha_dev, void* const* m_dev,
+                           void* const* v_dev, int32_t* const* t_dev, double* const* loss_dev);
+
+extern "C" int pdf_step_multi(int32_t n, pdf_handle* const* hs, void* const* alpha_dev, void* const* m_dev,
+                              void* const* v_dev, int32_t* const* t_dev, double* const* loss_dev) {
+  g_last_error = "no error";
+  for (int i = 0; hs && i < n; ++i)
+    if (hs[i]) hs[i]->err_msg.clear();
+  const int rc = step_multi_impl(n, hs, alpha_dev, m_dev, v_dev, t_dev, loss_dev);
+  // the message of a failure goes to pdf_last_error(NULL) whichever handle it came from
+  for (int i = 0; rc && hs && i < n; ++i)
+    if (hs[i] && !hs[i]->err_msg.empty()) {
+      g_last_error = "handle " + std::to_string(i) + ": " + hs[i]->err_msg;
+      break;
+    }
+  return rc;
+}
+
+static int step_multi_impl(int32_t n, pdf_handle* const* hs, void* const* alpha_dev, void* const* m_dev,
+                           void* const* v_dev, int32_t* const* t_dev, double* const* loss_dev) {
+  if (n < 1 || !hs || !alpha_dev || !m_dev || !v_dev || !t_dev) return fail(nullptr, PDF_EINVAL, "pdf_step_multi: null argument");
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !alpha_dev[i] || !m_dev[i] || !v_dev[i] || !t_dev[i])
+      return fail(nullptr, PDF_EINVAL, "pdf_step_multi: null entry " + std::to_string(i));
+    if (!hs[i]->data_set) return fail(hs[i], PDF_EINVAL, "pdf_set_data has not been called");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i], PDF_EINVAL, "a handle appears twice");
+  }
+  // shape classes of FP32 handles as in pdf_reconstruct_multi; the class's first member's tile
+  // choice serves all (every choice computes the same values)
+  std::map<std::array<int, 4>, std::vector<int>> classes;
+  std::vector<int> single;
+  for (int i = 0; i < n; ++i) {
+    pdf_handle* h = hs[i];
+    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1)
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
+    else
+      single.push_back(i);
+  }
+  auto loss_of = [&](int i) { return loss_dev ? loss_dev[i] : nullptr; };
+  for (auto& kv : classes)
+    if (kv.second.size() == 1) single.push_back(kv.second[0]);
+  for (int i : single)
+    if (int rc = pdf_step(hs[i], alpha_dev[i], m_dev[i], v_dev[i], t_dev[i], loss_of(i))) return rc;
+  for (auto& kv : classes) {
+    const std::vector<int>& idx = kv.second;
+    if (idx.size() < 2) continue;
+    std::vector<pdf_handle*> gh;
+    std::vector<void*> ga;
+    StepBufs sb;
+    for (int i : idx) {
+      gh.push_back(hs[i]);
+      ga.push_back(alpha_dev[i]);
+      sb.m.push_back(m_dev[i]);
+      sb.v.push_back(v_dev[i]);
+      sb.t.push_back(t_dev[i]);
+      sb.loss.push_back(loss_of(i));
+    }
+    pdf_handle* h = gh[0];
+    Group g;
+    if (int rc = group_build(&g, gh, ga, &sb)) return rc;
+    // the lead stream waits for every member's stream, runs the grouped step, and every member's
+    // stream waits for it
+    std::vector<hipEvent_t> ev(gh.size(), nullptr);
+    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (size_t k = 1; k < gh.size(); ++k) {
+      HIP_TRY(hipEventRecord(ev[k], gh[k]->stream));
+      HIP_TRY(hipStreamWaitEvent(h->stream, ev[k], 0));
+    }
+    const int rc = group_iterate(&g, 1);
+    HIP_TRY(hipEventRecord(ev[0], h->stream));
+    for (size_t k = 1; k < gh.size(); ++k) HIP_TRY(hipStreamWaitEvent(gh[k]->stream, ev[0], 0));
+    // the argument table is freed when g leaves this scope: wait for the launches that read it
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+  }
+  return PDF_OK;
 }
 
 extern "C" const char* pdf_last_error(const pdf_handle* h) {

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_big_adj_rows(AdjArgs<T> a, cx<T>* __res
     cx<T> gJ = (-beta) * gs + wd * a.h[off + n];
     if (a.gR) {
       const cx<T> g = a.gR[boff + n];
-      const T inv = T(1) / a.den[boff + n];
+      const T inv = a.gr_w / a.den[boff + n];
       const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
       gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
       gJ = gJ + (beta * inv) * (g * E);

@@ -404,6 +404,7 @@ struct AdjArgs {
   T* m;
   T* v;
   const int* frozen;   // [B] nonzero: skip the update, or null
+  T gr_w;              // weight of the regulariser part (1; 1 / ||E_inc,f||^2 when den sums frequencies)
   const double* adam_c;  // [B][2] lr / (1 - b1^t), 1 / (1 - b2^t) of this step (with alpha)
   double b1, b2, eps;
   int Ni, K;
@@ -476,7 +477,7 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
       cx<T> gJ = (-beta) * gs + wd * Hv[q];
       if (has_gr) {
         const cx<T> g = Gv[q];
-        const T inv = T(1) / Dv[q];
+        const T inv = a.gr_w / Dv[q];
         const T re = g.x * R.x + g.y * R.y;  // Re(conj(g) R)
         gE = gE + inv * (beta * cmul_conj_a(g, J) - (T(2) * re) * E);
         gJ = gJ + (beta * inv) * (g * E);

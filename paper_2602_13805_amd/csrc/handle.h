@@ -58,6 +58,19 @@ struct pdf_handle {
   void* S = nullptr;        // [B][Ni][M][2M]
   void* GJ = nullptr;       // [B][Ni][N]
   void* big_ws = nullptr;
+  // several frequencies: F > 1 makes this handle the container of one handle
+  // per frequency (batch 1 each), joined through the shared contrast; its own
+  // per-pixel buffers (R, den, chi, gR, lsp) hold the joint values
+  int F = 1;
+  pdf_handle* sub[8] = {};
+  double* mf_wsum = nullptr;   // a frequency handle: where its pixel reduction writes weighted sums (or null)
+  double mf_w = 1.0;           // and their weight 1 / ||E_inc||^2
+  double ss_host = 0.0;        // ||E_inc||^2 on the host
+  double* wsum = nullptr;      // container: [F][N][4] weighted pixel sums
+  double* one = nullptr;       // container: device 1.0 (the joint state loss is weighted already)
+  double* dn = nullptr;        // container: [F] ||G_S,f J_f - E_sca,f||^2
+  double* gn = nullptr;        // container: [F] ||g_f||^2 of the start value
+  double* sdf = nullptr;       // container: [F] ||E_sca,f||^2
   // coefficient-network workspace (activations and gradients of one step), grown on demand
   void* fc_ws = nullptr;
   size_t fc_bytes = 0;

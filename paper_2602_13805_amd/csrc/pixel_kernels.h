@@ -51,6 +51,8 @@ struct ReduceArgs {
   cx<T>* chi;           // [B][N] out
   double* lsp;          // [B][ntiles] out: partial sum_p |R E_p - beta J_p|^2
   cx<T>* Dpart;         // [B][ntiles][Ni][Ns] out: partial G_S J over the tile
+  double* wsum;         // null, or [B][N][4] out: wgt (Re num, Im num, den, sum |J|^2) per pixel
+  double wgt;
   int Ni, Ns, N, ntiles;
   T beta;
 };
@@ -99,6 +101,13 @@ __global__ __launch_bounds__(256) void k_pixel_reduce(ReduceArgs<T> a) {
     // sum_p |R E_p - beta J_p|^2
     lpix = (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
     a.den[size_t(b) * a.N + n] = T(dd);
+    if (a.wsum) {
+      double* ws = a.wsum + (size_t(b) * a.N + n) * 4;
+      ws[0] = a.wgt * nr;
+      ws[1] = a.wgt * ni;
+      ws[2] = a.wgt * dd;
+      ws[3] = a.wgt * jj;
+    }
     // chi = R / (beta (1 - R))
     const double xr = 1.0 - rr, xi = -ri;
     const double q = beta * (xr * xr + xi * xi);
@@ -237,6 +246,13 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
       }
       lpix += (rr * rr + ri * ri) * dd - 2.0 * beta * (rr * nr + ri * ni) + beta * beta * jj;
       a.den[size_t(b) * N + n] = float(dd);
+      if (a.wsum) {
+        double* ws = a.wsum + (size_t(b) * N + n) * 4;
+        ws[0] = a.wgt * nr;
+        ws[1] = a.wgt * ni;
+        ws[2] = a.wgt * dd;
+        ws[3] = a.wgt * jj;
+      }
       const double xr = 1.0 - rr, xi = -ri;
       const double q = beta * (xr * xr + xi * xi);
       a.chi[size_t(b) * N + n] = cx<float>{float((rr * xr + ri * xi) / q), float((ri * xr - rr * xi) / q)};
@@ -331,6 +347,9 @@ __global__ __launch_bounds__(256, (NRT * NCT <= 2 && PB <= 4 ? 4 : 2)) void k_pi
 
 template <typename T>
 struct RegArgs {
+  int nfreq;            // > 1: L^Data = sum_f dn[f] / sdf[f] (per-frequency residual norms given)
+  const double* dn;     // [nfreq] ||G_S,f J_f - E_sca,f||^2
+  const double* sdf;    // [nfreq] ||E_sca,f||^2
   const cx<T>* chi;     // [B][N]
   const cx<T>* R;       // [B][N]
   const cx<T>* Dpart;   // [B][ntiles][Ni][Ns]
@@ -417,7 +436,7 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
     a.adam_c[2 * b + 1] = 1.0 / (1.0 - pow(a.b2, double(t)));
   }
   double dsum = 0.0;
-  const int NO = a.Ni * a.Ns;
+  const int NO = a.nfreq > 1 ? 0 : a.Ni * a.Ns;
   for (int o = tid; o < NO; o += nt) {
     double xr = 0.0, xi = 0.0;
     for (int t = 0; t < a.ntiles; ++t) {
@@ -469,7 +488,11 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
     double ls = 0.0;
     for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
     ls /= a.Ss[0];
-    const double ld = Sd / a.Sd[b];
+    double ld = 0.0;
+    if (a.nfreq > 1)
+      for (int f = 0; f < a.nfreq; ++f) ld += a.dn[f] / a.sdf[f];
+    else
+      ld = Sd / a.Sd[b];
     const double tot = ls + ld + a.lam_bound * Sb + a.lam_tv * St + a.lam_bridge * Sr;
     double* L = a.loss + size_t(b) * 8;
     L[0] = ls;

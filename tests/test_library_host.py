@@ -61,7 +61,7 @@ def test_ctypes_layout_matches_c(tmp_path):
     prog = tmp_path / "layout.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdf.h"', 'int main(void) {']
     for cname, py in (("pdf_params", B.Params), ("pdf_grid", B.Grid), ("pdf_array", B.Array),
-                      ("pdf_report", B.Report)):
+                      ("pdf_report", B.Report), ("pdf_freq", B.Freq)):
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
@@ -71,7 +71,7 @@ def test_ctypes_layout_matches_c(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = []
-    for py in (B.Params, B.Grid, B.Array, B.Report):
+    for py in (B.Params, B.Grid, B.Array, B.Report, B.Freq):
         want.append(ctypes.sizeof(py))
         want += [getattr(py, f).offset for f, _ in py._fields_]
     assert got == want
