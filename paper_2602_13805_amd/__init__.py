@@ -15,8 +15,8 @@ advances solvers of different shapes together; ``synthesize`` and
 """
 from .binding import (FP32, FP64, LOSS_NAMES, LOSS_STRIDE, Mlp, PdfError, PdfLoss, Solver, default_params,
                       mean_abs2,
-                      load, reconstruct_multi, synthesize, synthesize_batch, tables_host)
+                      load, reconstruct_multi, step_multi, synthesize, synthesize_batch, tables_host)
 
 __all__ = ["FP32", "FP64", "LOSS_NAMES", "LOSS_STRIDE", "Mlp", "PdfError", "PdfLoss", "Solver", "default_params",
            "mean_abs2",
-           "load", "reconstruct_multi", "synthesize", "synthesize_batch", "tables_host"]
+           "load", "reconstruct_multi", "step_multi", "synthesize", "synthesize_batch", "tables_host"]

@@ -16,6 +16,8 @@
 // kernel over all layers (k_fc_adam).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
@@ -376,84 +378,120 @@ struct FcAdamArgs {
 
 // Weight gradients dW[k][n] = sum_r in[r][k] g[r][n] (in[r][n_in] = 1: bias row)
 // of every layer, each followed at once by its bias-corrected Adam update.
-// Grid (tiles per reconstruction, B), 256 threads; a tile is 64 rows x 64
-// columns of one layer's block, 16 rows per wave, so each staged gradient
-// tile serves 64 weight rows.
-template <typename T>
+// Grid (tiles per reconstruction, B), 256 threads; a tile is 64 / V rows x
+// 64 V columns of one layer's block, 16 / V rows per wave and V adjacent
+// columns per lane (V = 2: every theta, m, v access moves two values, which
+// halves the memory instructions; it needs even widths and block offsets), so
+// each staged gradient tile serves 64 / V weight rows.  Each weight's sum runs
+// over the rows in the same order for either V.
+template <int V>
+struct FcAdamTile {
+  static constexpr int ROWS = kFcAdamRows / V, COLS = kFcCols * V, RW = ROWS / 4;
+};
+
+template <typename T, int V>
 __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
-  constexpr int RW = kFcAdamRows / 4;   // weight rows per wave
-  __shared__ T Is[kFcMaxRows * kFcAdamRows];
-  __shared__ T Gs[kFcMaxRows * kFcCols];
+  using Tl = FcAdamTile<V>;
+  constexpr int ROWS = Tl::ROWS, COLS = Tl::COLS, RW = Tl::RW;
+  __shared__ T Is[kFcMaxRows * ROWS];
+  __shared__ T Gs[kFcMaxRows * COLS];
   const int b = blockIdx.y;
   int l = 0;
   while (l < 2 && int(blockIdx.x) >= a.tile_start[l + 1]) ++l;
   const int n_in = a.n_in[l], n_out = a.n_out[l];
-  const int ntn = (n_out + kFcCols - 1) / kFcCols;
+  const int ntn = (n_out + COLS - 1) / COLS;
   const int t = blockIdx.x - a.tile_start[l];
-  const int k0 = (t / ntn) * kFcAdamRows, n0 = (t % ntn) * kFcCols;
+  const int k0 = (t / ntn) * ROWS, n0 = (t % ntn) * COLS;
   FcRows<T> in = a.in[l], g = a.g[l];
   if (in.cxv) in.cxv += size_t(b) * a.in_stride[l]; else in.re += size_t(b) * a.in_stride[l];
   if (g.cxv) g.cxv += size_t(b) * a.g_stride[l]; else g.re += size_t(b) * a.g_stride[l];
   const int R = a.R;
-  constexpr int NI = kFcMaxRows * kFcAdamRows / kFcThreads, NG = kFcMaxRows * kFcCols / kFcThreads;
+  constexpr int NI = kFcMaxRows * ROWS / kFcThreads, NG = kFcMaxRows * COLS / kFcThreads;
   T iv[NI], gv_[NG];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    const int e = threadIdx.x + i * kFcThreads, r = e / kFcAdamRows, k = k0 + e % kFcAdamRows;
+    const int e = threadIdx.x + i * kFcThreads, r = e / ROWS, k = k0 + e % ROWS;
     iv[i] = (r < R && k < n_in) ? in.at(r, k) : (k == n_in ? T(1) : T(0));
   }
 #pragma unroll
   for (int i = 0; i < NG; ++i) {
-    const int e = threadIdx.x + i * kFcThreads, r = e / kFcCols, n = n0 + e % kFcCols;
+    const int e = threadIdx.x + i * kFcThreads, r = e / COLS, n = n0 + e % COLS;
     gv_[i] = (r < R && n < n_out) ? g.at(r, n) : T(0);
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int e = threadIdx.x + i * kFcThreads;
-    if (e < R * kFcAdamRows) Is[e] = iv[i];
+    if (e < R * ROWS) Is[e] = iv[i];
   }
 #pragma unroll
   for (int i = 0; i < NG; ++i) {
     const int e = threadIdx.x + i * kFcThreads;
-    if (e < R * kFcCols) Gs[e] = gv_[i];
+    if (e < R * COLS) Gs[e] = gv_[i];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + lane;
-  if (n >= n_out) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = n0 + V * lane;
+  if (n >= n_out) return;   // with V = 2 and an even width, n + 1 < n_out too
   const size_t base = size_t(b) * a.theta_stride + a.off[l];
   // every row's theta, m, v requested before the gradient is formed (their HBM
   // latency overlaps the LDS products) and before the first store (the three
   // arrays may not be proven disjoint, so loads after a store would wait for it)
-  T th[RW], mo[RW], ve[RW];
+  using VT = typename std::conditional<V == 2, typename std::conditional<sizeof(T) == 4, float2, double2>::type,
+                                       T>::type;
+  VT th[RW], mo[RW], ve[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
     const int k = k0 + wv * RW + i;
     const size_t idx = base + size_t(k) * n_out + n;
-    th[i] = k <= n_in ? a.theta[idx] : T(0);
-    mo[i] = k <= n_in ? a.m[idx] : T(0);
-    ve[i] = k <= n_in ? a.v[idx] : T(0);
+    if (k <= n_in) {
+      th[i] = *reinterpret_cast<const VT*>(a.theta + idx);
+      mo[i] = *reinterpret_cast<const VT*>(a.m + idx);
+      ve[i] = *reinterpret_cast<const VT*>(a.v + idx);
+    } else {
+      th[i] = VT{};
+      mo[i] = VT{};
+      ve[i] = VT{};
+    }
   }
-  T acc[RW];
+  T acc[RW][V];
 #pragma unroll
-  for (int i = 0; i < RW; ++i) acc[i] = T(0);
+  for (int i = 0; i < RW; ++i)
+#pragma unroll
+    for (int c = 0; c < V; ++c) acc[i][c] = T(0);
   for (int r = 0; r < R; ++r) {
-    const T gv = Gs[r * kFcCols + lane];
-    const T* irow = Is + r * kFcAdamRows + wv * RW;
+    T gv[V];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] += irow[i] * gv;
+    for (int c = 0; c < V; ++c) gv[c] = Gs[r * COLS + V * lane + c];
+    const T* irow = Is + r * ROWS + wv * RW;
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+      for (int c = 0; c < V; ++c) acc[i][c] += irow[i] * gv[c];
   }
   const T b1 = T(a.b1), b2 = T(a.b2), lr1 = T(a.lr1), ic2 = T(a.ic2), eps = T(a.eps);
+  auto upd = [&](T gw, T th0, T m0, T v0, T& th1, T& m1, T& v1) {
+    m1 = b1 * m0 + (T(1) - b1) * gw;
+    v1 = b2 * v0 + (T(1) - b2) * (gw * gw);
+    th1 = th0 - lr1 * m1 / (sqrt(v1 * ic2) + eps);
+  };
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
     const int k = k0 + wv * RW + i;
     if (k > n_in) break;
     const size_t idx = base + size_t(k) * n_out + n;
-    const T gw = acc[i];
-    const T mm = b1 * mo[i] + (T(1) - b1) * gw;
-    const T vv = b2 * ve[i] + (T(1) - b2) * (gw * gw);
-    a.m[idx] = mm;
-    a.v[idx] = vv;
-    a.theta[idx] = th[i] - lr1 * mm / (sqrt(vv * ic2) + eps);
+    if constexpr (V == 2) {
+      VT t1, m1, v1;
+      upd(acc[i][0], th[i].x, mo[i].x, ve[i].x, t1.x, m1.x, v1.x);
+      upd(acc[i][1], th[i].y, mo[i].y, ve[i].y, t1.y, m1.y, v1.y);
+      *reinterpret_cast<VT*>(a.m + idx) = m1;
+      *reinterpret_cast<VT*>(a.v + idx) = v1;
+      *reinterpret_cast<VT*>(a.theta + idx) = t1;
+    } else {
+      T t1, m1, v1;
+      upd(acc[i][0], th[i], mo[i], ve[i], t1, m1, v1);
+      a.m[idx] = m1;
+      a.v[idx] = v1;
+      a.theta[idx] = t1;
+    }
   }
 }
 

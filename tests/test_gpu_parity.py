@@ -481,3 +481,30 @@ def test_resume_100_plus_100_equals_200_steps(prec):
     assert torch.equal(a2, a) and torch.equal(m2, m) and torch.equal(v2, v) and torch.equal(t2, t)
     assert int(t2[0]) == 200
     s2.close()
+
+
+def test_step_multi_equals_separate_steps():
+    """A grouped step over handles of uneven shapes (two classes of several FP32 handles, an FP64
+    handle, a lone class member) equals separate steps bit for bit, and so do three steps in a row."""
+    specs = [(32, 9, 16, 24, "fp32", 2), (32, 7, 12, 20, "fp32", 1), (32, 11, 16, 24, "fp32", 3),
+             (16, 7, 6, 8, "fp32", 2), (16, 5, 6, 8, "fp32", 1), (16, 7, 6, 8, "fp64", 2), (48, 9, 8, 12, "fp32", 1)]
+    solvers, states = [], []
+    for M, K, Ni, Ns, prec, B in specs:
+        case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
+        s = solver_for(case, prec)
+        solvers.append(s)
+        a = s.init_alpha()
+        states.append([a, *s.new_state()])
+    ref = [[x.clone() for x in st] for st in states]
+    for _ in range(3):
+        pdf.step_multi(solvers, *[[st[k] for st in states] for k in range(4)])
+        for s, st in zip(solvers, ref):
+            s.step(*st)
+    torch.cuda.synchronize()
+    for st, rf in zip(states, ref):
+        for x, y in zip(st, rf):
+            assert torch.equal(x, y)
+    with pytest.raises(pdf.PdfError):
+        pdf.step_multi([solvers[0], solvers[0]], *[[st[k] for st in states[:1] * 2] for k in range(4)])
+    for s in solvers:
+        s.close()
