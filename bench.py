@@ -336,6 +336,11 @@ def main():
                     help="instances per (beta, M_F, SNR) combination of the parameter-sweep leg (0: skip it)")
     ap.add_argument("--uneven", type=int, default=512,
                     help="instances of the uneven-shape batch leg (0: skip it)")
+    ap.add_argument("--large", type=int, default=500,
+                    help="Adam steps of the large multi-frequency leg (256x256, 4 frequencies, K=41; 0: skip it)")
+    ap.add_argument("--large-fields", metavar="NPZ",
+                    help="the large leg's measured fields: loaded from this file if it exists, else synthesised "
+                         "and written to it (with --save-fields: written, then exit)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
     ap.add_argument("--summary-kind", choices=["stats", "pmc", "mfma"], default="stats")
@@ -381,6 +386,8 @@ def main():
     synth_s = time.time() - t0
     if args.save_fields:
         np.savez(args.save_fields, esca=esca, eps=eps, seed0=0)
+        if args.large_fields:
+            large_fields(pdf, si, dev, args.large_fields)
         return
 
     if args.copy_calibration_mib:
@@ -493,6 +500,9 @@ def main():
     if args.uneven > 0:
         extra["uneven_batch"] = uneven_leg(pdf, si, wl, args.uneven, 200, dev)
         log(f"uneven batch: {extra['uneven_batch']}")
+    if args.large > 0:
+        extra["large_multifrequency"] = large_leg(pdf, si, args.large, dev, args.large_fields)
+        log(f"large multi-frequency: {extra['large_multifrequency']}")
     s.close()
 
     out = {
@@ -748,6 +758,15 @@ def positions_leg(pdf, si, wl, n_real, dev):
     es = pdf.synthesize_batch(wl.M_fine, wl.side, wl.freq_hz, txs, rxs, np.repeat(epsf[None], B, 0), tol=1e-10,
                               device=dev)
     synth_s = time.time() - t0
+    # what a position error does to the data: relative change of the measured field against the
+    # exact positions' (about linear in sigma); and, to separate it from the solver's own sensitivity
+    # to any data change, n_real data sets with exact positions and random noise of the same
+    # relative size as the 1 mm position errors' mean change
+    change = np.linalg.norm((es - es[0]).reshape(B, -1), axis=1) / np.linalg.norm(es[0])
+    nu = float(change[1:1 + n_real].mean())
+    extra = np.stack([si.add_noise(es[0], nu, *si.draw_noise(50000 + r, es[0].shape)) for r in range(n_real)])
+    es = np.concatenate([es, extra])
+    B = es.shape[0]
     s = pdf.Solver(wl.M, wl.side, wl.freq_hz, tx0, rx0, wl.K, batch=B, device=dev)
     s.set_data(torch.tensor(es, dtype=s.cdtype, device=dev))
     eps_t = torch.tensor(np.repeat(eps[None], B, 0), dtype=s.cdtype, device=dev)
@@ -759,14 +778,19 @@ def positions_leg(pdf, si, wl, n_real, dev):
     for sg in sigmas:
         n = n_real if sg > 0 else 1
         out[f"sigma={sg * 1e3:g}mm"] = dict(
-            realisations=n,
+            realisations=n, data_change=dict(mean=float(change[i:i + n].mean()), std=float(change[i:i + n].std())),
             direct=dict(mean=float(e_dir[i:i + n].mean()), std=float(e_dir[i:i + n].std())),
             network=dict(mean=float(e_net[i:i + n].mean()), std=float(e_net[i:i + n].std())))
         i += n
+    out["exact positions, noise of the 1 mm data change"] = dict(
+        realisations=n_real, relative_noise=nu,
+        direct=dict(mean=float(e_dir[i:].mean()), std=float(e_dir[i:].std())),
+        network=dict(mean=float(e_net[i:].mean()), std=float(e_net[i:].std())))
     s.close()
     return dict(instances=B, per_sigma=out, synthesis_seconds=synth_s,
                 recipe="cfg2 profile seed 0, FP64 MoM on 128x128 at displaced antennas, no noise; "
-                       "inversion with the nominal positions; image error after 100 iterations")
+                       "inversion with the nominal positions; image error after 100 iterations; data_change "
+                       "= ||E_sca - E_sca(exact positions)|| / ||E_sca(exact positions)||")
 
 
 def sweep_leg(pdf, si, wl, Bs, dev):
@@ -942,6 +966,91 @@ def uneven_leg(pdf, si, wl, n_inst, iters, dev):
                 sequential_instance_iters_per_s=work / seq_s, sequential_seconds=seq_s,
                 speedup_over_sequential=seq_s / multi_s, setup_seconds=setup_s,
                 tile_choices_by_instances=tiles)
+
+
+def large_fields(pdf, si, dev, path=None):
+    """Measured fields of the large multi-frequency leg [F][Ni][Ns] and the true permittivity:
+    from `path` if it exists, else synthesised (and written to `path` if given)."""
+    import numpy as np
+    wl = si.WORKLOADS["cfg5"]
+    shapes = si.draw_profile(wl, 0)
+    eps = si.rasterize(shapes, wl.M, wl.side)
+    if path and os.path.exists(path):
+        with np.load(path) as f:
+            return f["esca"], eps, 0.0
+    freqs = [wl.freq_hz * m for m in wl.freq_mult]
+    tx = si.antenna_positions(wl.n_tx, wl.radius)
+    rx = si.antenna_positions(wl.n_rx, wl.radius)
+    t0 = time.time()
+    es = []
+    for f, fr in enumerate(freqs):
+        # an iterative-solve tolerance far below the 5 % noise: at 2.5 x 400 MHz over 8 wavelengths
+        # BiCGSTAB stalls near 1e-5
+        e = pdf.synthesize_batch(wl.M, wl.side, fr, [tx], [rx], eps[None], tol=1e-4, device=dev)[0]
+        es.append(si.add_noise(e, wl.noise, *si.draw_noise(f, e.shape)))
+    es = np.stack(es)
+    if path:
+        np.savez(path, esca=es)
+    return es, eps, time.time() - t0
+
+
+def large_leg(pdf, si, iters, dev, fields=None):
+    """The large multi-frequency reconstruction: 256x256 over 8 wavelengths, 64 Tx / 64 Rx on a
+    10-wavelength circle, frequencies 1, 1.5, 2 and 2.5 x 400 MHz, K = 41 per incidence and frequency,
+    5-10 discs and rings with eps_r in [1.5, 3.5], 5 % noise, FP32; one contrast for all frequencies.
+    Measured fields: the library's FP64 MoM on the 256x256 grid itself (a 512x512 support has too many
+    pixels for the dense support solve), iterated to a relative residual of 1e-4.  Timed: `iters` Adam steps (loss, adjoint, update), after
+    the start value and a warm-up."""
+    import numpy as np
+    import torch
+    wl = si.WORKLOADS["cfg5"]
+    freqs = [wl.freq_hz * m for m in wl.freq_mult]
+    F, Ni, Ns, M, K = len(freqs), wl.n_tx, wl.n_rx, wl.M, wl.K
+    tx = si.antenna_positions(Ni, wl.radius)
+    rx = si.antenna_positions(Ns, wl.radius)
+    es, eps, synth_s = large_fields(pdf, si, dev, fields)
+    s = pdf.Solver(M, wl.side, freqs, tx, rx, K, batch=1, device=dev)
+    s.set_data(torch.tensor(es.reshape(1, F * Ni, Ns), dtype=s.cdtype, device=dev))
+    tuned, _ = s.autotune(3)
+    eps_t = torch.tensor(eps[None], dtype=s.cdtype, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a = s.init_alpha()
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t1) * 1e3
+    _, _, e0 = s.image(a, eps_t)
+    m, v, t = s.new_state()
+    loss = torch.empty((1, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
+    for _ in range(5):
+        s.step(a, m, v, t, loss)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(iters):
+        s.step(a, m, v, t, loss)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    _, _, e1 = s.image(a, eps_t)
+    lo = loss.cpu().numpy()[0]
+    if not np.isfinite(lo[5]):
+        raise RuntimeError("non-finite loss in the large multi-frequency leg")
+    floor = F * floor_bytes(M, Ni, Ns, K)
+    # flops per iteration: per frequency and incidence the forward and adjoint convolutions
+    # (2 x (row, column, row) length-2M transforms over the padded half), synthesis and analysis,
+    # plus the receiver GEMMs (8 N_s real flops per pixel and incidence, forward and adjoint)
+    P = 2 * M
+    conv = 2 * (2 * M * 5 * P * np.log2(P) + 2 * P * 5 * P * np.log2(P))
+    flops = F * Ni * (conv + 2 * (M + K) * 5 * M * np.log2(M) + 2 * 8 * Ns * M * M)
+    s.close()
+    return dict(grid=M, frequencies=freqs, n_tx=Ni, n_rx=Ns, K=K, precision="fp32", iterations=iters,
+                ms_per_iteration=dt / iters * 1e3, iters_per_s=iters / dt, start_ms=init_ms,
+                start_image_error=float(e0.item()), image_error_after=float(e1.item()),
+                loss_after=float(lo[5]), tiles=list(tuned), synthesis_seconds=synth_s,
+                effective_hbm=dict(floor_bytes=floor, GBps=floor / (dt / iters) / 1e9,
+                                   frac=floor / (dt / iters) / HBM_PEAK),
+                flops_per_iteration=float(flops), tflops=float(flops / (dt / iters) / 1e12),
+                adjoint="recompute mode: the adjoint keeps no FFT intermediates of the forward pass (only J "
+                        "and E) and recomputes its transforms",
+                data="FP64 MoM on the 256x256 inversion grid per frequency, 5 % noise; cfg5 profile seed 0")
 
 
 def floor_bytes(M, n_tx, n_rx, K, csz=8):

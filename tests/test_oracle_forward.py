@@ -106,3 +106,21 @@ def test_noise_level_and_reproducibility():
         noisy = forward.add_noise(e, nu, n1, n2)
         ratio = np.linalg.norm(noisy - e) / np.linalg.norm(e)
         assert abs(ratio / nu - 1) < 0.03
+
+
+def test_position_errors_change_the_data_linearly_in_sigma():
+    """The antenna-position study's premise: displacing every antenna by sigma times a fixed random
+    direction changes the scattered field by an amount proportional to sigma (first order), so the
+    relative data change at 2 sigma is twice that at sigma."""
+    wl = si.WORKLOADS["cfg1"]
+    k0 = ops.wavenumber(wl.freq_hz)
+    tx = si.antenna_positions(6, wl.radius)
+    rx = si.antenna_positions(8, wl.radius)
+    eps = si.rasterize(si.draw_profile(wl, 0), 16, wl.side)
+    e0, _ = forward.mom_solve(eps, wl.side, k0, tx, rx)
+    dt, dr = si.draw_position_errors(3, 6, 8, 1.0)
+    ch = []
+    for sg in (1e-4, 2e-4):
+        e, _ = forward.mom_solve(eps, wl.side, k0, tx + sg * dt, rx + sg * dr)
+        ch.append(np.linalg.norm(e - e0) / np.linalg.norm(e0))
+    assert abs(ch[1] / ch[0] - 2.0) < 0.01
