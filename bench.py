@@ -923,14 +923,17 @@ def uneven_leg(pdf, si, wl, n_inst, iters, dev):
     sols = []
     t0 = time.time()
     for (M, a, K), idx in sorted(groups.items()):
-        w = dataclasses.replace(wl, M=M, n_tx=a, n_rx=a, K=K, M_fine=2 * M)
-        txs, rxs, epsf = [], [], np.zeros((len(idx), 2 * M, 2 * M), np.complex128)
+        # fields from the MoM on the 2M grid; the 128^2 instances on their own grid, since a 256^2
+        # support of up to three cfg2 objects can exceed the dense support solve's 20000 pixels
+        Mf = 2 * M if 2 * M <= 128 else M
+        w = dataclasses.replace(wl, M=M, n_tx=a, n_rx=a, K=K, M_fine=Mf)
+        txs, rxs, epsf = [], [], np.zeros((len(idx), Mf, Mf), np.complex128)
         for j, seed in enumerate(idx):
             jt, jr = si.draw_jitter(seed, a, a, w.jitter_deg)
             txs.append(si.antenna_positions(a, w.radius, angle_offsets=jt))
             rxs.append(si.antenna_positions(a, w.radius, angle_offsets=jr))
-            epsf[j] = si.rasterize(si.draw_profile(w, seed), 2 * M, w.side)
-        es = pdf.synthesize_batch(2 * M, w.side, w.freq_hz, txs, rxs, epsf, tol=1e-10, device=dev)
+            epsf[j] = si.rasterize(si.draw_profile(w, seed), Mf, w.side)
+        es = pdf.synthesize_batch(Mf, w.side, w.freq_hz, txs, rxs, epsf, tol=1e-10, device=dev)
         for j, seed in enumerate(idx):
             n1, n2 = si.draw_noise(seed, es[j].shape)
             es[j] = si.add_noise(es[j], w.noise, n1, n2)
@@ -961,7 +964,7 @@ def uneven_leg(pdf, si, wl, n_inst, iters, dev):
                                          "(E_inc once, G_S and the G_D spectrum twice, data, alpha/m/v read "
                                          "and written), summed over the instances, per batched iteration"),
                 shapes="M from {32, 48, 64, 96, 128}, N_i = N_s from {16, 24, 32, 48, 64}, K odd 7..21 (K <= M), "
-                       "cfg2 profiles",
+                       "cfg2 profiles; fields from MoM on the 2M grid (128^2: on the 128^2 grid)",
                 instance_iters_per_s=work / multi_s, seconds=multi_s,
                 sequential_instance_iters_per_s=work / seq_s, sequential_seconds=seq_s,
                 speedup_over_sequential=seq_s / multi_s, setup_seconds=setup_s,
