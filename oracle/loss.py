@@ -17,6 +17,11 @@ Given Fourier coefficients alpha[F, N_i, K, K] (F frequencies, N_i incidences):
   L_Bridge = sum sigma((|chi| - tau_B)/tau_B) exp(-(D_x a)^2 - (D_y a)^2),
              a = sqrt(|chi|^2 + eps_abs)                          (Eq. 19)
   L = L_State + L_Data + lam1 L_Bound + lam2 L_TV + lam3 L_Bridge (Eqs. 13-14)
+With cco_in_loss (an option; the paper applies the CCO of Sec. 2.4 to the
+final image only) every chi-dependent term sees chi_c = CCO(chi) instead:
+the regularisers are evaluated on chi_c and the state residual takes
+R_c = beta chi_c / (1 + beta chi_c) (Eq. 7) in place of R, s = R_c E - beta J;
+the gradient runs through the CCO as well.
 D_x, D_y are forward differences with a zero difference on the last column /
 row.  Defaults: beta = 6 (Sec. 4.1), lam = 1e-3, 1e-5, 1e-5 (Sec. 3.2),
 tau_B = 0.5 (Sec. 3.2).
@@ -33,7 +38,7 @@ from typing import Optional
 
 import numpy as np
 
-from . import fourier, operators as ops
+from . import cco as occo, fourier, operators as ops
 
 
 @dataclasses.dataclass
@@ -45,6 +50,12 @@ class Params:
     tau_b: float = 0.5
     eps_tv: float = 1e-12
     eps_abs: float = 1e-12
+    cco_in_loss: bool = False
+    cco_tau: float = 3.0
+    cco_eta_max: float = 0.1
+    cco_delta: float = 0.5
+    gf_radius: int = 1
+    gf_eps: float = 1e-2
 
 
 @dataclasses.dataclass
@@ -179,17 +190,23 @@ def evaluate(alpha: np.ndarray, prob: Problem, grad: bool = True,
     den = np.einsum("f,fpij->ij", w, np.abs(E) ** 2)
     R = beta * num / den
     chi = R / (beta * (1.0 - R))
-    s = R[None, None] * E - beta * J
+    ckw = dict(tau=p.cco_tau, eta_max=p.cco_eta_max, delta=p.cco_delta, r=p.gf_radius, eps_gf=p.gf_eps)
+    if p.cco_in_loss:
+        chi_c = occo.cco(chi, **ckw)
+        R_c = beta * chi_c / (1.0 + beta * chi_c)
+    else:
+        chi_c, R_c = chi, R
+    s = R_c[None, None] * E - beta * J
     L_state = float(np.sum(w * np.sum(np.abs(s) ** 2, axis=(1, 2, 3))))
     Jflat = J.reshape(F, prob.Ni, M * M)
     D = np.einsum("fqn,fpn->fpq", prob.gs, Jflat)          # [F, Ni, Ns]
     d = D - prob.esca
     L_data = float(np.sum(np.sum(np.abs(d) ** 2, axis=(1, 2)) / prob.S_d))
-    Lb, gb = reg_bound(chi)
-    Lt, gt = reg_tv(chi, p.eps_tv)
-    Lr, gr = reg_bridge(chi, p.tau_b, p.eps_abs)
+    Lb, gb = reg_bound(chi_c)
+    Lt, gt = reg_tv(chi_c, p.eps_tv)
+    Lr, gr = reg_bridge(chi_c, p.tau_b, p.eps_abs)
     L = L_state + L_data + p.lam_bound * Lb + p.lam_tv * Lt + p.lam_bridge * Lr
-    out = dict(J=J, E=E, num=num, den=den, R=R, chi=chi, s=s, D=D, d=d,
+    out = dict(J=J, E=E, num=num, den=den, R=R, chi=chi, chi_c=chi_c, R_c=R_c, s=s, D=D, d=d,
                L_state=L_state, L_data=L_data, L_bound=Lb, L_tv=Lt, L_bridge=Lr, L=L)
     if not grad:
         return out
@@ -198,13 +215,19 @@ def evaluate(alpha: np.ndarray, prob: Problem, grad: bool = True,
     g_chi = p.lam_bound * gb + p.lam_tv * gt + p.lam_bridge * gr
     if r_stopgrad:
         g_R = np.zeros_like(R)
+    elif p.cco_in_loss:
+        # the state term through its contrast R_c = beta chi_c / (1 + beta chi_c), then back
+        # through the CCO to chi and R
+        g_chi = g_chi + np.conj(beta / (1.0 + beta * chi_c) ** 2) * 2.0 * (R_c * den - beta * num)
+        g_chi = occo.cco_vjp(chi, g_chi, **ckw)
+        g_R = np.conj(1.0 / (beta * (1.0 - R) ** 2)) * g_chi
     else:
         g_R = np.conj(1.0 / (beta * (1.0 - R) ** 2)) * g_chi
         # state term through R; zero when R is the exact least-squares optimum
         g_R = g_R + 2.0 * (R * den - beta * num)
     g_s = 2.0 * w[:, None, None, None] * s
     wf = w[:, None, None, None]
-    g_E = np.conj(R)[None, None] * g_s \
+    g_E = np.conj(R_c)[None, None] * g_s \
         + wf * (beta * np.conj(g_R)[None, None] * J
                 - 2.0 * np.real(np.conj(g_R) * R)[None, None] * E) / den[None, None]
     g_J = -beta * g_s + wf * beta * g_R[None, None] * E / den[None, None]
