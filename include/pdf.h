@@ -49,7 +49,7 @@ enum {
 
 enum { PDF_FP32 = 0, PDF_FP64 = 1 };
 
-#define PDF_PARAMS_VERSION 1
+#define PDF_PARAMS_VERSION 2
 #define PDF_LOSS_STRIDE 8   /* doubles per instance in a loss buffer */
 
 /* Loss buffer layout, per instance: [State, Data, Bound, TV, Bridge, Total,
@@ -86,6 +86,14 @@ typedef struct {
   double lr;           /* Adam learning rate (Sec. 3.3); paper: 1e-2                  */
   double adam_b1, adam_b2, adam_eps;   /* 0.9, 0.999, 1e-8                             */
   int32_t r_stopgrad;  /* 1: treat R as a constant in the gradient                     */
+  /* Added in version 2 (a version-1 struct ends before it and reads as 0). */
+  int32_t cco_in_loss; /* 1: evaluate the chi-dependent loss terms on chi_CCO (Sec. 2.4,
+                          Eqs. 10-11) instead of chi: the regularisers (Eqs. 17-19) on
+                          chi_CCO and the state residual (Eq. 15) with R_c = beta chi_CCO /
+                          (1 + beta chi_CCO), the gradient taken through the CCO.  The paper
+                          applies the CCO after the iterations only (0, the default).
+                          Single-frequency handles on grids up to 64 x 64 (96 x 96 in FP32);
+                          PDF_EUNSUPPORTED otherwise.                                  */
 } pdf_params;
 
 /* Fill *p with the paper's defaults (precision PDF_FP32).  Host only. */

@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                 ("cco_tau", c_f64), ("cco_eta_max", c_f64), ("cco_delta", c_f64),
                 ("gf_radius", c_i32), ("gf_eps", c_f64),
                 ("lr", c_f64), ("adam_b1", c_f64), ("adam_b2", c_f64), ("adam_eps", c_f64),
-                ("r_stopgrad", c_i32)]
+                ("r_stopgrad", c_i32), ("cco_in_loss", c_i32)]
 
 
 class Freq(ctypes.Structure):

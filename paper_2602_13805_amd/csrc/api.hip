@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "cco_loss_kernels.h"
 #include "conv_big.h"
 #include "conv_kernels.h"
 #include "fcnn_kernels.h"
@@ -393,12 +394,61 @@ static RegArgs<T> reg_args(pdf_handle* h, double* loss, int* tstep, const int* f
   a.eps_tv = h->prm.eps_tv;
   a.eps_abs = h->prm.eps_abs;
   a.r_stopgrad = h->prm.r_stopgrad;
+  a.lse = nullptr;
+  a.nlse = 0;
+  a.graw = 0;
   return a;
+}
+
+// The loss on the CCO image: chi_c and R_c from chi, the regularisers on chi_c
+// (their dL/dchi_c kept unconverted in gR), then the gradient back through the
+// CCO to g_R (unless R is held fixed).
+template <typename T>
+static int launch_reg_cco(pdf_handle* h, RegArgs<T> a) {
+  const int N = h->N, nblk = (N + 255) / 256;
+  CcoLossArgs<T> c;
+  c.chi = (const cx<T>*)h->chi;
+  c.R = (const cx<T>*)h->R;
+  c.den = (const T*)h->den;
+  c.Ss = h->Ss;
+  c.ws = (T*)h->ccl_ws;
+  c.chic = (cx<T>*)h->chic;
+  c.Rc = (cx<T>*)h->Rc;
+  c.part = h->ccl_part;
+  c.g = (cx<T>*)h->gR;
+  c.loss = a.loss;
+  c.M = h->M;
+  c.r = h->prm.gf_radius;
+  c.r_stopgrad = h->prm.r_stopgrad;
+  c.beta = h->prm.beta;
+  c.gf_eps = h->prm.gf_eps;
+  c.tau = h->prm.cco_tau;
+  c.eta_max = h->prm.cco_eta_max;
+  c.delta = h->prm.cco_delta;
+  const dim3 grid(nblk, h->B);
+  hipLaunchKernelGGL(k_ccl_coef<T>, grid, dim3(256), 0, h->stream, c);
+  hipLaunchKernelGGL(k_ccl_apply<T>, grid, dim3(256), 0, h->stream, c);
+  int rc = check_launch(h, "k_ccl_coef/apply");
+  if (rc) return rc;
+  a.chi = c.chic;
+  a.lse = h->ccl_part;
+  a.nlse = nblk;
+  a.graw = h->prm.r_stopgrad ? 0 : 1;
+  const size_t lds = sizeof(cx<T>) * size_t(N) + 16 * sizeof(double);
+  set_lds(k_image_reg<T>, lds);
+  hipLaunchKernelGGL(k_image_reg<T>, dim3(h->B), dim3(N < 1024 ? N : 1024), lds, h->stream, a);
+  if ((rc = check_launch(h, "k_image_reg"))) return rc;
+  if (h->prm.r_stopgrad) return PDF_OK;  // g_R = 0, written by the regulariser pass
+  hipLaunchKernelGGL(k_ccl_adj1<T>, grid, dim3(256), 0, h->stream, c);
+  hipLaunchKernelGGL(k_ccl_adj2<T>, grid, dim3(256), 0, h->stream, c);
+  hipLaunchKernelGGL(k_ccl_adj3<T>, grid, dim3(256), 0, h->stream, c);
+  return check_launch(h, "k_ccl_adj");
 }
 
 template <typename T>
 static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen) {
   const RegArgs<T> a = reg_args<T>(h, loss, tstep, frozen);
+  if (h->prm.cco_in_loss) return launch_reg_cco<T>(h, a);
   const int nt = h->N < 1024 ? h->N : 1024;
   if (h->big) {  // chi read from global memory
     hipLaunchKernelGGL((k_image_reg<T, true>), dim3(h->B), dim3(nt), 16 * sizeof(double), h->stream, a);
@@ -488,6 +538,7 @@ static AdjArgs<T> adj_args(pdf_handle* h, void* grad, void* alpha_upd, void* m, 
   a.e_shared = 0;
   a.h = (const cx<T>*)h->h;
   a.R = (const cx<T>*)h->R;
+  a.Rs = nullptr;
   a.den = (const T*)h->den;
   a.gR = (const cx<T>*)h->gR;
   a.Ss = h->Ss;
@@ -538,7 +589,9 @@ static int run_iteration(pdf_handle* h, const void* alpha, void* grad, double* l
   if ((rc = mark(h))) return rc;
   if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
   if ((rc = mark(h))) return rc;
-  if ((rc = launch_adj<T>(h, adj_args<T>(h, grad, alpha_upd, m, v, frozen)))) return rc;
+  AdjArgs<T> a = adj_args<T>(h, grad, alpha_upd, m, v, frozen);
+  if (h->prm.cco_in_loss) a.Rs = (const cx<T>*)h->Rc;  // the state residual's contrast
+  if ((rc = launch_adj<T>(h, a))) return rc;
   return mark(h);
 }
 
@@ -1179,6 +1232,12 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
     const size_t nblk = (N + 255) / 256;
     HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * B * 4 * N + sizeof(double) * B * nblk * 2));
   }
+  if (h->prm.cco_in_loss) {
+    HIP_TRY(hipMalloc(&h->ccl_ws, sizeof(T) * B * kCclArrays * N));
+    HIP_TRY(hipMalloc(&h->chic, sizeof(cx<T>) * B * N));
+    HIP_TRY(hipMalloc(&h->Rc, sizeof(cx<T>) * B * N));
+    HIP_TRY(hipMalloc(&h->ccl_part, sizeof(double) * B * ((N + 255) / 256)));
+  }
   return PDF_OK;
 }
 
@@ -1260,7 +1319,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
                   h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws, h->csi_ws, h->S,     h->GJ,
-                  h->big_ws};
+                  h->big_ws, h->ccl_ws, h->chic, h->Rc, h->ccl_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -1274,8 +1333,15 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
   if (rc) return rc;
   pdf_params prm;
   if (params) {
-    if (params->version != PDF_PARAMS_VERSION) return fail(nullptr, PDF_EINVAL, "pdf_params version mismatch");
-    prm = *params;
+    if (params->version == PDF_PARAMS_VERSION) {
+      prm = *params;
+    } else if (params->version == 1) {  // the version-1 struct ends before cco_in_loss
+      pdf_default_params(&prm);
+      std::memcpy(&prm, params, offsetof(pdf_params, cco_in_loss));
+      prm.version = PDF_PARAMS_VERSION;
+    } else {
+      return fail(nullptr, PDF_EINVAL, "pdf_params version mismatch");
+    }
   } else {
     pdf_default_params(&prm);
   }
@@ -1287,6 +1353,9 @@ extern "C" int pdf_setup(const pdf_grid* grid, double freq_hz, const pdf_array* 
     return fail(nullptr, PDF_EUNSUPPORTED, "M must be 8, 16, 32, 48, 64, 96, 128 or 256");
   if (rx->n > 64) return fail(nullptr, PDF_EUNSUPPORTED, "at most 64 receivers");
   if (!(prm.beta > 0) || prm.gf_radius < 0) return fail(nullptr, PDF_EINVAL, "beta must be > 0");
+  if (prm.cco_in_loss != 0 && prm.cco_in_loss != 1) return fail(nullptr, PDF_EINVAL, "cco_in_loss must be 0 or 1");
+  if (prm.cco_in_loss && big_grid(prm.precision, grid->M))
+    return fail(nullptr, PDF_EUNSUPPORTED, "the loss on the CCO image covers the LDS-resident grids");
   pdf_handle* h = new pdf_handle();
   h->prec = prm.precision;
   h->prm = prm;
@@ -1378,6 +1447,8 @@ extern "C" int pdf_setup_freq(const pdf_grid* grid, const pdf_freq* freq, const 
   if (freq->n_freq == 1) return pdf_setup(grid, freq->hz[0], tx, rx, K, batch, params, stream, out);
   if (batch != 1)
     return fail(nullptr, PDF_EUNSUPPORTED, "several frequencies: one reconstruction per handle (batch 1)");
+  if (params && params->version == PDF_PARAMS_VERSION && params->cco_in_loss)
+    return fail(nullptr, PDF_EUNSUPPORTED, "the loss on the CCO image covers single-frequency handles");
   pdf_handle* h = new pdf_handle();
   h->F = freq->n_freq;
   for (int f = 0; f < h->F; ++f) {
@@ -2379,7 +2450,7 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
   std::vector<std::unique_ptr<Unit>> units;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
-    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1)
+    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
       classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
     else {
       units.emplace_back(new Unit());
@@ -2446,7 +2517,7 @@ static int step_multi_impl(int32_t n, pdf_handle* const* hs, void* const* alpha_
   std::vector<int> single;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
-    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1)
+    if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
       classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
     else
       single.push_back(i);

@@ -392,6 +392,7 @@ struct AdjArgs {
   int e_shared;
   const cx<T>* h;      // [BP][N] G_S^H (data residual or measured field)
   const cx<T>* R;      // [B][N]
+  const cx<T>* Rs;     // [B][N] contrast of the state residual, or null (R): R_c with the loss on the CCO image
   const T* den;        // [B][N]  sum_p |E_p|^2
   const cx<T>* gR;     // [B][N] dL/dR from the regularisers, or null
   const double* Ss;    // ||E_inc||^2 (scalar)
@@ -417,7 +418,9 @@ struct AdjArgs {
 //   g_J = -beta g_s + beta g_R E / den + beta g_E + G_D^H g_E + 2 G_S^H d / ||E_sca||^2
 //   g_alpha = B^H g_J  (unnormalised forward DFT on the kept modes)
 // The state loss's own derivative in R vanishes because R is its per-pixel
-// least-squares minimiser, so only the regulariser part g_R reaches R.
+// least-squares minimiser, so only the regulariser part g_R reaches R.  With
+// the loss on the CCO image the residual takes R_c (Rs) in s and in g_E's
+// first term, and g_R carries the state term through the CCO as well.
 template <typename T, int M, bool PP>
 __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = ConvCfg<T, M>;
@@ -438,13 +441,13 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
   // g_J, which stays in registers through the convolution.
   constexpr int QB = C::PPT <= 4 ? C::PPT : (C::PPT % 4 == 0 ? 4 : (C::PPT % 3 == 0 ? 3 : (C::PPT % 2 == 0 ? 2 : 1)));
   static_assert(C::PPT % QB == 0, "whole batches");
-  const bool has_j = a.J != nullptr, has_gr = a.gR != nullptr;
+  const bool has_j = a.J != nullptr, has_gr = a.gR != nullptr, has_rs = a.Rs != nullptr;
   for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
   cx<T> gj[C::PPT];
   cx<T>* gjs = tw + C::P;  // [GJ_LDS][NT], each thread's own entries
 #pragma unroll
   for (int q0 = 0; q0 < C::PPT; q0 += QB) {
-    cx<T> Jv[QB], Ev[QB], Rv[QB], Hv[QB], Gv[QB];
+    cx<T> Jv[QB], Ev[QB], Rv[QB], Hv[QB], Gv[QB], Sv[QB];
     T Dv[QB];
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
@@ -467,13 +470,20 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
         Dv[q] = a.den[boff + tid + (q0 + q) * C::NT];
       }
     }
+    if (has_rs) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) Sv[q] = a.Rs[boff + tid + (q0 + q) * C::NT];
+    } else {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) Sv[q] = Rv[q];
+    }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int n = tid + (q0 + q) * C::NT;
-      const cx<T> J = Jv[q], E = Ev[q], R = Rv[q];
-      const cx<T> s = R * E - beta * J;
+      const cx<T> J = Jv[q], E = Ev[q], R = Rv[q], Rs = Sv[q];
+      const cx<T> s = Rs * E - beta * J;
       const cx<T> gs = ws * s;
-      cx<T> gE = cmul_conj_a(R, gs);
+      cx<T> gE = cmul_conj_a(Rs, gs);
       cx<T> gJ = (-beta) * gs + wd * Hv[q];
       if (has_gr) {
         const cx<T> g = Gv[q];

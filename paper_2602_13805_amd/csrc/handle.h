@@ -58,6 +58,12 @@ struct pdf_handle {
   void* S = nullptr;        // [B][Ni][M][2M]
   void* GJ = nullptr;       // [B][Ni][N]
   void* big_ws = nullptr;
+  // the loss on the CCO image (cco_in_loss): filter workspace [B][kCclArrays][N],
+  // chi_c and R_c [B][N], per-workgroup state sums [B][ceil(N / 256)]
+  void* ccl_ws = nullptr;
+  void* chic = nullptr;
+  void* Rc = nullptr;
+  double* ccl_part = nullptr;
   // several frequencies: F > 1 makes this handle the container of one handle
   // per frequency (batch 1 each), joined through the shared contrast; its own
   // per-pixel buffers (R, den, chi, gR, lsp) hold the joint values

@@ -367,6 +367,11 @@ struct RegArgs {
   int M, Ni, Ns, ntiles;
   double beta, lam_bound, lam_tv, lam_bridge, tau_b, eps_tv, eps_abs;
   int r_stopgrad;
+  // the loss on the CCO image: chi is chi_c, L^State gains the nlse sums lse
+  // [B][nlse] (over ||E_inc||^2 like the rest), and gR receives dL/dchi_c of
+  // the regularisers unconverted (graw)
+  const double* lse;
+  int nlse, graw;
 };
 
 template <typename T>
@@ -468,7 +473,9 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
     const cx<T> R = a.R[size_t(b) * N + n];
     rmax = fmax(rmax, sqrt(double(norm2(R))));
     cx<T> gR{T(0), T(0)};
-    if (!a.r_stopgrad) {
+    if (a.graw) {
+      gR = g;
+    } else if (!a.r_stopgrad) {
       // conj(1 / (beta (1 - R)^2)) * g
       const cx<T> om{T(1) - R.x, -R.y};
       const cx<T> w = om * om;
@@ -487,6 +494,7 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
   if (tid == 0 && a.loss) {
     double ls = 0.0;
     for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
+    for (int t = 0; t < a.nlse; ++t) ls += a.lse[size_t(b) * a.nlse + t];
     ls /= a.Ss[0];
     double ld = 0.0;
     if (a.nfreq > 1)

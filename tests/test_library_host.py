@@ -120,12 +120,32 @@ def test_argument_errors_without_device():
     p.version = 99
     assert lib.pdf_setup(ctypes.byref(g), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
                          ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EINVAL
-    p.version = 1
+    p.version = 1  # a version-1 struct (without cco_in_loss) is still accepted
     for m_bad, prec in ((40, B.FP32), (100, B.FP64), (512, B.FP32)):  # grids without a plan
         p.precision = prec
         gb = B.Grid(m_bad, 1.5, 0.0, 0.0)
         assert lib.pdf_setup(ctypes.byref(gb), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
                              ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EUNSUPPORTED, m_bad
+    p.precision = B.FP32
+    # the loss on the CCO image: 0 or 1 only, LDS-resident grids only (a current-version struct:
+    # version 1 ends before the field)
+    p.version = pdf.default_params().version
+    assert p.version == 2
+    p.cco_in_loss = 2
+    assert lib.pdf_setup(ctypes.byref(g), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
+                         ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EINVAL
+    assert b"cco_in_loss" in lib.pdf_last_error(None)
+    p.cco_in_loss = 1
+    for m_big, prec in ((128, B.FP32), (96, B.FP64)):
+        p.precision = prec
+        gb = B.Grid(m_big, 1.5, 0.0, 0.0)
+        assert lib.pdf_setup(ctypes.byref(gb), 4e8, ctypes.byref(arr), ctypes.byref(arr), 9, 1, ctypes.byref(p),
+                             ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EUNSUPPORTED, m_big
+    f2 = np.array([4e8, 5e8])
+    fr = B.Freq(2, f2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert lib.pdf_setup_freq(ctypes.byref(g), ctypes.byref(fr), ctypes.byref(arr), ctypes.byref(arr), 9, 1,
+                              ctypes.byref(p), ctypes.c_void_p(1), ctypes.byref(h)) == B.PDF_EUNSUPPORTED
+    p.cco_in_loss = 0
     p.precision = B.FP32
     bad = np.array([[np.nan, 0.0]] * 4)
     arr2 = B.Array(4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
