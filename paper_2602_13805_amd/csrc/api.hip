@@ -121,6 +121,11 @@ static void set_lds(K kernel, size_t bytes) {
                               int(bytes));
 }
 
+// The band-limited forward and adjoint on the compact tile: FP32 at 64 x 64 with K <= 32.
+static bool fwd_compact(const pdf_handle* h) {
+  return h->prec == PDF_FP32 && h->M == 64 && !h->big && h->K <= CompactCfg<float, 64>::KC;
+}
+
 template <typename T, int M, bool FA, bool PP>
 static void launch_fwd_t(pdf_handle* h, const FwdArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
@@ -132,6 +137,14 @@ static void launch_fwd_t(pdf_handle* h, const FwdArgs<T>& a, int nblk) {
 template <typename T, int M>
 static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int nblk) {
   using C = ConvCfg<T, M>;
+  if constexpr (sizeof(T) == 4 && M == 64) {
+    if (from_alpha && fwd_compact(h)) {  // every plan choice: one kernel from coefficients
+      using CC = CompactCfg<T, M>;
+      set_lds(k_fwd_conv_c<T, M>, CC::LDS);
+      hipLaunchKernelGGL((k_fwd_conv_c<T, M>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      return check_launch(h, "k_fwd_conv_c");
+    }
+  }
   if constexpr (C::fwd_lds(false, true) <= 160 * 1024) {
     // FP64 handles keep the default plan (no tuning there)
     const bool pp = sizeof(T) == 4 && h->tune_fpp != 0;
@@ -270,6 +283,14 @@ static void launch_adj_t(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
 template <typename T, int M>
 static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
   using C = ConvCfg<T, M>;
+  if constexpr (sizeof(T) == 4 && M == 64) {
+    if (fwd_compact(h)) {  // every plan choice: the band-limited adjoint on the compact tile
+      using CC = CompactCfg<T, M>;
+      set_lds(k_adj_conv_c<T, M>, CC::LDS);
+      hipLaunchKernelGGL((k_adj_conv_c<T, M>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      return check_launch(h, "k_adj_conv_c");
+    }
+  }
   if constexpr (C::adj_lds(false) <= 160 * 1024) {
     if constexpr (sizeof(T) == 4 && C::adj_lds(true) <= 160 * 1024) {
       if (h->tune_app != 0) {
@@ -613,6 +634,7 @@ struct Group {
   const int* st[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // [n + 1] workgroup starts per kernel
   int tot[5] = {0, 0, 0, 0, 0};
   int n = 0, M = 0, ntiles = 0, nbx = 0, nt_reg = 0, nrt = 0, nct = 0, nrta = 0, ct = 2, pb = 4, fpp = 0, app = 0;
+  bool compact = false;  // the forward on the compact tile (every member eligible)
   size_t lds_reg = 0, lds_ag = 0;
   ~Group() {
     if (dmem) (void)hipFree(dmem);
@@ -638,6 +660,8 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
   g->nct = (h0->Ni + 31) / 32;
   g->nrta = (h0->Ni + 15) / 16;
   g->ct = h0->tune_ct;
+  g->compact = true;
+  for (pdf_handle* h : hs) g->compact = g->compact && fwd_compact(h);
   g->pb = h0->tune_pb;
   g->fpp = h0->tune_fpp;
   g->app = h0->tune_app;
@@ -719,6 +743,19 @@ static void group_conv_m(const Group* g, hipStream_t st, bool adjoint) {
 }
 
 static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
+  if (g->compact) {
+    using CC = CompactCfg<float, 64>;
+    if (!adjoint) {
+      set_lds(k_fwd_conv_c_group<float, 64>, CC::LDS);
+      hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
+                         g->st[0], g->n);
+    } else {
+      set_lds(k_adj_conv_c_group<float, 64>, CC::LDS);
+      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
+                         g->st[4], g->n);
+    }
+    return;
+  }
   switch (g->M) {
     case 8: group_conv_m<8>(g, st, adjoint); break;
     case 16: group_conv_m<16>(g, st, adjoint); break;
@@ -2446,12 +2483,12 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
     rs.push_back(own.back().get());
   }
   // shape classes of FP32 handles: one tile choice each (tuned on the member with the largest batch)
-  std::map<std::array<int, 4>, std::vector<int>> classes;
+  std::map<std::array<int, 5>, std::vector<int>> classes;
   std::vector<std::unique_ptr<Unit>> units;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
     if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
-      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, fwd_compact(h) ? 1 : 0}].push_back(i);
     else {
       units.emplace_back(new Unit());
       units.back()->rs.push_back(rs[i]);
@@ -2513,12 +2550,12 @@ static int step_multi_impl(int32_t n, pdf_handle* const* hs, void* const* alpha_
   }
   // shape classes of FP32 handles as in pdf_reconstruct_multi; the class's first member's tile
   // choice serves all (every choice computes the same values)
-  std::map<std::array<int, 4>, std::vector<int>> classes;
+  std::map<std::array<int, 5>, std::vector<int>> classes;
   std::vector<int> single;
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
     if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
-      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16}].push_back(i);
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, fwd_compact(h) ? 1 : 0}].push_back(i);
     else
       single.push_back(i);
   }

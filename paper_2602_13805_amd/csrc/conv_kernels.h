@@ -81,26 +81,17 @@ struct ConvCfg {
 // forward path below): column c < M is spectrum column 2c + 1, column M + j
 // (j < ncols - M) is spectrum column 2 wrap(kmin + j); columns from ncols on
 // are skipped.  Otherwise column c is spectrum column c and all P are done.
-template <typename T, int M, bool BANDED = false>
-__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint,
-                                         int ncols = 2 * M, int kmin = 0) {
-  using C = ConvCfg<T, M>;
-  constexpr int P = C::P, EPT = C::EPT_C;
-  using F = Fft<T, M, EPT, C::NT, typename C::Cols, 2>;   // tw[2k] = exp(-2 pi i k / M)
+// The two chains of every column of the wave-local set `cols` (EPT elements
+// per thread, NT threads); spec_col(v) is the spectrum column of vector v.
+// Ends with each wavefront's own columns written back (no workgroup barrier).
+template <typename T, int M, int EPT, int NT, class V, class SpecCol>
+__device__ __forceinline__ void col_chains(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint, const V& cols,
+                                           const SpecCol& spec_col) {
+  constexpr int P = 2 * M;
+  using F = Fft<T, M, EPT, NT, V, 2>;                     // tw[2k] = exp(-2 pi i k / M)
   constexpr int R1 = F::radix(1), R2 = M / R1;            // forward radices R1 then R2, inverse R2 then R1
   static_assert(R2 == 1 || (R2 <= 16 && EPT % R2 == 0), "a chain takes one or two passes");
-  typename C::Cols cols;
-  cols.nv = ncols;
   const F f{buf, tw, cols};
-  auto spec_col = [&](int c) {
-    if constexpr (BANDED) {
-      if (c < M) return 2 * c + 1;
-      const int k = kmin + c - M;  // in (-M, M)
-      return 2 * (k < 0 ? k + M : k);
-    } else {
-      return c;
-    }
-  };
   typename F::Regs x;
   f.assign(x);
   f.template load<R1, 1, -1, R1>(x, NoLoad());  // butterfly j holds elements j + (M / R1) r
@@ -187,6 +178,24 @@ __device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T
       }
     }
   });
+}
+
+template <typename T, int M, bool BANDED = false>
+__device__ __forceinline__ void col_conv(cx<T>* buf, const cx<T>* tw, const cx<T>* ghat, bool adjoint,
+                                         int ncols = 2 * M, int kmin = 0) {
+  using C = ConvCfg<T, M>;
+  typename C::Cols cols;
+  cols.nv = ncols;
+  auto spec_col = [&](int c) {
+    if constexpr (BANDED) {
+      if (c < M) return 2 * c + 1;
+      const int k = kmin + c - M;  // in (-M, M)
+      return 2 * (k < 0 ? k + M : k);
+    } else {
+      return c;
+    }
+  };
+  col_chains<T, M, C::EPT_C, C::NT>(buf, tw, ghat, adjoint, cols, spec_col);
   __syncthreads();  // the row pass that follows reads every column
 }
 
@@ -385,6 +394,145 @@ __global__ __launch_bounds__((ConvCfg<T, M>::NT), (ConvCfg<T, M>::wpe(PP))) void
   fwd_conv_body<T, M, FROM_ALPHA, PP>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
+// ---- the band-limited forward on a compact tile
+//
+// From coefficients the tile needs only the M odd-frequency columns and the K
+// kept even ones, so a tile of M rows x (M + KC) columns (KC >= K) serves, and
+// column chains of 8 elements per thread keep the registers low: at M = 64 in
+// FP32 (KC = 32: 50 KB) three 512-thread workgroups share a CU instead of two.
+// The odd columns take one chain per 8 lanes on all wavefronts, the K even
+// columns a second round on the first wavefronts.  The cropped inverse row
+// transform runs on the M x M block twice: the odd part (times conj(w)) into
+// registers, then the even part placed back in natural order.  Same
+// arithmetic as fwd_conv_body up to the radices of the column chains.
+template <typename T, int M>
+struct CompactCfg {
+  static constexpr int KC = M / 2;            // largest K on the compact tile
+  static constexpr int PC = M + KC;           // row: M odd-frequency (pixel) columns, then KC even ones
+  using TileC = Tile<PC>;                     // row stride PC + 1 (odd)
+  static constexpr int NT = ConvCfg<T, M>::NT;
+  static constexpr int N = M * M, PPT = N / NT;
+  static constexpr int EPT = 8;               // basis transforms and column chains
+  static constexpr size_t LDS = sizeof(cx<T>) * (size_t(M) * TileC::LD + 2 * M);  // + the P twiddles
+  static constexpr int WPE = int((160 * 1024) / LDS) * (NT / 64) / 4 > 8 ? 8 : int((160 * 1024) / LDS) * (NT / 64) / 4;
+  using RowsM = Vecs<PC, M, true>;
+  using ModeCols = Vecs<PC, M, false, true>;
+};
+
+// Wave-local columns c0 .. c0 + nv - 1 of a Tile<TP> (at most NV of them).
+template <int TP, int NV_>
+struct OffCols {
+  static constexpr int NV = NV_;
+  static constexpr bool WL = true;
+  int nv = NV_;
+  int c0 = 0;
+  __device__ __forceinline__ int addr(int v, int k) const { return Tile<TP>::at(k, c0 + v); }
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void fwd_conv_compact_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
+  using C = CompactCfg<T, M>;
+  using TC = typename C::TileC;
+  constexpr int NT = C::NT, PPT = C::PPT;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + M * TC::LD;
+  const int p = bp % a.Ni;
+  const int tid = threadIdx.x;
+  const size_t off = size_t(bp) * C::N;
+  const int K = a.K, KK = K * K, kmin = -(K / 2);
+  const cx<T>* al = a.in + size_t(bp) * KK;
+  cx<T> av[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) av[q] = al[min(tid + q * NT, KK - 1)];
+  for (int k = tid; k < 2 * M; k += NT) tw[k] = a.tw[k];
+  for (int e = tid; e < C::N; e += NT) buf[TC::at(e / M, e % M)] = cx<T>{T(0), T(0)};
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int e = tid + q * NT;
+    if (e < KK) buf[TC::at(wrap_mode(kmin + e / K, M), wrap_mode(kmin + e % K, M))] = av[q];
+  }
+  __syncthreads();
+  // U: inverse transforms along y of the K kept mode columns
+  typename C::ModeCols mc;
+  mc.nv = K;
+  mc.kmin = kmin;
+  Fft<T, M, C::EPT, NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<+1>();
+  // even frequencies M U[y][k] of the kept k, compact in columns M..M+K-1
+  for (int e = tid; e < M * K; e += NT) {
+    const int y = e / K, j = e % K;
+    buf[TC::at(y, M + j)] = T(M) * buf[TC::at(y, wrap_mode(kmin + j, M))];
+  }
+  // J: inverse transforms along x of all M rows (the first pass stores only after its barrier)
+  const Fft<T, M, C::EPT, NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
+  rowsm.template run<+1>();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT;
+    a.J[off + n] = buf[TC::at(n / M, n % M)];
+  }
+  // odd frequencies FFT_M(J w) of each row, in place
+  rowsm.template run<-1>(TwistLoad<T>{tw});
+  // the column phase: the M odd columns (spectrum column 2c + 1), then the K even ones
+  {
+    OffCols<C::PC, M> odd;
+    col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, false, odd, [](int c) { return 2 * c + 1; });
+    OffCols<C::PC, C::KC> even;
+    even.nv = K;
+    even.c0 = M;
+    col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, false, even, [&](int j) { return 2 * wrap_mode(kmin + j, M); });
+  }
+  __syncthreads();
+  // the odd part: conj(w) IFFT_M of each row, kept per pixel
+  rowsm.template run<+1>();
+  cx<T> eo[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT, x = n % M;
+    cx<T> w = tw[x];
+    w.y = -w.y;
+    eo[q] = buf[TC::at(n / M, x)] * w;
+  }
+  __syncthreads();
+  // the even part in natural order (zero where no mode is kept), then its inverse
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT, y = n / M, j = wrap_mode(n % M - kmin, M);
+    buf[TC::at(y, n % M)] = j < K ? buf[TC::at(y, M + j)] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  rowsm.template run<+1>();
+  cx<T> ei[PPT], jr[PPT];
+  if (a.einc) {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) ei[q] = a.einc[size_t(p) * C::N + tid + q * NT];
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) ei[q] = cx<T>{T(0), T(0)};
+  }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) jr[q] = a.J[off + tid + q * NT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT;
+    a.E[off + n] = buf[TC::at(n / M, n % M)] + eo[q] + a.beta * jr[q] + ei[q];
+  }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_fwd_conv_c(FwdArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fwd_conv_compact_body<T, M>(a, blockIdx.x, smem_raw);
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_fwd_conv_c_group(
+    const FwdArgs<T>* __restrict__ a, const int* __restrict__ start, int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = group_of(start, n, blockIdx.x);
+  fwd_conv_compact_body<T, M>(a[g], blockIdx.x - start[g], smem_raw);
+}
+
 template <typename T>
 struct AdjArgs {
   const cx<T>* J;      // [BP][N] currents, or null (alpha = 0)
@@ -421,44 +569,40 @@ struct AdjArgs {
 // least-squares minimiser, so only the regulariser part g_R reaches R.  With
 // the loss on the CCO image the residual takes R_c (Rs) in s and in g_E's
 // first term, and g_R carries the state term through the CCO as well.
-template <typename T, int M, bool PP>
-__device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
-  using C = ConvCfg<T, M>;
-  constexpr int GJL = C::gj_lds(PP);
-  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* tw = buf + (PP ? 2 : 1) * C::M * C::TileL::LD;
+// The adjoint's per-pixel part: g_E and g_J of the pixels n = tid + q NT (q <
+// PPT) handed to emit(q, n, g_E, g_J).  The loads are issued in batches of QB
+// pixels per thread, all loads of a batch before their use; optional inputs
+// are uniform branches around whole groups of loads.  Batches bound the
+// registers live next to g_J, which the callers keep through the convolution.
+template <typename T, int M, int NT, int QB_MAX = 4, class Emit>
+__device__ __forceinline__ void adj_pixels(const AdjArgs<T>& a, int bp, const Emit& emit) {
+  constexpr int N = M * M, PPT = N / NT;
   const int b = bp / a.Ni, p = bp % a.Ni;
   const int tid = threadIdx.x;
-  const size_t off = size_t(bp) * C::N;
-  const size_t eoff = size_t(a.e_shared ? p : bp) * C::N;
-  const size_t boff = size_t(b) * C::N;
+  const size_t off = size_t(bp) * N;
+  const size_t eoff = size_t(a.e_shared ? p : bp) * N;
+  const size_t boff = size_t(b) * N;
   const T ws = T(2) / T(a.Ss[0]);
   const T wd = T(2 * a.hsign) / T(a.Sd[b]);
   const T beta = a.beta;
-  // the prologue's loads are issued in batches of QB pixels per thread, all
-  // loads of a batch before their use; optional inputs are uniform branches
-  // around whole groups of loads.  Batches bound the registers live next to
-  // g_J, which stays in registers through the convolution.
-  constexpr int QB = C::PPT <= 4 ? C::PPT : (C::PPT % 4 == 0 ? 4 : (C::PPT % 3 == 0 ? 3 : (C::PPT % 2 == 0 ? 2 : 1)));
-  static_assert(C::PPT % QB == 0, "whole batches");
+  constexpr int QB = PPT <= QB_MAX ? PPT
+                                   : (PPT % QB_MAX == 0 ? QB_MAX : (PPT % 3 == 0 && QB_MAX >= 3 ? 3 : (PPT % 2 == 0 ? 2 : 1)));
+  static_assert(PPT % QB == 0, "whole batches");
   const bool has_j = a.J != nullptr, has_gr = a.gR != nullptr, has_rs = a.Rs != nullptr;
-  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
-  cx<T> gj[C::PPT];
-  cx<T>* gjs = tw + C::P;  // [GJ_LDS][NT], each thread's own entries
 #pragma unroll
-  for (int q0 = 0; q0 < C::PPT; q0 += QB) {
+  for (int q0 = 0; q0 < PPT; q0 += QB) {
     cx<T> Jv[QB], Ev[QB], Rv[QB], Hv[QB], Gv[QB], Sv[QB];
     T Dv[QB];
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      const int n = tid + (q0 + q) * C::NT;
+      const int n = tid + (q0 + q) * NT;
       Ev[q] = a.E[eoff + n];
       Rv[q] = a.R[boff + n];
       Hv[q] = a.h[off + n];
     }
     if (has_j) {
 #pragma unroll
-      for (int q = 0; q < QB; ++q) Jv[q] = a.J[off + tid + (q0 + q) * C::NT];
+      for (int q = 0; q < QB; ++q) Jv[q] = a.J[off + tid + (q0 + q) * NT];
     } else {
 #pragma unroll
       for (int q = 0; q < QB; ++q) Jv[q] = cx<T>{T(0), T(0)};
@@ -466,20 +610,20 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
     if (has_gr) {
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
-        Gv[q] = a.gR[boff + tid + (q0 + q) * C::NT];
-        Dv[q] = a.den[boff + tid + (q0 + q) * C::NT];
+        Gv[q] = a.gR[boff + tid + (q0 + q) * NT];
+        Dv[q] = a.den[boff + tid + (q0 + q) * NT];
       }
     }
     if (has_rs) {
 #pragma unroll
-      for (int q = 0; q < QB; ++q) Sv[q] = a.Rs[boff + tid + (q0 + q) * C::NT];
+      for (int q = 0; q < QB; ++q) Sv[q] = a.Rs[boff + tid + (q0 + q) * NT];
     } else {
 #pragma unroll
       for (int q = 0; q < QB; ++q) Sv[q] = Rv[q];
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      const int n = tid + (q0 + q) * C::NT;
+      const int n = tid + (q0 + q) * NT;
       const cx<T> J = Jv[q], E = Ev[q], R = Rv[q], Rs = Sv[q];
       const cx<T> s = Rs * E - beta * J;
       const cx<T> gs = ws * s;
@@ -493,37 +637,26 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
         gJ = gJ + (beta * inv) * (g * E);
       }
       gJ = gJ + beta * gE;
-      buf[C::TileL::at(n / M, n % M)] = gE;
-      if (q0 + q < GJL)
-        gjs[(q0 + q) * C::NT + tid] = gJ;
-      else
-        gj[q0 + q] = gJ;
+      emit(q0 + q, n, gE, gJ);
     }
   }
-  __syncthreads();
-  const int r = conv_core<T, M, PP>(buf, tw, a.ghat, true, 0);  // offset of the result in the tile
-#pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int n = tid + q * C::NT;
-    cx<T>& x = buf[r + C::TileL::at(n / M, n % M)];
-    x = x + (q < GJL ? gjs[q * C::NT + tid] : gj[q]);
-  }
-  __syncthreads();
+}
+
+// g_alpha of the K x K kept modes read(iy, ix) of the analysed tile, and the
+// Adam update of alpha (bias corrections of this step from adam_c).
+template <typename T, int M, int NT, class Read>
+__device__ __forceinline__ void adj_modes(const AdjArgs<T>& a, int bp, const Read& read) {
+  const int b = bp / a.Ni, tid = threadIdx.x;
   const int K = a.K, kmin = -(K / 2);
-  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>(NoLoad(), r);
-  typename C::ModeCols mc;
-  mc.nv = K;
-  mc.kmin = kmin;
-  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(NoLoad(), r);
   const bool upd = a.alpha && !(a.frozen && a.frozen[b]);
   T lr1 = T(0), ic2 = T(0);
   if (upd) {
     lr1 = T(a.adam_c[2 * b]);
     ic2 = T(a.adam_c[2 * b + 1]);
   }
-  for (int e = tid; e < K * K; e += C::NT) {
+  for (int e = tid; e < K * K; e += NT) {
     const int iy = wrap_mode(kmin + e / K, M), ix = wrap_mode(kmin + e % K, M);
-    const cx<T> g = buf[r + C::TileL::at(iy, ix)];
+    const cx<T> g = read(iy, ix);
     const size_t idx = size_t(bp) * K * K + e;
     if (a.galpha) a.galpha[idx] = g;
     if (upd) {
@@ -543,6 +676,140 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
       a.alpha[idx] = al;
     }
   }
+}
+
+template <typename T, int M, bool PP>
+__device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
+  using C = ConvCfg<T, M>;
+  constexpr int GJL = C::gj_lds(PP);
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + (PP ? 2 : 1) * C::M * C::TileL::LD;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < C::P; k += C::NT) tw[k] = a.tw[k];
+  cx<T> gj[C::PPT];
+  cx<T>* gjs = tw + C::P;  // [GJ_LDS][NT], each thread's own entries
+  adj_pixels<T, M, C::NT>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
+    buf[C::TileL::at(n / M, n % M)] = gE;
+    if (q < GJL)
+      gjs[q * C::NT + tid] = gJ;
+    else
+      gj[q] = gJ;
+  });
+  __syncthreads();
+  const int r = conv_core<T, M, PP>(buf, tw, a.ghat, true, 0);  // offset of the result in the tile
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int n = tid + q * C::NT;
+    cx<T>& x = buf[r + C::TileL::at(n / M, n % M)];
+    x = x + (q < GJL ? gjs[q * C::NT + tid] : gj[q]);
+  }
+  __syncthreads();
+  const int K = a.K, kmin = -(K / 2);
+  Fft<T, M, C::EPT_M, C::NT, typename C::RowsM, 2>{buf, tw, typename C::RowsM{}}.template run<-1>(NoLoad(), r);
+  typename C::ModeCols mc;
+  mc.nv = K;
+  mc.kmin = kmin;
+  Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(NoLoad(), r);
+  adj_modes<T, M, C::NT>(a, bp, [&](int iy, int ix) { return buf[r + C::TileL::at(iy, ix)]; });
+}
+
+// First-pass load of the kept mode column j (row k) plus s times column OFF + j
+// of the same row of a Tile<TP> (the compact even frequencies).
+template <typename T, int TP, int OFF>
+struct EvenJoinLoad {
+  const cx<T>* buf;
+  T s;
+  template <typename Cx>
+  __device__ __forceinline__ Cx operator()(int j, int k, Cx x) const { return x + s * buf[Tile<TP>::at(k, OFF + j)]; }
+};
+
+// The adjoint on the compact tile (64 x 64 FP32, K <= 32; as the compact
+// forward).  Only the K x K kept modes of B^H (G_D^H g_E + g_J) are wanted:
+// with the padded row transform's even and odd frequencies (Z_even =
+// FFT_M(g_E), Z_odd = FFT_M(w g_E) per row, w[x] = exp(-2 pi i x / P)), the
+// column phase with conj(ghat) gives W_even, W_odd and
+//   G_D^H g_E = IFFT_M(W_even) + conj(w) IFFT_M(W_odd)   (per row);
+// B^H takes the first term to M times the kept columns of W_even under the
+// column transform, so only the K kept even columns are convolved:
+//   g_alpha = colFFT_kept(M W_even + rowFFT(conj(w) IFFT_M(W_odd) + g_J)).
+// g_E is kept in registers between the two row transforms, g_J through the
+// convolution.
+template <typename T, int M>
+__device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
+  using C = CompactCfg<T, M>;
+  using TC = typename C::TileC;
+  constexpr int NT = C::NT, PPT = C::PPT;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = buf + M * TC::LD;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 2 * M; k += NT) tw[k] = a.tw[k];
+  cx<T> ge[PPT], gj[PPT];
+  adj_pixels<T, M, NT, 2>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
+    buf[TC::at(n / M, n % M)] = gE;
+    ge[q] = gE;
+    gj[q] = gJ;
+  });
+  __syncthreads();
+  const int K = a.K, kmin = -(K / 2);
+  const Fft<T, M, C::EPT, NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
+  // even frequencies FFT_M(g_E) of each row; the K kept ones compact in columns M..M+K-1
+  rowsm.template run<-1>();
+  for (int e = tid; e < M * K; e += NT) {
+    const int y = e / K, j = e % K;
+    buf[TC::at(y, M + j)] = buf[TC::at(y, wrap_mode(kmin + j, M))];
+  }
+  __syncthreads();
+  // odd frequencies FFT_M(w g_E) of each row, in place
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT;
+    buf[TC::at(n / M, n % M)] = ge[q];
+  }
+  __syncthreads();
+  rowsm.template run<-1>(TwistLoad<T>{tw});
+  // the column phase with conj(ghat): the M odd columns, then the K kept even ones
+  {
+    OffCols<C::PC, M> odd;
+    col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, true, odd, [](int c) { return 2 * c + 1; });
+    OffCols<C::PC, C::KC> even;
+    even.nv = K;
+    even.c0 = M;
+    col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, true, even, [&](int j) { return 2 * wrap_mode(kmin + j, M); });
+  }
+  __syncthreads();
+  // the odd part back to pixels, conj(w) IFFT_M, plus g_J
+  rowsm.template run<+1>();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int n = tid + q * NT, x = n % M;
+    cx<T> w = tw[x];
+    w.y = -w.y;
+    cx<T>& d = buf[TC::at(n / M, x)];
+    d = d * w + gj[q];
+  }
+  __syncthreads();
+  rowsm.template run<-1>();
+  // column transforms of the kept modes, the even part (times M) joining in their first pass
+  typename C::ModeCols mc;
+  mc.nv = K;
+  mc.kmin = kmin;
+  Fft<T, M, C::EPT, NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(EvenJoinLoad<T, C::PC, M>{buf, T(M)});
+  adj_modes<T, M, NT>(a, bp, [&](int iy, int ix) { return buf[TC::at(iy, ix)]; });
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_adj_conv_c(AdjArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  adj_conv_compact_body<T, M>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_adj_conv_c_group(
+    const AdjArgs<T>* __restrict__ a, const int* __restrict__ start, int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int bx = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = group_of(start, n, bx);
+  adj_conv_compact_body<T, M>(a[g], bx - start[g], smem_raw);
 }
 
 template <typename T, int M, bool PP>
