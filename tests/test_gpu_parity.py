@@ -78,6 +78,9 @@ CASES = [
     (48, 21, 36, 36, 1, "fp32", 1e-4),  # largest truncation of the uneven draws, the paper's antenna count
     (64, 15, 8, 12, 1, "fp64", 1e-9),   # the benchmark grid in FP64
     (96, 15, 12, 16, 1, "fp32", 1e-4),  # P = 192: 12-, 8- and 2-point row passes, 96-point column chains
+    (64, 32, 8, 12, 1, "fp32", 1e-4),   # the compact tile at its largest K (even: corner blocks)
+    (64, 33, 8, 12, 1, "fp32", 1e-4),   # one mode more: the full tile
+    (64, 1, 4, 6, 2, "fp32", 1e-4),     # the compact tile with a single mode
 ]
 
 
@@ -484,10 +487,12 @@ def test_resume_100_plus_100_equals_200_steps(prec):
 
 
 def test_step_multi_equals_separate_steps():
-    """A grouped step over handles of uneven shapes (two classes of several FP32 handles, an FP64
-    handle, a lone class member) equals separate steps bit for bit, and so do three steps in a row."""
+    """A grouped step over handles of uneven shapes (three classes of several FP32 handles, an FP64
+    handle, lone class members) equals separate steps bit for bit, and so do three steps in a row."""
+    # the 64 x 64 handles with K <= 32 form a class on the compact tile; K = 33 stands alone
     specs = [(32, 9, 16, 24, "fp32", 2), (32, 7, 12, 20, "fp32", 1), (32, 11, 16, 24, "fp32", 3),
-             (16, 7, 6, 8, "fp32", 2), (16, 5, 6, 8, "fp32", 1), (16, 7, 6, 8, "fp64", 2), (48, 9, 8, 12, "fp32", 1)]
+             (16, 7, 6, 8, "fp32", 2), (16, 5, 6, 8, "fp32", 1), (16, 7, 6, 8, "fp64", 2), (48, 9, 8, 12, "fp32", 1),
+             (64, 15, 8, 12, "fp32", 1), (64, 9, 6, 10, "fp32", 2), (64, 33, 8, 12, "fp32", 1)]
     solvers, states = [], []
     for M, K, Ni, Ns, prec, B in specs:
         case = make_case(M, K, Ni, Ns, seeds=tuple(range(B)))
