@@ -43,13 +43,14 @@ def log(*a):
 
 
 # kernel names in the library's timing order, and how they appear in profiler output
-KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant)
-    "fwd_conv": "k_fwd_conv<float, 64, true,",
-    "pixel_reduce": "k_pixel_reduce_mfma<",
-    "image_reg": "k_image_reg<float>",
-    "adj_gemm": "k_adj_gemm_mfma<",
-    "adj_conv": "k_adj_conv<float, 64,",
+KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant, both tiles)
+    "fwd_conv": ("k_fwd_conv<float, 64, true,", "k_fwd_conv_c<float, 64>"),
+    "pixel_reduce": ("k_pixel_reduce_mfma<",),
+    "image_reg": ("k_image_reg<float>",),
+    "adj_gemm": ("k_adj_gemm_mfma<",),
+    "adj_conv": ("k_adj_conv<float, 64,", "k_adj_conv_c<float, 64>"),
 }
+COMPACT_MAX_K = 32   # 64 x 64 FP32 with K <= 32: the convolutions run on the compact tile
 
 
 def kernel_variant(name):
@@ -63,11 +64,12 @@ def tuned_variants(wl, tuned):
     ct, pb, fpp, app = tuned
     tf = lambda b: "true" if b else "false"
     nrt, nct, nrta = -(-wl.n_rx // 16), -(-wl.n_tx // 32), -(-wl.n_tx // 16)
-    return {"fwd_conv": f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
+    compact = wl.M == 64 and wl.K <= COMPACT_MAX_K   # every plan choice runs the compact kernels
+    return {"fwd_conv": f"k_fwd_conv_c<float,{wl.M}>" if compact else f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
             "pixel_reduce": f"k_pixel_reduce_mfma<{nrt},{nct},{pb}>",
             "image_reg": "k_image_reg<float>",
             "adj_gemm": f"k_adj_gemm_mfma<{nrta},{ct}>",
-            "adj_conv": f"k_adj_conv<float,{wl.M},{tf(app)}>"}
+            "adj_conv": f"k_adj_conv_c<float,{wl.M}>" if compact else f"k_adj_conv<float,{wl.M},{tf(app)}>"}
 CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")
 
@@ -91,8 +93,8 @@ def kernel_source_hash():
 
 
 def _short_kernel(name):
-    for k, sym in KERNEL_SYMBOLS.items():
-        if sym in name:
+    for k, syms in KERNEL_SYMBOLS.items():
+        if any(sym in name for sym in syms):
             return k
     if CALIBRATION_SYMBOL in name:
         return "calibration_copy"

@@ -574,7 +574,7 @@ struct AdjArgs {
 // pixels per thread, all loads of a batch before their use; optional inputs
 // are uniform branches around whole groups of loads.  Batches bound the
 // registers live next to g_J, which the callers keep through the convolution.
-template <typename T, int M, int NT, int QB_MAX = 4, class Emit>
+template <typename T, int M, int NT, class Emit>
 __device__ __forceinline__ void adj_pixels(const AdjArgs<T>& a, int bp, const Emit& emit) {
   constexpr int N = M * M, PPT = N / NT;
   const int b = bp / a.Ni, p = bp % a.Ni;
@@ -585,8 +585,7 @@ __device__ __forceinline__ void adj_pixels(const AdjArgs<T>& a, int bp, const Em
   const T ws = T(2) / T(a.Ss[0]);
   const T wd = T(2 * a.hsign) / T(a.Sd[b]);
   const T beta = a.beta;
-  constexpr int QB = PPT <= QB_MAX ? PPT
-                                   : (PPT % QB_MAX == 0 ? QB_MAX : (PPT % 3 == 0 && QB_MAX >= 3 ? 3 : (PPT % 2 == 0 ? 2 : 1)));
+  constexpr int QB = PPT <= 4 ? PPT : (PPT % 4 == 0 ? 4 : (PPT % 3 == 0 ? 3 : (PPT % 2 == 0 ? 2 : 1)));
   static_assert(PPT % QB == 0, "whole batches");
   const bool has_j = a.J != nullptr, has_gr = a.gR != nullptr, has_rs = a.Rs != nullptr;
 #pragma unroll
@@ -744,7 +743,7 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
   const int tid = threadIdx.x;
   for (int k = tid; k < 2 * M; k += NT) tw[k] = a.tw[k];
   cx<T> ge[PPT], gj[PPT];
-  adj_pixels<T, M, NT, 2>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
+  adj_pixels<T, M, NT>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
     buf[TC::at(n / M, n % M)] = gE;
     ge[q] = gE;
     gj[q] = gJ;
