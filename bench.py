@@ -48,7 +48,7 @@ KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant
     "pixel_reduce": ("k_pixel_reduce_mfma<",),
     "image_reg": ("k_image_reg<float>",),
     "adj_gemm": ("k_adj_gemm_mfma<",),
-    "adj_conv": ("k_adj_conv<float, 64,", "k_adj_conv_c<float, 64>"),
+    "adj_conv": ("k_adj_conv<float, 64,", "k_adj_conv_c<float, 64,"),
 }
 COMPACT_MAX_K = 32   # 64 x 64 FP32 with K <= 32: the convolutions run on the compact tile
 
@@ -69,7 +69,9 @@ def tuned_variants(wl, tuned):
             "pixel_reduce": f"k_pixel_reduce_mfma<{nrt},{nct},{pb}>",
             "image_reg": "k_image_reg<float>",
             "adj_gemm": f"k_adj_gemm_mfma<{nrta},{ct}>",
-            "adj_conv": f"k_adj_conv_c<float,{wl.M}>" if compact else f"k_adj_conv<float,{wl.M},{tf(app)}>"}
+            # K <= 16: the adjoint's g_J row transform waits in the compact tile's spare columns
+            "adj_conv": (f"k_adj_conv_c<float,{wl.M},{tf(2 * wl.K <= COMPACT_MAX_K)}>" if compact
+                         else f"k_adj_conv<float,{wl.M},{tf(app)}>")}
 CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")
 

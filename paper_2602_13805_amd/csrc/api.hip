@@ -121,10 +121,13 @@ static void set_lds(K kernel, size_t bytes) {
                               int(bytes));
 }
 
-// The band-limited forward and adjoint on the compact tile: FP32 at 64 x 64 with K <= 32.
+// The band-limited forward and adjoint on the compact tile: FP32 at 64 x 64 with K <= 32;
+// with K <= 16 the adjoint keeps the row transform of g_J in the tile's spare columns.
 static bool fwd_compact(const pdf_handle* h) {
   return h->prec == PDF_FP32 && h->M == 64 && !h->big && h->K <= CompactCfg<float, 64>::KC;
 }
+static bool adj_gj_spare(const pdf_handle* h) { return fwd_compact(h) && 2 * h->K <= CompactCfg<float, 64>::KC; }
+static int compact_mode(const pdf_handle* h) { return fwd_compact(h) ? (adj_gj_spare(h) ? 2 : 1) : 0; }
 
 template <typename T, int M, bool FA, bool PP>
 static void launch_fwd_t(pdf_handle* h, const FwdArgs<T>& a, int nblk) {
@@ -286,8 +289,13 @@ static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
   if constexpr (sizeof(T) == 4 && M == 64) {
     if (fwd_compact(h)) {  // every plan choice: the band-limited adjoint on the compact tile
       using CC = CompactCfg<T, M>;
-      set_lds(k_adj_conv_c<T, M>, CC::LDS);
-      hipLaunchKernelGGL((k_adj_conv_c<T, M>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      if (adj_gj_spare(h)) {
+        set_lds(k_adj_conv_c<T, M, true>, CC::LDS);
+        hipLaunchKernelGGL((k_adj_conv_c<T, M, true>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      } else {
+        set_lds(k_adj_conv_c<T, M, false>, CC::LDS);
+        hipLaunchKernelGGL((k_adj_conv_c<T, M, false>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      }
       return check_launch(h, "k_adj_conv_c");
     }
   }
@@ -634,7 +642,7 @@ struct Group {
   const int* st[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // [n + 1] workgroup starts per kernel
   int tot[5] = {0, 0, 0, 0, 0};
   int n = 0, M = 0, ntiles = 0, nbx = 0, nt_reg = 0, nrt = 0, nct = 0, nrta = 0, ct = 2, pb = 4, fpp = 0, app = 0;
-  bool compact = false;  // the forward on the compact tile (every member eligible)
+  int compact = 0;  // compact_mode of every member (one class)
   size_t lds_reg = 0, lds_ag = 0;
   ~Group() {
     if (dmem) (void)hipFree(dmem);
@@ -660,8 +668,9 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
   g->nct = (h0->Ni + 31) / 32;
   g->nrta = (h0->Ni + 15) / 16;
   g->ct = h0->tune_ct;
-  g->compact = true;
-  for (pdf_handle* h : hs) g->compact = g->compact && fwd_compact(h);
+  g->compact = compact_mode(h0);
+  for (pdf_handle* h : hs)
+    if (compact_mode(h) != g->compact) return fail(h0, PDF_EINVAL, "internal: one class, one convolution tile");
   g->pb = h0->tune_pb;
   g->fpp = h0->tune_fpp;
   g->app = h0->tune_app;
@@ -749,9 +758,13 @@ static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
       set_lds(k_fwd_conv_c_group<float, 64>, CC::LDS);
       hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
                          g->st[0], g->n);
+    } else if (g->compact == 2) {
+      set_lds(k_adj_conv_c_group<float, 64, true>, CC::LDS);
+      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, true>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
+                         g->st[4], g->n);
     } else {
-      set_lds(k_adj_conv_c_group<float, 64>, CC::LDS);
-      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
+      set_lds(k_adj_conv_c_group<float, 64, false>, CC::LDS);
+      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, false>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
                          g->st[4], g->n);
     }
     return;
@@ -2488,7 +2501,7 @@ extern "C" int pdf_reconstruct_multi(int32_t n, pdf_handle* const* hs, int32_t n
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
     if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
-      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, fwd_compact(h) ? 1 : 0}].push_back(i);
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, compact_mode(h)}].push_back(i);
     else {
       units.emplace_back(new Unit());
       units.back()->rs.push_back(rs[i]);
@@ -2555,7 +2568,7 @@ static int step_multi_impl(int32_t n, pdf_handle* const* hs, void* const* alpha_
   for (int i = 0; i < n; ++i) {
     pdf_handle* h = hs[i];
     if (h->prec == PDF_FP32 && h->N % 32 == 0 && !h->big && h->F == 1 && !h->prm.cco_in_loss)
-      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, fwd_compact(h) ? 1 : 0}].push_back(i);
+      classes[{h->M, (h->Ns + 15) / 16, (h->Ni + 31) / 32, (h->Ni + 15) / 16, compact_mode(h)}].push_back(i);
     else
       single.push_back(i);
   }

@@ -713,13 +713,19 @@ __device__ __forceinline__ void adj_conv_body(const AdjArgs<T>& a, int bp, unsig
 }
 
 // First-pass load of the kept mode column j (row k) plus s times column OFF + j
-// of the same row of a Tile<TP> (the compact even frequencies).
-template <typename T, int TP, int OFF>
+// of the same row of a Tile<TP> (the compact even frequencies) and, with
+// GJ, plus column OFF + K + j (the kept columns of the row transform of g_J).
+template <typename T, int TP, int OFF, bool GJ>
 struct EvenJoinLoad {
   const cx<T>* buf;
   T s;
+  int K;
   template <typename Cx>
-  __device__ __forceinline__ Cx operator()(int j, int k, Cx x) const { return x + s * buf[Tile<TP>::at(k, OFF + j)]; }
+  __device__ __forceinline__ Cx operator()(int j, int k, Cx x) const {
+    x = x + s * buf[Tile<TP>::at(k, OFF + j)];
+    if constexpr (GJ) x = x + buf[Tile<TP>::at(k, OFF + K + j)];
+    return x;
+  }
 };
 
 // The adjoint on the compact tile (64 x 64 FP32, K <= 32; as the compact
@@ -730,10 +736,14 @@ struct EvenJoinLoad {
 //   G_D^H g_E = IFFT_M(W_even) + conj(w) IFFT_M(W_odd)   (per row);
 // B^H takes the first term to M times the kept columns of W_even under the
 // column transform, so only the K kept even columns are convolved:
-//   g_alpha = colFFT_kept(M W_even + rowFFT(conj(w) IFFT_M(W_odd) + g_J)).
-// g_E is kept in registers between the two row transforms, g_J through the
-// convolution.
-template <typename T, int M>
+//   g_alpha = colFFT_kept(M W_even + rowFFT(conj(w) IFFT_M(W_odd)) + rowFFT(g_J)).
+// g_E waits in registers between its row transforms.  GJ (K <= 16): the kept
+// columns of rowFFT(g_J) are formed first and wait in the compact tile's
+// spare columns M + K.., so no g_J is held through the convolution (the
+// registers it would take push the column phase past the 80 that three
+// workgroups per CU leave); otherwise g_J waits in registers and joins in the
+// pixel domain.
+template <typename T, int M, bool GJ>
 __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = CompactCfg<T, M>;
   using TC = typename C::TileC;
@@ -742,15 +752,34 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
   cx<T>* tw = buf + M * TC::LD;
   const int tid = threadIdx.x;
   for (int k = tid; k < 2 * M; k += NT) tw[k] = a.tw[k];
-  cx<T> ge[PPT], gj[PPT];
-  adj_pixels<T, M, NT>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
-    buf[TC::at(n / M, n % M)] = gE;
-    ge[q] = gE;
-    gj[q] = gJ;
-  });
-  __syncthreads();
   const int K = a.K, kmin = -(K / 2);
   const Fft<T, M, C::EPT, NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
+  cx<T> ge[PPT], gj[GJ ? 1 : PPT];
+  if constexpr (GJ) {
+    adj_pixels<T, M, NT>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
+      buf[TC::at(n / M, n % M)] = gJ;
+      ge[q] = gE;
+    });
+    __syncthreads();
+    rowsm.template run<-1>();
+    for (int e = tid; e < M * K; e += NT) {
+      const int y = e / K, j = e % K;
+      buf[TC::at(y, M + K + j)] = buf[TC::at(y, wrap_mode(kmin + j, M))];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int n = tid + q * NT;
+      buf[TC::at(n / M, n % M)] = ge[q];
+    }
+  } else {
+    adj_pixels<T, M, NT>(a, bp, [&](int q, int n, const cx<T>& gE, const cx<T>& gJ) {
+      buf[TC::at(n / M, n % M)] = gE;
+      ge[q] = gE;
+      gj[q] = gJ;
+    });
+  }
+  __syncthreads();
   // even frequencies FFT_M(g_E) of each row; the K kept ones compact in columns M..M+K-1
   rowsm.template run<-1>();
   for (int e = tid; e < M * K; e += NT) {
@@ -776,7 +805,7 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
     col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, true, even, [&](int j) { return 2 * wrap_mode(kmin + j, M); });
   }
   __syncthreads();
-  // the odd part back to pixels, conj(w) IFFT_M, plus g_J
+  // the odd part back to pixels, conj(w) IFFT_M (plus g_J when it waited in registers)
   rowsm.template run<+1>();
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -784,31 +813,35 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
     cx<T> w = tw[x];
     w.y = -w.y;
     cx<T>& d = buf[TC::at(n / M, x)];
-    d = d * w + gj[q];
+    if constexpr (GJ)
+      d = d * w;
+    else
+      d = d * w + gj[q];
   }
   __syncthreads();
   rowsm.template run<-1>();
-  // column transforms of the kept modes, the even part (times M) joining in their first pass
+  // column transforms of the kept modes, M W_even (and rowFFT(g_J)) joining in their first pass
   typename C::ModeCols mc;
   mc.nv = K;
   mc.kmin = kmin;
-  Fft<T, M, C::EPT, NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(EvenJoinLoad<T, C::PC, M>{buf, T(M)});
+  Fft<T, M, C::EPT, NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<-1>(
+      EvenJoinLoad<T, C::PC, M, GJ>{buf, T(M), K});
   adj_modes<T, M, NT>(a, bp, [&](int iy, int ix) { return buf[TC::at(iy, ix)]; });
 }
 
-template <typename T, int M>
+template <typename T, int M, bool GJ>
 __global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_adj_conv_c(AdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  adj_conv_compact_body<T, M>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
+  adj_conv_compact_body<T, M, GJ>(a, xcd_remap(blockIdx.x, gridDim.x), smem_raw);
 }
 
-template <typename T, int M>
+template <typename T, int M, bool GJ>
 __global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_adj_conv_c_group(
     const AdjArgs<T>* __restrict__ a, const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int bx = xcd_remap(blockIdx.x, gridDim.x);
   const int g = group_of(start, n, bx);
-  adj_conv_compact_body<T, M>(a[g], bx - start[g], smem_raw);
+  adj_conv_compact_body<T, M, GJ>(a[g], bx - start[g], smem_raw);
 }
 
 template <typename T, int M, bool PP>
