@@ -479,9 +479,11 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
   const RegArgs<T> a = reg_args<T>(h, loss, tstep, frozen);
   if (h->prm.cco_in_loss) return launch_reg_cco<T>(h, a);
   const int nt = h->N < 1024 ? h->N : 1024;
-  if (h->big) {  // chi read from global memory
-    hipLaunchKernelGGL((k_image_reg<T, true>), dim3(h->B), dim3(nt), 16 * sizeof(double), h->stream, a);
-    return check_launch(h, "k_image_reg");
+  if (h->big) {  // chi read from global memory, 256 pixels per workgroup
+    const int nblk = (h->N + 255) / 256;
+    hipLaunchKernelGGL(k_image_reg_part<T>, dim3(nblk, h->B), dim3(256), 0, h->stream, a, h->reg_part);
+    hipLaunchKernelGGL(k_image_reg_fin<T>, dim3(h->B), dim3(1), 0, h->stream, a, (const double*)h->reg_part, nblk);
+    return check_launch(h, "k_image_reg_part/fin");
   }
   const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
   set_lds(k_image_reg<T>, lds);
@@ -1033,7 +1035,7 @@ static int run_csi(pdf_handle* h, int n_iter, void* alpha_out, void* ws) {
     FwdArgs<T> f = fwd_args<T>(h, alpha);
     if ((rc = launch_fwd<T>(h, f, true))) return rc;
     if ((rc = launch_reduce<T>(h, (const cx<T>*)h->J, (const cx<T>*)h->E, R0))) return rc;
-    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, h->B), dim3(256), 0, h->stream,
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 15) / 16, h->B), dim3(256), 0, h->stream,
                        (const cx<T>*)h->Dpart, h->ntiles, (const cx<T>*)h->esca, (cx<T>*)h->dres, NO);
     if ((rc = check_launch(h, "k_csi_residual"))) return rc;
     if ((rc = launch_adj_gemm<T>(h, (const cx<T>*)h->dres, (cx<T>*)h->h))) return rc;
@@ -1085,7 +1087,7 @@ static int mf_forward(pdf_handle* h, const void* alpha) {
   for (int f = 0; f < h->F; ++f) {
     pdf_handle* s = h->sub[f];
     const int NO = s->Ni * s->Ns;
-    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, 1), dim3(256), 0, h->stream, (const cx<T>*)s->Dpart,
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 15) / 16, 1), dim3(256), 0, h->stream, (const cx<T>*)s->Dpart,
                        s->ntiles, (const cx<T>*)s->esca, (cx<T>*)s->dres, NO);
     hipLaunchKernelGGL(k_sumsq<T>, dim3(1), dim3(256), 0, h->stream, (const cx<T>*)s->dres, size_t(NO), h->dn + f);
   }
@@ -1281,6 +1283,7 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
     HIP_TRY(hipMalloc(&h->GJ, C * B * Ni * N));
     const size_t nblk = (N + 255) / 256;
     HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * B * 4 * N + sizeof(double) * B * nblk * 2));
+    HIP_TRY(hipMalloc(&h->reg_part, sizeof(double) * B * nblk * 6));
   }
   if (h->prm.cco_in_loss) {
     HIP_TRY(hipMalloc(&h->ccl_ws, sizeof(T) * B * kCclArrays * N));
@@ -1369,7 +1372,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
                   h->E,    h->h,    h->R,    h->den,  h->chi,   h->gR,     h->Dpart,  h->dres,
                   h->lsp,  h->R0,   h->g0,   h->gnorm, h->err,  h->frozen, h->tstep,  h->m,
                   h->v,    h->loss, h->loss_w, h->adam_c, h->fc_ws, h->csi_ws, h->S,     h->GJ,
-                  h->big_ws, h->ccl_ws, h->chic, h->Rc, h->ccl_part};
+                  h->big_ws, h->ccl_ws, h->chic, h->Rc, h->ccl_part, h->reg_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -1484,7 +1487,10 @@ static int setup_mf_buffers(pdf_handle* h) {
   HIP_TRY(hipMalloc(&h->dn, sizeof(double) * h->F));
   HIP_TRY(hipMalloc(&h->gn, sizeof(double) * h->F));
   HIP_TRY(hipMalloc(&h->sdf, sizeof(double) * h->F));
-  if (h->big) HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * 4 * N + sizeof(double) * ((N + 255) / 256) * 2));
+  if (h->big) {
+    HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * 4 * N + sizeof(double) * ((N + 255) / 256) * 2));
+    HIP_TRY(hipMalloc(&h->reg_part, sizeof(double) * ((N + 255) / 256) * 6));
+  }
   return PDF_OK;
 }
 
@@ -1689,7 +1695,7 @@ static int run_apply(pdf_handle* h, int op, const void* x, void* y) {
     if ((rc = fill(h->dres, nb * h->Ni * h->Ns, 0.0))) return rc;
     if ((rc = launch_reduce<T>(h, (const cx<T>*)x, (const cx<T>*)x, (const cx<T>*)h->R))) return rc;
     const int NO = h->Ni * h->Ns;
-    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 255) / 256, h->B), dim3(256), 0, h->stream,
+    hipLaunchKernelGGL(k_csi_residual<T>, dim3((NO + 15) / 16, h->B), dim3(256), 0, h->stream,
                        (const cx<T>*)h->Dpart, h->ntiles, (const cx<T>*)h->dres, (cx<T>*)y, NO);
     return check_launch(h, "k_csi_residual");
   }

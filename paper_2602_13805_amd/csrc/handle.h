@@ -64,6 +64,7 @@ struct pdf_handle {
   void* chic = nullptr;
   void* Rc = nullptr;
   double* ccl_part = nullptr;
+  double* reg_part = nullptr;  // big grids: per-workgroup sums of the regulariser pass [B][ceil(N / 256)][6]
   // several frequencies: F > 1 makes this handle the container of one handle
   // per frequency (batch 1 each), joined through the shared contrast; its own
   // per-pixel buffers (R, den, chi, gR, lsp) hold the joint values

@@ -160,21 +160,37 @@ __global__ void k_fill_zero(T* x, size_t n) {
 
 // ---- the full CSI start (Sec. 3.1): conjugate gradients on the quadratic L^CSI, R fixed at R_0
 
-// Data residual of L^CSI: dres = (sum of the split-K parts of G_S J) - E_sca.
-// Grid (ceil(Ni Ns / 256), B).
+// Data residual (of L^CSI, and per frequency of L^Data) d = sum over the
+// split-K parts of G_S J - E_sca, per (incidence, receiver)
+// output o of instance b: 16 outputs per workgroup, the parts of each summed by
+// 16 threads (every 16th part) and the 16 sums added in a fixed order.
+// Grid (ceil(Ni Ns / 16), B), 256 threads.
 template <typename T>
 __global__ __launch_bounds__(256) void k_csi_residual(const cx<T>* Dpart, int ntiles, const cx<T>* esca, cx<T>* dres,
                                                       int NO) {
-  const int b = blockIdx.y, o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= NO) return;
+  constexpr int OUT = 16, SL = 16;
+  __shared__ double sr[SL][OUT], si[SL][OUT];
+  const int b = blockIdx.y, lo = threadIdx.x % OUT, sl = threadIdx.x / OUT;
+  const int o = blockIdx.x * OUT + lo;
   double xr = 0.0, xi = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
-    const cx<T> v = Dpart[(size_t(b) * ntiles + t) * NO + o];
-    xr += v.x;
-    xi += v.y;
+  if (o < NO)
+    for (int t = sl; t < ntiles; t += SL) {
+      const cx<T> v = Dpart[(size_t(b) * ntiles + t) * NO + o];
+      xr += v.x;
+      xi += v.y;
+    }
+  sr[sl][lo] = xr;
+  si[sl][lo] = xi;
+  __syncthreads();
+  if (sl == 0 && o < NO) {
+    double ar = 0.0, ai = 0.0;
+    for (int k = 0; k < SL; ++k) {
+      ar += sr[k][lo];
+      ai += si[k][lo];
+    }
+    const cx<T> e = esca[size_t(b) * NO + o];
+    dres[size_t(b) * NO + o] = cx<T>{T(ar - double(e.x)), T(ai - double(e.y))};
   }
-  const cx<T> e = esca[size_t(b) * NO + o];
-  dres[size_t(b) * NO + o] = cx<T>{T(xr - double(e.x)), T(xi - double(e.y))};
 }
 
 // Conjugate direction p = -g + (||g||^2 / ||g_prev||^2) p (p = -g when first), the

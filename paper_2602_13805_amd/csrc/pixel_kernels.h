@@ -421,103 +421,159 @@ __device__ __forceinline__ RegTerm<T> reg_term(const cx<T>* c, int i, int j, int
   return r;
 }
 
-// One instance per block: data residual and L^Data from the split-K parts,
-// L^State from its partial sums, the three regularisers on chi with their
-// gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.
-// GCHI: chi is read from global memory (grids whose chi does not fit LDS)
-// instead of being staged in LDS.
-template <typename T, bool GCHI = false>
-__device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsigned char* smem_raw) {
-  const int M = a.M, N = M * M;
-  const cx<T>* c = GCHI ? a.chi + size_t(b) * N : reinterpret_cast<const cx<T>*>(smem_raw);   // chi [M][M]
-  double* red = reinterpret_cast<double*>(smem_raw + (GCHI ? 0 : sizeof(cx<T>) * size_t(N)));
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (a.tstep && tid == 0 && !(a.frozen && a.frozen[b])) {
-    // the step is counted here, so the adjoint's Adam epilogue reads its bias
-    // corrections instead of evaluating them in every thread
+// Step counter and this step's Adam bias corrections of instance b (thread 0
+// of one block), counted here so that the adjoint's Adam epilogue reads them
+// instead of evaluating them in every thread.
+template <typename T>
+__device__ __forceinline__ void reg_count_step(const RegArgs<T>& a, int b) {
+  if (a.tstep && !(a.frozen && a.frozen[b])) {
     const int t = a.tstep[b] + 1;
     a.tstep[b] = t;
     a.adam_c[2 * b] = a.lr / (1.0 - pow(a.b1, double(t)));
     a.adam_c[2 * b + 1] = 1.0 / (1.0 - pow(a.b2, double(t)));
   }
+}
+
+// Data residual d = G_S J - E_sca of output o of instance b from the split-K
+// parts; returns |d|^2.
+template <typename T>
+__device__ __forceinline__ double reg_data(const RegArgs<T>& a, int b, int o, int NO) {
+  double xr = 0.0, xi = 0.0;
+  for (int t = 0; t < a.ntiles; ++t) {
+    const cx<T> v = a.Dpart[(size_t(b) * a.ntiles + t) * NO + o];
+    xr += v.x;
+    xi += v.y;
+  }
+  const cx<T> e = a.esca[size_t(b) * NO + o];
+  const double rr = xr - e.x, ri = xi - e.y;
+  a.d[size_t(b) * NO + o] = cx<T>{T(rr), T(ri)};
+  return rr * rr + ri * ri;
+}
+
+// The regularisers anchored at pixel n of the image c (Eqs. 17-19): adds their
+// values to vb, vt, vr, writes g_R = conj(1 / (beta (1 - R)^2)) g_chi (g_chi
+// itself with graw, zero with R held fixed) and tracks max |R| and non-finite
+// gradients.
+template <typename T>
+__device__ __forceinline__ void reg_pixel(const RegArgs<T>& a, const cx<T>* c, int b, int n, double& vb, double& vt,
+                                          double& vr, double& rmax, bool& bad) {
+  const int M = a.M, N = M * M;
+  const int i = n / M, j = n % M;
+  RegTerm<T> t0 = reg_term<T>(c, i, j, M, a);
+  vb += t0.val_bound;
+  vt += t0.val_tv;
+  vr += t0.val_bridge;
+  cx<T> g = t0.g_self;
+  if (j > 0) g = g + reg_term<T>(c, i, j - 1, M, a).g_right;
+  if (i > 0) g = g + reg_term<T>(c, i - 1, j, M, a).g_down;
+  const cx<T> R = a.R[size_t(b) * N + n];
+  rmax = fmax(rmax, sqrt(double(norm2(R))));
+  cx<T> gR{T(0), T(0)};
+  if (a.graw) {
+    gR = g;
+  } else if (!a.r_stopgrad) {
+    // conj(1 / (beta (1 - R)^2)) * g
+    const cx<T> om{T(1) - R.x, -R.y};
+    const cx<T> w = om * om;
+    const T den = T(a.beta) * norm2(w);
+    gR = cx<T>{(w.x * g.x - w.y * g.y) / den, (w.x * g.y + w.y * g.x) / den};
+  }
+  if (!(isfinite(gR.x) && isfinite(gR.y))) bad = true;
+  a.gR[size_t(b) * N + n] = gR;
+}
+
+// The loss row of instance b from the block sums (thread 0).
+template <typename T>
+__device__ __forceinline__ void reg_finish(const RegArgs<T>& a, int b, double Sd, double Sb, double St, double Sr,
+                                           double Rm, double nb) {
+  if (!a.loss) return;
+  double ls = 0.0;
+  for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
+  for (int t = 0; t < a.nlse; ++t) ls += a.lse[size_t(b) * a.nlse + t];
+  ls /= a.Ss[0];
+  double ld = 0.0;
+  if (a.nfreq > 1)
+    for (int f = 0; f < a.nfreq; ++f) ld += a.dn[f] / a.sdf[f];
+  else
+    ld = Sd / a.Sd[b];
+  const double tot = ls + ld + a.lam_bound * Sb + a.lam_tv * St + a.lam_bridge * Sr;
+  double* L = a.loss + size_t(b) * 8;
+  L[0] = ls;
+  L[1] = ld;
+  L[2] = Sb;
+  L[3] = St;
+  L[4] = Sr;
+  L[5] = tot;
+  L[6] = Rm;
+  L[7] = (isfinite(tot) && nb == 0.0) ? 0.0 : 1.0;
+}
+
+// One instance per block: data residual and L^Data from the split-K parts,
+// L^State from its partial sums, the three regularisers on chi with their
+// gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.  chi staged in LDS.
+template <typename T>
+__device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsigned char* smem_raw) {
+  const int M = a.M, N = M * M;
+  const cx<T>* c = reinterpret_cast<const cx<T>*>(smem_raw);   // chi [M][M]
+  double* red = reinterpret_cast<double*>(smem_raw + sizeof(cx<T>) * size_t(N));
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) reg_count_step(a, b);
   double dsum = 0.0;
   const int NO = a.nfreq > 1 ? 0 : a.Ni * a.Ns;
-  for (int o = tid; o < NO; o += nt) {
-    double xr = 0.0, xi = 0.0;
-    for (int t = 0; t < a.ntiles; ++t) {
-      const cx<T> v = a.Dpart[(size_t(b) * a.ntiles + t) * NO + o];
-      xr += v.x;
-      xi += v.y;
-    }
-    const cx<T> e = a.esca[size_t(b) * NO + o];
-    const double rr = xr - e.x, ri = xi - e.y;
-    dsum += rr * rr + ri * ri;
-    a.d[size_t(b) * NO + o] = cx<T>{T(rr), T(ri)};
-  }
-  if constexpr (!GCHI) {
-    cx<T>* cs = reinterpret_cast<cx<T>*>(smem_raw);
-    for (int n = tid; n < N; n += nt) cs[n] = a.chi[size_t(b) * N + n];
-  }
+  for (int o = tid; o < NO; o += nt) dsum += reg_data(a, b, o, NO);
+  cx<T>* cs = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int n = tid; n < N; n += nt) cs[n] = a.chi[size_t(b) * N + n];
   __syncthreads();
   double vb = 0, vt = 0, vr = 0, rmax = 0;
   bool bad = false;
-  for (int n = tid; n < N; n += nt) {
-    const int i = n / M, j = n % M;
-    RegTerm<T> t0 = reg_term<T>(c, i, j, M, a);
-    vb += t0.val_bound;
-    vt += t0.val_tv;
-    vr += t0.val_bridge;
-    cx<T> g = t0.g_self;
-    if (j > 0) g = g + reg_term<T>(c, i, j - 1, M, a).g_right;
-    if (i > 0) g = g + reg_term<T>(c, i - 1, j, M, a).g_down;
-    const cx<T> R = a.R[size_t(b) * N + n];
-    rmax = fmax(rmax, sqrt(double(norm2(R))));
-    cx<T> gR{T(0), T(0)};
-    if (a.graw) {
-      gR = g;
-    } else if (!a.r_stopgrad) {
-      // conj(1 / (beta (1 - R)^2)) * g
-      const cx<T> om{T(1) - R.x, -R.y};
-      const cx<T> w = om * om;
-      const T den = T(a.beta) * norm2(w);
-      gR = cx<T>{(w.x * g.x - w.y * g.y) / den, (w.x * g.y + w.y * g.x) / den};
-    }
-    if (!(isfinite(gR.x) && isfinite(gR.y))) bad = true;
-    a.gR[size_t(b) * N + n] = gR;
-  }
+  for (int n = tid; n < N; n += nt) reg_pixel(a, c, b, n, vb, vt, vr, rmax, bad);
   const double Sd = block_sum(dsum, red);
   const double Sb = block_sum(vb, red);
   const double St = block_sum(vt, red);
   const double Sr = block_sum(vr, red);
   const double Rm = block_max(rmax, red);
   const double nb = block_sum(bad ? 1.0 : 0.0, red);
-  if (tid == 0 && a.loss) {
-    double ls = 0.0;
-    for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
-    for (int t = 0; t < a.nlse; ++t) ls += a.lse[size_t(b) * a.nlse + t];
-    ls /= a.Ss[0];
-    double ld = 0.0;
-    if (a.nfreq > 1)
-      for (int f = 0; f < a.nfreq; ++f) ld += a.dn[f] / a.sdf[f];
-    else
-      ld = Sd / a.Sd[b];
-    const double tot = ls + ld + a.lam_bound * Sb + a.lam_tv * St + a.lam_bridge * Sr;
-    double* L = a.loss + size_t(b) * 8;
-    L[0] = ls;
-    L[1] = ld;
-    L[2] = Sb;
-    L[3] = St;
-    L[4] = Sr;
-    L[5] = tot;
-    L[6] = Rm;
-    L[7] = (isfinite(tot) && nb == 0.0) ? 0.0 : 1.0;
-  }
+  if (tid == 0) reg_finish(a, b, Sd, Sb, St, Sr, Rm, nb);
 }
 
-template <typename T, bool GCHI = false>
+// Images beyond one workgroup's LDS: chi read from global memory, 256 pixels
+// (and data outputs) per workgroup of a grid (nblk, B); each workgroup's sums
+// (|d|^2, bound, TV, bridge, max |R|, non-finite count) go to part[B][nblk][6]
+// and k_image_reg_fin adds them in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_image_reg_part(RegArgs<T> a, double* __restrict__ part) {
+  __shared__ double red[16];
+  const int M = a.M, N = M * M, b = blockIdx.y;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int NO = a.nfreq > 1 ? 0 : a.Ni * a.Ns;
+  double dsum = 0.0;
+  for (int o = n; o < NO; o += gridDim.x * 256) dsum += reg_data(a, b, o, NO);
+  double vb = 0, vt = 0, vr = 0, rmax = 0;
+  bool bad = false;
+  if (n < N) reg_pixel(a, a.chi + size_t(b) * N, b, n, vb, vt, vr, rmax, bad);
+  const double v[6] = {block_sum(dsum, red), block_sum(vb, red), block_sum(vt, red), block_sum(vr, red),
+                       block_max(rmax, red), block_sum(bad ? 1.0 : 0.0, red)};
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) part[(size_t(b) * gridDim.x + blockIdx.x) * 6 + k] = v[k];
+}
+
+// The loss rows and step counters from k_image_reg_part's sums.  Grid B, one thread.
+template <typename T>
+__global__ void k_image_reg_fin(RegArgs<T> a, const double* __restrict__ part, int nblk) {
+  const int b = blockIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < nblk; ++k) {
+    const double* p = part + (size_t(b) * nblk + k) * 6;
+    for (int q = 0; q < 6; ++q) s[q] = q == 4 ? fmax(s[q], p[q]) : s[q] + p[q];
+  }
+  reg_count_step(a, b);
+  reg_finish(a, b, s[0], s[1], s[2], s[3], s[4], s[5]);
+}
+
+template <typename T>
 __global__ __launch_bounds__(1024) void k_image_reg(RegArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  image_reg_body<T, GCHI>(a, blockIdx.x, smem_raw);
+  image_reg_body<T>(a, blockIdx.x, smem_raw);
 }
 
 template <typename T>
