@@ -226,8 +226,9 @@ static int launch_adj_tail_big_m(pdf_handle* h, const AdjArgs<T>& a, int npairs,
     hipLaunchKernelGGL((k_big_adj_rows_inv<T, M, false>), dim3(npairs * C::RBLK), dim3(C::NT), C::ROW_LDS,
                        h->stream, a.tw, S, src, a.K);
   }
-  hipLaunchKernelGGL((k_big_adj_final<T, M>), dim3(npairs), dim3(256), sizeof(cx<T>) * C::P, h->stream, a,
-                     (const cx<T>*)S, scale);
+  // the kept rows split over up to 8 workgroups per pair
+  hipLaunchKernelGGL((k_big_adj_final<T, M>), dim3(npairs, a.K < 8 ? a.K : 8), dim3(256), sizeof(cx<T>) * C::P,
+                     h->stream, a, (const cx<T>*)S, scale);
   return check_launch(h, "big-grid analysis");
 }
 
@@ -1179,7 +1180,11 @@ static int run_init_mf(pdf_handle* h, void* alpha_out) {
     if ((rc = launch_fwd<T>(s, fa, true))) return fail(h, rc, s->err_msg);
     if ((rc = launch_reduce<T>(s, (const cx<T>*)s->J, (const cx<T>*)s->E, (const cx<T>*)h->R0)))
       return fail(h, rc, s->err_msg);
-    ls.Dpart[f] = (const cx<T>*)s->Dpart;
+    const int NO = s->Ni * s->Ns, ndp = (NO + 15) / 16;
+    hipLaunchKernelGGL(k_mf_dnorm<T>, dim3(ndp), dim3(256), 0, h->stream, (const cx<T>*)s->Dpart, s->ntiles, NO,
+                       h->mf_dp + size_t(f) * ndp);
+    ls.dpart[f] = h->mf_dp + size_t(f) * ndp;
+    ls.ndp = ndp;
     ls.lsp[f] = s->lsp;
     ls.Sd[f] = s->Sd;
     ls.Ss[f] = s->Ss;
@@ -1188,7 +1193,6 @@ static int run_init_mf(pdf_handle* h, void* alpha_out) {
   ls.gn = h->gn;
   ls.alpha = (cx<T>*)alpha_out;
   ls.ntiles = h->sub[0]->ntiles;
-  ls.NO = h->sub[0]->Ni * h->Ns;
   ls.len = int(len);
   hipLaunchKernelGGL(k_mf_line_search<T>, dim3(1), dim3(256), 0, h->stream, ls);
   return check_launch(h, "k_mf_line_search");
@@ -1365,7 +1369,7 @@ extern "C" void pdf_destroy(pdf_handle* h) {
     pdf_destroy(s);
     s = nullptr;
   }
-  for (void* p : {(void*)h->wsum, (void*)h->dn, (void*)h->gn, (void*)h->sdf})
+  for (void* p : {(void*)h->wsum, (void*)h->dn, (void*)h->gn, (void*)h->sdf, (void*)h->mf_dp})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   void* ptrs[] = {h->gsT, h->gsA, h->ghat, h->tw,   h->gs,   h->einc, h->Ss,    h->Sd,     h->esca,   h->J,
@@ -1487,6 +1491,7 @@ static int setup_mf_buffers(pdf_handle* h) {
   HIP_TRY(hipMalloc(&h->dn, sizeof(double) * h->F));
   HIP_TRY(hipMalloc(&h->gn, sizeof(double) * h->F));
   HIP_TRY(hipMalloc(&h->sdf, sizeof(double) * h->F));
+  HIP_TRY(hipMalloc(&h->mf_dp, sizeof(double) * h->F * ((h->sub[0]->Ni * h->Ns + 15) / 16)));
   if (h->big) {
     HIP_TRY(hipMalloc(&h->big_ws, sizeof(T) * 4 * N + sizeof(double) * ((N + 255) / 256) * 2));
     HIP_TRY(hipMalloc(&h->reg_part, sizeof(double) * ((N + 255) / 256) * 6));

@@ -253,11 +253,12 @@ __global__ __launch_bounds__(256) void k_big_adj_rows_inv(const cx<T>* __restric
   }
 }
 
-// Adjoint, last pass, one workgroup per pair: the forward DFT along y of the K
-// kept columns, restricted to the K kept rows, g_alpha[ky][kx] =
-// sum_i V[i][kx] exp(-2 pi i ky i / M) (g_alpha = B^H g_J), then the gradient
-// output and the Adam update exactly as in adj_conv_body.  scale multiplies
-// the result (1 for the gradient; 1 / M^2 for the analysis F_T).
+// Adjoint, last pass, gridDim.y workgroups per pair (each a share of the kept
+// rows): the forward DFT along y of the K kept columns, restricted to the K
+// kept rows, g_alpha[ky][kx] = sum_i V[i][kx] exp(-2 pi i ky i / M) (g_alpha =
+// B^H g_J), then the gradient output and the Adam update exactly as in the
+// LDS-resident adjoint.  scale multiplies the result (1 for the gradient;
+// 1 / M^2 for the analysis F_T).
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_big_adj_final(AdjArgs<T> a, const cx<T>* __restrict__ S, T scale) {
   using C = BigCfg<T, M>;
@@ -275,7 +276,8 @@ __global__ __launch_bounds__(256) void k_big_adj_final(AdjArgs<T> a, const cx<T>
     lr1 = T(a.adam_c[2 * b]);
     ic2 = T(a.adam_c[2 * b + 1]);
   }
-  for (int e = tid; e < K * K; e += blockDim.x) {
+  const int rows = (K + gridDim.y - 1) / gridDim.y, r0 = blockIdx.y * rows, r1 = min(K, r0 + rows);
+  for (int e = r0 * K + tid; e < r1 * K; e += blockDim.x) {
     const int ky = kmin + e / K, kxi = e % K;
     cx<T> g{T(0), T(0)};
     for (int i = 0; i < M; ++i) {

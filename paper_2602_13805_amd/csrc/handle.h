@@ -78,6 +78,7 @@ struct pdf_handle {
   double* dn = nullptr;        // container: [F] ||G_S,f J_f - E_sca,f||^2
   double* gn = nullptr;        // container: [F] ||g_f||^2 of the start value
   double* sdf = nullptr;       // container: [F] ||E_sca,f||^2
+  double* mf_dp = nullptr;     // container: [F][ceil(Ni Ns / 16)] parts of the start's ||G_S,f J_g||^2
   // coefficient-network workspace (activations and gradients of one step), grown on demand
   void* fc_ws = nullptr;
   size_t fc_bytes = 0;

@@ -91,45 +91,68 @@ __global__ __launch_bounds__(256) void k_mf_bp_contrast(MfPairs<T> a, double bet
   R0[n] = cx<T>{T((ar * br + ai * bi) / q), T((ai * br - ar * bi) / q)};
 }
 
+// ||sum over the split-K parts||^2 of one frequency's outputs, in parts: 16
+// outputs per workgroup, each summed by 16 threads (every 16th part) and
+// combined in a fixed order; part[blockIdx.x] = the workgroup's sum of |x|^2.
+// Grid ceil(NO / 16), 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mf_dnorm(const cx<T>* __restrict__ Dpart, int ntiles, int NO,
+                                                  double* __restrict__ part) {
+  constexpr int OUT = 16, SL = 16;
+  __shared__ double sr[SL][OUT], si[SL][OUT];
+  const int lo = threadIdx.x % OUT, sl = threadIdx.x / OUT;
+  const int o = blockIdx.x * OUT + lo;
+  double xr = 0.0, xi = 0.0;
+  if (o < NO)
+    for (int t = sl; t < ntiles; t += SL) {
+      const cx<T> v = Dpart[size_t(t) * NO + o];
+      xr += v.x;
+      xi += v.y;
+    }
+  sr[sl][lo] = xr;
+  si[sl][lo] = xi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < OUT; ++q) {
+      double ar = 0.0, ai = 0.0;
+      for (int k = 0; k < SL; ++k) {
+        ar += sr[k][q];
+        ai += si[k][q];
+      }
+      s += ar * ar + ai * ai;
+    }
+    part[blockIdx.x] = s;
+  }
+}
+
 template <typename T>
 struct MfLineSearch {
-  const cx<T>* Dpart[kMaxFreq];   // [ntiles][Ni][Ns] split-K parts of G_S,f J_g per frequency
+  const double* dpart[kMaxFreq];  // [ndp] parts of ||G_S,f J_g||^2 per frequency (k_mf_dnorm)
   const double* lsp[kMaxFreq];    // [ntiles] sum_p |R_0 E - beta J|^2 per frequency (unweighted)
   const double* Sd[kMaxFreq];     // ||E_sca,f||^2
   const double* Ss[kMaxFreq];     // ||E_inc,f||^2
   const double* gn;               // [F] ||g_f||^2
   const cx<T>* g0[kMaxFreq];      // [Ni][K][K] gradient of L^CSI at zero per frequency
   cx<T>* alpha;                   // [F][Ni][K][K] out
-  int F, ntiles, NO, len;         // NO = Ni Ns, len = Ni K^2
+  int F, ndp, ntiles, len;        // ntiles: parts of lsp, len = Ni K^2
 };
 
 // The exact line search of the summed L^CSI along -g (one workgroup):
 // t* = (sum_f ||g_f||^2 / 2) / sum_f (||A_d,f g_f||^2 / S_d,f + ||A_s,f g_f||^2 / S_s,f), alpha_f = -t* g_f.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mf_line_search(MfLineSearch<T> a) {
-  __shared__ double red[16];
   __shared__ double tstar;
   const int tid = threadIdx.x;
   double q = 0.0, gsum = 0.0;
-  for (int f = 0; f < a.F; ++f) {
-    double dsum = 0.0;
-    for (int o = tid; o < a.NO; o += blockDim.x) {
-      double xr = 0, xi = 0;
-      for (int t = 0; t < a.ntiles; ++t) {
-        const cx<T> v = a.Dpart[f][size_t(t) * a.NO + o];
-        xr += v.x;
-        xi += v.y;
-      }
-      dsum += xr * xr + xi * xi;
-    }
-    const double sd = block_sum(dsum, red);
-    if (tid == 0) {
-      double ss = 0.0;
+  if (tid == 0)
+    for (int f = 0; f < a.F; ++f) {
+      double sd = 0.0, ss = 0.0;
+      for (int k = 0; k < a.ndp; ++k) sd += a.dpart[f][k];
       for (int t = 0; t < a.ntiles; ++t) ss += a.lsp[f][t];
       q += sd / a.Sd[f][0] + ss / a.Ss[f][0];
       gsum += a.gn[f];
     }
-  }
   if (tid == 0) tstar = q > 0 ? 0.5 * gsum / q : 0.0;
   __syncthreads();
   const T t = T(tstar);
