@@ -483,7 +483,7 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
   if (h->big) {  // chi read from global memory, 256 pixels per workgroup
     const int nblk = (h->N + 255) / 256;
     hipLaunchKernelGGL(k_image_reg_part<T>, dim3(nblk, h->B), dim3(256), 0, h->stream, a, h->reg_part);
-    hipLaunchKernelGGL(k_image_reg_fin<T>, dim3(h->B), dim3(1), 0, h->stream, a, (const double*)h->reg_part, nblk);
+    hipLaunchKernelGGL(k_image_reg_fin<T>, dim3(h->B), dim3(256), 0, h->stream, a, (const double*)h->reg_part, nblk);
     return check_launch(h, "k_image_reg_part/fin");
   }
   const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);

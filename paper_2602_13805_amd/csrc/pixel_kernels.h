@@ -482,14 +482,12 @@ __device__ __forceinline__ void reg_pixel(const RegArgs<T>& a, const cx<T>* c, i
   a.gR[size_t(b) * N + n] = gR;
 }
 
-// The loss row of instance b from the block sums (thread 0).
+// The loss row of instance b from the block sums (thread 0); ls: the sum of
+// the state-loss parts lsp and lse (before the division by ||E_inc||^2).
 template <typename T>
-__device__ __forceinline__ void reg_finish(const RegArgs<T>& a, int b, double Sd, double Sb, double St, double Sr,
-                                           double Rm, double nb) {
+__device__ __forceinline__ void reg_finish(const RegArgs<T>& a, int b, double ls, double Sd, double Sb, double St,
+                                           double Sr, double Rm, double nb) {
   if (!a.loss) return;
-  double ls = 0.0;
-  for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
-  for (int t = 0; t < a.nlse; ++t) ls += a.lse[size_t(b) * a.nlse + t];
   ls /= a.Ss[0];
   double ld = 0.0;
   if (a.nfreq > 1)
@@ -533,7 +531,12 @@ __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsig
   const double Sr = block_sum(vr, red);
   const double Rm = block_max(rmax, red);
   const double nb = block_sum(bad ? 1.0 : 0.0, red);
-  if (tid == 0) reg_finish(a, b, Sd, Sb, St, Sr, Rm, nb);
+  if (tid == 0 && a.loss) {
+    double ls = 0.0;
+    for (int t = 0; t < a.ntiles; ++t) ls += a.lsp[size_t(b) * a.ntiles + t];
+    for (int t = 0; t < a.nlse; ++t) ls += a.lse[size_t(b) * a.nlse + t];
+    reg_finish(a, b, ls, Sd, Sb, St, Sr, Rm, nb);
+  }
 }
 
 // Images beyond one workgroup's LDS: chi read from global memory, 256 pixels
@@ -557,17 +560,27 @@ __global__ __launch_bounds__(256) void k_image_reg_part(RegArgs<T> a, double* __
     for (int k = 0; k < 6; ++k) part[(size_t(b) * gridDim.x + blockIdx.x) * 6 + k] = v[k];
 }
 
-// The loss rows and step counters from k_image_reg_part's sums.  Grid B, one thread.
+// The loss rows and step counters from k_image_reg_part's sums and the
+// state-loss parts, each added by 256 threads (every 256th part) and a fixed
+// tree.  Grid B, 256 threads.
 template <typename T>
-__global__ void k_image_reg_fin(RegArgs<T> a, const double* __restrict__ part, int nblk) {
-  const int b = blockIdx.x;
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < nblk; ++k) {
+__global__ __launch_bounds__(256) void k_image_reg_fin(RegArgs<T> a, const double* __restrict__ part, int nblk) {
+  __shared__ double red[16];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0}, ls = 0.0;
+  for (int k = tid; k < nblk; k += 256) {
     const double* p = part + (size_t(b) * nblk + k) * 6;
     for (int q = 0; q < 6; ++q) s[q] = q == 4 ? fmax(s[q], p[q]) : s[q] + p[q];
   }
-  reg_count_step(a, b);
-  reg_finish(a, b, s[0], s[1], s[2], s[3], s[4], s[5]);
+  for (int t = tid; t < a.ntiles; t += 256) ls += a.lsp[size_t(b) * a.ntiles + t];
+  for (int t = tid; t < a.nlse; t += 256) ls += a.lse[size_t(b) * a.nlse + t];
+  double S[6];
+  for (int q = 0; q < 6; ++q) S[q] = q == 4 ? block_max(s[q], red) : block_sum(s[q], red);
+  const double L = block_sum(ls, red);
+  if (tid == 0) {
+    reg_count_step(a, b);
+    reg_finish(a, b, L, S[0], S[1], S[2], S[3], S[4], S[5]);
+  }
 }
 
 template <typename T>
