@@ -39,7 +39,8 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-constexpr int GK = 32, LDK = GK + 8;  // K step, padded LDS row (bf16)
+constexpr int GK = 64, LDK = GK + 8;  // K step, padded LDS row (bf16)
+constexpr size_t kMlpSplitFloats = size_t(16) << 20;  // split-K workspace (64 MB)
 
 enum Epi { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_GELU_GRAD = 3 };
 
@@ -55,19 +56,56 @@ struct GemmArgs {
   const float* bias;  // [Nc]
   const float* zprev; // EPI_GELU_GRAD: pre-activation at (m, n), same layout as C
   u16* Cb;            // optional bfloat16 copy of the stored value, same layout as C
+  // split K (products with few output tiles and a long K): workgroup z of the grid takes
+  // K steps [z kchunk, (z + 1) kchunk) and writes its raw tile to part[z][Mr][Nc]; the
+  // epilogue then runs in k_gemm_splitk_reduce over the parts in order.  kchunk = K: no split.
+  int kchunk;
+  float* part;
 };
 
-// Loads an operand tile of GT rows (m or n) x GK k into LDS as [row][k].
+// The epilogue of output (m, n) with product v.
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
+  const size_t o = size_t(m) * g.ldc + n;
+  if constexpr (EPI == EPI_BIAS_GELU) {
+    v += g.bias[n];
+    g.C[o] = v;
+    g.Cb[o] = f2bf(gelu(v));
+  } else if constexpr (EPI == EPI_BIAS) {
+    g.C[o] = g.out_scale * (v + g.bias[n]);
+  } else if constexpr (EPI == EPI_GELU_GRAD) {
+    v *= gelu_grad(g.zprev[o]);
+    g.C[o] = v;
+    g.Cb[o] = f2bf(v);
+  } else {
+    g.C[o] = v;
+  }
+}
+
+// An operand tile of GT rows (m or n) x GK k in flight: IT vectors of 8
+// bfloat16 per thread, loaded from global memory (stage_load) into registers
+// and later written to LDS as [row][k] (stage_store), so that the next K step's
+// loads overlap the current step's products.
+template <int GT>
+struct StageRegs {
+  static constexpr int IT = GT * GK / 8 / 256;
+  uint4 v[IT];
+};
+
+__device__ __forceinline__ uint4 pack8(const u16 (&e)[8]) {
+  return make_uint4(e[0] | (unsigned(e[1]) << 16), e[2] | (unsigned(e[3]) << 16), e[4] | (unsigned(e[5]) << 16),
+                    e[6] | (unsigned(e[7]) << 16));
+}
+
 template <int GT, bool KCONTIG>
-__device__ __forceinline__ void stage(u16* S, const u16* src, int ld, int row0, int nrows, int k0, int K,
-                                      int tid) {
-  constexpr int IT = GT * GK / 8 / 256;  // vectors of 8 per thread
-  if constexpr (KCONTIG) {
-    // GT rows x 32 k = GT * 4 vectors of 8
+__device__ __forceinline__ void stage_load(StageRegs<GT>& R, const u16* src, int ld, int row0, int nrows, int k0,
+                                           int K, int tid) {
+  constexpr int IT = StageRegs<GT>::IT;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int v = tid + it * 256;
-      const int r = v >> 2, kq = (v & 3) * 8;
+  for (int it = 0; it < IT; ++it) {
+    const int v = tid + it * 256;
+    if constexpr (KCONTIG) {  // GT rows x GK k: a vector is 8 consecutive k of one row
+      const int r = v / (GK / 8), kq = (v % (GK / 8)) * 8;
       const int row = row0 + r, k = k0 + kq;
       uint4 val = make_uint4(0, 0, 0, 0);
       if (row < nrows && k < K) {
@@ -78,43 +116,54 @@ __device__ __forceinline__ void stage(u16* S, const u16* src, int ld, int row0, 
           u16 e[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) e[j] = (k + j < K) ? p[j] : u16(0);
-          val = make_uint4(e[0] | (unsigned(e[1]) << 16), e[2] | (unsigned(e[3]) << 16),
-                           e[4] | (unsigned(e[5]) << 16), e[6] | (unsigned(e[7]) << 16));
+          val = pack8(e);
         }
       }
-      *reinterpret_cast<uint4*>(S + r * LDK + kq) = val;
-    }
-  } else {
-    // 32 k-rows x GT rows: each vector is 8 consecutive rows of one k
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int v = tid + it * 256;
+      R.v[it] = val;
+    } else {  // GK k-rows x GT rows: a vector is 8 consecutive rows of one k
       const int kk = v / (GT / 8), rq = (v % (GT / 8)) * 8;
       const int k = k0 + kk, row = row0 + rq;
       u16 e[8];
       if (k < K && row + 8 <= nrows) {
         const u16* p = src + size_t(k) * ld + row;
         if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-          const uint4 val = *reinterpret_cast<const uint4*>(p);
-          e[0] = u16(val.x); e[1] = u16(val.x >> 16); e[2] = u16(val.y); e[3] = u16(val.y >> 16);
-          e[4] = u16(val.z); e[5] = u16(val.z >> 16); e[6] = u16(val.w); e[7] = u16(val.w >> 16);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) e[j] = p[j];
+          R.v[it] = *reinterpret_cast<const uint4*>(p);
+          continue;
         }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = p[j];
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) e[j] = (k < K && row + j < nrows) ? src[size_t(k) * ld + row + j] : u16(0);
       }
+      R.v[it] = pack8(e);
+    }
+  }
+}
+
+template <int GT, bool KCONTIG>
+__device__ __forceinline__ void stage_store(u16* S, const StageRegs<GT>& R, int tid) {
+  constexpr int IT = StageRegs<GT>::IT;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) S[(rq + j) * LDK + kk] = e[j];
+  for (int it = 0; it < IT; ++it) {
+    const int v = tid + it * 256;
+    if constexpr (KCONTIG) {
+      const int r = v / (GK / 8), kq = (v % (GK / 8)) * 8;
+      *reinterpret_cast<uint4*>(S + r * LDK + kq) = R.v[it];
+    } else {
+      const int kk = v / (GT / 8), rq = (v % (GT / 8)) * 8;
+      const uint4 val = R.v[it];
+      const unsigned w[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) S[(rq + j) * LDK + kk] = u16(w[j >> 1] >> (16 * (j & 1)));
     }
   }
 }
 
 // GT x GT output tile per workgroup (GT = 128: each wave 2 x 2 MFMA tiles of
 // 32 x 32; GT = 64: one tile each, for products too small to fill the chip
-// with 128-wide tiles).
+// with 128-wide tiles).  The next K step's operands are loaded into registers
+// while the current step's products run.
 template <int GT, bool AK, bool BK, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   constexpr int WT = GT / 64;  // MFMA tiles per wave and dimension
@@ -130,10 +179,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  for (int k0 = 0; k0 < g.K; k0 += GK) {
-    stage<GT, AK>(sA, g.A, g.lda, m0, g.Mr, k0, g.K, tid);
-    stage<GT, BK>(sB, g.B, g.ldb, n0, g.Nc, k0, g.K, tid);
+  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);  // this workgroup's K range
+  StageRegs<GT> ra, rb;
+  stage_load<GT, AK>(ra, g.A, g.lda, m0, g.Mr, kb, ke, tid);
+  stage_load<GT, BK>(rb, g.B, g.ldb, n0, g.Nc, kb, ke, tid);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    stage_store<GT, AK>(sA, ra, tid);
+    stage_store<GT, BK>(sB, rb, tid);
     __syncthreads();
+    if (k0 + GK < ke) {
+      stage_load<GT, AK>(ra, g.A, g.lda, m0, g.Mr, k0 + GK, ke, tid);
+      stage_load<GT, BK>(rb, g.B, g.ldb, n0, g.Nc, k0 + GK, ke, tid);
+    }
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
       bf16x8 a[WT], b[WT];
@@ -161,22 +218,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         const int m = m0 + wm + 32 * i + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
         const int n = n0 + wn + 32 * j + (lane & 31);
         if (m >= g.Mr || n >= g.Nc) continue;
-        float v = acc[i][j][r];
-        const size_t o = size_t(m) * g.ldc + n;
-        if constexpr (EPI == EPI_BIAS_GELU) {
-          v += g.bias[n];
-          g.C[o] = v;
-          g.Cb[o] = f2bf(gelu(v));
-        } else if constexpr (EPI == EPI_BIAS) {
-          g.C[o] = g.out_scale * (v + g.bias[n]);
-        } else if constexpr (EPI == EPI_GELU_GRAD) {
-          v *= gelu_grad(g.zprev[o]);
-          g.C[o] = v;
-          g.Cb[o] = f2bf(v);
-        } else {
-          g.C[o] = v;
-        }
+        if (gridDim.z > 1)
+          g.part[(size_t(blockIdx.z) * g.Mr + m) * g.Nc + n] = acc[i][j][r];
+        else
+          gemm_epilogue<EPI>(g, m, n, acc[i][j][r]);
       }
+}
+
+// The split-K parts of each output added in order, then the epilogue.  Grid ceil(Mr Nc / 256).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_splitk_reduce(GemmArgs g, int nsplit) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x, mn = size_t(g.Mr) * g.Nc;
+  if (e >= mn) return;
+  float v = 0.f;
+  for (int z = 0; z < nsplit; ++z) v += g.part[z * mn + e];
+  gemm_epilogue<EPI>(g, int(e / g.Nc), int(e % g.Nc), v);
 }
 
 // Input of the first layer: bfloat16 of s_in * x, rows gathered through idx.
@@ -222,13 +278,23 @@ __global__ void k_mse_total(const double* rowsum, int B, int n, double* loss) {
   *loss = s / (double(B) * n);
 }
 
-// Bias gradient: column sums over the batch, rows in order.
-__global__ void k_colsum(const float* g, int B, int n, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// Bias gradient: column sums over the batch; 16 columns per workgroup, each
+// summed by 16 threads (every 16th row) and the 16 parts added in a fixed
+// order.  Grid ceil(n / 16), 256 threads.
+__global__ __launch_bounds__(256) void k_colsum(const float* g, int B, int n, float* out) {
+  constexpr int C = 16, S = 16;
+  __shared__ float part[S][C];
+  const int lc = threadIdx.x % C, sl = threadIdx.x / C, c = blockIdx.x * C + lc;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += g[size_t(b) * n + c];
-  out[c] = s;
+  if (c < n)
+    for (int b = sl; b < B; b += S) s += g[size_t(b) * n + c];
+  part[sl][lc] = s;
+  __syncthreads();
+  if (sl == 0 && c < n) {
+    float t = 0.f;
+    for (int k = 0; k < S; ++k) t += part[k][lc];
+    out[c] = t;
+  }
 }
 
 // Adam on FP32 master values; the bfloat16 copy follows.
@@ -268,6 +334,7 @@ struct pdf_mlp {
   float* dz[2] = {nullptr, nullptr};  // gradients of the pre-activations [bmax][max width], alternating
   u16* dzb[2] = {nullptr, nullptr};   // their bfloat16 copies
   double *rowsum = nullptr, *loss = nullptr;
+  float* part = nullptr;  // split-K parts of the products [kMlpSplitFloats]
   std::vector<void*> owned;
 };
 
@@ -293,17 +360,33 @@ int mcheck(pdf_mlp* n, const char* what) {
   return PDF_OK;
 }
 
-// 128-wide tiles when they give at least two workgroups per CU, else 64-wide.
+// 128-wide tiles when they give at least two workgroups per CU, else 64-wide;
+// with fewer than 512 tiles the K steps split over up to 16 workgroups per tile
+// (at least four steps each, parts within the workspace) and a reduction
+// applies the epilogue.
 template <bool AK, bool BK, int EPI>
-void launch_gemm(pdf_mlp* n, const GemmArgs& g) {
+void launch_gemm(pdf_mlp* n, GemmArgs g) {
   const long big = long((g.Nc + 127) / 128) * ((g.Mr + 127) / 128);
+  const long tiles = big >= 512 ? big : long((g.Nc + 63) / 64) * ((g.Mr + 63) / 64);
+  const size_t mn = size_t(g.Mr) * g.Nc;
+  int nsplit = 1;
+  if (tiles < 512) {
+    nsplit = int(std::min<long>(16, (1024 + tiles - 1) / tiles));
+    nsplit = std::min(nsplit, std::max(1, g.K / (4 * GK)));
+    nsplit = int(std::min<size_t>(size_t(nsplit), std::max<size_t>(1, kMlpSplitFloats / mn)));
+  }
+  g.kchunk = ((g.K + nsplit - 1) / nsplit + GK - 1) / GK * GK;
+  nsplit = (g.K + g.kchunk - 1) / g.kchunk;
+  g.part = n->part;
   if (big >= 512) {
-    dim3 grid((g.Nc + 127) / 128, (g.Mr + 127) / 128);
+    dim3 grid((g.Nc + 127) / 128, (g.Mr + 127) / 128, nsplit);
     hipLaunchKernelGGL((k_gemm_bf16<128, AK, BK, EPI>), grid, dim3(256), 0, n->stream, g);
   } else {
-    dim3 grid((g.Nc + 63) / 64, (g.Mr + 63) / 64);
+    dim3 grid((g.Nc + 63) / 64, (g.Mr + 63) / 64, nsplit);
     hipLaunchKernelGGL((k_gemm_bf16<64, AK, BK, EPI>), grid, dim3(256), 0, n->stream, g);
   }
+  if (nsplit > 1)
+    hipLaunchKernelGGL(k_gemm_splitk_reduce<EPI>, dim3((mn + 255) / 256), dim3(256), 0, n->stream, g, nsplit);
 }
 
 // forward of B rows from the bfloat16 input a[0] (already staged); y = out_scale * output
@@ -377,6 +460,7 @@ extern "C" int pdf_mlp_create(int32_t n_layers, const int32_t* sizes, int32_t ba
     rc = rc ? rc : dalloc(n, &n->dz[q], size_t(batch_max) * maxw);
     rc = rc ? rc : dalloc(n, &n->dzb[q], size_t(batch_max) * maxw);
   }
+  rc = rc ? rc : dalloc(n, &n->part, kMlpSplitFloats);
   rc = rc ? rc : dalloc(n, &n->rowsum, batch_max);
   rc = rc ? rc : dalloc(n, &n->loss, 1);
   if (rc) {
@@ -464,7 +548,7 @@ extern "C" int pdf_mlp_train_step(pdf_mlp* n, const float* x_dev, const float* t
       g.ldc = ni;
       launch_gemm<false, false, EPI_STORE>(n, g);
     }
-    hipLaunchKernelGGL(k_colsum, dim3((no + 255) / 256), dim3(256), 0, n->stream, n->dz[cur], B, no, n->gb[l]);
+    hipLaunchKernelGGL(k_colsum, dim3((no + 15) / 16), dim3(256), 0, n->stream, n->dz[cur], B, no, n->gb[l]);
     if (l > 0) {  // dz_prev[b][i] = gelu'(z_prev) * sum_o dz[b][o] W[o][i]
       GemmArgs g{};
       g.A = n->dzb[cur];
