@@ -124,6 +124,8 @@ def summarize_rocprof(dirs, kind, copy_mib):
         return "\n".join(lines)
     if kind == "mfma":
         return _summarize_mfma(dirs)
+    if kind == "valu":
+        return _summarize_valu(dirs)
     acc = {}
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
@@ -160,10 +162,9 @@ def summarize_rocprof(dirs, kind, copy_mib):
     return "\n".join(lines)
 
 
-def _summarize_mfma(dirs):
-    """Matrix-core use per step kernel from one counter pass (SQ_INSTS_MFMA, SQ_VALU_MFMA_BUSY_CYCLES)
-    taken together with a kernel trace: busy cycles over the kernel's duration times the clock and the
-    1024 SIMDs of the chip."""
+def _counters_and_durations(dirs):
+    """Per step-kernel variant: the mean of each counter over its dispatches, and the sorted
+    durations (s) of the kernel trace taken in the same run."""
     import csv
     import glob
     cnt, dur = {}, {}
@@ -183,19 +184,60 @@ def _summarize_mfma(dirs):
                         key = (k, kernel_variant(r["Kernel_Name"]))
                         dur.setdefault(key, []).append(
                             (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    order = list(KERNEL_SYMBOLS)
+    out = []
+    for key in sorted(cnt, key=lambda k: (order.index(k[0]), k[1])):
+        ts = sorted(dur.get(key, []))
+        if ts:
+            out.append((key, {n: sum(v) / len(v) for n, v in cnt[key].items()}, ts))
+    return out
+
+
+def _summarize_mfma(dirs):
+    """Matrix-core use per step kernel from one counter pass (SQ_INSTS_MFMA, SQ_VALU_MFMA_BUSY_CYCLES)
+    taken together with a kernel trace: busy cycles over the kernel's duration times the clock and the
+    1024 SIMDs of the chip."""
     lines = [f"source_sha256: {kernel_source_hash()}",
              f"clock_hz: {CLOCK_HZ:.3g}", f"simds: {4 * N_CU}"]
-    order = list(KERNEL_SYMBOLS)
-    for key in sorted(cnt, key=lambda k: (order.index(k[0]), k[1])):
-        c = {n: sum(v) / len(v) for n, v in cnt[key].items()}
-        ts = sorted(dur.get(key, []))
-        if not ts or "SQ_VALU_MFMA_BUSY_CYCLES" not in c:
+    for key, c, ts in _counters_and_durations(dirs):
+        if "SQ_VALU_MFMA_BUSY_CYCLES" not in c:
             continue
         t = ts[len(ts) // 2]
         busy = c["SQ_VALU_MFMA_BUSY_CYCLES"]
         lines.append(f"kernel {key[0]} {key[1]} dispatches={len(ts)} mfma_insts={c.get('SQ_INSTS_MFMA', 0.0):.0f} "
                      f"mfma_busy_cycles={busy:.0f} median_us={t * 1e6:.1f} "
                      f"mfma_busy_frac={busy / (t * CLOCK_HZ * 4 * N_CU):.3f}")
+    return "\n".join(lines)
+
+
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+                 "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT")
+
+
+def _summarize_valu(dirs):
+    """Vector-unit use per step kernel from one counter pass (VALU_COUNTERS) taken together with a
+    kernel trace.  A wave64 VALU instruction holds one 16-lane SIMD for four cycles, so the chip
+    issues at most N_CU of them per cycle: valu_issue_frac = SQ_INSTS_VALU / (median duration x
+    clock x N_CU).  valu_busy_frac is rocprof's VALUBusy (SQ_ACTIVE_INST_VALU over CUs x cycles).
+    fp32_flops counts 64 lanes per instruction, an FMA as two; fp32_frac is the resulting rate over
+    FP32_PEAK (which counts packed two-lane instructions; the library is built without them, so
+    its vector code reaches at most half of it)."""
+    lines = [f"source_sha256: {kernel_source_hash()}",
+             f"clock_hz: {CLOCK_HZ:.3g}", f"compute_units: {N_CU}"]
+    for key, c, ts in _counters_and_durations(dirs):
+        if "SQ_INSTS_VALU" not in c:
+            continue
+        t = ts[len(ts) // 2]
+        cycles = t * CLOCK_HZ * N_CU
+        flops = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_ADD_F32", 0.0)
+                        + c.get("SQ_INSTS_VALU_MUL_F32", 0.0) + c.get("SQ_INSTS_VALU_TRANS_F32", 0.0))
+        lines.append(f"kernel {key[0]} {key[1]} dispatches={len(ts)} median_us={t * 1e6:.1f} "
+                     f"valu_insts={c['SQ_INSTS_VALU']:.0f} valu_issue_frac={c['SQ_INSTS_VALU'] / cycles:.3f} "
+                     f"valu_busy_frac={c.get('SQ_ACTIVE_INST_VALU', 0.0) / cycles:.3f} "
+                     f"fp32_flops={flops:.4g} flops_per_valu_inst={flops / max(c['SQ_INSTS_VALU'], 1.0):.1f} "
+                     f"fp32_frac={flops / t / FP32_PEAK:.3f} "
+                     f"lds_insts={c.get('SQ_INSTS_LDS', 0.0):.0f} "
+                     f"lds_bank_conflict_frac={c.get('SQ_LDS_BANK_CONFLICT', 0.0) / cycles:.3f}")
     return "\n".join(lines)
 
 
@@ -347,7 +389,7 @@ def main():
                          "and written to it (with --save-fields: written, then exit)")
     ap.add_argument("--summarize-rocprof", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output in these directories and exit")
-    ap.add_argument("--summary-kind", choices=["stats", "pmc", "mfma"], default="stats")
+    ap.add_argument("--summary-kind", choices=["stats", "pmc", "mfma", "valu"], default="stats")
     ap.add_argument("--save-fields", metavar="NPZ",
                     help="synthesise the batch's measured fields, write them to this file and exit")
     ap.add_argument("--load-fields", metavar="NPZ",

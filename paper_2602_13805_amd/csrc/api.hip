@@ -2124,7 +2124,9 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
     const int tiles = ((d.n_in[l] + 1 + rows_t - 1) / rows_t) * ((d.n_out[l] + cols_t - 1) / cols_t);
     d.tile_start[l + 1] = d.tile_start[l] + tiles;
   }
+  if (int64_t(d.tile_start[3]) * h->B > INT32_MAX) return fail(h, PDF_EINVAL, "k_fc_adam: grid too large");
   d.R = n.R;
+  d.xcd_order = h->B % 8 == 0;
   d.theta = theta;
   d.m = m;
   d.v = v;
@@ -2136,11 +2138,11 @@ static int fc_step(pdf_handle* h, int H, double s_in, double s_out, const cx<T>*
   d.ic2 = 1.0 / (1.0 - std::pow(h->prm.adam_b2, double(t)));
   if constexpr (F32) {
     if (v2) {
-      hipLaunchKernelGGL((k_fc_adam<T, 2>), dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
+      hipLaunchKernelGGL((k_fc_adam<T, 2>), dim3(d.tile_start[3] * h->B), dim3(256), 0, h->stream, d);
       return check_launch(h, "k_fc_adam");
     }
   }
-  hipLaunchKernelGGL((k_fc_adam<T, 1>), dim3(d.tile_start[3], h->B), dim3(256), 0, h->stream, d);
+  hipLaunchKernelGGL((k_fc_adam<T, 1>), dim3(d.tile_start[3] * h->B), dim3(256), 0, h->stream, d);
   return check_launch(h, "k_fc_adam");
 }
 

@@ -368,6 +368,7 @@ struct FcAdamArgs {
   size_t off[3];          // parameter block offsets
   int tile_start[4];      // first tile of each layer (tile_start[3] = tiles per reconstruction)
   int R;
+  int xcd_order;          // 1: the tiles of a reconstruction on one XCD (needs B % 8 == 0)
   T* theta;
   T* m;
   T* v;
@@ -378,7 +379,7 @@ struct FcAdamArgs {
 
 // Weight gradients dW[k][n] = sum_r in[r][k] g[r][n] (in[r][n_in] = 1: bias row)
 // of every layer, each followed at once by its bias-corrected Adam update.
-// Grid (tiles per reconstruction, B), 256 threads; a tile is 64 / V rows x
+// Grid tiles per reconstruction x B (one-dimensional), 256 threads; a tile is 64 / V rows x
 // 64 V columns of one layer's block, 16 / V rows per wave and V adjacent
 // columns per lane (V = 2: every theta, m, v access moves two values, which
 // halves the memory instructions; it needs even widths and block offsets), so
@@ -395,12 +396,25 @@ __global__ void __launch_bounds__(256) k_fc_adam(FcAdamArgs<T> a) {
   constexpr int ROWS = Tl::ROWS, COLS = Tl::COLS, RW = Tl::RW;
   __shared__ T Is[kFcMaxRows * ROWS];
   __shared__ T Gs[kFcMaxRows * COLS];
-  const int b = blockIdx.y;
+  // one-dimensional grid of tiles x B workgroups.  Consecutive workgroups go
+  // to the eight XCDs in turn, each with its own L2; with B a multiple of 8
+  // the tiles of one reconstruction are given to workgroups of one XCD, so its
+  // staged rows are fetched into one L2 instead of eight
+  const int tiles = a.tile_start[3];
+  int b, tt;
+  if (a.xcd_order) {
+    const int id = blockIdx.x, x = id & 7, s = id >> 3;
+    b = x + 8 * (s / tiles);
+    tt = s % tiles;
+  } else {
+    b = blockIdx.x / tiles;
+    tt = blockIdx.x % tiles;
+  }
   int l = 0;
-  while (l < 2 && int(blockIdx.x) >= a.tile_start[l + 1]) ++l;
+  while (l < 2 && tt >= a.tile_start[l + 1]) ++l;
   const int n_in = a.n_in[l], n_out = a.n_out[l];
   const int ntn = (n_out + COLS - 1) / COLS;
-  const int t = blockIdx.x - a.tile_start[l];
+  const int t = tt - a.tile_start[l];
   const int k0 = (t / ntn) * ROWS, n0 = (t % ntn) * COLS;
   FcRows<T> in = a.in[l], g = a.g[l];
   if (in.cxv) in.cxv += size_t(b) * a.in_stride[l]; else in.re += size_t(b) * a.in_stride[l];

@@ -153,3 +153,24 @@ def test_floor_bytes_of_the_benchmark_instance():
     import bench
     # 8 B x [32*4096 + 2*32*4096 + 2*128^2 + 32*32 + 6*32*225]
     assert bench.floor_bytes(64, 32, 32, 15) == 8 * (32 * 4096 + 64 * 4096 + 2 * 16384 + 1024 + 6 * 32 * 225)
+
+
+def test_valu_summary_issue_fraction(tmp_path):
+    name = "void pdfk::k_adj_conv_c<float, 64, true>(pdfk::AdjArgs<float>)"
+    _write_counters(str(tmp_path), [(name, "SQ_INSTS_VALU", 3.0e6), (name, "SQ_ACTIVE_INST_VALU", 1.5e6),
+                                    (name, "SQ_INSTS_VALU_FMA_F32", 1.0e6), (name, "SQ_INSTS_VALU_ADD_F32", 0.5e6),
+                                    (name, "SQ_INSTS_VALU_MUL_F32", 0.25e6), (name, "SQ_INSTS_LDS", 7.0)])
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerow({"Kernel_Name": name, "Start_Timestamp": 0, "End_Timestamp": 100_000})
+    text = bench.summarize_rocprof([str(tmp_path)], "valu", 256)
+    row = [l for l in text.splitlines() if l.startswith("kernel adj_conv")][0]
+    got = dict(kv.split("=") for kv in row.split()[3:])
+    cycles = 100e-6 * 2.4e9 * 256
+    assert float(got["valu_issue_frac"]) == pytest.approx(3.0e6 / cycles, abs=1e-3)
+    assert float(got["valu_busy_frac"]) == pytest.approx(1.5e6 / cycles, abs=1e-3)
+    flops = 64 * (2 * 1.0e6 + 0.5e6 + 0.25e6)
+    assert float(got["fp32_flops"]) == pytest.approx(flops, rel=1e-3)
+    assert float(got["flops_per_valu_inst"]) == pytest.approx(flops / 3.0e6, abs=0.05)
+    assert float(got["fp32_frac"]) == pytest.approx(flops / 100e-6 / 157.3e12, abs=1e-3)
