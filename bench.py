@@ -44,7 +44,7 @@ def log(*a):
 
 # kernel names in the library's timing order, and how they appear in profiler output
 KERNEL_SYMBOLS = {   # symbol prefixes of the step kernels (every tuning variant, both tiles)
-    "fwd_conv": ("k_fwd_conv<float, 64, true,", "k_fwd_conv_c<float, 64>"),
+    "fwd_conv": ("k_fwd_conv<float, 64, true,", "k_fwd_conv_c<float, 64,"),
     "pixel_reduce": ("k_pixel_reduce_mfma<",),
     "image_reg": ("k_image_reg<float>",),
     "adj_gemm": ("k_adj_gemm_mfma<",),
@@ -65,12 +65,13 @@ def tuned_variants(wl, tuned):
     tf = lambda b: "true" if b else "false"
     nrt, nct, nrta = -(-wl.n_rx // 16), -(-wl.n_tx // 32), -(-wl.n_tx // 16)
     compact = wl.M == 64 and wl.K <= COMPACT_MAX_K   # every plan choice runs the compact kernels
-    return {"fwd_conv": f"k_fwd_conv_c<float,{wl.M}>" if compact else f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
+    # K <= 16: the forward's beta U and the adjoint's g_J row transform wait in the compact tile's spare columns
+    spare = tf(2 * wl.K <= COMPACT_MAX_K)
+    return {"fwd_conv": f"k_fwd_conv_c<float,{wl.M},{spare}>" if compact else f"k_fwd_conv<float,{wl.M},true,{tf(fpp)}>",
             "pixel_reduce": f"k_pixel_reduce_mfma<{nrt},{nct},{pb}>",
             "image_reg": "k_image_reg<float>",
             "adj_gemm": f"k_adj_gemm_mfma<{nrta},{ct}>",
-            # K <= 16: the adjoint's g_J row transform waits in the compact tile's spare columns
-            "adj_conv": (f"k_adj_conv_c<float,{wl.M},{tf(2 * wl.K <= COMPACT_MAX_K)}>" if compact
+            "adj_conv": (f"k_adj_conv_c<float,{wl.M},{spare}>" if compact
                          else f"k_adj_conv<float,{wl.M},{tf(app)}>")}
 CALIBRATION_SYMBOL = "AUnaryFunctor<float, float"   # torch.mul(src, 1.0, out=dst)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg2_b256.txt")

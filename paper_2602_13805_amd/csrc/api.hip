@@ -122,7 +122,8 @@ static void set_lds(K kernel, size_t bytes) {
 }
 
 // The band-limited forward and adjoint on the compact tile: FP32 at 64 x 64 with K <= 32;
-// with K <= 16 the adjoint keeps the row transform of g_J in the tile's spare columns.
+// with K <= 16 the adjoint keeps the row transform of g_J, and the forward beta U, in the
+// tile's spare columns.
 static bool fwd_compact(const pdf_handle* h) {
   return h->prec == PDF_FP32 && h->M == 64 && !h->big && h->K <= CompactCfg<float, 64>::KC;
 }
@@ -143,8 +144,13 @@ static int launch_fwd_m(pdf_handle* h, const FwdArgs<T>& a, bool from_alpha, int
   if constexpr (sizeof(T) == 4 && M == 64) {
     if (from_alpha && fwd_compact(h)) {  // every plan choice: one kernel from coefficients
       using CC = CompactCfg<T, M>;
-      set_lds(k_fwd_conv_c<T, M>, CC::LDS);
-      hipLaunchKernelGGL((k_fwd_conv_c<T, M>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      if (adj_gj_spare(h)) {
+        set_lds(k_fwd_conv_c<T, M, true>, CC::LDS);
+        hipLaunchKernelGGL((k_fwd_conv_c<T, M, true>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      } else {
+        set_lds(k_fwd_conv_c<T, M, false>, CC::LDS);
+        hipLaunchKernelGGL((k_fwd_conv_c<T, M, false>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+      }
       return check_launch(h, "k_fwd_conv_c");
     }
   }
@@ -757,9 +763,13 @@ static void group_conv_m(const Group* g, hipStream_t st, bool adjoint) {
 static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
   if (g->compact) {
     using CC = CompactCfg<float, 64>;
-    if (!adjoint) {
-      set_lds(k_fwd_conv_c_group<float, 64>, CC::LDS);
-      hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
+    if (!adjoint && g->compact == 2) {
+      set_lds(k_fwd_conv_c_group<float, 64, true>, CC::LDS);
+      hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64, true>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
+                         g->st[0], g->n);
+    } else if (!adjoint) {
+      set_lds(k_fwd_conv_c_group<float, 64, false>, CC::LDS);
+      hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64, false>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
                          g->st[0], g->n);
     } else if (g->compact == 2) {
       set_lds(k_adj_conv_c_group<float, 64, true>, CC::LDS);

@@ -429,7 +429,13 @@ struct OffCols {
   __device__ __forceinline__ int addr(int v, int k) const { return Tile<TP>::at(k, c0 + v); }
 };
 
-template <typename T, int M>
+// BJ (K <= 16): beta J joins in the row spectrum instead of the pixel domain.
+// J's row transform is M U on the kept columns, so beta U waits in the spare
+// columns M + K .. M + 2K - 1 through the column phase and is added to the
+// convolved even columns before their inverse row transform; E then needs no
+// second read of the J this kernel stored (the result differs from adding the
+// stored J by FP32 rounding only).
+template <typename T, int M, bool BJ>
 __device__ __forceinline__ void fwd_conv_compact_body(const FwdArgs<T>& a, int bp, unsigned char* smem_raw) {
   using C = CompactCfg<T, M>;
   using TC = typename C::TileC;
@@ -459,9 +465,12 @@ __device__ __forceinline__ void fwd_conv_compact_body(const FwdArgs<T>& a, int b
   mc.kmin = kmin;
   Fft<T, M, C::EPT, NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<+1>();
   // even frequencies M U[y][k] of the kept k, compact in columns M..M+K-1
+  // (BJ: and beta U in columns M+K..M+2K-1)
   for (int e = tid; e < M * K; e += NT) {
     const int y = e / K, j = e % K;
-    buf[TC::at(y, M + j)] = T(M) * buf[TC::at(y, wrap_mode(kmin + j, M))];
+    const cx<T> u = buf[TC::at(y, wrap_mode(kmin + j, M))];
+    buf[TC::at(y, M + j)] = T(M) * u;
+    if constexpr (BJ) buf[TC::at(y, M + K + j)] = a.beta * u;
   }
   // J: inverse transforms along x of all M rows (the first pass stores only after its barrier)
   const Fft<T, M, C::EPT, NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
@@ -494,15 +503,20 @@ __device__ __forceinline__ void fwd_conv_compact_body(const FwdArgs<T>& a, int b
     eo[q] = buf[TC::at(n / M, x)] * w;
   }
   __syncthreads();
-  // the even part in natural order (zero where no mode is kept), then its inverse
+  // the even part in natural order (zero where no mode is kept; BJ: plus beta U), then its inverse
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int n = tid + q * NT, y = n / M, j = wrap_mode(n % M - kmin, M);
-    buf[TC::at(y, n % M)] = j < K ? buf[TC::at(y, M + j)] : cx<T>{T(0), T(0)};
+    cx<T> z{T(0), T(0)};
+    if (j < K) {
+      z = buf[TC::at(y, M + j)];
+      if constexpr (BJ) z = z + buf[TC::at(y, M + K + j)];
+    }
+    buf[TC::at(y, n % M)] = z;
   }
   __syncthreads();
   rowsm.template run<+1>();
-  cx<T> ei[PPT], jr[PPT];
+  cx<T> ei[PPT];
   if (a.einc) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q) ei[q] = a.einc[size_t(p) * C::N + tid + q * NT];
@@ -510,27 +524,36 @@ __device__ __forceinline__ void fwd_conv_compact_body(const FwdArgs<T>& a, int b
 #pragma unroll
     for (int q = 0; q < PPT; ++q) ei[q] = cx<T>{T(0), T(0)};
   }
+  if constexpr (BJ) {
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) jr[q] = a.J[off + tid + q * NT];
+    for (int q = 0; q < PPT; ++q) {
+      const int n = tid + q * NT;
+      a.E[off + n] = buf[TC::at(n / M, n % M)] + eo[q] + ei[q];
+    }
+  } else {
+    cx<T> jr[PPT];
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int n = tid + q * NT;
-    a.E[off + n] = buf[TC::at(n / M, n % M)] + eo[q] + a.beta * jr[q] + ei[q];
+    for (int q = 0; q < PPT; ++q) jr[q] = a.J[off + tid + q * NT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int n = tid + q * NT;
+      a.E[off + n] = buf[TC::at(n / M, n % M)] + eo[q] + a.beta * jr[q] + ei[q];
+    }
   }
 }
 
-template <typename T, int M>
+template <typename T, int M, bool BJ>
 __global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_fwd_conv_c(FwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fwd_conv_compact_body<T, M>(a, blockIdx.x, smem_raw);
+  fwd_conv_compact_body<T, M, BJ>(a, blockIdx.x, smem_raw);
 }
 
-template <typename T, int M>
+template <typename T, int M, bool BJ>
 __global__ __launch_bounds__((CompactCfg<T, M>::NT), (CompactCfg<T, M>::WPE)) void k_fwd_conv_c_group(
     const FwdArgs<T>* __restrict__ a, const int* __restrict__ start, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = group_of(start, n, blockIdx.x);
-  fwd_conv_compact_body<T, M>(a[g], blockIdx.x - start[g], smem_raw);
+  fwd_conv_compact_body<T, M, BJ>(a[g], blockIdx.x - start[g], smem_raw);
 }
 
 template <typename T>

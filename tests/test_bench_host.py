@@ -83,14 +83,14 @@ def test_kernel_variants_of_the_tile_choices():
     v = bench.tuned_variants(wl, (4, 8, 0, 1))
     assert v["pixel_reduce"] == "k_pixel_reduce_mfma<2,1,8>" and v["adj_gemm"] == "k_adj_gemm_mfma<2,4>"
     # K = 15 <= 32: the convolutions run on the compact tile under every plan choice
-    assert v["fwd_conv"] == "k_fwd_conv_c<float,64>" and v["adj_conv"] == "k_adj_conv_c<float,64,true>"
+    assert v["fwd_conv"] == "k_fwd_conv_c<float,64,true>" and v["adj_conv"] == "k_adj_conv_c<float,64,true>"
     assert bench.tuned_variants(dataclasses.replace(wl, K=21), (4, 8, 0, 1))["adj_conv"] == "k_adj_conv_c<float,64,false>"
     wide = dataclasses.replace(wl, K=33)
     v = bench.tuned_variants(wide, (4, 8, 0, 1))
     assert v["fwd_conv"] == "k_fwd_conv<float,64,true,false>" and v["adj_conv"] == "k_adj_conv<float,64,true>"
     assert bench.kernel_variant(ADJ) == "k_adj_conv<float,64,false>"
     assert bench._short_kernel("void pdfk::k_adj_conv_c<float, 64, true>(pdfk::AdjArgs<float>)") == "adj_conv"
-    assert bench._short_kernel("void pdfk::k_fwd_conv_c<float, 64>(pdfk::FwdArgs<float>)") == "fwd_conv"
+    assert bench._short_kernel("void pdfk::k_fwd_conv_c<float, 64, true>(pdfk::FwdArgs<float>)") == "fwd_conv"
 
 
 def test_cost_models():
