@@ -265,7 +265,11 @@ struct FwdArgs {
 // 0..M-1 and the K even ones in columns M..M+K-1, so the column phase
 // convolves M + K columns instead of 2M; the cropped inverse row transform is
 // then IFFT_M(even) + conj(w) IFFT_M(odd) on the two halves of each row.
-// From given currents (the start value) the general convolution runs.
+// With 2K <= M (grids up to 64), beta J joins in the row spectrum: J's row transform is M U on
+// the kept columns, so beta U waits in the free columns M+K..M+2K-1 through
+// the column phase and is added to the even half before its inverse, and E
+// needs no second read of the stored J (equal to adding it up to FP32 or FP64
+// rounding).  From given currents (the start value) the general convolution runs.
 // PP: the plan of the row passes of the general convolution (see ConvCfg), a
 // tuning choice with identical results; the band-limited path has one plan.
 template <typename T, int M, bool FROM_ALPHA, bool PP>
@@ -309,10 +313,14 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     mc.nv = K;
     mc.kmin = kmin;
     Fft<T, M, C::EPT_M, C::NT, typename C::ModeCols, 2>{buf, tw, mc}.template run<+1>();
-    // even frequencies M U[y][k] of the kept k, compact in columns M..M+K-1
+    // even frequencies M U[y][k] of the kept k, compact in columns M..M+K-1 (and
+    // beta U in columns M+K..M+2K-1 when they fit)
+    const bool bj = M <= 64 && 2 * K <= M;  // at 96 the second epilogue would add spills
     for (int e = tid; e < M * K; e += C::NT) {
       const int y = e / K, j = e % K;
-      buf[C::TileL::at(y, M + j)] = T(M) * buf[C::TileL::at(y, wrap_mode(kmin + j, M))];
+      const cx<T> u = buf[C::TileL::at(y, wrap_mode(kmin + j, M))];
+      buf[C::TileL::at(y, M + j)] = T(M) * u;
+      if (bj) buf[C::TileL::at(y, M + K + j)] = a.beta * u;
     }
     // (the next pass stores to columns 0..M-1 only after its first barrier)
     // J: inverse transforms along x of all M rows
@@ -329,13 +337,17 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     // odd frequencies FFT_M(J w) of each row, in place in columns 0..M-1
     rowsm.template run<-1>(TwistLoad<T>{tw});
     col_conv<T, M, true>(buf, tw, a.ghat, false, M + K, kmin);
-    // even part back to natural order (zero where no mode is kept) in columns M..P-1
+    // even part back to natural order (zero where no mode is kept; plus beta U) in columns M..P-1
     cx<T> ev[C::PPT];
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int e = tid + q * C::NT;
       const int y = e / M, k = e % M, j = wrap_mode(k - kmin, M);
-      ev[q] = j < K ? buf[C::TileL::at(y, M + j)] : cx<T>{T(0), T(0)};
+      ev[q] = cx<T>{T(0), T(0)};
+      if (j < K) {
+        ev[q] = buf[C::TileL::at(y, M + j)];
+        if (bj) ev[q] = ev[q] + buf[C::TileL::at(y, M + K + j)];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -346,16 +358,27 @@ __device__ __forceinline__ void fwd_conv_body(const FwdArgs<T>& a, int bp, unsig
     __syncthreads();
     // inverse transforms of both halves of every row
     Fft<T, M, C::EPT_M, C::NT, HalfRows<P>, 2>{buf, tw, HalfRows<P>{}}.template run<+1>();
-    cx<T> ei[C::PPT], jr[C::PPT];
+    cx<T> ei[C::PPT];
     load_einc(ei);
+    if (bj) {
 #pragma unroll
-    for (int q = 0; q < C::PPT; ++q) jr[q] = a.J[off + tid + q * C::NT];
+      for (int q = 0; q < C::PPT; ++q) {
+        const int n = tid + q * C::NT, y = n / M, x = n % M;
+        cx<T> w = tw[x];
+        w.y = -w.y;
+        a.E[off + n] = buf[C::TileL::at(y, M + x)] + buf[C::TileL::at(y, x)] * w + ei[q];
+      }
+    } else {
+      cx<T> jr[C::PPT];
 #pragma unroll
-    for (int q = 0; q < C::PPT; ++q) {
-      const int n = tid + q * C::NT, y = n / M, x = n % M;
-      cx<T> w = tw[x];
-      w.y = -w.y;
-      a.E[off + n] = buf[C::TileL::at(y, M + x)] + buf[C::TileL::at(y, x)] * w + a.beta * jr[q] + ei[q];
+      for (int q = 0; q < C::PPT; ++q) jr[q] = a.J[off + tid + q * C::NT];
+#pragma unroll
+      for (int q = 0; q < C::PPT; ++q) {
+        const int n = tid + q * C::NT, y = n / M, x = n % M;
+        cx<T> w = tw[x];
+        w.y = -w.y;
+        a.E[off + n] = buf[C::TileL::at(y, M + x)] + buf[C::TileL::at(y, x)] * w + a.beta * jr[q] + ei[q];
+      }
     }
   } else {
     cx<T> jr[C::PPT];
