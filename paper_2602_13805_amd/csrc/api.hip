@@ -297,11 +297,11 @@ static int launch_adj_m(pdf_handle* h, const AdjArgs<T>& a, int nblk) {
     if (fwd_compact(h)) {  // every plan choice: the band-limited adjoint on the compact tile
       using CC = CompactCfg<T, M>;
       if (adj_gj_spare(h)) {
-        set_lds(k_adj_conv_c<T, M, true>, CC::LDS);
-        hipLaunchKernelGGL((k_adj_conv_c<T, M, true>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+        set_lds(k_adj_conv_c<T, M, true>, CC::LDS_ADJ);
+        hipLaunchKernelGGL((k_adj_conv_c<T, M, true>), dim3(nblk), dim3(CC::NT), CC::LDS_ADJ, h->stream, a);
       } else {
-        set_lds(k_adj_conv_c<T, M, false>, CC::LDS);
-        hipLaunchKernelGGL((k_adj_conv_c<T, M, false>), dim3(nblk), dim3(CC::NT), CC::LDS, h->stream, a);
+        set_lds(k_adj_conv_c<T, M, false>, CC::LDS_ADJ);
+        hipLaunchKernelGGL((k_adj_conv_c<T, M, false>), dim3(nblk), dim3(CC::NT), CC::LDS_ADJ, h->stream, a);
       }
       return check_launch(h, "k_adj_conv_c");
     }
@@ -772,12 +772,12 @@ static void group_conv(const Group* g, hipStream_t st, bool adjoint) {
       hipLaunchKernelGGL((k_fwd_conv_c_group<float, 64, false>), dim3(g->tot[0]), dim3(CC::NT), CC::LDS, st, g->fwd,
                          g->st[0], g->n);
     } else if (g->compact == 2) {
-      set_lds(k_adj_conv_c_group<float, 64, true>, CC::LDS);
-      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, true>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
+      set_lds(k_adj_conv_c_group<float, 64, true>, CC::LDS_ADJ);
+      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, true>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS_ADJ, st, g->adj,
                          g->st[4], g->n);
     } else {
-      set_lds(k_adj_conv_c_group<float, 64, false>, CC::LDS);
-      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, false>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS, st, g->adj,
+      set_lds(k_adj_conv_c_group<float, 64, false>, CC::LDS_ADJ);
+      hipLaunchKernelGGL((k_adj_conv_c_group<float, 64, false>), dim3(g->tot[4]), dim3(CC::NT), CC::LDS_ADJ, st, g->adj,
                          g->st[4], g->n);
     }
     return;
@@ -1224,8 +1224,15 @@ static int setup_impl(pdf_handle* h, const pdfh::Tables& t) {
   int rc;
   const double inv = 1.0 / (double(h->P) * h->P);
   if ((rc = upload<T>(h, &h->ghat, t.ghat, inv))) return rc;
-  std::vector<std::complex<double>> tw(h->P);
+  // the P twiddles exp(-2 pi i k / P), then the half-shift values
+  // hs[m] = 2 / (1 - exp(-i pi (2m + 1) / M)) of the compact tile's row products over two
+  // periods from m = -M/2
+  std::vector<std::complex<double>> tw(h->P + 2 * h->M);
   for (int k = 0; k < h->P; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * k / h->P);
+  for (int p = 0; p < 2 * h->M; ++p) {
+    const int m = (p + h->M - h->M / 2) % h->M;   // (p - M/2) mod M
+    tw[h->P + p] = 2.0 / (1.0 - std::polar(1.0, -M_PI * (2.0 * m + 1.0) / h->M));
+  }
   if ((rc = upload<T>(h, &h->tw, tw, 1.0))) return rc;
   if ((rc = upload<T>(h, &h->gs, t.gs, 1.0))) return rc;
   {

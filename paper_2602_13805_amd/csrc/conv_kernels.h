@@ -436,8 +436,10 @@ struct CompactCfg {
   static constexpr int NT = ConvCfg<T, M>::NT;
   static constexpr int N = M * M, PPT = N / NT;
   static constexpr int EPT = 8;               // basis transforms and column chains
-  static constexpr size_t LDS = sizeof(cx<T>) * (size_t(M) * TileC::LD + 2 * M);  // + the P twiddles
-  static constexpr int WPE = int((160 * 1024) / LDS) * (NT / 64) / 4 > 8 ? 8 : int((160 * 1024) / LDS) * (NT / 64) / 4;
+  // + the P twiddles (forward), and the half-shift values over two periods (adjoint)
+  static constexpr size_t LDS = sizeof(cx<T>) * (size_t(M) * TileC::LD + 2 * M);
+  static constexpr size_t LDS_ADJ = LDS + sizeof(cx<T>) * 2 * M;
+  static constexpr int WPE = int((160 * 1024) / LDS_ADJ) * (NT / 64) / 4 > 8 ? 8 : int((160 * 1024) / LDS_ADJ) * (NT / 64) / 4;
   using RowsM = Vecs<PC, M, true>;
   using ModeCols = Vecs<PC, M, false, true>;
 };
@@ -451,6 +453,81 @@ struct OffCols {
   int c0 = 0;
   __device__ __forceinline__ int addr(int v, int k) const { return Tile<TP>::at(k, c0 + v); }
 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Row products on the matrix cores for the compact tile (64 x 64 FP32).  The
+// complex product Y = X C is the real one
+//   [Re Y, Im Y] = [Re X, Im X] [[Re C, Im C], [-Im C, Re C]]
+// on v_mfma_f32_16x16x4f32, two complex input columns per instruction: lane
+// l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and register e returns
+// D[e + 4 (l / 16)][l % 16].  So lane l works on row i = l % 16 of A, on part
+// l / 16 % 2 (0 Re, 1 Im) of input column (l / 16) / 2 of a step, and on
+// output column (l % 16) / 2, part l % 2; B takes component sel = (l / 16 %
+// 2) xor (l % 2) of C, negated for A's imaginary part against a real output.
+// Every output sums over the input columns in one fixed order.
+//
+// The coefficients are the half-shift values hs[m] = 2 / (1 - exp(-i pi (2m
+// + 1) / M)), stored after the P twiddles (layout at kept_rows_hs): with
+// w[x] = exp(-2 pi i x / P),
+//   sum_x w[x] exp(2 pi i (k - c) x / M) = hs[(c - k) mod M]
+// (a geometric sum of ratio exp(-i pi (2 (c - k) + 1) / M), whose M-th power
+// is -1), i.e. the length-M transform of w times one mode.
+struct RowProdLane {
+  int i, kq, pa, sel;
+  float sg;
+  __device__ __forceinline__ RowProdLane() {
+    const int l = threadIdx.x & 63;
+    i = l & 15;
+    kq = l >> 4;
+    pa = kq & 1;
+    sel = pa ^ (i & 1);
+    sg = (pa == 1 && (i & 1) == 0) ? -1.f : 1.f;
+  }
+};
+
+// Y[r][j] = s sum_{c < M} X[r][c] conj(hs[c - k_j]) for r < M and j < K <= 16
+// (k_j = kmin + j), X the first M columns of the tile; wave w of eight takes
+// rows 16 (w % 4) .. + 15 and outputs 8 (w / 4) .. + 7.  This lane's results:
+// acc[e] is part `part` of Y[row + e][j] (valid for j < K).  The half-shift
+// values are stored over two periods from -M/2 (tw[P + p] = hs[(p - M/2) mod
+// M], p < 2M; index c - k_j + M/2 lies in [M/2 - K/2, 3M/2 + K/2) for c < M),
+// so that a lane's coefficients of successive steps sit at constant offsets;
+// the even and the odd steps accumulate separately and are added at the end.
+struct KeptOut {
+  f32x4 acc;
+  int row, j, part;
+};
+template <int M, int LD>
+__device__ __forceinline__ KeptOut kept_rows_hs(const cx<float>* buf, const cx<float>* tw, int K, int kmin,
+                                                float scale) {
+  const RowProdLane ln;
+  const int w = threadIdx.x >> 6;
+  KeptOut o;
+  o.row = 16 * (w & 3) + 4 * ln.kq;
+  o.j = 8 * (w >> 2) + (ln.i >> 1);
+  o.part = ln.i & 1;
+  o.acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (8 * (w >> 2) >= K) return o;  // no output column of this wave
+  const int jc = o.j < K ? o.j : K - 1;
+  // the role's sign, conj on the imaginary component, and the scale
+  const float f = o.j < K ? (ln.sel ? -ln.sg : ln.sg) * scale : 0.f;
+  const float* xr = reinterpret_cast<const float*>(buf + (16 * (w & 3) + ln.i) * LD) + 2 * (ln.kq >> 1) + ln.pa;
+  // step s reads table entry 2 s + (kq / 2) - k_j + M/2
+  const float* hr = reinterpret_cast<const float*>(tw + 2 * M + (ln.kq >> 1) - (kmin + jc) + M / 2) + ln.sel;
+  f32x4 a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < M / 2; s += 2) {
+    o.acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[4 * s], f * hr[4 * s], o.acc, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[4 * s + 4], f * hr[4 * s + 4], a1, 0, 0, 0);
+  }
+  o.acc = o.acc + a1;
+  return o;
+}
+
+__device__ __forceinline__ void set_part(cx<float>& z, int part, float v) {
+  reinterpret_cast<float*>(&z)[part] = v;
+}
 
 // BJ (K <= 16): beta J joins in the row spectrum instead of the pixel domain.
 // J's row transform is M U on the kept columns, so beta U waits in the spare
@@ -787,7 +864,9 @@ struct EvenJoinLoad {
 // columns of rowFFT(g_J) are formed first and wait in the compact tile's
 // spare columns M + K.., so no g_J is held through the convolution (the
 // registers it would take push the column phase past the 80 that three
-// workgroups per CU leave); otherwise g_J waits in registers and joins in the
+// workgroups per CU leave), and the odd part's two row transforms are one
+// product on the matrix cores with the half-shift values (only its K kept
+// columns are needed); otherwise g_J waits in registers and joins in the
 // pixel domain.
 template <typename T, int M, bool GJ>
 __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int bp, unsigned char* smem_raw) {
@@ -797,7 +876,7 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = buf + M * TC::LD;
   const int tid = threadIdx.x;
-  for (int k = tid; k < 2 * M; k += NT) tw[k] = a.tw[k];
+  for (int k = tid; k < 4 * M; k += NT) tw[k] = a.tw[k];
   const int K = a.K, kmin = -(K / 2);
   const Fft<T, M, C::EPT, NT, typename C::RowsM, 2> rowsm{buf, tw, typename C::RowsM{}};
   cx<T> ge[PPT], gj[GJ ? 1 : PPT];
@@ -851,21 +930,29 @@ __device__ __forceinline__ void adj_conv_compact_body(const AdjArgs<T>& a, int b
     col_chains<T, M, C::EPT, NT>(buf, tw, a.ghat, true, even, [&](int j) { return 2 * wrap_mode(kmin + j, M); });
   }
   __syncthreads();
-  // the odd part back to pixels, conj(w) IFFT_M (plus g_J when it waited in registers)
-  rowsm.template run<+1>();
+  if constexpr (GJ) {
+    // the odd part: the kept columns of FFT_M(conj(w) IFFT_M(W_odd)) = sum_c W_odd[c] conj(hs[c - k_j]),
+    // to their natural columns once every wave has read W_odd (matrix cores)
+    const KeptOut o = kept_rows_hs<M, TC::LD>(buf, tw, K, kmin, T(1));
+    __syncthreads();
+    if (o.j < K)
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int n = tid + q * NT, x = n % M;
-    cx<T> w = tw[x];
-    w.y = -w.y;
-    cx<T>& d = buf[TC::at(n / M, x)];
-    if constexpr (GJ)
-      d = d * w;
-    else
+      for (int e = 0; e < 4; ++e) set_part(buf[TC::at(o.row + e, wrap_mode(kmin + o.j, M))], o.part, o.acc[e]);
+  } else {
+    // the odd part back to pixels, conj(w) IFFT_M, plus g_J, then the row transform
+    rowsm.template run<+1>();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int n = tid + q * NT, x = n % M;
+      cx<T> w = tw[x];
+      w.y = -w.y;
+      cx<T>& d = buf[TC::at(n / M, x)];
       d = d * w + gj[q];
+    }
+    __syncthreads();
+    rowsm.template run<-1>();
   }
   __syncthreads();
-  rowsm.template run<-1>();
   // column transforms of the kept modes, M W_even (and rowFFT(g_J)) joining in their first pass
   typename C::ModeCols mc;
   mc.nv = K;

@@ -19,7 +19,7 @@ struct pdf_handle {
   std::string scratch_err;        // why scratch_dev is null, if it is
   // operator tables (handle precision)
   void* ghat = nullptr;   // [P][P] spectrum / P^2
-  void* tw = nullptr;     // [P] exp(-2 pi i k / P)
+  void* tw = nullptr;     // [P + M] exp(-2 pi i k / P), then the half-shift values hs[m]
   void* gs = nullptr;     // [Ns][N]
   void* gsT = nullptr;    // [N][Ns] (transposed copy for the MFMA receiver GEMM)
   float* gsA = nullptr;   // FP32: [N][ceil(Ns/16)][64] A operands of that GEMM in lane order
