@@ -196,13 +196,15 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
     // by a multiplication): a load whose value feeds only one arm of a select
     // is moved under a branch by the compiler and waited for on its own.
     const float vm = valid ? 1.f : 0.f;
+    // each sum is a chain of FP64 fused multiply-adds, in the same order for every load batch
     auto accumulate = [&](int p, cx<float> J, cx<float> E) {
       J = cx<float>{vm * J.x, vm * J.y};
       E = cx<float>{vm * E.x, vm * E.y};
-      nr += double(J.x) * E.x + double(J.y) * E.y;
-      ni += double(J.y) * E.x - double(J.x) * E.y;
-      dd += double(E.x) * E.x + double(E.y) * E.y;
-      jj += double(J.x) * J.x + double(J.y) * J.y;
+      const double jx = J.x, jy = J.y, ex = E.x, ey = E.y;
+      nr = fma(jy, ey, fma(jx, ex, nr));
+      ni = fma(-jx, ey, fma(jy, ex, ni));
+      dd = fma(ey, ey, fma(ex, ex, dd));
+      jj = fma(jy, jy, fma(jx, jx, jj));
       Jr[px * LDJ + p] = J.x;
       Ji[px * LDJ + p] = J.y;
     };
@@ -265,7 +267,23 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
     const int kmax = min(SUB, N - sub0);
     const int k0 = w * (SUB / 4), k1 = min(k0 + SUB / 4, kmax);
     constexpr int KC = 4;
-    if (k0 < k1) {  // wave-uniform
+    if (k1 - k0 == SUB / 4) {  // a whole quarter (wave-uniform): no clamping or masking, constant offsets
+      const float* Ab = a.gsA + (size_t(sub0) + k0) * NRT * 64 + lane;
+      const float* Bb = Jsrc + k0 * LDJ + m;
+#pragma unroll
+      for (int kk = 0; kk < SUB / 4; ++kk) {
+        float av[NRT], bv[NCT];
+#pragma unroll
+        for (int h = 0; h < NRT; ++h) av[h] = Ab[(kk * NRT + h) * 64];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) bv[t] = Bb[kk * LDJ + 32 * t];
+#pragma unroll
+        for (int h = 0; h < NRT; ++h)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t)
+            acc[h][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[h], bv[t], acc[h][t], 0, 0, 0);
+      }
+    } else if (k0 < k1) {  // wave-uniform
       const float* Ab = a.gsA + size_t(sub0) * NRT * 64 + lane;
       // pixels past the range (clamped loads) are masked by a zero operand
       auto load_a = [&](float (&av)[KC][NRT], int kb) {
