@@ -3,6 +3,8 @@
 // regularisers with their gradient, the CCO image, and small reductions.
 #pragma once
 
+#include <type_traits>
+
 #include "cplx.h"
 
 namespace pdfk {
@@ -190,36 +192,51 @@ __device__ __forceinline__ void pixel_reduce_mfma_body(const ReduceArgs<float>& 
     // 1. reduction over this thread's incidences
     double nr = 0, ni = 0, dd = 0, jj = 0;
     const int nc = min(n, N - 1);
-    const cx<float>* Jb = a.J + size_t(b) * Ni * N + nc;
-    const cx<float>* Eb = a.E + size_t(b) * Ni * N + nc;
-    // Loaded values are used unconditionally (a pixel past the end is masked
-    // by a multiplication): a load whose value feeds only one arm of a select
-    // is moved under a branch by the compiler and waited for on its own.
-    const float vm = valid ? 1.f : 0.f;
-    // each sum is a chain of FP64 fused multiply-adds, in the same order for every load batch
-    auto accumulate = [&](int p, cx<float> J, cx<float> E) {
-      J = cx<float>{vm * J.x, vm * J.y};
-      E = cx<float>{vm * E.x, vm * E.y};
-      const double jx = J.x, jy = J.y, ex = E.x, ey = E.y;
-      nr = fma(jy, ey, fma(jx, ex, nr));
-      ni = fma(-jx, ey, fma(jy, ex, ni));
-      dd = fma(ey, ey, fma(ex, ex, dd));
-      jj = fma(jy, jy, fma(jx, jx, jj));
-      Jr[px * LDJ + p] = J.x;
-      Ji[px * LDJ + p] = J.y;
+    // the instance's blocks (workgroup-uniform) and 32-bit byte offsets (8 Ni N <= 8 x 64 x 256^2)
+    const char* Jb = reinterpret_cast<const char*>(a.J + size_t(b) * Ni * N);
+    const char* Eb = reinterpret_cast<const char*>(a.E + size_t(b) * Ni * N);
+    auto ld = [&](const char* base, int p) {
+      return *reinterpret_cast<const cx<float>*>(base + 8u * unsigned(p * N + nc));
     };
+    // Loaded values are used unconditionally (in a sub-tile past the end, a
+    // pixel beyond it is masked by a multiplication): a load whose value feeds
+    // only one arm of a select is moved under a branch by the compiler and
+    // waited for on its own.
+    const float vm = valid ? 1.f : 0.f;
     int p0 = half;
-    for (; p0 + 2 * (PB - 1) < Ni; p0 += 2 * PB) {  // whole batches: loads issued before use
-      cx<float> Jv[PB], Ev[PB];
+    // the sub-tile's incidences; MASK: the sub-tile reaches past the end (a block-uniform choice)
+    auto incidences = [&](auto mask_c) {
+      constexpr bool MASK = decltype(mask_c)::value;
+      // each sum is a chain of FP64 fused multiply-adds, in the same order for every load batch
+      auto accumulate = [&](int p, cx<float> J, cx<float> E) {
+        if constexpr (MASK) {
+          J = cx<float>{vm * J.x, vm * J.y};
+          E = cx<float>{vm * E.x, vm * E.y};
+        }
+        const double jx = J.x, jy = J.y, ex = E.x, ey = E.y;
+        nr = fma(jy, ey, fma(jx, ex, nr));
+        ni = fma(-jx, ey, fma(jy, ex, ni));
+        dd = fma(ey, ey, fma(ex, ex, dd));
+        jj = fma(jy, jy, fma(jx, jx, jj));
+        Jr[px * LDJ + p] = J.x;
+        Ji[px * LDJ + p] = J.y;
+      };
+      for (; p0 + 2 * (PB - 1) < Ni; p0 += 2 * PB) {  // whole batches: loads issued before use
+        cx<float> Jv[PB], Ev[PB];
 #pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        Jv[u] = Jb[size_t(p0 + 2 * u) * N];
-        Ev[u] = Eb[size_t(p0 + 2 * u) * N];
+        for (int u = 0; u < PB; ++u) {
+          Jv[u] = ld(Jb, p0 + 2 * u);
+          Ev[u] = ld(Eb, p0 + 2 * u);
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) accumulate(p0 + 2 * u, Jv[u], Ev[u]);
       }
-#pragma unroll
-      for (int u = 0; u < PB; ++u) accumulate(p0 + 2 * u, Jv[u], Ev[u]);
-    }
-    for (; p0 < Ni; p0 += 2) accumulate(p0, Jb[size_t(p0) * N], Eb[size_t(p0) * N]);
+      for (; p0 < Ni; p0 += 2) accumulate(p0, ld(Jb, p0), ld(Eb, p0));
+    };
+    if (sub0 + SUB <= N)
+      incidences(std::false_type{});
+    else
+      incidences(std::true_type{});
     for (; p0 < 32 * NCT; p0 += 2) {  // zero incidences pad the MFMA tile
       Jr[px * LDJ + p0] = 0.f;
       Ji[px * LDJ + p0] = 0.f;
