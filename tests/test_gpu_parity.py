@@ -81,6 +81,10 @@ CASES = [
     (64, 32, 8, 12, 1, "fp32", 1e-4),   # the compact tile at its largest K (even: corner blocks)
     (64, 33, 8, 12, 1, "fp32", 1e-4),   # one mode more: the full tile
     (64, 1, 4, 6, 2, "fp32", 1e-4),     # the compact tile with a single mode
+    (64, 16, 8, 12, 1, "fp32", 1e-4),   # the compact tile's largest K with beta U and g_J's kept columns in
+                                        # its spare columns, and the adjoint's odd-part product (even K)
+    (64, 17, 8, 12, 1, "fp32", 1e-4),   # one mode more: both wait elsewhere, the odd part by row transforms
+    (32, 16, 6, 8, 1, "fp64", 1e-9),    # 2K = M: the last K at which the full tile's forward folds beta J
 ]
 
 
