@@ -2001,15 +2001,15 @@ static void fc_launch_mfma(pdf_handle* h, const FcLayerArgs<float>& a, int kind)
   const size_t lds = kFcMfmaLds;
   if (kind == 0) {
     set_lds(k_fc_fwd_mfma<RT, false>, lds);
-    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, false>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, false>), dim3((a.n_out + kFcCols - 1) / kFcCols * h->B), dim3(256), lds,
                        h->stream, a);
   } else if (kind == 1) {
     set_lds(k_fc_fwd_mfma<RT, true>, lds);
-    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, true>), dim3((a.n_out + kFcCols - 1) / kFcCols, h->B), dim3(256), lds,
+    hipLaunchKernelGGL((k_fc_fwd_mfma<RT, true>), dim3((a.n_out + kFcCols - 1) / kFcCols * h->B), dim3(256), lds,
                        h->stream, a);
   } else {
     set_lds(k_fc_bwd_mfma<RT>, lds);
-    hipLaunchKernelGGL((k_fc_bwd_mfma<RT>), dim3((a.n_in + kFcCols - 1) / kFcCols, h->B), dim3(256), lds, h->stream,
+    hipLaunchKernelGGL((k_fc_bwd_mfma<RT>), dim3((a.n_in + kFcCols - 1) / kFcCols * h->B), dim3(256), lds, h->stream,
                        a);
   }
 }

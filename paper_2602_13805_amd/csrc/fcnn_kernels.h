@@ -276,14 +276,31 @@ __device__ __forceinline__ int fc_mfma_row(int t, int j) {
 }
 __device__ __forceinline__ int fc_mfma_col(int n0) { return n0 + ((threadIdx.x >> 6) & 1) * 32 + (threadIdx.x & 31); }
 
+// Reconstruction b and column tile t of this workgroup in a one-dimensional grid of ntiles x B.
+// Consecutive workgroups go to the eight XCDs in turn; with B a multiple of 8 the tiles of one
+// reconstruction are given to workgroups of one XCD, so its staged rows are fetched into one L2.
+__device__ __forceinline__ void fc_tile_of(int ntiles, int& b, int& t) {
+  const int id = blockIdx.x, B = gridDim.x / ntiles;
+  if (B % 8 == 0) {
+    const int x = id & 7, sl = id >> 3;
+    b = x + 8 * (sl / ntiles);
+    t = sl % ntiles;
+  } else {
+    b = id / ntiles;
+    t = id % ntiles;
+  }
+}
+
 // Forward of one layer, FP32 on MFMA: tanh rows of a hidden layer, or the output layer's plain
-// rows (OUT).  Grid (ceil(n_out / 64), B), 256 threads; R <= 32 RT.
+// rows (OUT).  Grid ceil(n_out / 64) x B (one-dimensional, fc_tile_of), 256 threads; R <= 32 RT.
 template <int RT, bool OUT>
 __global__ void __launch_bounds__(256) k_fc_fwd_mfma(FcLayerArgs<float> a) {
   extern __shared__ unsigned char fc_smem[];
   float* As = reinterpret_cast<float*>(fc_smem);
   float* Ws = As + kFcMaxRows * kFcLdA;
-  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  int b, tile;
+  fc_tile_of((a.n_out + kFcCols - 1) / kFcCols, b, tile);
+  const int n0 = tile * kFcCols;
   FcRows<float> in = a.in;
   if (in.cxv) in.cxv += size_t(b) * a.in_stride; else in.re += size_t(b) * a.in_stride;
   const float* W = a.theta + size_t(b) * a.theta_stride;
@@ -305,13 +322,16 @@ __global__ void __launch_bounds__(256) k_fc_fwd_mfma(FcLayerArgs<float> a) {
     }
 }
 
-// Pre-activation gradient of a hidden layer, FP32 on MFMA.  Grid (ceil(n_in / 64), B), 256 threads.
+// Pre-activation gradient of a hidden layer, FP32 on MFMA.  Grid ceil(n_in / 64) x B
+// (one-dimensional, fc_tile_of), 256 threads.
 template <int RT>
 __global__ void __launch_bounds__(256) k_fc_bwd_mfma(FcLayerArgs<float> a) {
   extern __shared__ unsigned char fc_smem[];
   float* As = reinterpret_cast<float*>(fc_smem);
   float* Ws = As + kFcMaxRows * kFcLdA;
-  const int b = blockIdx.y, n0 = blockIdx.x * kFcCols;
+  int b, tile;
+  fc_tile_of((a.n_in + kFcCols - 1) / kFcCols, b, tile);
+  const int n0 = tile * kFcCols;
   FcRows<float> g = a.in;
   if (g.cxv) g.cxv += size_t(b) * a.in_stride; else g.re += size_t(b) * a.in_stride;
   const float* W = a.theta + size_t(b) * a.theta_stride;
