@@ -470,7 +470,7 @@ static int launch_reg_cco(pdf_handle* h, RegArgs<T> a) {
   a.lse = h->ccl_part;
   a.nlse = nblk;
   a.graw = h->prm.r_stopgrad ? 0 : 1;
-  const size_t lds = sizeof(cx<T>) * size_t(N) + 16 * sizeof(double);
+  const size_t lds = 2 * sizeof(cx<T>) * size_t(N) + 16 * sizeof(double);
   set_lds(k_image_reg<T>, lds);
   hipLaunchKernelGGL(k_image_reg<T>, dim3(h->B), dim3(N < 1024 ? N : 1024), lds, h->stream, a);
   if ((rc = check_launch(h, "k_image_reg"))) return rc;
@@ -492,7 +492,8 @@ static int launch_reg(pdf_handle* h, double* loss, int* tstep, const int* frozen
     hipLaunchKernelGGL(k_image_reg_fin<T>, dim3(h->B), dim3(256), 0, h->stream, a, (const double*)h->reg_part, nblk);
     return check_launch(h, "k_image_reg_part/fin");
   }
-  const size_t lds = sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
+  if (h->N > reg_pix_max<T>() * nt) return fail(h, PDF_EUNSUPPORTED, "grid too large for the one-workgroup regulariser");
+  const size_t lds = 2 * sizeof(cx<T>) * size_t(h->N) + 16 * sizeof(double);
   set_lds(k_image_reg<T>, lds);
   hipLaunchKernelGGL(k_image_reg<T>, dim3(h->B), dim3(nt), lds, h->stream, a);
   return check_launch(h, "k_image_reg");
@@ -685,7 +686,7 @@ static int group_build(Group* g, const std::vector<pdf_handle*>& hs, const std::
   g->app = h0->tune_app;
   g->nbx = (h0->N + 128 * g->ct - 1) / (128 * g->ct);
   g->nt_reg = h0->N < 1024 ? h0->N : 1024;
-  g->lds_reg = sizeof(cx<float>) * size_t(h0->N) + 16 * sizeof(double);
+  g->lds_reg = 2 * sizeof(cx<float>) * size_t(h0->N) + 16 * sizeof(double);
   int max_ns = 0;
   for (pdf_handle* h : hs) max_ns = std::max(max_ns, h->Ns);
   g->lds_ag = sizeof(cx<float>) * size_t(max_ns) * 16 * g->nrta;

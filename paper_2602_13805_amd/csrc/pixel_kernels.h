@@ -485,10 +485,29 @@ __device__ __forceinline__ double reg_data(const RegArgs<T>& a, int b, int o, in
   return rr * rr + ri * ri;
 }
 
+// g_R = conj(1 / (beta (1 - R)^2)) g_chi at pixel n from g_chi = g (g itself
+// with graw, zero with R held fixed); tracks max |R| and non-finite gradients.
+template <typename T>
+__device__ __forceinline__ void reg_grad_out(const RegArgs<T>& a, int b, int n, const cx<T>& R, const cx<T>& g,
+                                             double& rmax, bool& bad) {
+  const int N = a.M * a.M;
+  rmax = fmax(rmax, sqrt(double(norm2(R))));
+  cx<T> gR{T(0), T(0)};
+  if (a.graw) {
+    gR = g;
+  } else if (!a.r_stopgrad) {
+    const cx<T> om{T(1) - R.x, -R.y};
+    const cx<T> w = om * om;
+    const T den = T(a.beta) * norm2(w);
+    gR = cx<T>{(w.x * g.x - w.y * g.y) / den, (w.x * g.y + w.y * g.x) / den};
+  }
+  if (!(isfinite(gR.x) && isfinite(gR.y))) bad = true;
+  a.gR[size_t(b) * N + n] = gR;
+}
+
 // The regularisers anchored at pixel n of the image c (Eqs. 17-19): adds their
-// values to vb, vt, vr, writes g_R = conj(1 / (beta (1 - R)^2)) g_chi (g_chi
-// itself with graw, zero with R held fixed) and tracks max |R| and non-finite
-// gradients.
+// values to vb, vt, vr and writes g_R from their gradient g_chi at n (its own
+// terms, then those anchored at its left and upper neighbours).
 template <typename T>
 __device__ __forceinline__ void reg_pixel(const RegArgs<T>& a, const cx<T>* c, int b, int n, double& vb, double& vt,
                                           double& vr, double& rmax, bool& bad) {
@@ -501,20 +520,7 @@ __device__ __forceinline__ void reg_pixel(const RegArgs<T>& a, const cx<T>* c, i
   cx<T> g = t0.g_self;
   if (j > 0) g = g + reg_term<T>(c, i, j - 1, M, a).g_right;
   if (i > 0) g = g + reg_term<T>(c, i - 1, j, M, a).g_down;
-  const cx<T> R = a.R[size_t(b) * N + n];
-  rmax = fmax(rmax, sqrt(double(norm2(R))));
-  cx<T> gR{T(0), T(0)};
-  if (a.graw) {
-    gR = g;
-  } else if (!a.r_stopgrad) {
-    // conj(1 / (beta (1 - R)^2)) * g
-    const cx<T> om{T(1) - R.x, -R.y};
-    const cx<T> w = om * om;
-    const T den = T(a.beta) * norm2(w);
-    gR = cx<T>{(w.x * g.x - w.y * g.y) / den, (w.x * g.y + w.y * g.x) / den};
-  }
-  if (!(isfinite(gR.x) && isfinite(gR.y))) bad = true;
-  a.gR[size_t(b) * N + n] = gR;
+  reg_grad_out(a, b, n, a.R[size_t(b) * N + n], g, rmax, bad);
 }
 
 // The loss row of instance b from the block sums (thread 0); ls: the sum of
@@ -541,25 +547,72 @@ __device__ __forceinline__ void reg_finish(const RegArgs<T>& a, int b, double ls
   L[7] = (isfinite(tot) && nb == 0.0) ? 0.0 : 1.0;
 }
 
+// Pixels per thread of the one-workgroup regulariser: grids up to 96 x 96 in
+// FP32 and 64 x 64 in FP64 at 1024 threads (larger ones take k_image_reg_part).
+template <typename T>
+constexpr int reg_pix_max() { return sizeof(T) == 4 ? 9 : 4; }
+
 // One instance per block: data residual and L^Data from the split-K parts,
 // L^State from its partial sums, the three regularisers on chi with their
-// gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.  chi staged in LDS.
+// gradient g_chi, and g_R = conj(1 / (beta (1 - R)^2)) g_chi.  chi staged in
+// LDS.  Each pixel's terms are evaluated once; the parts of their gradient that
+// belong to the right and lower neighbours reach those through LDS, and each
+// pixel adds them in the same order as evaluating the neighbours' terms again.
+// LDS: 2 N complex values and 16 doubles; N <= reg_pix_max<T>() x blockDim.x.
 template <typename T>
 __device__ __forceinline__ void image_reg_body(const RegArgs<T>& a, int b, unsigned char* smem_raw) {
+  constexpr int PMAX = reg_pix_max<T>();
   const int M = a.M, N = M * M;
-  const cx<T>* c = reinterpret_cast<const cx<T>*>(smem_raw);   // chi [M][M]
-  double* red = reinterpret_cast<double*>(smem_raw + sizeof(cx<T>) * size_t(N));
+  cx<T>* cs = reinterpret_cast<cx<T>*>(smem_raw);   // chi [M][M], then the g_down parts
+  cx<T>* xs = cs + N;                                // the g_right parts
+  double* red = reinterpret_cast<double*>(xs + N);
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) reg_count_step(a, b);
+  for (int n = tid; n < N; n += nt) cs[n] = a.chi[size_t(b) * N + n];
+  cx<T> Rv[PMAX], g[PMAX], gd[PMAX];
+#pragma unroll
+  for (int q = 0; q < PMAX; ++q) {
+    const int n = tid + q * nt;
+    Rv[q] = n < N ? a.R[size_t(b) * N + n] : cx<T>{T(0), T(0)};
+  }
   double dsum = 0.0;
   const int NO = a.nfreq > 1 ? 0 : a.Ni * a.Ns;
   for (int o = tid; o < NO; o += nt) dsum += reg_data(a, b, o, NO);
-  cx<T>* cs = reinterpret_cast<cx<T>*>(smem_raw);
-  for (int n = tid; n < N; n += nt) cs[n] = a.chi[size_t(b) * N + n];
   __syncthreads();
   double vb = 0, vt = 0, vr = 0, rmax = 0;
   bool bad = false;
-  for (int n = tid; n < N; n += nt) reg_pixel(a, c, b, n, vb, vt, vr, rmax, bad);
+#pragma unroll
+  for (int q = 0; q < PMAX; ++q) {
+    const int n = tid + q * nt;
+    g[q] = gd[q] = cx<T>{T(0), T(0)};
+    if (n < N) {
+      const RegTerm<T> t = reg_term<T>(cs, n / M, n % M, M, a);
+      vb += t.val_bound;
+      vt += t.val_tv;
+      vr += t.val_bridge;
+      g[q] = t.g_self;
+      gd[q] = t.g_down;
+      xs[n] = t.g_right;
+    }
+  }
+  __syncthreads();  // chi read, every g_right written
+#pragma unroll
+  for (int q = 0; q < PMAX; ++q) {
+    const int n = tid + q * nt;
+    if (n < N) {
+      if (n % M > 0) g[q] = g[q] + xs[n - 1];
+      cs[n] = gd[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PMAX; ++q) {
+    const int n = tid + q * nt;
+    if (n < N) {
+      if (n >= M) g[q] = g[q] + cs[n - M];
+      reg_grad_out(a, b, n, Rv[q], g[q], rmax, bad);
+    }
+  }
   const double Sd = block_sum(dsum, red);
   const double Sb = block_sum(vb, red);
   const double St = block_sum(vt, red);
