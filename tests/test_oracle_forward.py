@@ -2,6 +2,7 @@
 agreement, reciprocity, Born limit, the CIE data equation, noise level."""
 import numpy as np
 import pytest
+from scipy import special
 
 import seeded_inputs as si
 from oracle import forward, operators as ops
@@ -124,3 +125,61 @@ def test_position_errors_change_the_data_linearly_in_sigma():
         e, _ = forward.mom_solve(eps, wl.side, k0, tx + sg * dt, rx + sg * dr)
         ch.append(np.linalg.norm(e - e0) / np.linalg.norm(e0))
     assert abs(ch[1] / ch[0] - 2.0) < 0.01
+
+
+def _shift_case(M=16):
+    """A disc well inside a 16 x 16 grid (the border rows and columns stay background)."""
+    eps = si.rasterize([disc(2.5, r=0.3, c=(0.05, -0.1))], M, WL.side)
+    assert np.all(eps[0] == 1) and np.all(eps[-1] == 1) and np.all(eps[:, 0] == 1) and np.all(eps[:, -1] == 1)
+    return eps, WL.side / M
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_antenna_displacement_equals_object_shift(axis):
+    """What the antenna-position study rests on (Sec. 4): the scattered field depends only on where
+    the antennas are relative to the object.  Every Tx and Rx moved by one pixel width h along x
+    (axis 1: column index) or y (axis 0: row index) sees the same field as the fixed antennas with
+    the object moved by -h, which on the pixel grid is the raster shifted by one index.  The MoM
+    matrix depends only on pixel offsets, so the two solves agree to rounding once each source's
+    amplitude is divided out (a source is normalised to unit field magnitude at the grid centre,
+    so moving it changes its amplitude by |H_0(k0 r_c)| / |H_0(k0 r_c')|); swapping x and y in the
+    pixel centres, or the sign of a displacement, breaks it."""
+    eps, h = _shift_case()
+    tx = si.antenna_positions(8, WL.radius)
+    rx = si.antenna_positions(12, WL.radius)
+    d = np.zeros(2)
+    d[1 - axis] = h                     # (x, y) displacement: axis 1 -> x, axis 0 -> y
+    amp = lambda t: 1.0 / np.abs(special.hankel1(0, K0 * np.hypot(t[:, 0], t[:, 1])))[:, None]
+    moved, _ = forward.mom_solve(eps, WL.side, K0, tx + d, rx + d)
+    moved = moved / amp(tx + d)
+    shifted = np.roll(eps, -1, axis=axis)   # eps'(r) = eps(r + d)
+    fixed, _ = forward.mom_solve(shifted, WL.side, K0, tx, rx)
+    fixed = fixed / amp(tx)
+    scale = np.max(np.abs(fixed))
+    assert np.max(np.abs(moved - fixed)) < 1e-11 * scale
+    # and the displacement matters at all: the unshifted object gives another field
+    base, _ = forward.mom_solve(eps, WL.side, K0, tx, rx)
+    base = base / amp(tx)
+    assert np.max(np.abs(moved - base)) > 1e-3 * scale
+    # the other axis's shift does not reproduce it
+    other, _ = forward.mom_solve(np.roll(eps, -1, axis=1 - axis), WL.side, K0, tx, rx)
+    other = other / amp(tx)
+    assert np.max(np.abs(moved - other)) > 1e-3 * scale
+
+
+def test_data_change_is_linear_in_small_position_errors():
+    """The field is smooth in the antenna positions, so the relative data change
+    ||E(x0 + s u) - E(x0)|| / ||E(x0)|| of one displacement direction u grows linearly in s for
+    displacements far below a wavelength (first order of the Taylor expansion; the mm-scale study
+    reports it per sigma)."""
+    eps, _ = _shift_case()
+    tx = si.antenna_positions(8, WL.radius)
+    rx = si.antenna_positions(12, WL.radius)
+    dt, dr = si.draw_position_errors(7, 8, 12, 1.0)     # direction; unit standard deviation
+    e0, _ = forward.mom_solve(eps, WL.side, K0, tx, rx)
+    ch = []
+    for s in (1e-3, 2e-3, 3e-3):
+        e, _ = forward.mom_solve(eps, WL.side, K0, tx + s * dt, rx + s * dr)
+        ch.append(np.linalg.norm(e - e0) / np.linalg.norm(e0))
+    assert 1e-4 < ch[0] < 1e-1
+    assert abs(ch[1] / ch[0] - 2.0) < 0.02 and abs(ch[2] / ch[0] - 3.0) < 0.03
