@@ -373,6 +373,9 @@ def main():
     ap.add_argument("--warm-pairs", type=int, default=20000,
                     help="training pairs of the warm-start network (0: skip the warm-start leg)")
     ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--mlp-forward-only", type=int, default=0, metavar="CALLS",
+                    help="only time this many forwards of 256 rows through the warm-start network (seeded "
+                         "weights, seeded inputs, no data synthesis) and print the per-call time")
     ap.add_argument("--fcnn-iters", type=int, default=300,
                     help="Adam steps of the coefficient-network leg (0: skip it)")
     ap.add_argument("--fcnn-hidden", type=int, default=256, help="hidden width of the coefficient network")
@@ -418,6 +421,9 @@ def main():
     import seeded_inputs as si
 
     dev = "cuda:0"
+    if args.mlp_forward_only:
+        print(json.dumps(mlp_forward_only(pdf, si, args.mlp_forward_only, dev)))
+        return
     wl = si.WORKLOADS["cfg2"]
     B = args.batch
     t0 = time.time()
@@ -1106,6 +1112,32 @@ def large_leg(pdf, si, iters, dev, fields=None):
                 adjoint="recompute mode: the adjoint keeps no FFT intermediates of the forward pass (only J "
                         "and E) and recomputes its transforms",
                 data="FP64 MoM on the 256x256 inversion grid per frequency, 5 % noise; cfg5 profile seed 0")
+
+
+def mlp_forward_only(pdf, si, calls, dev):
+    """Forward passes of 256 rows through the warm-start network at its trained widths (the
+    flattened 32 x 32 complex field in, 32 x 15 x 15 complex coefficients out), with seeded weights
+    and inputs: its kernels without the data synthesis the trained network needs."""
+    import torch
+    from paper_2602_13805_amd import warmstart
+    wl = si.WORKLOADS["cfg2"]
+    sizes = [2 * wl.n_tx * wl.n_rx, *warmstart.HIDDEN, 2 * wl.n_tx * wl.K * wl.K]
+    net = pdf.Mlp(sizes, 256, device=dev)
+    net.init_weights(1)
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn(256, sizes[0], generator=g).to(dev)
+    for _ in range(5):
+        net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        net.forward(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / calls
+    flops = 2.0 * 256 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    net.close()
+    return dict(widths=sizes, rows=256, calls=calls, us_per_call=dt * 1e6, tflops_per_call=flops / dt / 1e12,
+                note="per call, host marshalling included; the kernels' own durations come from a kernel trace")
 
 
 def floor_bytes(M, n_tx, n_rx, K, csz=8):
